@@ -1,0 +1,187 @@
+"""Benchmark: TensorNet energy+forces atom-steps/s on one MI355X.
+
+One step = one full energy-and-forces evaluation (cell-list neighbour search,
+embedding, interaction layers, output network, reverse sweep for forces) of
+the periodic 6000-atom box (hidden 128, 2 layers, 32 RBF, cutoff 5 A) with all
+inputs resident in HBM.  Prints one JSON line on stdout.
+
+The timed variants are the fused path (FP32, BF16) and the plain unfused path
+(FP32).  `value` is the fused FP32 path when it is available.  Each variant's
+result is compared with the FP64 oracle's stored energies and forces.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TensorNet energy+forces atom-steps/s, fused vs plain, at stated force error"
+PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp64": 78.6e12}   # dense MFMA peaks, FLOP/s
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops_per_atom_step(F, K, L, p):
+    """Forward FLOPs per atom (edge filter once per unordered pair, p = pairs/atom); E+F = 2x."""
+    fwd = (p * (6 * K * F + L * 2 * (K * F + 2 * F * F + 6 * F * F)) + 2 * p * 20 * F + L * 2 * p * 18 * F
+           + 34 * F * F + L * (36 * F * F + 162 * F) + 2 * (3 * F * F + F * F / 2 + F / 2))
+    return 2.0 * fwd
+
+
+def edge_filter_flops_per_pair(F, K):
+    return 2.0 * (K * F + 2 * F * F + 6 * F * F)
+
+
+# dominant kernel of each path: (timer name, algorithmic FLOP per unordered pair per launch)
+def dominant(path, F, K):
+    if path == "plain":
+        return "plain_edge_gemm_c", 2.0 * (2 * F) * (3 * F)
+    return "edge_fwd", edge_filter_flops_per_pair(F, K)
+
+
+def cpu_baseline(n_atoms, F, K, L, r_c, seed):
+    import numpy as np
+    import torch
+    from oracle import TensorNetOracle
+    from synth import make_weights, periodic_box, write_blob
+    box_in = periodic_box(n_atoms, seed=5001)
+    o = TensorNetOracle(write_blob(make_weights(F, K, L, 100, seed=seed), F, K, L, 100, r_c))
+    pairs = o.pairs(box_in["pos"], box_in["batch"], box_in["box"])
+    t = time.perf_counter()
+    o.energy_forces(box_in["pos"], box_in["z"], box_in["batch"], box_in["box"], 1, pairs=pairs)
+    dt = time.perf_counter() - t
+    return dict(value=n_atoms / dt, unit="atom-steps/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"one FP64 energy+forces evaluation of a {n_atoms}-atom periodic box at 0.1 atoms/A^3 "
+                       f"(same model sizes, {len(pairs)} pairs), {dt:.1f} s incl. autograd; neighbour list excluded")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--variants", default="fused:fp32,fused:bf16,plain:fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-atoms", type=int, default=1000)
+    ap.add_argument("--budget", type=float, default=1.05, help="max_pairs = budget * true pair count")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); run it with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2402_17660_amd import TensorNet, TensorNetError, lib
+    from synth import make_config, make_weights, write_blob
+
+    cfg = 1
+    c = make_config(cfg)
+    F, K, L, r_c = c["F"], c["K"], c["L"], c["r_c"]
+    N = len(c["pos"])
+    dev = torch.device("cuda", 0)
+    blob = write_blob(make_weights(F, K, L, c["max_z"], seed=c["weight_seed"]), F, K, L, c["max_z"], r_c)
+    model = TensorNet(blob, dev)
+    pos = torch.tensor(c["pos"], device=dev)
+    z = torch.tensor(c["z"], device=dev)
+    batch = torch.tensor(c["batch"], device=dev)
+    box = c["box"]
+    golden = np.load(os.path.join(ROOT, "tests", "golden", f"oracle_cfg{cfg}.npz"))
+
+    # static pair budget from one untimed call
+    model.energy_forces(pos, z, batch, 1, box=box, max_pairs=64 * N, precision="fp32", path="plain")
+    n_pairs = int(model.n_pairs.item())
+    max_pairs = int(math.ceil(args.budget * n_pairs / 1024.0) * 1024)
+    log(f"workload: N={N} pairs={n_pairs} max_pairs={max_pairs}")
+
+    L_ = lib()
+    results = []
+    for spec in args.variants.split(","):
+        path, prec = spec.split(":")
+        try:
+            E_out = torch.empty(1, dtype=torch.float64, device=dev)
+            F_out = torch.empty((N, 3), dtype=torch.float32, device=dev)
+            run = lambda: model.energy_forces(pos, z, batch, 1, box=box, max_pairs=max_pairs, precision=prec,
+                                              path=path, check=False, energy_out=E_out, forces_out=F_out)
+            run()
+            model.check()
+        except TensorNetError as e:
+            log(f"{path}/{prec}: unavailable ({e})")
+            results.append(dict(path=path, precision=prec, available=False))
+            continue
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        timer, flop_per_pair = dominant(path, F, K)
+        L_.tn_timing_reset()
+        L_.tn_timing_enable(1)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            run()
+        stop.record()
+        torch.cuda.synchronize()
+        L_.tn_timing_enable(0)
+        ms = start.elapsed_time(stop) / args.steps
+        import ctypes
+        tot, cnt = ctypes.c_double(), ctypes.c_int64()
+        L_.tn_timing_read(timer.encode(), ctypes.byref(tot), ctypes.byref(cnt))
+        model.check()
+        E = E_out.cpu().numpy()
+        Fo = F_out.double().cpu().numpy()
+        e_err = float(np.max(np.abs(E - golden["E"]) / np.abs(golden["E"])))
+        f_err = float(np.linalg.norm(Fo - golden["F"]) / np.linalg.norm(golden["F"]))
+        kernel_ms = tot.value / max(cnt.value, 1)
+        flop_per_launch = flop_per_pair * n_pairs
+        achieved = flop_per_launch / (kernel_ms * 1e-3) if cnt.value else None
+        peak = PEAK[prec]
+        res = dict(path=path, precision=prec, available=True, ms_per_step=ms, value=N / (ms * 1e-3),
+                   energy_rel_err=e_err, force_rel_rms=f_err,
+                   kernel=dict(name=timer, launches_per_step=cnt.value / args.steps, avg_ms=kernel_ms,
+                               flop_per_launch=flop_per_launch,
+                               achieved_tflops=(achieved / 1e12) if achieved else None, peak_tflops=peak / 1e12))
+        log(f"{path}/{prec}: {ms:.3f} ms/step, {res['value']:.3e} atom-steps/s, E err {e_err:.2e}, "
+            f"F err {f_err:.2e}, {timer} {kernel_ms:.3f} ms/launch")
+        results.append(res)
+
+    avail = [r for r in results if r.get("available")]
+    head = next((r for r in avail if r["path"] == "fused" and r["precision"] == "fp32"), None) or avail[0]
+    k = head["kernel"]
+    roofline = dict(bound="mfma", achieved=k["achieved_tflops"], peak=k["peak_tflops"], unit="TFLOP/s",
+                    frac=(k["achieved_tflops"] / k["peak_tflops"]) if k["achieved_tflops"] else None, traffic=None,
+                    kernel=k["name"], avg_launch_ms=k["avg_ms"], flop_per_launch=k["flop_per_launch"])
+    p_atom = n_pairs / N
+    step_flop = algorithmic_flops_per_atom_step(F, K, L, p_atom) * N
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host ...")
+        cpu = cpu_baseline(args.cpu_atoms, F, K, L, r_c, c["weight_seed"])
+    out = dict(metric=METRIC, value=head["value"], unit="atom-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32" if head["precision"] == "fp32" else head["precision"],
+               data="synthetic",
+               config=dict(workload="periodic cubic box, 6000 atoms at 0.1/A^3, Z in {H,C,N,O}; TensorNet hidden 128, "
+                                    "2 layers, 32 RBF, cutoff 5 A; energy+forces incl. cell-list neighbour search",
+                           n_atoms=N, n_pairs=n_pairs, max_pairs=max_pairs, path=head["path"],
+                           precision=head["precision"]),
+               roofline=roofline, cpu_baseline=cpu,
+               step_algorithmic_tflop=step_flop / 1e12,
+               step_tflops=step_flop / (head["ms_per_step"] * 1e-3) / 1e12,
+               errors=dict(energy_rel=head["energy_rel_err"], force_rel_rms=head["force_rel_rms"]),
+               variants=results)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,144 @@
+/*
+ * tensornet.h - C ABI of the MI355X TensorNet energy-and-forces library.
+ *
+ * One TensorNet evaluation (TorchMD-Net 2.0, arXiv 2402.17660): the neighbour
+ * search of Sec. 2.5.1 (cell list with rectangular periodic boundaries, or a
+ * brute-force search inside each isolated system), the TensorNet network of
+ * Sec. 2.1.1 with the hyper-parameters of Sec. 2.4, and forces as the negative
+ * position gradient of the per-system energy (Sec. 2, model composition).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller, except
+ *     `box` and `blob`, which are host pointers.  The library allocates no
+ *     memory per call: scratch space is the caller's `ws` buffer, sized by the
+ *     matching *_workspace_bytes query.
+ *   - `stream` is a hipStream_t passed as void*.  All work is enqueued on it
+ *     and no call synchronises the host, so every call may be captured into a
+ *     HIP graph (pointers and sizes stay fixed across replays).
+ *   - Return value: TN_OK (0) or a negative tn_status for errors that the host
+ *     can see without reading device memory (bad arguments, box too small,
+ *     bad blob, HIP launch failure).  Data-dependent errors are OR-ed into the
+ *     device word `*status` (TN_STATUS_* bits) which the call first clears;
+ *     read it after your own synchronisation.  Outputs are undefined whenever
+ *     the return value or *status is non-zero.
+ *   - Positions are angstrom, energies eV, forces eV/angstrom.  `box` is a
+ *     row-major 3x3 of lattice vectors; only rectangular boxes (zero
+ *     off-diagonal entries) are accepted, each side at least twice the cutoff
+ *     (the minimum image is then unique).  box == NULL means isolated systems.
+ *   - `batch[i]` is the system index of atom i.  It must be sorted ascending
+ *     (systems contiguous) with values in [0, n_systems); violations set
+ *     TN_STATUS_BATCH.  Systems never interact (Sec. 2.5.1).
+ */
+#ifndef TENSORNET_H
+#define TENSORNET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tn_model tn_model;
+
+typedef enum {
+  TN_OK = 0,
+  TN_E_ARG = -1,        /* invalid argument (null pointer, size, enum, non-rectangular box) */
+  TN_E_BLOB = -2,       /* weight blob: bad magic, version, size or hyper-parameters */
+  TN_E_HIP = -3,        /* a HIP runtime call or kernel launch failed */
+  TN_E_BOX = -4,        /* a box side is shorter than twice the cutoff */
+  TN_E_WORKSPACE = -5,  /* ws_bytes smaller than the workspace query returned */
+  TN_E_UNSUPPORTED = -6 /* valid request this build does not implement (e.g. precision/path pair) */
+} tn_status;
+
+/* Bits of the device status word. */
+#define TN_STATUS_OVERFLOW 1   /* more pairs than max_pairs; *n_pairs holds the true count */
+#define TN_STATUS_BATCH 2      /* batch not sorted, or outside [0, n_systems) */
+#define TN_STATUS_Z 4          /* atomic number outside [0, max_z) */
+#define TN_STATUS_NONFINITE 8  /* non-finite position or energy */
+
+typedef enum { TN_FP32 = 0, TN_BF16 = 1, TN_FP64 = 2 } tn_precision;
+typedef enum { TN_FUSED = 0, TN_PLAIN = 1 } tn_path;
+
+/* Status code to a static English string. */
+const char *tn_status_string(int status);
+
+/* ---------------------------------------------------------------- model ---
+ * tn_model_create: parse a weight blob (host bytes, copied) and upload the
+ * weights to `device` in FP64, FP32 and BF16.  Blob layout: 8-byte magic
+ * "TNETBLOB", u32 version (1), F, K, L, max_z, activation (1 = SiLU), two
+ * reserved u32, f64 r_lo, f64 r_c, then the float64 tensors in the fixed order
+ * of the generator (embedding, L interaction layers, output network).
+ * Errors: TN_E_ARG (null pointers), TN_E_BLOB (format), TN_E_HIP (upload).
+ * The model is owned by the caller and freed by tn_model_destroy. */
+int tn_model_create(const void *blob, size_t blob_bytes, int device, tn_model **out);
+void tn_model_destroy(tn_model *m);
+
+/* Hyper-parameters of a created model (any pointer may be NULL). */
+int tn_model_info(const tn_model *m, int32_t *F, int32_t *K, int32_t *L, int32_t *max_z,
+                  double *r_lo, double *r_c);
+
+/* ------------------------------------------------------ neighbour search ---
+ * The unordered pair set {(i,j) : i<j, batch_i == batch_j, d_ij^2 < cutoff^2}
+ * (Sec. 2.5.1), d by the minimum image when `box` is given.  The decision is
+ * taken in FP64 on the positions promoted to FP64:
+ *   v_a = D_a - L_a * rint(D_a / L_a),  D_a = x_ja - x_ia  (box only)
+ *   d^2 = (v_x*v_x + v_y*v_y) + v_z*v_z  (each product rounded, no FMA)
+ * box != NULL: one cell list over all systems (cells of side >= cutoff).
+ * box == NULL: brute force over the atoms of each system.
+ * Output: pairs[0][p], pairs[1][p] (int32, layout [2, max_pairs]) for
+ * p < *n_pairs, sorted by (i, j); slots p >= *n_pairs hold -1.  *n_pairs
+ * (device int64) is always the true count; if it exceeds max_pairs,
+ * TN_STATUS_OVERFLOW is set and `pairs` is only padding.
+ * pos: [n_atoms, 3] float32 (pos_f64 == 0) or float64 (pos_f64 != 0). */
+size_t tn_neighbor_workspace_bytes(int64_t n_atoms, int64_t max_pairs, const double *box, double cutoff);
+int tn_build_neighbors(void *stream, int64_t n_atoms, const void *pos, int pos_f64, const int32_t *batch,
+                       const double *box, double cutoff, int64_t max_pairs, int32_t *pairs, int64_t *n_pairs,
+                       int32_t *status, void *ws, size_t ws_bytes);
+
+/* -------------------------------------------------------------- energies ---
+ * tn_workspace_bytes returns the ws size needed by tn_energy (want_forces 0)
+ * or tn_energy_forces (want_forces 1) for these sizes, box and cutoff, or 0
+ * for an invalid request.
+ * Per-system energies E_s = sum over atoms of system s of the per-atom output
+ * of the network (Sec. 2: representation model -> scalar output model ->
+ * sum aggregation), accumulated in FP64.  The neighbour search above runs
+ * inside the call with the model's cutoff.
+ *   pos     [n_atoms, 3]: float64 for TN_FP64, float32 otherwise
+ *   z       [n_atoms] int32 atomic numbers (embedding rows), < max_z
+ *   batch   [n_atoms] int32 sorted system index
+ *   energy  [n_systems] float64 output
+ * precision: TN_FP64 (plain path only), TN_FP32, TN_BF16 (GEMM operands in
+ * BF16, FP32 accumulation; fused path only).  path: TN_FUSED or TN_PLAIN
+ * (one kernel per operation, every intermediate through memory). */
+size_t tn_workspace_bytes(const tn_model *m, int64_t n_atoms, int64_t n_systems, int64_t max_pairs,
+                          const double *box, int precision, int path, int want_forces);
+int tn_energy(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, const void *pos,
+              const int32_t *z, const int32_t *batch, const double *box, int64_t max_pairs, int precision,
+              int path, double *energy, int64_t *n_pairs, int32_t *status, void *ws, size_t ws_bytes);
+
+/* Energies and forces F = -dE/dpos (Sec. 2): a hand-written reverse sweep of
+ * the network that recomputes the per-pair geometry, cutoff and radial basis,
+ * with the per-pair position gradients summed per atom in FP64.
+ *   forces [n_atoms, 3]: float64 for TN_FP64, float32 otherwise. */
+int tn_energy_forces(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, const void *pos,
+                     const int32_t *z, const int32_t *batch, const double *box, int64_t max_pairs,
+                     int precision, int path, double *energy, void *forces, int64_t *n_pairs, int32_t *status,
+                     void *ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------ diagnostics ---
+ * Kernel timing for measurement tools.  While enabled, the library records a
+ * HIP event pair on the launch stream around every launch of a timed kernel
+ * (the dominant pair-tile kernels; names such as "edge_fwd").  tn_timing_read
+ * waits for the recorded events and returns the summed duration (ms) and the
+ * number of launches since the last reset.  Not for use under graph capture.
+ * Returns TN_OK, TN_E_ARG (unknown name / null pointers) or TN_E_HIP. */
+int tn_timing_enable(int on);
+int tn_timing_reset(void);
+int tn_timing_read(const char *name, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TENSORNET_H */

@@ -1,0 +1,205 @@
+"""Python binding over the C ABI: argument marshalling only.
+
+Torch tensors provide device memory and the current HIP stream; every step of
+the computation runs in libtensornet.so.  There is no CPU fallback: without
+the built library or a GPU these functions raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PREC = {"fp32": L.TN_FP32, "bf16": L.TN_BF16, "fp64": L.TN_FP64}
+_PATH = {"fused": L.TN_FUSED, "plain": L.TN_PLAIN}
+
+
+class TensorNetError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != L.TN_OK:
+        raise TensorNetError(f"{what}: {L.status_string(rc)} ({rc})")
+
+
+def _status_bits(word: int) -> str:
+    names = [(L.TN_STATUS_OVERFLOW, "pair overflow"), (L.TN_STATUS_BATCH, "bad batch vector"),
+             (L.TN_STATUS_Z, "atomic number out of range"), (L.TN_STATUS_NONFINITE, "non-finite value")]
+    return ", ".join(n for b, n in names if word & b) or "ok"
+
+
+def _box_arg(box):
+    if box is None:
+        return None, None
+    arr = (ctypes.c_double * 9)(*np.asarray(box, dtype=np.float64).reshape(9).tolist())
+    return arr, ctypes.cast(arr, ctypes.c_void_p)
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require_device(t: torch.Tensor, name: str, dtype, device):
+    if not t.is_cuda or t.device != device:
+        raise TensorNetError(f"{name} must live on {device}")
+    if t.dtype != dtype:
+        raise TensorNetError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise TensorNetError(f"{name} must be contiguous")
+
+
+class Workspace:
+    """Grow-only device scratch buffer (a uint8 tensor)."""
+
+    def __init__(self, device):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def build_neighbors(pos: torch.Tensor, batch: torch.Tensor, cutoff: float, max_pairs: int, box=None,
+                    check: bool = True, ws: Workspace | None = None):
+    """Unordered neighbour pairs (tn_build_neighbors): returns (pairs [2, max_pairs] int32, n_pairs, status)."""
+    device = pos.device
+    pos_f64 = pos.dtype == torch.float64
+    _require_device(pos, "pos", torch.float64 if pos_f64 else torch.float32, device)
+    _require_device(batch, "batch", torch.int32, device)
+    n = pos.shape[0]
+    boxarr, boxp = _box_arg(box)
+    nbytes = L.lib().tn_neighbor_workspace_bytes(n, max_pairs, boxp, float(cutoff))
+    if nbytes == 0:
+        raise TensorNetError("invalid neighbour-search request (box or sizes)")
+    ws = ws or Workspace(device)
+    buf = ws.get(nbytes)
+    pairs = torch.empty((2, max_pairs), dtype=torch.int32, device=device)
+    n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
+    status = torch.zeros(1, dtype=torch.int32, device=device)
+    rc = L.lib().tn_build_neighbors(_stream(device), n, _ptr(pos), int(pos_f64), _ptr(batch), boxp, float(cutoff),
+                                    max_pairs, _ptr(pairs), _ptr(n_pairs), _ptr(status), _ptr(buf), buf.numel())
+    _check(rc, "tn_build_neighbors")
+    if check:
+        word = int(status.item())
+        if word & ~L.TN_STATUS_OVERFLOW:
+            raise TensorNetError(f"neighbour search: {_status_bits(word)}")
+    return pairs, n_pairs, status
+
+
+class TensorNet:
+    """A TensorNet model on one GPU (tn_model_create over a weight blob)."""
+
+    def __init__(self, blob: bytes, device: int | str | torch.device = 0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self._blob = bytes(blob)
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(self._blob, len(self._blob))
+        _check(L.lib().tn_model_create(ctypes.cast(buf, ctypes.c_void_p), len(self._blob), self.device.index,
+                                       ctypes.byref(h)), "tn_model_create")
+        self._h = h
+        F, K, Ly, Z = (ctypes.c_int32() for _ in range(4))
+        rlo, rc = ctypes.c_double(), ctypes.c_double()
+        _check(L.lib().tn_model_info(self._h, ctypes.byref(F), ctypes.byref(K), ctypes.byref(Ly), ctypes.byref(Z),
+                                     ctypes.byref(rlo), ctypes.byref(rc)), "tn_model_info")
+        self.F, self.K, self.L, self.max_z = F.value, K.value, Ly.value, Z.value
+        self.r_lo, self.r_c = rlo.value, rc.value
+        self.ws = Workspace(self.device)
+        self.n_pairs = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().tn_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, n_atoms, n_systems, max_pairs, box=None, precision="fp32", path="fused",
+                        forces=True) -> int:
+        _, boxp = _box_arg(box)
+        return int(L.lib().tn_workspace_bytes(self._h, n_atoms, n_systems, max_pairs, boxp, _PREC[precision],
+                                              _PATH[path], int(forces)))
+
+    def _run(self, pos, z, batch, n_systems, box, max_pairs, precision, path, forces, check, energy_out=None,
+             forces_out=None):
+        dev = self.device
+        pdt = torch.float64 if precision == "fp64" else torch.float32
+        _require_device(pos, "pos", pdt, dev)
+        _require_device(z, "z", torch.int32, dev)
+        _require_device(batch, "batch", torch.int32, dev)
+        n = pos.shape[0]
+        if max_pairs is None:
+            max_pairs = max(64 * n, 1)
+        boxarr, boxp = _box_arg(box)
+        nbytes = L.lib().tn_workspace_bytes(self._h, n, n_systems, max_pairs, boxp, _PREC[precision], _PATH[path],
+                                            int(forces))
+        if nbytes == 0:
+            raise TensorNetError(f"invalid request (precision={precision}, path={path}, box, sizes)")
+        buf = self.ws.get(nbytes)
+        E = energy_out if energy_out is not None else torch.empty(n_systems, dtype=torch.float64, device=dev)
+        args_head = (self._h, _stream(dev), n, n_systems, _ptr(pos), _ptr(z), _ptr(batch), boxp, max_pairs,
+                     _PREC[precision], _PATH[path], _ptr(E))
+        if forces:
+            Fo = forces_out if forces_out is not None else torch.empty((n, 3), dtype=pdt, device=dev)
+            rc = L.lib().tn_energy_forces(*args_head, _ptr(Fo), _ptr(self.n_pairs), _ptr(self.status), _ptr(buf),
+                                          buf.numel())
+            _check(rc, "tn_energy_forces")
+        else:
+            Fo = None
+            rc = L.lib().tn_energy(*args_head, _ptr(self.n_pairs), _ptr(self.status), _ptr(buf), buf.numel())
+            _check(rc, "tn_energy")
+        if check:
+            self.check()
+        return E, Fo
+
+    def check(self):
+        """Synchronise and raise if the device status word is non-zero."""
+        word = int(self.status.item())
+        if word:
+            raise TensorNetError(f"device status {word}: {_status_bits(word)} (n_pairs={int(self.n_pairs.item())})")
+
+    def energy(self, pos, z, batch, n_systems, box=None, max_pairs=None, precision="fp32", path="fused",
+               check=True, out=None):
+        return self._run(pos, z, batch, n_systems, box, max_pairs, precision, path, False, check, energy_out=out)[0]
+
+    def energy_forces(self, pos, z, batch, n_systems, box=None, max_pairs=None, precision="fp32", path="fused",
+                      check=True, energy_out=None, forces_out=None):
+        return self._run(pos, z, batch, n_systems, box, max_pairs, precision, path, True, check,
+                         energy_out=energy_out, forces_out=forces_out)
+
+
+class TensorNetEF(torch.autograd.Function):
+    """E = TensorNetEF.apply(model, pos, z, batch, n_systems, box, max_pairs, precision, path).
+
+    Backward returns dL/dpos = -F * dL/dE[batch] from the library's forces.
+    """
+
+    @staticmethod
+    def forward(ctx, model, pos, z, batch, n_systems, box, max_pairs, precision, path):
+        E, Fo = model.energy_forces(pos.detach(), z, batch, n_systems, box=box, max_pairs=max_pairs,
+                                    precision=precision, path=path)
+        ctx.save_for_backward(Fo, batch)
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        Fo, batch = ctx.saved_tensors
+        g = -(Fo.to(torch.float64) * gE[batch.long()][:, None]).to(Fo.dtype)
+        return None, g, None, None, None, None, None, None, None

@@ -1,0 +1,155 @@
+// Device-side math shared by the plain and fused paths.
+//
+// Per-atom features are F channels of 3x3 matrices X = t*1 + A0(a) + S(s),
+// stored as nine coordinates per channel in the order
+//   c = 0      t          (scalar part I = t * identity)
+//   c = 1..3   a_x a_y a_z (antisymmetric part, A0(a) w = a x w)
+//   c = 4..8   s_xx s_yy s_xy s_xz s_yz (symmetric traceless part, s_zz = -s_xx - s_yy)
+// so that the per-part channel mixing of TensorNet is one [rows, F] x [F, F]
+// product per coordinate.  The helpers below convert between coordinates and
+// 3x3 matrices and give the adjoints of those linear maps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tn {
+
+constexpr int kCoord = 9;
+
+__host__ __device__ inline int coord_part(int c) { return c == 0 ? 0 : (c < 4 ? 1 : 2); }
+
+__device__ inline float dexp(float x) { return expf(x); }
+__device__ inline double dexp(double x) { return exp(x); }
+__device__ inline float dsqrt(float x) { return sqrtf(x); }
+__device__ inline double dsqrt(double x) { return sqrt(x); }
+__device__ inline float dcos(float x) { return cosf(x); }
+__device__ inline double dcos(double x) { return cos(x); }
+__device__ inline float dsin(float x) { return sinf(x); }
+__device__ inline double dsin(double x) { return sin(x); }
+__device__ inline float drint(float x) { return rintf(x); }
+__device__ inline double drint(double x) { return rint(x); }
+
+// SiLU x*sigmoid(x) and its derivative sigmoid(x) * (1 + x * (1 - sigmoid(x))).
+template <class T> __device__ inline T sigmoid(T x) { return T(1) / (T(1) + dexp(-x)); }
+template <class T> __device__ inline T silu(T x) { return x * sigmoid(x); }
+template <class T> __device__ inline T silu_grad(T x) {
+  T s = sigmoid(x);
+  return s * (T(1) + x * (T(1) - s));
+}
+
+// Coordinates -> row-major 3x3 matrix.
+template <class T> __device__ inline void rec(const T c[9], T X[9]) {
+  const T t = c[0], ax = c[1], ay = c[2], az = c[3];
+  const T xx = c[4], yy = c[5], xy = c[6], xz = c[7], yz = c[8];
+  X[0] = t + xx;  X[1] = -az + xy; X[2] = ay + xz;
+  X[3] = az + xy; X[4] = t + yy;   X[5] = -ax + yz;
+  X[6] = -ay + xz; X[7] = ax + yz; X[8] = t - xx - yy;
+}
+
+// 3x3 matrix -> coordinates of its I, A and S parts.
+template <class T> __device__ inline void dec(const T X[9], T c[9]) {
+  const T t = (X[0] + X[4] + X[8]) * (T(1) / T(3));
+  c[0] = t;
+  c[1] = T(0.5) * (X[7] - X[5]);
+  c[2] = T(0.5) * (X[2] - X[6]);
+  c[3] = T(0.5) * (X[3] - X[1]);
+  c[4] = X[0] - t;
+  c[5] = X[4] - t;
+  c[6] = T(0.5) * (X[1] + X[3]);
+  c[7] = T(0.5) * (X[2] + X[6]);
+  c[8] = T(0.5) * (X[5] + X[7]);
+}
+
+// Adjoint of rec: gradient w.r.t. coordinates from a gradient w.r.t. matrix entries.
+template <class T> __device__ inline void rec_adj(const T G[9], T d[9]) {
+  d[0] = G[0] + G[4] + G[8];
+  d[1] = G[7] - G[5];
+  d[2] = G[2] - G[6];
+  d[3] = G[3] - G[1];
+  d[4] = G[0] - G[8];
+  d[5] = G[4] - G[8];
+  d[6] = G[1] + G[3];
+  d[7] = G[2] + G[6];
+  d[8] = G[5] + G[7];
+}
+
+// Adjoint of dec: gradient w.r.t. matrix entries from a gradient w.r.t. coordinates.
+template <class T> __device__ inline void dec_adj(const T d[9], T G[9]) {
+  const T t3 = d[0] * (T(1) / T(3));
+  const T h = T(0.5);
+  G[0] = t3 + (T(2) * d[4] - d[5]) * (T(1) / T(3));
+  G[4] = t3 + (T(2) * d[5] - d[4]) * (T(1) / T(3));
+  G[8] = t3 - (d[4] + d[5]) * (T(1) / T(3));
+  G[1] = h * (d[6] - d[3]); G[3] = h * (d[6] + d[3]);
+  G[2] = h * (d[7] + d[2]); G[6] = h * (d[7] - d[2]);
+  G[5] = h * (d[8] - d[1]); G[7] = h * (d[8] + d[1]);
+}
+
+// Squared Frobenius norm of rec(c) and its parts.
+template <class T> __device__ inline T norm_I(const T c[9]) { return T(3) * c[0] * c[0]; }
+template <class T> __device__ inline T norm_A(const T c[9]) {
+  return T(2) * (c[1] * c[1] + c[2] * c[2] + c[3] * c[3]);
+}
+template <class T> __device__ inline T norm_S(const T c[9]) {
+  const T zz = c[4] + c[5];
+  return c[4] * c[4] + c[5] * c[5] + zz * zz + T(2) * (c[6] * c[6] + c[7] * c[7] + c[8] * c[8]);
+}
+template <class T> __device__ inline T norm9(const T c[9]) { return norm_I(c) + norm_A(c) + norm_S(c); }
+
+// d(norm)/dc scaled: out[k] = s_I * d norm_I/dc_k + s_A * ... + s_S * ... (s_* per part).
+template <class T> __device__ inline void norm_grad_parts(const T c[9], T sI, T sA, T sS, T out[9]) {
+  out[0] = sI * T(6) * c[0];
+  out[1] = sA * T(4) * c[1];
+  out[2] = sA * T(4) * c[2];
+  out[3] = sA * T(4) * c[3];
+  out[4] = sS * (T(4) * c[4] + T(2) * c[5]);
+  out[5] = sS * (T(4) * c[5] + T(2) * c[4]);
+  out[6] = sS * T(4) * c[6];
+  out[7] = sS * T(4) * c[7];
+  out[8] = sS * T(4) * c[8];
+}
+
+// 3x3 row-major products.
+template <class T> __device__ inline void mm(const T A[9], const T B[9], T C[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) C[r * 3 + q] = A[r * 3] * B[q] + A[r * 3 + 1] * B[3 + q] + A[r * 3 + 2] * B[6 + q];
+}
+// C = A^T B
+template <class T> __device__ inline void mtm(const T A[9], const T B[9], T C[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) C[r * 3 + q] = A[r] * B[q] + A[3 + r] * B[3 + q] + A[6 + r] * B[6 + q];
+}
+// C = A B^T
+template <class T> __device__ inline void mmt(const T A[9], const T B[9], T C[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) C[r * 3 + q] = A[r * 3] * B[q * 3] + A[r * 3 + 1] * B[q * 3 + 1] + A[r * 3 + 2] * B[q * 3 + 2];
+}
+
+// Coordinates of S0(u) = u u^T - 1/3 for a unit vector u.
+template <class T> __device__ inline void s0_coords(T ux, T uy, T uz, T s[5]) {
+  s[0] = ux * ux - T(1) / T(3);
+  s[1] = uy * uy - T(1) / T(3);
+  s[2] = ux * uy;
+  s[3] = ux * uz;
+  s[4] = uy * uz;
+}
+
+// Gradient w.r.t. u of <w, s0_coords(u)> (plain dot over the five coordinates).
+template <class T> __device__ inline void s0_dot_grad(const T w[5], T ux, T uy, T uz, T g[3]) {
+  g[0] = T(2) * w[0] * ux + w[2] * uy + w[3] * uz;
+  g[1] = T(2) * w[1] * uy + w[2] * ux + w[4] * uz;
+  g[2] = w[3] * ux + w[4] * uy;
+}
+
+// Flag a bit in the device status word.
+__device__ inline void set_status(int32_t *status, int32_t bit) {
+  if (status) atomicOr(reinterpret_cast<int *>(status), bit);
+}
+
+}  // namespace tn

@@ -1,0 +1,144 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "tensornet.h"
+
+#define TN_HIP(call)                                                   \
+  do {                                                                 \
+    hipError_t e_ = (call);                                            \
+    if (e_ != hipSuccess) {                                            \
+      std::fprintf(stderr, "tensornet: %s failed: %s (%s:%d)\n", #call, \
+                   hipGetErrorString(e_), __FILE__, __LINE__);         \
+      return TN_E_HIP;                                                 \
+    }                                                                  \
+  } while (0)
+
+#define TN_LAUNCH_CHECK() TN_HIP(hipGetLastError())
+
+namespace tn {
+
+constexpr int kMaxK = 64;          // radial basis functions supported by the kernels
+constexpr int kWsAlign = 256;
+
+// ------------------------------------------------------------------ weights
+struct LayerOff {
+  size_t Wa, ba, Wb, bb, Wc, bc, W1[3], W2[3];
+};
+
+struct WeightOff {
+  size_t E, Wz, bz, W0, b0, ln_g, ln_b, W1, b1, W2, b2, Wmix[3];
+  std::vector<LayerOff> layer;
+  size_t oln_g, oln_b, Wo, bo, Wh, bh, wout, bout;
+  size_t U, V;      // species tables [max_z, F]: Z_ij = U[z_i] + V[z_j]
+  size_t mu, beta;  // radial basis constants [K]
+  size_t total;     // element count of one packed copy
+};
+
+}  // namespace tn
+
+struct tn_model {
+  int device = 0;
+  int F = 0, K = 0, L = 0, max_z = 0;
+  double r_lo = 0.0, r_c = 0.0, alpha = 0.0;
+  tn::WeightOff off;
+  double *w64 = nullptr;           // packed FP64 weights (device)
+  float *w32 = nullptr;            // packed FP32 weights (device)
+  __hip_bfloat16 *w16 = nullptr;   // packed BF16 weights (device)
+};
+
+namespace tn {
+
+template <class T> inline const T *wptr(const tn_model *m, size_t off);
+template <> inline const double *wptr<double>(const tn_model *m, size_t off) { return m->w64 + off; }
+template <> inline const float *wptr<float>(const tn_model *m, size_t off) { return m->w32 + off; }
+
+// ------------------------------------------------------------------ workspace planning
+// Bump allocator: run once with base == nullptr to size the workspace, then
+// again with the caller's buffer to hand out aligned sub-buffers.
+struct WsPlan {
+  char *base = nullptr;
+  size_t off = 0;
+  explicit WsPlan(void *b) : base(static_cast<char *>(b)) {}
+  template <class T> T *take(size_t count) {
+    off = (off + kWsAlign - 1) / kWsAlign * kWsAlign;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T) + kWsAlign;   // keep a guard gap between buffers
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------ neighbour search
+struct BoxInfo {
+  int periodic = 0;
+  double len[3] = {0, 0, 0};
+  int nc[3] = {1, 1, 1};
+  double side[3] = {0, 0, 0};
+};
+
+// Validates the box; returns TN_OK, TN_E_ARG or TN_E_BOX.
+int box_info(const double *box, double cutoff, BoxInfo *bi);
+
+struct NbrWs {
+  int32_t *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr,
+          *cell_atoms = nullptr;
+  int32_t *deg = nullptr, *nup = nullptr;       // [N+1], scanned in place into rowptr / pair base
+  int32_t *nbr = nullptr, *pid = nullptr;       // [2*max_pairs] CSR rows (sorted by neighbour)
+  int32_t *scan_tmp = nullptr;                  // block sums
+  int64_t *count64 = nullptr;                   // [2]: total pairs, total directed edges
+  int32_t *flags = nullptr;                     // [0]: batch vector not sorted
+};
+
+void plan_neighbors(WsPlan &p, int64_t n, int64_t max_pairs, const BoxInfo &bi, NbrWs *w);
+
+// Builds the CSR graph (rowptr = w.deg, nbr, pid), the pair list pairs[0..1][max_pairs]
+// padded with -1, and *n_pairs.  T is the position type.
+template <class T>
+int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *batch, const BoxInfo &bi,
+                    double cutoff, int64_t max_pairs, int32_t *pairs, int64_t *n_pairs, int32_t *status,
+                    const NbrWs &w);
+
+// ------------------------------------------------------------------ scans and fills
+int exclusive_scan_i32(hipStream_t s, int32_t *data, int64_t n, int32_t *block_tmp, int64_t *total_out);
+size_t scan_tmp_count(int64_t n);
+int fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v);
+int fill_bytes_zero(hipStream_t s, void *p, size_t bytes);
+
+// ------------------------------------------------------------------ model paths
+struct Problem {
+  int64_t n = 0, S = 0, max_pairs = 0;
+  const void *pos = nullptr;
+  const int32_t *z = nullptr, *batch = nullptr;
+  BoxInfo box;
+  double *energy = nullptr;
+  void *forces = nullptr;
+  int64_t *n_pairs = nullptr;
+  int32_t *status = nullptr;
+  bool want_forces = false;
+};
+
+size_t plain_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t max_pairs, const BoxInfo &bi, int prec,
+                             int want_forces);
+int plain_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, void *ws, size_t ws_bytes);
+
+size_t fused_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t max_pairs, const BoxInfo &bi, int prec,
+                             int want_forces);
+int fused_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, void *ws, size_t ws_bytes);
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// Event pair around the launches of a named kernel while timing is enabled.
+struct TimedScope {
+  TimedScope(const char *name, hipStream_t s);
+  ~TimedScope();
+  int slot = -1;
+  hipStream_t stream = nullptr;
+};
+
+}  // namespace tn

@@ -1,0 +1,502 @@
+// Neighbour search (Sec. 2.5.1 of the paper): unordered pairs of atoms of the
+// same system closer than the cutoff, minimum image in a rectangular box.
+//
+// MI355X design.  The output is a receiver-major CSR graph that the model
+// kernels consume directly, plus the public [2, max_pairs] pair list:
+//   1. periodic boxes: bin atoms into cells of side >= cutoff (counting sort:
+//      atomic histogram, device scan, scatter); isolated systems: each atom
+//      binary-searches its system's atom range in the sorted batch vector
+//      (no system count or offsets are ever needed on the host);
+//   2. one thread per atom counts its neighbours (full and j > i), two device
+//      scans turn the counts into CSR row offsets and pair offsets; the pair
+//      budget is checked on the device (no host round trip);
+//   3. the rows are written, sorted by neighbour index, and every directed edge
+//      gets the id of its unordered pair (binary search in the partner's row),
+//      which orders the public list by (i, j) and makes it deterministic.
+// Pair writes use scanned offsets instead of one global atomic counter per
+// pair.  The cutoff decision is an FP64 predicate with contraction disabled.
+#include "tn_internal.h"
+#include "tn_device.h"
+
+#include <cmath>
+
+namespace tn {
+
+// ------------------------------------------------------------------ fills
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u8_zero(uint8_t *p, size_t n) {
+  const size_t n4 = n / 4;
+  uint32_t *q = reinterpret_cast<uint32_t *>(p);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) q[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) p[n4 * 4 + threadIdx.x] = 0;
+}
+
+static unsigned fill_grid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 4096) g = 4096;
+  return (unsigned)g;
+}
+
+int fill_i32(hipStream_t s, int32_t *p, int64_t n, int32_t v) {
+  if (n <= 0) return TN_OK;
+  hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(n)), dim3(256), 0, s, p, n, v);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+int fill_bytes_zero(hipStream_t s, void *p, size_t bytes) {
+  if (bytes == 0) return TN_OK;
+  hipLaunchKernelGGL(k_fill_u8_zero, dim3(fill_grid((int64_t)(bytes / 4 + 1))), dim3(256), 0, s,
+                     static_cast<uint8_t *>(p), bytes);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+// ------------------------------------------------------------------ exclusive scan (int32)
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+size_t scan_tmp_count(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+
+__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t *lds, int32_t *total) {
+  const int t = threadIdx.x;
+  lds[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int32_t add = (t >= off) ? lds[t - off] : 0;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  int32_t incl = lds[t];
+  if (total) *total = lds[kScanThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tile(int32_t *data, int64_t n, int32_t *block_sums) {
+  __shared__ int32_t lds[kScanThreads];
+  __shared__ int32_t tot;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int32_t v[kScanItems];
+  int32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? data[base + k] : 0;
+    sum += v[k];
+  }
+  int32_t run = block_exclusive_scan(sum, lds, &tot);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) data[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// One block scans the block sums (any count, chunked with a carry), writes the
+// grand total to data[n] and *total_out.
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(int32_t *block_sums, int64_t nblk, int32_t *data,
+                                                            int64_t n, int64_t *total_out) {
+  __shared__ int32_t lds[kScanThreads];
+  __shared__ int32_t tot;
+  int32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nblk; b0 += kScanThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    int32_t v = (b < nblk) ? block_sums[b] : 0;
+    int32_t ex = block_exclusive_scan(v, lds, &tot);
+    if (b < nblk) block_sums[b] = ex + carry;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    data[n] = carry;
+    if (total_out) *total_out = (int64_t)carry;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_add(int32_t *data, int64_t n, const int32_t *block_sums) {
+  const int32_t add = block_sums[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) data[base + k] += add;
+}
+
+// In-place exclusive scan of data[0..n); data[n] receives the total (data must hold n+1).
+int exclusive_scan_i32(hipStream_t s, int32_t *data, int64_t n, int32_t *block_tmp, int64_t *total_out) {
+  const int64_t nblk = (n + kScanTile - 1) / kScanTile;
+  if (nblk > 0) {
+    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nblk), dim3(kScanThreads), 0, s, data, n, block_tmp);
+    TN_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, block_tmp, nblk, data, n, total_out);
+  TN_LAUNCH_CHECK();
+  if (nblk > 0) {
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nblk), dim3(kScanThreads), 0, s, data, n, block_tmp);
+    TN_LAUNCH_CHECK();
+  }
+  return TN_OK;
+}
+
+// ------------------------------------------------------------------ geometry of the box
+int box_info(const double *box, double cutoff, BoxInfo *bi) {
+  *bi = BoxInfo{};
+  if (!(cutoff > 0.0) || !std::isfinite(cutoff)) return TN_E_ARG;
+  if (!box) return TN_OK;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      if (r != c && box[r * 3 + c] != 0.0) return TN_E_ARG;   // rectangular boxes only
+  bi->periodic = 1;
+  for (int a = 0; a < 3; ++a) {
+    const double L = box[a * 4];
+    if (!(L > 0.0) || !std::isfinite(L)) return TN_E_ARG;
+    if (L < 2.0 * cutoff) return TN_E_BOX;
+    // cells of side >= cutoff with a relative margin: rounding in the binning
+    // can then never put two atoms closer than the cutoff two cells apart
+    int nc = (int)std::floor(L / (cutoff * (1.0 + 1e-6)));
+    if (nc < 1) nc = 1;
+    if (nc > 512) nc = 512;
+    bi->len[a] = L;
+    bi->nc[a] = nc;
+    bi->side[a] = L / nc;
+  }
+  return TN_OK;
+}
+
+void plan_neighbors(WsPlan &p, int64_t n, int64_t max_pairs, const BoxInfo &bi, NbrWs *w) {
+  const int64_t ncell = bi.periodic ? (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2] : 0;
+  if (bi.periodic) {
+    w->cell_of = p.take<int32_t>(n);
+    w->cell_count = p.take<int32_t>(ncell + 1);
+    w->cell_fill = p.take<int32_t>(ncell);
+    w->cell_atoms = p.take<int32_t>(n);
+    w->cell_start = w->cell_count;   // scanned in place
+  }
+  w->deg = p.take<int32_t>(n + 1);
+  w->nup = p.take<int32_t>(n + 1);
+  w->nbr = p.take<int32_t>(2 * max_pairs);
+  w->pid = p.take<int32_t>(2 * max_pairs);
+  w->scan_tmp = p.take<int32_t>(scan_tmp_count(n > ncell ? n : ncell));
+  w->count64 = p.take<int64_t>(4);
+  w->flags = p.take<int32_t>(4);
+}
+
+struct BoxDev {
+  int periodic;
+  double len[3];
+  double side[3];
+  int nc[3];
+};
+
+static BoxDev to_dev(const BoxInfo &bi) {
+  BoxDev b;
+  b.periodic = bi.periodic;
+  for (int a = 0; a < 3; ++a) {
+    b.len[a] = bi.len[a];
+    b.side[a] = bi.side[a];
+    b.nc[a] = bi.nc[a];
+  }
+  return b;
+}
+
+// The pinned FP64 cutoff predicate (no contraction into FMA).
+__device__ inline bool pair_within(double xi, double yi, double zi, double xj, double yj, double zj,
+                                         const BoxDev &b, double rc2) {
+#pragma clang fp contract(off)
+  double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+  if (b.periodic) {
+    double sx = b.len[0] * rint(dx / b.len[0]);
+    double sy = b.len[1] * rint(dy / b.len[1]);
+    double sz = b.len[2] * rint(dz / b.len[2]);
+    dx = dx - sx;
+    dy = dy - sy;
+    dz = dz - sz;
+  }
+  double xx = dx * dx;
+  double yy = dy * dy;
+  double zz = dz * dz;
+  double d2 = (xx + yy) + zz;
+  return d2 < rc2;
+}
+
+template <class T>
+__device__ inline void load_pos(const T *pos, int64_t i, double &x, double &y, double &z) {
+  x = (double)pos[3 * i];
+  y = (double)pos[3 * i + 1];
+  z = (double)pos[3 * i + 2];
+}
+
+__device__ inline int cell_coord(double x, double L, double side, int nc) {
+  double w = x - L * floor(x / L);
+  int c = (int)floor(w / side);
+  if (!(c >= 0)) c = 0;       // also catches NaN
+  if (c > nc - 1) c = nc - 1;
+  return c;
+}
+
+template <class T>
+__global__ void k_cell_assign(const T *pos, int64_t n, BoxDev b, int32_t *cell_of, int32_t *cell_count,
+                              int32_t *status) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x, y, z;
+  load_pos(pos, i, x, y, z);
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) set_status(status, TN_STATUS_NONFINITE);
+  const int cx = cell_coord(x, b.len[0], b.side[0], b.nc[0]);
+  const int cy = cell_coord(y, b.len[1], b.side[1], b.nc[1]);
+  const int cz = cell_coord(z, b.len[2], b.side[2], b.nc[2]);
+  const int c = (cx * b.nc[1] + cy) * b.nc[2] + cz;
+  cell_of[i] = c;
+  atomicAdd(&cell_count[c], 1);
+}
+
+__global__ void k_cell_scatter(int64_t n, const int32_t *cell_of, const int32_t *cell_start, int32_t *cell_fill,
+                               int32_t *cell_atoms) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell_of[i];
+  const int slot = atomicAdd(&cell_fill[c], 1);
+  cell_atoms[cell_start[c] + slot] = (int32_t)i;
+}
+
+// Range of atoms sharing batch value bv (lower/upper bound in a sorted vector).
+__device__ inline void system_range(const int32_t *batch, int64_t n, int32_t bv, int64_t &lo, int64_t &hi) {
+  int64_t a = 0, e = n;
+  while (a < e) {
+    int64_t m = (a + e) >> 1;
+    if (batch[m] < bv) a = m + 1; else e = m;
+  }
+  lo = a;
+  e = n;
+  while (a < e) {
+    int64_t m = (a + e) >> 1;
+    if (batch[m] <= bv) a = m + 1; else e = m;
+  }
+  hi = a;
+}
+
+// Visit every neighbour j of atom i; f(j) is called in a deterministic order.
+// With an unsorted batch vector the isolated search scans all atoms, which keeps the
+// neighbour relation symmetric (and the result correct) at O(N^2) cost.
+template <class T, class Fn>
+__device__ inline void for_each_neighbor(int64_t i, const T *pos, const int32_t *batch, int64_t n, const BoxDev &b,
+                                         double rc2, const int32_t *cell_of, const int32_t *cell_start,
+                                         const int32_t *cell_atoms, const int32_t *unsorted, Fn &&f) {
+  double xi, yi, zi;
+  load_pos(pos, i, xi, yi, zi);
+  const int32_t bi = batch[i];
+  if (b.periodic) {
+    const int c = cell_of[i];
+    const int cz = c % b.nc[2];
+    const int cy = (c / b.nc[2]) % b.nc[1];
+    const int cx = c / (b.nc[1] * b.nc[2]);
+    // distinct neighbour cells only: 1 cell per side -> {0}, 2 -> {0, +1}, else {-1, 0, +1}
+    const int lox = b.nc[0] >= 3 ? -1 : 0, hix = b.nc[0] >= 2 ? 1 : 0;
+    const int loy = b.nc[1] >= 3 ? -1 : 0, hiy = b.nc[1] >= 2 ? 1 : 0;
+    const int loz = b.nc[2] >= 3 ? -1 : 0, hiz = b.nc[2] >= 2 ? 1 : 0;
+    for (int ox = lox; ox <= hix; ++ox) {
+      const int nx = (cx + ox + b.nc[0]) % b.nc[0];
+      for (int oy = loy; oy <= hiy; ++oy) {
+        const int ny = (cy + oy + b.nc[1]) % b.nc[1];
+        for (int oz = loz; oz <= hiz; ++oz) {
+          const int nz = (cz + oz + b.nc[2]) % b.nc[2];
+          const int cc = (nx * b.nc[1] + ny) * b.nc[2] + nz;
+          for (int k = cell_start[cc]; k < cell_start[cc + 1]; ++k) {
+            const int32_t j = cell_atoms[k];
+            if (j == i || batch[j] != bi) continue;
+            double xj, yj, zj;
+            load_pos(pos, j, xj, yj, zj);
+            if (pair_within(xi, yi, zi, xj, yj, zj, b, rc2)) f(j);
+          }
+        }
+      }
+    }
+  } else {
+    int64_t lo = 0, hi = n;
+    if (!*unsorted) system_range(batch, n, bi, lo, hi);
+    for (int64_t j = lo; j < hi; ++j) {
+      if (j == i || batch[j] != bi) continue;
+      double xj, yj, zj;
+      load_pos(pos, j, xj, yj, zj);
+      if (pair_within(xi, yi, zi, xj, yj, zj, b, rc2)) f((int32_t)j);
+    }
+  }
+}
+
+__global__ void k_batch_sorted(const int32_t *batch, int64_t n, int32_t *unsorted, int32_t *status) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || i == 0) return;
+  if (batch[i] < batch[i - 1]) {
+    atomicOr(reinterpret_cast<int *>(unsorted), 1);
+    set_status(status, TN_STATUS_BATCH);
+  }
+}
+
+template <class T>
+__global__ void k_nbr_count(const T *pos, const int32_t *batch, int64_t n, BoxDev b, double rc2,
+                            const int32_t *cell_of, const int32_t *cell_start, const int32_t *cell_atoms,
+                            const int32_t *unsorted, int32_t *deg, int32_t *nup, int32_t *status) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (!b.periodic) {
+    double x, y, z;
+    load_pos(pos, i, x, y, z);
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) set_status(status, TN_STATUS_NONFINITE);
+  }
+  int32_t full = 0, upper = 0;
+  for_each_neighbor(i, pos, batch, n, b, rc2, cell_of, cell_start, cell_atoms, unsorted, [&](int32_t j) {
+    ++full;
+    upper += (j > i);
+  });
+  deg[i] = full;
+  nup[i] = upper;
+}
+
+__global__ void k_nbr_total(const int64_t *count64, int64_t max_pairs, int64_t *n_pairs, int32_t *status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int64_t P = count64[0];
+    *n_pairs = P;
+    if (P > max_pairs) set_status(status, TN_STATUS_OVERFLOW);
+  }
+}
+
+template <class T>
+__global__ void k_nbr_write(const T *pos, const int32_t *batch, int64_t n, BoxDev b, double rc2,
+                            const int32_t *cell_of, const int32_t *cell_start, const int32_t *cell_atoms,
+                            const int32_t *unsorted, const int32_t *rowptr, const int64_t *count64,
+                            int64_t max_pairs, int32_t *nbr) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || count64[0] > max_pairs) return;
+  int32_t e = rowptr[i];
+  for_each_neighbor(i, pos, batch, n, b, rc2, cell_of, cell_start, cell_atoms, unsorted,
+                    [&](int32_t j) { nbr[e++] = j; });
+}
+
+__global__ void k_row_sort(int64_t n, const int32_t *rowptr, const int64_t *count64, int64_t max_pairs,
+                           int32_t *nbr) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || count64[0] > max_pairs) return;
+  const int32_t a = rowptr[i], e = rowptr[i + 1];
+  for (int32_t k = a + 1; k < e; ++k) {
+    const int32_t v = nbr[k];
+    int32_t q = k - 1;
+    while (q >= a && nbr[q] > v) {
+      nbr[q + 1] = nbr[q];
+      --q;
+    }
+    nbr[q + 1] = v;
+  }
+}
+
+// Pair id of every directed edge; the public list gets (i, j) for j > i.
+__global__ void k_pair_ids(int64_t n, const int32_t *rowptr, const int32_t *pbase,
+                           const int32_t *nbr, const int64_t *count64, int64_t max_pairs, int32_t *pid,
+                           int32_t *pairs) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || count64[0] > max_pairs) return;
+  const int32_t a = rowptr[i], e = rowptr[i + 1];
+  const int32_t nlow_i = (e - a) - (pbase[i + 1] - pbase[i]);
+  for (int32_t k = a; k < e; ++k) {
+    const int32_t j = nbr[k];
+    int32_t p;
+    if (j > i) {
+      p = pbase[i] + (k - a - nlow_i);
+      pairs[p] = (int32_t)i;
+      pairs[max_pairs + p] = j;
+    } else {
+      // find i in row j (sorted), rank it among row j's upper neighbours
+      const int32_t aj = rowptr[j], ej = rowptr[j + 1];
+      int32_t lo = aj, hi = ej;
+      while (lo < hi) {
+        const int32_t m = (lo + hi) >> 1;
+        if (nbr[m] < (int32_t)i) lo = m + 1; else hi = m;
+      }
+      const int32_t nlow_j = (ej - aj) - (pbase[j + 1] - pbase[j]);
+      p = pbase[j] + (lo - aj - nlow_j);
+      // the relation is symmetric, so i is always found; clamp defensively anyway
+      const int32_t P = (int32_t)count64[0];
+      if (p < 0) p = 0;
+      if (p > P - 1) p = P - 1;
+    }
+    pid[k] = p;
+  }
+}
+
+__global__ void k_pad_pairs(const int64_t *count64, int64_t max_pairs, int32_t *pairs) {
+  const int64_t P = count64[0];
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < max_pairs;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    if (p >= P || P > max_pairs) {
+      pairs[p] = -1;
+      pairs[max_pairs + p] = -1;
+    }
+  }
+}
+
+template <class T>
+int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *batch, const BoxInfo &bi, double cutoff,
+                    int64_t max_pairs, int32_t *pairs, int64_t *n_pairs, int32_t *status, const NbrWs &w) {
+  const BoxDev b = to_dev(bi);
+  const double rc2 = cutoff * cutoff;
+  const int blk = 128;
+  const unsigned g = grid_for(n > 0 ? n : 1, blk);
+  int rc;
+  if (bi.periodic) {
+    const int64_t ncell = (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2];
+    if ((rc = fill_i32(s, w.cell_count, ncell + 1, 0))) return rc;
+    if ((rc = fill_i32(s, w.cell_fill, ncell, 0))) return rc;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_cell_assign<T>, dim3(g), dim3(blk), 0, s, pos, n, b, w.cell_of, w.cell_count, status);
+      TN_LAUNCH_CHECK();
+    }
+    if ((rc = exclusive_scan_i32(s, w.cell_count, ncell, w.scan_tmp, nullptr))) return rc;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_cell_scatter, dim3(g), dim3(blk), 0, s, n, w.cell_of, w.cell_start, w.cell_fill,
+                         w.cell_atoms);
+      TN_LAUNCH_CHECK();
+    }
+  }
+  if ((rc = fill_i32(s, w.flags, 4, 0))) return rc;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_batch_sorted, dim3(g), dim3(blk), 0, s, batch, n, w.flags, status);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_nbr_count<T>, dim3(g), dim3(blk), 0, s, pos, batch, n, b, rc2, w.cell_of, w.cell_start,
+                       w.cell_atoms, w.flags, w.deg, w.nup, status);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = exclusive_scan_i32(s, w.deg, n, w.scan_tmp, w.count64 + 1))) return rc;
+  if ((rc = exclusive_scan_i32(s, w.nup, n, w.scan_tmp, w.count64 + 0))) return rc;
+  hipLaunchKernelGGL(k_nbr_total, dim3(1), dim3(64), 0, s, w.count64, max_pairs, n_pairs, status);
+  TN_LAUNCH_CHECK();
+  if (n > 0) {
+    hipLaunchKernelGGL(k_nbr_write<T>, dim3(g), dim3(blk), 0, s, pos, batch, n, b, rc2, w.cell_of, w.cell_start,
+                       w.cell_atoms, w.flags, w.deg, w.count64, max_pairs, w.nbr);
+    TN_LAUNCH_CHECK();
+    if (bi.periodic) {
+      hipLaunchKernelGGL(k_row_sort, dim3(g), dim3(blk), 0, s, n, w.deg, w.count64, max_pairs, w.nbr);
+      TN_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_pair_ids, dim3(g), dim3(blk), 0, s, n, w.deg, w.nup, w.nbr, w.count64, max_pairs,
+                       w.pid, pairs);
+    TN_LAUNCH_CHECK();
+  }
+  if (max_pairs > 0) {
+    hipLaunchKernelGGL(k_pad_pairs, dim3(fill_grid(max_pairs)), dim3(256), 0, s, w.count64, max_pairs, pairs);
+    TN_LAUNCH_CHECK();
+  }
+  return TN_OK;
+}
+
+template int build_neighbors<float>(hipStream_t, int64_t, const float *, const int32_t *, const BoxInfo &, double,
+                                    int64_t, int32_t *, int64_t *, int32_t *, const NbrWs &);
+template int build_neighbors<double>(hipStream_t, int64_t, const double *, const int32_t *, const BoxInfo &, double,
+                                     int64_t, int32_t *, int64_t *, int32_t *, const NbrWs &);
+
+}  // namespace tn

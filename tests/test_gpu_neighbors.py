@@ -1,0 +1,122 @@
+"""GPU neighbour search (tn_build_neighbors) against the oracle's pair set: bit-exact
+as sorted sets, including tiny boxes with 1-3 cells per side, padding, overflow,
+empty inputs, float64 positions and the 100k-atom box."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.neighbors import brute_force_pairs, neighbor_pairs
+from paper_2402_17660_amd import _lib as L
+from paper_2402_17660_amd import build_neighbors
+from synth import make_config
+from tests.util import random_box, random_molecule
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_pairs(dev, pos, batch, box, cutoff, max_pairs, f64=False):
+    p = torch.tensor(np.asarray(pos), dtype=torch.float64 if f64 else torch.float32, device=dev)
+    b = torch.tensor(np.asarray(batch), dtype=torch.int32, device=dev)
+    pairs, n_pairs, status = build_neighbors(p, b, cutoff, max_pairs, box=box, check=False)
+    torch.cuda.synchronize()
+    return pairs.cpu().numpy(), int(n_pairs.item()), int(status.item())
+
+
+def check_against_oracle(dev, pos, batch, box, cutoff, slack=1000, f64=False):
+    ref = neighbor_pairs(np.asarray(pos, dtype=np.float64 if f64 else np.float32), batch, box, cutoff)
+    max_pairs = len(ref) + slack
+    pr, n, st = gpu_pairs(dev, pos, batch, box, cutoff, max_pairs, f64=f64)
+    assert st == 0, st
+    assert n == len(ref)
+    got = pr[:, :n].T.astype(np.int64)
+    assert np.array_equal(got, ref)          # same set, and sorted by (i, j)
+    assert np.all(pr[:, n:] == -1)
+    return ref
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+def test_workload_pair_sets(dev, cfg):
+    c = make_config(cfg)
+    print(f"neighbours cfg={cfg} N={len(c['pos'])}", flush=True)
+    check_against_oracle(dev, c["pos"], c["batch"], c["box"], c["r_c"])
+
+
+def test_100k_box_pair_set(dev):
+    c = make_config(3)
+    ref = check_against_oracle(dev, c["pos"], c["batch"], c["box"], c["r_c"], slack=50_000)
+    assert len(ref) > 2_500_000
+
+
+@pytest.mark.parametrize("box_len,n,seed", [(9.0, 60, 1), (10.0, 90, 2), (13.6, 200, 3), (17.0, 300, 4)])
+def test_tiny_boxes_unwrapped_input(dev, box_len, n, seed):
+    pos, _, box = random_box(n, seed, box_len)
+    rng = np.random.default_rng(seed)
+    pos = (pos + box_len * rng.integers(-2, 3, size=pos.shape)).astype(np.float32)
+    check_against_oracle(dev, pos, np.zeros(n, np.int32), box, 4.5)
+
+
+def test_float64_positions(dev):
+    pos, _, box = random_box(300, 5, 15.0)
+    check_against_oracle(dev, pos.astype(np.float64), np.zeros(300, np.int32), box, 4.5, f64=True)
+    mol, _ = random_molecule(64, 6)
+    check_against_oracle(dev, mol.astype(np.float64), np.zeros(64, np.int32), None, 5.0, f64=True)
+
+
+def test_periodic_batch_isolation(dev):
+    # two systems sharing one box: one cell list, no cross-system pairs
+    p1, _, box = random_box(150, 7, 16.0)
+    p2, _, _ = random_box(120, 8, 16.0)
+    pos = np.concatenate([p1, p2]).astype(np.float32)
+    batch = np.array([0] * 150 + [1] * 120, np.int32)
+    ref = check_against_oracle(dev, pos, batch, box, 4.5)
+    assert np.all(batch[ref[:, 0]] == batch[ref[:, 1]])
+
+
+def test_max_pairs_independence_and_padding(dev):
+    c = make_config(0)
+    ref = brute_force_pairs(c["pos"], c["batch"], None, c["r_c"])
+    outs = []
+    for mp in (len(ref), len(ref) + 1, 4 * len(ref)):
+        pr, n, st = gpu_pairs(dev, c["pos"], c["batch"], None, c["r_c"], mp)
+        assert st == 0 and n == len(ref)
+        assert np.all(pr[:, n:] == -1)
+        outs.append(pr[:, :n])
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+def test_overflow_reports_true_count(dev):
+    c = make_config(1)
+    ref = neighbor_pairs(c["pos"], c["batch"], c["box"], c["r_c"])
+    pr, n, st = gpu_pairs(dev, c["pos"], c["batch"], c["box"], c["r_c"], len(ref) - 1)
+    assert st & L.TN_STATUS_OVERFLOW
+    assert n == len(ref)
+    assert np.all(pr == -1)
+    pr, n, st = gpu_pairs(dev, c["pos"], c["batch"], c["box"], c["r_c"], 0)
+    assert st & L.TN_STATUS_OVERFLOW and n == len(ref)
+
+
+def test_empty_and_single_atom(dev):
+    pr, n, st = gpu_pairs(dev, np.zeros((0, 3)), np.zeros(0, np.int32), None, 5.0, 16)
+    assert n == 0 and st == 0 and np.all(pr == -1)
+    pr, n, st = gpu_pairs(dev, np.zeros((1, 3)), np.zeros(1, np.int32), np.diag([12.0] * 3), 5.0, 16)
+    assert n == 0 and st == 0 and np.all(pr == -1)
+
+
+def test_unsorted_batch_flagged(dev):
+    pos, _ = random_molecule(40, 9)
+    batch = np.array([1] * 20 + [0] * 20, np.int32)
+    pr, n, st = gpu_pairs(dev, pos, batch, None, 5.0, 4000)
+    assert st & L.TN_STATUS_BATCH
+    ref = brute_force_pairs(pos.astype(np.float32), batch, None, 5.0)
+    assert n == len(ref)
+    assert np.array_equal(pr[:, :n].T, ref)
+
+
+def test_nonfinite_position_flagged(dev):
+    pos, _, box = random_box(50, 10, 12.0)
+    pos = pos.astype(np.float32)
+    pos[3, 1] = np.nan
+    pr, n, st = gpu_pairs(dev, pos, np.zeros(50, np.int32), box, 4.5, 4000)
+    assert st & L.TN_STATUS_NONFINITE
+    assert not np.any(pr[:, :n] == 3)
