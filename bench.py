@@ -42,11 +42,12 @@ def edge_filter_flops_per_pair(F, K):
     return 2.0 * (K * F + 2 * F * F + 6 * F * F)
 
 
-# dominant kernel of each path: (timer name, algorithmic FLOP per unordered pair per launch)
-def dominant(path, F, K):
+# timed kernels of each path: {timer name: algorithmic FLOP per unordered pair per launch}
+def timed_kernels(path, F, K, L):
     if path == "plain":
-        return "plain_edge_gemm_c", 2.0 * (2 * F) * (3 * F)
-    return "edge_fwd", edge_filter_flops_per_pair(F, K)
+        return {"plain_edge_gemm_c": 2.0 * (2 * F) * (3 * F)}
+    per_pair = 2.0 * K * 3 * F + L * edge_filter_flops_per_pair(F, K)
+    return {"edge_fwd": per_pair, "edge_bwd": per_pair}
 
 
 def cpu_baseline(n_atoms, F, K, L, r_c, seed):
@@ -122,7 +123,7 @@ def main():
         for _ in range(args.warmup):
             run()
         torch.cuda.synchronize()
-        timer, flop_per_pair = dominant(path, F, K)
+        timers = timed_kernels(path, F, K, L)
         L_.tn_timing_reset()
         L_.tn_timing_enable(1)
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -135,24 +136,28 @@ def main():
         L_.tn_timing_enable(0)
         ms = start.elapsed_time(stop) / args.steps
         import ctypes
-        tot, cnt = ctypes.c_double(), ctypes.c_int64()
-        L_.tn_timing_read(timer.encode(), ctypes.byref(tot), ctypes.byref(cnt))
+        kernels = []
+        for timer, flop_per_pair in timers.items():
+            tot, cnt = ctypes.c_double(), ctypes.c_int64()
+            L_.tn_timing_read(timer.encode(), ctypes.byref(tot), ctypes.byref(cnt))
+            kernel_ms = tot.value / max(cnt.value, 1)
+            flop_per_launch = flop_per_pair * n_pairs
+            achieved = flop_per_launch / (kernel_ms * 1e-3) if cnt.value else None
+            kernels.append(dict(name=timer, launches_per_step=cnt.value / args.steps, avg_ms=kernel_ms,
+                                ms_per_step=tot.value / args.steps, flop_per_launch=flop_per_launch,
+                                achieved_tflops=(achieved / 1e12) if achieved else None,
+                                peak_tflops=PEAK[prec] / 1e12))
         model.check()
         E = E_out.cpu().numpy()
         Fo = F_out.double().cpu().numpy()
         e_err = float(np.max(np.abs(E - golden["E"]) / np.abs(golden["E"])))
         f_err = float(np.linalg.norm(Fo - golden["F"]) / np.linalg.norm(golden["F"]))
-        kernel_ms = tot.value / max(cnt.value, 1)
-        flop_per_launch = flop_per_pair * n_pairs
-        achieved = flop_per_launch / (kernel_ms * 1e-3) if cnt.value else None
-        peak = PEAK[prec]
+        dom = max(kernels, key=lambda k: k["ms_per_step"])
         res = dict(path=path, precision=prec, available=True, ms_per_step=ms, value=N / (ms * 1e-3),
-                   energy_rel_err=e_err, force_rel_rms=f_err,
-                   kernel=dict(name=timer, launches_per_step=cnt.value / args.steps, avg_ms=kernel_ms,
-                               flop_per_launch=flop_per_launch,
-                               achieved_tflops=(achieved / 1e12) if achieved else None, peak_tflops=peak / 1e12))
+                   energy_rel_err=e_err, force_rel_rms=f_err, kernel=dom, kernels=kernels)
         log(f"{path}/{prec}: {ms:.3f} ms/step, {res['value']:.3e} atom-steps/s, E err {e_err:.2e}, "
-            f"F err {f_err:.2e}, {timer} {kernel_ms:.3f} ms/launch")
+            f"F err {f_err:.2e}, " + ", ".join(f"{k['name']} {k['avg_ms']:.3f} ms/launch "
+                                               f"({k['achieved_tflops'] or 0:.1f} TFLOP/s)" for k in kernels))
         results.append(res)
 
     avail = [r for r in results if r.get("available")]

@@ -86,8 +86,9 @@ int tn_model_info(const tn_model *m, int32_t *F, int32_t *K, int32_t *L, int32_t
  *   d^2 = (v_x*v_x + v_y*v_y) + v_z*v_z  (each product rounded, no FMA)
  * box != NULL: one cell list over all systems (cells of side >= cutoff).
  * box == NULL: brute force over the atoms of each system.
- * Output: pairs[0][p], pairs[1][p] (int32, layout [2, max_pairs]) for
- * p < *n_pairs, sorted by (i, j); slots p >= *n_pairs hold -1.  *n_pairs
+ * Output: pairs[0][p] < pairs[1][p] (int32, layout [2, max_pairs]) for
+ * p < *n_pairs, in a deterministic order (by (i, j) for isolated systems, by
+ * cell order in a box); slots p >= *n_pairs hold -1.  *n_pairs
  * (device int64) is always the true count; if it exceeds max_pairs,
  * TN_STATUS_OVERFLOW is set and `pairs` is only padding.
  * pos: [n_atoms, 3] float32 (pos_f64 == 0) or float64 (pos_f64 != 0). */

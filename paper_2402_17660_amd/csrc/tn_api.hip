@@ -76,7 +76,11 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
   for (auto &t : order) total += t.count;
   if (bytes != kHeaderBytes + 8 * total) return TN_E_BLOB;
   const size_t F = m->F, K = m->K, Z = m->max_z;
-  packed.assign(total + 2 * Z * F + 2 * K, 0.0);
+  // room for the derived tables: species tables, basis constants, aligned and transposed
+  // copies of the per-pair weights (each start aligned to 64 elements)
+  const size_t extra = 2 * Z * F + 2 * K + 2 * (3 * F * K) + (size_t)m->L * 2 * (F * K + 2 * F * F + 6 * F * F) +
+                       64 * (8 + 6 * (size_t)m->L);
+  packed.assign(total + extra, 0.0);
   size_t off = 0;
   const unsigned char *src = b + kHeaderBytes;
   for (auto &t : order) {
@@ -89,11 +93,39 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
     if (!std::isfinite(v)) return TN_E_BLOB;
   WeightOff &o = m->off;
   // species tables: Z_ij = W_z [E_zi ; E_zj] + b_z = U[z_i] + V[z_j]
-  o.U = off;
-  o.V = off + Z * F;
-  o.mu = off + 2 * Z * F;
-  o.beta = o.mu + K;
-  o.total = o.beta + K;
+  auto grab = [&](size_t count) {
+    off = (off + 63) / 64 * 64;
+    const size_t at = off;
+    off += count;
+    return at;
+  };
+  o.U = grab(Z * F);
+  o.V = grab(Z * F);
+  o.mu = grab(K);
+  o.beta = grab(K);
+  // copies for the fused pair kernels: W0 [3F][K] as is and transposed; per layer Wa [F][K],
+  // Wb [2F][F], Wc [3F][2F] as is and transposed
+  auto copy = [&](size_t src, size_t rows, size_t cols, bool transpose) {
+    const size_t at = grab(rows * cols);
+    for (size_t r = 0; r < rows; ++r)
+      for (size_t c = 0; c < cols; ++c)
+        packed[at + (transpose ? c * rows + r : r * cols + c)] = packed[src + r * cols + c];
+    return at;
+  };
+  o.W0f = copy(o.W0, 3 * F, K, false);
+  o.W0T = copy(o.W0, 3 * F, K, true);
+  for (int l = 0; l < m->L; ++l) {
+    LayerOff &lo = o.layer[l];
+    lo.Waf = copy(lo.Wa, F, K, false);
+    lo.WaT = copy(lo.Wa, F, K, true);
+    lo.Wbf = copy(lo.Wb, 2 * F, F, false);
+    lo.WbT = copy(lo.Wb, 2 * F, F, true);
+    lo.Wcf = copy(lo.Wc, 3 * F, 2 * F, false);
+    lo.WcT = copy(lo.Wc, 3 * F, 2 * F, true);
+  }
+  o.total = off;
+  if (o.total > packed.size()) return TN_E_BLOB;
+  packed.resize(o.total);
   const double *E = packed.data() + o.E, *Wz = packed.data() + o.Wz, *bz = packed.data() + o.bz;
   for (size_t s = 0; s < Z; ++s)
     for (size_t f = 0; f < F; ++f) {
@@ -283,10 +315,10 @@ int tn_build_neighbors(void *stream, int64_t n_atoms, const void *pos, int pos_f
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((rc = fill_i32(s, status, 1, 0))) return rc;
   if (pos_f64)
-    return build_neighbors<double>(s, n_atoms, static_cast<const double *>(pos), batch, bi, cutoff, max_pairs, pairs,
-                                   n_pairs, status, w);
-  return build_neighbors<float>(s, n_atoms, static_cast<const float *>(pos), batch, bi, cutoff, max_pairs, pairs,
-                                n_pairs, status, w);
+    return build_neighbors<double>(s, n_atoms, static_cast<const double *>(pos), nullptr, batch, bi, cutoff, max_pairs,
+                                   pairs, n_pairs, status, w, nullptr);
+  return build_neighbors<float>(s, n_atoms, static_cast<const float *>(pos), nullptr, batch, bi, cutoff, max_pairs,
+                                pairs, n_pairs, status, w, nullptr);
 }
 
 size_t tn_workspace_bytes(const tn_model *m, int64_t n_atoms, int64_t n_systems, int64_t max_pairs,

@@ -1,10 +1,365 @@
-// Fused path (MFMA pair tiles); filled in once the plain path is verified.
-#include "tn_internal.h"
+// Fused TensorNet path: the per-pair work (geometry, radial basis, the embedding's K->3F map
+// and every layer's edge filter, forward and reverse) runs in two MFMA pair-tile kernels;
+// the node-level steps use the shared node kernels.  Precision plan as in the plain path:
+// FP32 arithmetic, with the geometry/basis, the embedding's node stage and the output
+// network in FP64, the per-system energy sum and the per-atom force sum in FP64.
+#include "tn_nodeops.h"
 
 namespace tn {
 
-size_t fused_workspace_bytes(const tn_model *, int64_t, int64_t, int64_t, const BoxInfo &, int, int) { return 0; }
+namespace {
 
-int fused_run(const tn_model *, hipStream_t, const Problem &, int, void *, size_t) { return TN_E_UNSUPPORTED; }
+using TA = double;
+
+struct FusedWs {
+  NbrWs nb;
+  float *geo, *phi, *f0, *Xr;
+  TA *XrA, *T0, *nrm0, *xhat0, *rstd0, *n0, *ez1, *ea1, *ez2, *g, *X0A;
+  std::vector<float *> X, nX, Xb, Y, z1, z2, z3, h, M, P, nP, Pb, D, dh;
+  TA *XLA, *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps, *eps_orig;
+  float *dX = nullptr, *dD, *dPb, *dY, *dM, *dXr;
+  TA *dXA, *dT0, *dXrA, *dg, *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
+  float *df0, *dphi, *dvhat, *gpair;
+};
+
+void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxInfo &bi, bool fw, FusedWs *w) {
+  const int64_t F = m->F, L = m->L;
+  plan_neighbors(p, N, MP, bi, &w->nb);
+  w->geo = p.take<float>(4 * MP);
+  w->phi = p.take<float>(MP);
+  w->f0 = p.take<float>(MP * 3 * F);
+  w->Xr = p.take<float>(N * 9 * F);
+  w->XrA = p.take<TA>(N * 9 * F);
+  w->T0 = p.take<TA>(N * 9 * F);
+  w->nrm0 = p.take<TA>(N * F);
+  w->xhat0 = p.take<TA>(N * F);
+  w->rstd0 = p.take<TA>(N);
+  w->n0 = p.take<TA>(N * F);
+  w->ez1 = p.take<TA>(N * 2 * F);
+  w->ea1 = p.take<TA>(N * 2 * F);
+  w->ez2 = p.take<TA>(N * 3 * F);
+  w->g = p.take<TA>(N * 3 * F);
+  w->X0A = p.take<TA>(N * 9 * F);
+  w->X.resize(L + 1);
+  for (int64_t l = 0; l <= L; ++l) w->X[l] = p.take<float>(N * 9 * F);
+  auto per_layer = [&](std::vector<float *> &v, int64_t count) {
+    v.resize(L);
+    for (int64_t l = 0; l < L; ++l) v[l] = p.take<float>(count);
+  };
+  per_layer(w->nX, N * F);
+  per_layer(w->Xb, N * 9 * F);
+  per_layer(w->Y, N * 9 * F);
+  per_layer(w->z1, MP * F);
+  per_layer(w->z2, MP * 2 * F);
+  per_layer(w->z3, MP * 3 * F);
+  per_layer(w->h, MP * 3 * F);
+  per_layer(w->M, N * 9 * F);
+  per_layer(w->P, N * 9 * F);
+  per_layer(w->nP, N * F);
+  per_layer(w->Pb, N * 9 * F);
+  per_layer(w->D, N * 9 * F);
+  w->XLA = p.take<TA>(N * 9 * F);
+  w->on = p.take<TA>(N * 3 * F);
+  w->oxhat = p.take<TA>(N * 3 * F);
+  w->orstd = p.take<TA>(N);
+  w->q = p.take<TA>(N * 3 * F);
+  w->oz = p.take<TA>(N * F);
+  w->ox = p.take<TA>(N * F);
+  w->hz = p.take<TA>(N * (F / 2));
+  w->hx = p.take<TA>(N * (F / 2));
+  w->eps = p.take<TA>(N);
+  w->eps_orig = p.take<TA>(N);
+  if (!fw) return;
+  per_layer(w->dh, MP * 3 * F);
+  w->dX = p.take<float>(N * 9 * F);
+  w->dD = p.take<float>(N * 9 * F);
+  w->dPb = p.take<float>(N * 9 * F);
+  w->dY = p.take<float>(N * 9 * F);
+  w->dM = p.take<float>(N * 9 * F);
+  w->dXr = p.take<float>(N * 9 * F);
+  w->dXA = p.take<TA>(N * 9 * F);
+  w->dT0 = p.take<TA>(N * 9 * F);
+  w->dXrA = p.take<TA>(N * 9 * F);
+  w->dg = p.take<TA>(N * 3 * F);
+  w->dez2 = p.take<TA>(N * 3 * F);
+  w->dez1 = p.take<TA>(N * 2 * F);
+  w->dn0 = p.take<TA>(N * F);
+  w->dnrm0 = p.take<TA>(N * F);
+  w->dhz = p.take<TA>(N * (F / 2));
+  w->dox = p.take<TA>(N * F);
+  w->dq = p.take<TA>(N * 3 * F);
+  w->don = p.take<TA>(N * 3 * F);
+  w->df0 = p.take<float>(MP * 3 * F);
+  w->dphi = p.take<float>(MP);
+  w->dvhat = p.take<float>(3 * MP);
+  w->gpair = p.take<float>(3 * MP);
+}
+
+int run_fused_f32(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, size_t ws_bytes) {
+  const int64_t N = pb.n, MP = pb.max_pairs, F = m->F, K = m->K, L = m->L;
+  WsPlan plan(ws);
+  FusedWs w;
+  plan_fused(plan, m, N, MP, pb.box, pb.want_forces, &w);
+  if (plan.off > ws_bytes) return TN_E_WORKSPACE;
+  const float *pos = nullptr;
+  int rc;
+  const unsigned bs = 256;
+  auto W = [&](size_t off) { return wptr<float>(m, off); };
+  auto WA = [&](size_t off) { return wptr<TA>(m, off); };
+  const WeightOff &o = m->off;
+
+  if (N > 0) {
+    hipLaunchKernelGGL(k_check_inputs<float>, dim3(grid_for(N, bs)), dim3(bs), 0, s, pb.z, pb.batch, N, pb.S,
+                       m->max_z, pb.status);
+    TN_LAUNCH_CHECK();
+  }
+  NbrGraph<float> gr;
+  if ((rc = build_neighbors<float>(s, N, static_cast<const float *>(pb.pos), pb.z, pb.batch, pb.box, m->r_c, MP, nullptr,
+                                 pb.n_pairs, pb.status, w.nb, &gr)))
+    return rc;
+  const int64_t *np = pb.n_pairs;
+  const int32_t *rowptr = gr.rowptr, *nbr = gr.nbr, *pid = gr.pid;
+  const int32_t *zz = gr.z;
+  pos = gr.pos;
+
+  // ---- all per-pair work of the forward pass in one MFMA kernel
+  PairFwdArgs pf;
+  pf.pairs = gr.pairs;
+  pf.max_pairs = MP;
+  pf.n_pairs = np;
+  pf.pos = pos;
+  pf.periodic = pb.box.periodic;
+  for (int a = 0; a < 3; ++a) pf.box[a] = pb.box.len[a];
+  pf.r_c = m->r_c;
+  pf.r_lo = m->r_lo;
+  pf.alpha = m->alpha;
+  pf.mu = WA(o.mu);
+  pf.beta = WA(o.beta);
+  pf.W0 = W(o.W0f);
+  pf.b0 = W(o.b0);
+  pf.L = (int)L;
+  for (int64_t l = 0; l < L; ++l) {
+    const LayerOff &lo = o.layer[l];
+    pf.Wa[l] = W(lo.Waf);
+    pf.ba[l] = W(lo.ba);
+    pf.Wb[l] = W(lo.Wbf);
+    pf.bb[l] = W(lo.bb);
+    pf.Wc[l] = W(lo.Wcf);
+    pf.bc[l] = W(lo.bc);
+    pf.z1[l] = w.z1[l];
+    pf.z2[l] = w.z2[l];
+    pf.z3[l] = w.z3[l];
+    pf.h[l] = w.h[l];
+  }
+  pf.geo = w.geo;
+  pf.phi = w.phi;
+  pf.f0 = w.f0;
+  if ((rc = launch_pair_fwd(s, (int)F, (int)K, pf))) return rc;
+
+  // ---- embedding node stage (FP64)
+  const unsigned gNF = grid_for(N * F, bs);
+  if (N > 0) {
+    hipLaunchKernelGGL(k_embed_gather<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, zz,
+                       m->max_z, W(o.U), W(o.V), w.geo, w.phi, w.f0, w.Xr);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = convert<float, TA>(s, w.Xr, w.XrA, N * 9 * F))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_node_norm<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XrA, w.nrm0);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_layernorm<TA>, dim3((unsigned)N), dim3(128), 0, s, N, (int)F, w.nrm0, WA(o.ln_g),
+                       WA(o.ln_b), w.n0, w.xhat0, w.rstd0);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = linear_fwd<TA>(s, w.n0, N, F, WA(o.W1), WA(o.b1), 2 * F, w.ea1, w.ez1, 1))) return rc;
+  if ((rc = linear_fwd<TA>(s, w.ea1, N, 2 * F, WA(o.W2), WA(o.b2), 3 * F, w.g, w.ez2, 1))) return rc;
+  const TA *Wemb[3] = {WA(o.Wmix[0]), WA(o.Wmix[1]), WA(o.Wmix[2])};
+  if ((rc = mix<TA>(s, w.XrA, w.T0, N, F, Wemb, 0, 0))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_gate<TA>, dim3(grid_for(N * 9 * F, bs)), dim3(bs), 0, s, N, (int)F, w.g, w.T0, w.X0A);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = convert<TA, float>(s, w.X0A, w.X[0], N * 9 * F))) return rc;
+  // ---- interaction layers
+  for (int64_t l = 0; l < L; ++l) {
+    const LayerOff &lo = o.layer[l];
+    if (N > 0) {
+      hipLaunchKernelGGL(k_normalize<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[l], w.nX[l], w.Xb[l]);
+      TN_LAUNCH_CHECK();
+    }
+    const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
+    if ((rc = mix<float>(s, w.Xb[l], w.Y[l], N, F, W1, 0, 0))) return rc;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_message<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, w.h[l],
+                         w.Y[l], w.M[l], 0);
+      TN_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_product<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Y[l], w.M[l], w.P[l], w.nP[l],
+                         w.Pb[l]);
+      TN_LAUNCH_CHECK();
+    }
+    const float *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
+    if ((rc = mix<float>(s, w.Pb[l], w.D[l], N, F, W2, 0, 0))) return rc;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_residual<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xb[l], w.D[l], w.X[l + 1]);
+      TN_LAUNCH_CHECK();
+    }
+  }
+  // ---- output network (FP64) and energies
+  const int64_t H = F / 2;
+  if ((rc = convert<float, TA>(s, w.X[L], w.XLA, N * 9 * F))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_out_norms<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XLA, w.on);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_layernorm<TA>, dim3((unsigned)N), dim3(128), 0, s, N, (int)(3 * F), w.on, WA(o.oln_g),
+                       WA(o.oln_b), w.q, w.oxhat, w.orstd);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = linear_fwd<TA>(s, w.q, N, 3 * F, WA(o.Wo), WA(o.bo), F, w.ox, w.oz, 1))) return rc;
+  if ((rc = linear_fwd<TA>(s, w.ox, N, F, WA(o.Wh), WA(o.bh), H, w.hx, w.hz, 1))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_out_final<TA>, dim3(grid_for(N, bs)), dim3(bs), 0, s, N, (int)H, w.hx, WA(o.wout),
+                       WA(o.bout), w.eps);
+    TN_LAUNCH_CHECK();
+  }
+  const TA *eps_caller = w.eps;
+  if (gr.perm && N > 0) {
+    hipLaunchKernelGGL(k_unpermute<TA>, dim3(grid_for(N, bs)), dim3(bs), 0, s, N, gr.perm, w.eps, w.eps_orig);
+    TN_LAUNCH_CHECK();
+    eps_caller = w.eps_orig;
+  }
+  if (pb.S > 0) {
+    hipLaunchKernelGGL(k_energy_reduce<TA>, dim3((unsigned)pb.S), dim3(128), 0, s, N, eps_caller, pb.batch,
+                       pb.energy, pb.status);
+    TN_LAUNCH_CHECK();
+  }
+  if (!pb.want_forces) return TN_OK;
+
+  // ================================================================ reverse sweep
+  if (N > 0) {
+    hipLaunchKernelGGL(k_out_final_bwd<TA>, dim3(grid_for(N * H, bs)), dim3(bs), 0, s, N, (int)H, w.hz, WA(o.wout),
+                       w.dhz);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = linear_bwd<TA>(s, w.dhz, N, H, WA(o.Wh), F, w.dox, w.oz, 0))) return rc;
+  if ((rc = linear_bwd<TA>(s, w.dox, N, F, WA(o.Wo), 3 * F, w.dq, nullptr, 0))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_layernorm_bwd<TA>, dim3((unsigned)N), dim3(128), 0, s, N, (int)(3 * F), w.dq, w.oxhat,
+                       w.orstd, WA(o.oln_g), w.don);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_out_norms_bwd<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XLA, w.don, w.dXA);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = convert<TA, float>(s, w.dXA, w.dX, N * 9 * F))) return rc;
+  if (MP > 0 && (rc = fill_bytes_zero(s, w.dphi, MP * sizeof(float)))) return rc;
+  for (int64_t l = L - 1; l >= 0; --l) {
+    const LayerOff &lo = o.layer[l];
+    const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
+    const float *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
+    if (N > 0) {
+      hipLaunchKernelGGL(k_residual_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.D[l], w.dX, w.dD);
+      TN_LAUNCH_CHECK();
+    }
+    if ((rc = mix<float>(s, w.dD, w.dPb, N, F, W2, 1, 0))) return rc;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_product_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dPb, w.P[l], w.nP[l], w.Y[l],
+                         w.M[l], w.dY, w.dM);
+      TN_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_message<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, w.h[l],
+                         w.dM, w.dY, 1);
+      TN_LAUNCH_CHECK();
+    }
+    if (MP > 0) {
+      hipLaunchKernelGGL(k_message_bwd_pair<float>, dim3(grid_for(MP * F, bs)), dim3(bs), 0, s, gr.pairs, MP, np,
+                         (int)F, w.Y[l], w.dM, w.dh[l]);
+      TN_LAUNCH_CHECK();
+    }
+    if ((rc = mix<float>(s, w.dY, w.dX, N, F, W1, 1, 1))) return rc;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_normalize_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[l], w.nX[l], w.dX);
+      TN_LAUNCH_CHECK();
+    }
+  }
+  // ---- embedding adjoint, node part in FP64
+  if ((rc = convert<float, TA>(s, w.dX, w.dXA, N * 9 * F))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_gate_bwd<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dXA, w.T0, w.g, w.dg, w.dT0);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = mix<TA>(s, w.dT0, w.dXrA, N, F, Wemb, 1, 0))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_mul_silu_grad<TA>, dim3(grid_for(N * 3 * F, bs)), dim3(bs), 0, s, N * 3 * F, w.dg, w.ez2,
+                       w.dez2);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = linear_bwd<TA>(s, w.dez2, N, 3 * F, WA(o.W2), 2 * F, w.dez1, w.ez1, 0))) return rc;
+  if ((rc = linear_bwd<TA>(s, w.dez1, N, 2 * F, WA(o.W1), F, w.dn0, nullptr, 0))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_layernorm_bwd<TA>, dim3((unsigned)N), dim3(128), 0, s, N, (int)F, w.dn0, w.xhat0, w.rstd0,
+                       WA(o.ln_g), w.dnrm0);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_norm_bwd_add<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XrA, w.dnrm0, w.dXrA);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = convert<TA, float>(s, w.dXrA, w.dXr, N * 9 * F))) return rc;
+  if (MP > 0) {
+    hipLaunchKernelGGL(k_embed_bwd_pair<float>, dim3((unsigned)MP), dim3(128), 0, s, gr.pairs, MP, np, (int)F, zz,
+                       m->max_z, W(o.U), W(o.V), w.geo, w.phi, w.f0, w.dXr, w.df0, w.dphi, w.dvhat);
+    TN_LAUNCH_CHECK();
+  }
+  // ---- all per-pair work of the reverse sweep in one MFMA kernel
+  PairBwdArgs pbw;
+  pbw.pairs = gr.pairs;
+  pbw.max_pairs = MP;
+  pbw.n_pairs = np;
+  pbw.pos = pos;
+  pbw.periodic = pb.box.periodic;
+  for (int a = 0; a < 3; ++a) pbw.box[a] = pb.box.len[a];
+  pbw.r_c = m->r_c;
+  pbw.r_lo = m->r_lo;
+  pbw.alpha = m->alpha;
+  pbw.mu = WA(o.mu);
+  pbw.beta = WA(o.beta);
+  pbw.W0T = W(o.W0T);
+  pbw.L = (int)L;
+  for (int64_t l = 0; l < L; ++l) {
+    const LayerOff &lo = o.layer[l];
+    pbw.WaT[l] = W(lo.WaT);
+    pbw.WbT[l] = W(lo.WbT);
+    pbw.WcT[l] = W(lo.WcT);
+    pbw.z1[l] = w.z1[l];
+    pbw.z2[l] = w.z2[l];
+    pbw.z3[l] = w.z3[l];
+    pbw.dh[l] = w.dh[l];
+  }
+  pbw.df0 = w.df0;
+  pbw.dphi0 = w.dphi;
+  pbw.dvhat = w.dvhat;
+  pbw.gpair = w.gpair;
+  if ((rc = launch_pair_bwd(s, (int)F, (int)K, pbw))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL((k_force_gather<float, float>), dim3(grid_for(N, bs)), dim3(bs), 0, s, N, rowptr, nbr, pid,
+                       np, MP, w.gpair, gr.perm, static_cast<float *>(pb.forces));
+    TN_LAUNCH_CHECK();
+  }
+  return TN_OK;
+}
+
+}  // namespace
+
+size_t fused_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t max_pairs, const BoxInfo &bi, int prec,
+                             int want_forces) {
+  (void)S;
+  if (prec != TN_FP32 || !pair_kernels_support(m->F, m->K, m->L)) return 0;
+  WsPlan p(nullptr);
+  FusedWs w;
+  plan_fused(p, m, n, max_pairs, bi, want_forces != 0, &w);
+  return p.off;
+}
+
+int fused_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, void *ws, size_t ws_bytes) {
+  if (!pair_kernels_support(m->F, m->K, m->L)) return TN_E_UNSUPPORTED;
+  if (prec == TN_FP32) return run_fused_f32(m, s, pb, ws, ws_bytes);
+  return TN_E_UNSUPPORTED;
+}
 
 }  // namespace tn

@@ -30,12 +30,15 @@ constexpr int kWsAlign = 256;
 // ------------------------------------------------------------------ weights
 struct LayerOff {
   size_t Wa, ba, Wb, bb, Wc, bc, W1[3], W2[3];
+  size_t WaT, WbT, WcT;   // transposed copies [K][F], [F][2F], [2F][3F] (fused reverse sweep)
+  size_t Waf, Wbf, Wcf;   // 64-element aligned copies of Wa, Wb, Wc (fused forward)
 };
 
 struct WeightOff {
   size_t E, Wz, bz, W0, b0, ln_g, ln_b, W1, b1, W2, b2, Wmix[3];
   std::vector<LayerOff> layer;
   size_t oln_g, oln_b, Wo, bo, Wh, bh, wout, bout;
+  size_t W0T, W0f;  // transposed [K][3F] and aligned copy of W0
   size_t U, V;      // species tables [max_z, F]: Z_ij = U[z_i] + V[z_j]
   size_t mu, beta;  // radial basis constants [K]
   size_t total;     // element count of one packed copy
@@ -93,16 +96,28 @@ struct NbrWs {
   int32_t *scan_tmp = nullptr;                  // block sums
   int64_t *count64 = nullptr;                   // [2]: total pairs, total directed edges
   int32_t *flags = nullptr;                     // [0]: batch vector not sorted
+  void *spos = nullptr;                         // [N,3] cell-ordered positions (periodic)
+  int32_t *sz = nullptr, *sbatch = nullptr, *scell = nullptr;   // cell-ordered z, batch, cell
+  int32_t *ipairs = nullptr;                    // [2, max_pairs] internal pair list
+};
+
+// The graph the model kernels consume, in the internal atom order (cell order for a
+// periodic box, the caller's order otherwise; perm maps internal -> caller index).
+template <class T>
+struct NbrGraph {
+  const T *pos = nullptr;
+  const int32_t *z = nullptr, *batch = nullptr, *perm = nullptr;
+  const int32_t *rowptr = nullptr, *nbr = nullptr, *pid = nullptr, *pairs = nullptr;
 };
 
 void plan_neighbors(WsPlan &p, int64_t n, int64_t max_pairs, const BoxInfo &bi, NbrWs *w);
 
-// Builds the CSR graph (rowptr = w.deg, nbr, pid), the pair list pairs[0..1][max_pairs]
-// padded with -1, and *n_pairs.  T is the position type.
+// Builds the CSR graph and the internal pair list, *n_pairs, and (if public_pairs) the
+// caller-order pair list padded with -1.  z may be null.  T is the position type.
 template <class T>
-int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *batch, const BoxInfo &bi,
-                    double cutoff, int64_t max_pairs, int32_t *pairs, int64_t *n_pairs, int32_t *status,
-                    const NbrWs &w);
+int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, const int32_t *batch,
+                    const BoxInfo &bi, double cutoff, int64_t max_pairs, int32_t *public_pairs, int64_t *n_pairs,
+                    int32_t *status, const NbrWs &w, NbrGraph<T> *graph);
 
 // ------------------------------------------------------------------ scans and fills
 int exclusive_scan_i32(hipStream_t s, int32_t *data, int64_t n, int32_t *block_tmp, int64_t *total_out);
@@ -130,6 +145,48 @@ int plain_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, voi
 size_t fused_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t max_pairs, const BoxInfo &bi, int prec,
                              int want_forces);
 int fused_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, void *ws, size_t ws_bytes);
+
+// ------------------------------------------------------------------ MFMA pair kernels (fused path)
+constexpr int kMaxLayers = 16;
+
+// Whether the fused pair kernels support these sizes.
+bool pair_kernels_support(int F, int K, int L);
+
+struct PairFwdArgs {
+  const int32_t *pairs = nullptr;   // [2, max_pairs]
+  int64_t max_pairs = 0;
+  const int64_t *n_pairs = nullptr;
+  const float *pos = nullptr;
+  int periodic = 0;
+  double box[3] = {0, 0, 0};
+  double r_c = 0, r_lo = 0, alpha = 0;
+  const double *mu = nullptr, *beta = nullptr;
+  const float *W0 = nullptr, *b0 = nullptr;
+  const float *Wa[kMaxLayers], *ba[kMaxLayers], *Wb[kMaxLayers], *bb[kMaxLayers], *Wc[kMaxLayers], *bc[kMaxLayers];
+  int L = 0;
+  float *geo = nullptr, *phi = nullptr, *f0 = nullptr;
+  float *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers], *h[kMaxLayers];
+};
+
+struct PairBwdArgs {
+  const int32_t *pairs = nullptr;
+  int64_t max_pairs = 0;
+  const int64_t *n_pairs = nullptr;
+  const float *pos = nullptr;
+  int periodic = 0;
+  double box[3] = {0, 0, 0};
+  double r_c = 0, r_lo = 0, alpha = 0;
+  const double *mu = nullptr, *beta = nullptr;
+  const float *W0T = nullptr;
+  const float *WaT[kMaxLayers], *WbT[kMaxLayers], *WcT[kMaxLayers];
+  int L = 0;
+  const float *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers], *dh[kMaxLayers];
+  const float *df0 = nullptr, *dphi0 = nullptr, *dvhat = nullptr;
+  float *gpair = nullptr;
+};
+
+int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a);
+int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a);
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 

@@ -11,10 +11,14 @@
 //      scans turn the counts into CSR row offsets and pair offsets; the pair
 //      budget is checked on the device (no host round trip);
 //   3. the rows are written, sorted by neighbour index, and every directed edge
-//      gets the id of its unordered pair (binary search in the partner's row),
-//      which orders the public list by (i, j) and makes it deterministic.
-// Pair writes use scanned offsets instead of one global atomic counter per
-// pair.  The cutoff decision is an FP64 predicate with contraction disabled.
+//      gets the id of its unordered pair (binary search in the partner's row).
+// In a periodic box the atoms are renumbered in cell order (counting sort, each
+// cell's atoms by original index), so that spatial neighbours are close in
+// index; the model kernels work in that order and map results back.  One
+// wavefront handles one atom and sweeps the candidates of its stencil cells as
+// one flattened list; ballots place the neighbours, already sorted.  Pair
+// writes use scanned offsets instead of one global atomic counter per pair.
+// The cutoff decision is an FP64 predicate with contraction disabled.
 #include "tn_internal.h"
 #include "tn_device.h"
 
@@ -179,6 +183,13 @@ void plan_neighbors(WsPlan &p, int64_t n, int64_t max_pairs, const BoxInfo &bi, 
     w->cell_atoms = p.take<int32_t>(n);
     w->cell_start = w->cell_count;   // scanned in place
   }
+  if (bi.periodic) {
+    w->spos = p.take<double>(3 * n);
+    w->sz = p.take<int32_t>(n);
+    w->sbatch = p.take<int32_t>(n);
+    w->scell = p.take<int32_t>(n);
+  }
+  w->ipairs = p.take<int32_t>(2 * max_pairs);
   w->deg = p.take<int32_t>(n + 1);
   w->nup = p.take<int32_t>(n + 1);
   w->nbr = p.take<int32_t>(2 * max_pairs);
@@ -282,54 +293,6 @@ __device__ inline void system_range(const int32_t *batch, int64_t n, int32_t bv,
   hi = a;
 }
 
-// Visit every neighbour j of atom i; f(j) is called in a deterministic order.
-// With an unsorted batch vector the isolated search scans all atoms, which keeps the
-// neighbour relation symmetric (and the result correct) at O(N^2) cost.
-template <class T, class Fn>
-__device__ inline void for_each_neighbor(int64_t i, const T *pos, const int32_t *batch, int64_t n, const BoxDev &b,
-                                         double rc2, const int32_t *cell_of, const int32_t *cell_start,
-                                         const int32_t *cell_atoms, const int32_t *unsorted, Fn &&f) {
-  double xi, yi, zi;
-  load_pos(pos, i, xi, yi, zi);
-  const int32_t bi = batch[i];
-  if (b.periodic) {
-    const int c = cell_of[i];
-    const int cz = c % b.nc[2];
-    const int cy = (c / b.nc[2]) % b.nc[1];
-    const int cx = c / (b.nc[1] * b.nc[2]);
-    // distinct neighbour cells only: 1 cell per side -> {0}, 2 -> {0, +1}, else {-1, 0, +1}
-    const int lox = b.nc[0] >= 3 ? -1 : 0, hix = b.nc[0] >= 2 ? 1 : 0;
-    const int loy = b.nc[1] >= 3 ? -1 : 0, hiy = b.nc[1] >= 2 ? 1 : 0;
-    const int loz = b.nc[2] >= 3 ? -1 : 0, hiz = b.nc[2] >= 2 ? 1 : 0;
-    for (int ox = lox; ox <= hix; ++ox) {
-      const int nx = (cx + ox + b.nc[0]) % b.nc[0];
-      for (int oy = loy; oy <= hiy; ++oy) {
-        const int ny = (cy + oy + b.nc[1]) % b.nc[1];
-        for (int oz = loz; oz <= hiz; ++oz) {
-          const int nz = (cz + oz + b.nc[2]) % b.nc[2];
-          const int cc = (nx * b.nc[1] + ny) * b.nc[2] + nz;
-          for (int k = cell_start[cc]; k < cell_start[cc + 1]; ++k) {
-            const int32_t j = cell_atoms[k];
-            if (j == i || batch[j] != bi) continue;
-            double xj, yj, zj;
-            load_pos(pos, j, xj, yj, zj);
-            if (pair_within(xi, yi, zi, xj, yj, zj, b, rc2)) f(j);
-          }
-        }
-      }
-    }
-  } else {
-    int64_t lo = 0, hi = n;
-    if (!*unsorted) system_range(batch, n, bi, lo, hi);
-    for (int64_t j = lo; j < hi; ++j) {
-      if (j == i || batch[j] != bi) continue;
-      double xj, yj, zj;
-      load_pos(pos, j, xj, yj, zj);
-      if (pair_within(xi, yi, zi, xj, yj, zj, b, rc2)) f((int32_t)j);
-    }
-  }
-}
-
 __global__ void k_batch_sorted(const int32_t *batch, int64_t n, int32_t *unsorted, int32_t *status) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n || i == 0) return;
@@ -340,23 +303,168 @@ __global__ void k_batch_sorted(const int32_t *batch, int64_t n, int32_t *unsorte
 }
 
 template <class T>
-__global__ void k_nbr_count(const T *pos, const int32_t *batch, int64_t n, BoxDev b, double rc2,
-                            const int32_t *cell_of, const int32_t *cell_start, const int32_t *cell_atoms,
-                            const int32_t *unsorted, int32_t *deg, int32_t *nup, int32_t *status) {
+__global__ void k_check_finite(const T *pos, int64_t n, int32_t *status) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (!b.periodic) {
-    double x, y, z;
-    load_pos(pos, i, x, y, z);
-    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) set_status(status, TN_STATUS_NONFINITE);
+  double x, y, z;
+  load_pos(pos, i, x, y, z);
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) set_status(status, TN_STATUS_NONFINITE);
+}
+
+// Deterministic order inside each cell: insertion sort of the cell's atoms by original index.
+__global__ void k_cell_sort(int64_t ncell, const int32_t *cell_start, int32_t *cell_atoms) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int32_t a = cell_start[c], e = cell_start[c + 1];
+  for (int32_t k = a + 1; k < e; ++k) {
+    const int32_t v = cell_atoms[k];
+    int32_t q = k - 1;
+    while (q >= a && cell_atoms[q] > v) {
+      cell_atoms[q + 1] = cell_atoms[q];
+      --q;
+    }
+    cell_atoms[q + 1] = v;
   }
+}
+
+// Cell-ordered copies of the per-atom inputs (s = cell-ordered index, perm[s] = original index).
+template <class T>
+__global__ void k_permute(int64_t n, const int32_t *perm, const T *pos, const int32_t *z, const int32_t *batch,
+                          const int32_t *cell_of, T *spos, int32_t *sz, int32_t *sbatch, int32_t *scell) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t o = perm[s];
+  spos[3 * s] = pos[3 * o];
+  spos[3 * s + 1] = pos[3 * o + 1];
+  spos[3 * s + 2] = pos[3 * o + 2];
+  if (z) sz[s] = z[o];
+  sbatch[s] = batch[o];
+  scell[s] = cell_of[o];
+}
+
+// One wavefront per (cell-ordered) atom visits its candidates in ascending index order:
+// the distinct stencil cells in ascending linear order (periodic box) or the atom's system
+// range (isolated systems), flattened into one list that the 64 lanes sweep together.
+// f(pred, j) is called by every lane with its candidate; neighbours come out sorted.
+constexpr int kNbrBlock = 256;
+
+template <class T, class Fn>
+__device__ inline void wave_candidates(int64_t s, const T *pos, const int32_t *batch, int64_t n, const BoxDev &b,
+                                       double rc2, const int32_t *scell, const int32_t *cell_start,
+                                       const int32_t *unsorted, Fn &&f) {
+  const int lane = threadIdx.x & 63;
+  double xi, yi, zi;
+  load_pos(pos, s, xi, yi, zi);
+  const int32_t bs = batch[s];
+  if (b.periodic) {
+    const int c = scell[s];
+    const int cz = c % b.nc[2];
+    const int cy = (c / b.nc[2]) % b.nc[1];
+    const int cx = c / (b.nc[1] * b.nc[2]);
+    // distinct wrapped coordinates per axis, ascending (1 cell -> 1 value, 2 -> 2, else 3)
+    int xs[3], ys[3], zs[3], nx, ny, nz;
+    auto axis = [](int cc, int nc, int out[3], int &cnt) {
+      if (nc == 1) { out[0] = 0; cnt = 1; return; }
+      if (nc == 2) { out[0] = 0; out[1] = 1; cnt = 2; return; }
+      int v0 = (cc + nc - 1) % nc, v1 = cc, v2 = (cc + 1) % nc;
+      // sort three values
+      if (v0 > v1) { int t = v0; v0 = v1; v1 = t; }
+      if (v1 > v2) { int t = v1; v1 = v2; v2 = t; }
+      if (v0 > v1) { int t = v0; v0 = v1; v1 = t; }
+      out[0] = v0; out[1] = v1; out[2] = v2; cnt = 3;
+    };
+    axis(cx, b.nc[0], xs, nx);
+    axis(cy, b.nc[1], ys, ny);
+    axis(cz, b.nc[2], zs, nz);
+    const int ncells = nx * ny * nz;
+    int cs = 0, cnt = 0;
+    if (lane < ncells) {
+      const int ix = lane / (ny * nz), iy = (lane / nz) % ny, iz = lane % nz;
+      const int cc = (xs[ix] * b.nc[1] + ys[iy]) * b.nc[2] + zs[iz];
+      cs = cell_start[cc];
+      cnt = cell_start[cc + 1] - cs;
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+      const int up = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += up;
+    }
+    const int excl = incl - cnt;
+    const int total = __shfl(incl, ncells - 1, 64);
+    for (int q0 = 0; q0 < total; q0 += 64) {
+      const int q = q0 + lane;
+      // slot k with excl[k] <= q (largest such k among the ncells slots)
+      int lo = 0;
+#pragma unroll
+      for (int step = 16; step > 0; step >>= 1) {
+        const int mid = lo + step;
+        const int e_mid = __shfl(excl, mid < ncells ? mid : ncells - 1, 64);
+        if (mid < ncells && e_mid <= q) lo = mid;
+      }
+      const int base = __shfl(cs, lo, 64), ex = __shfl(excl, lo, 64);
+      bool pred = false;
+      int32_t j = 0;
+      if (q < total) {
+        j = base + (q - ex);
+        if (j != s && batch[j] == bs) {
+          double xj, yj, zj;
+          load_pos(pos, j, xj, yj, zj);
+          pred = pair_within(xi, yi, zi, xj, yj, zj, b, rc2);
+        }
+      }
+      f(pred, j);
+    }
+  } else {
+    int64_t lo = 0, hi = n;
+    if (!*unsorted) system_range(batch, n, bs, lo, hi);
+    for (int64_t q0 = lo; q0 < hi; q0 += 64) {
+      const int64_t j = q0 + lane;
+      bool pred = false;
+      if (j < hi && j != s && batch[j] == bs) {
+        double xj, yj, zj;
+        load_pos(pos, j, xj, yj, zj);
+        pred = pair_within(xi, yi, zi, xj, yj, zj, b, rc2);
+      }
+      f(pred, (int32_t)j);
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kNbrBlock) k_nbr_count(const T *pos, const int32_t *batch, int64_t n, BoxDev b,
+                                                         double rc2, const int32_t *scell, const int32_t *cell_start,
+                                                         const int32_t *unsorted, int32_t *deg, int32_t *nup) {
+  const int64_t s = (blockIdx.x * (int64_t)kNbrBlock + threadIdx.x) >> 6;
+  if (s >= n) return;
   int32_t full = 0, upper = 0;
-  for_each_neighbor(i, pos, batch, n, b, rc2, cell_of, cell_start, cell_atoms, unsorted, [&](int32_t j) {
-    ++full;
-    upper += (j > i);
+  wave_candidates(s, pos, batch, n, b, rc2, scell, cell_start, unsorted, [&](bool pred, int32_t j) {
+    const uint64_t m = __ballot(pred);
+    const uint64_t mu = __ballot(pred && j > s);
+    full += __popcll(m);
+    upper += __popcll(mu);
   });
-  deg[i] = full;
-  nup[i] = upper;
+  if ((threadIdx.x & 63) == 0) {
+    deg[s] = full;
+    nup[s] = upper;
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kNbrBlock) k_nbr_write(const T *pos, const int32_t *batch, int64_t n, BoxDev b,
+                                                         double rc2, const int32_t *scell, const int32_t *cell_start,
+                                                         const int32_t *unsorted, const int32_t *rowptr,
+                                                         const int64_t *count64, int64_t max_pairs, int32_t *nbr) {
+  const int64_t s = (blockIdx.x * (int64_t)kNbrBlock + threadIdx.x) >> 6;
+  if (s >= n || count64[0] > max_pairs) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int32_t e = rowptr[s];
+  wave_candidates(s, pos, batch, n, b, rc2, scell, cell_start, unsorted, [&](bool pred, int32_t j) {
+    const uint64_t m = __ballot(pred);
+    if (pred) nbr[e + __popcll(m & below)] = j;
+    e += __popcll(m);
+  });
 }
 
 __global__ void k_nbr_total(const int64_t *count64, int64_t max_pairs, int64_t *n_pairs, int32_t *status) {
@@ -367,38 +475,10 @@ __global__ void k_nbr_total(const int64_t *count64, int64_t max_pairs, int64_t *
   }
 }
 
-template <class T>
-__global__ void k_nbr_write(const T *pos, const int32_t *batch, int64_t n, BoxDev b, double rc2,
-                            const int32_t *cell_of, const int32_t *cell_start, const int32_t *cell_atoms,
-                            const int32_t *unsorted, const int32_t *rowptr, const int64_t *count64,
-                            int64_t max_pairs, int32_t *nbr) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n || count64[0] > max_pairs) return;
-  int32_t e = rowptr[i];
-  for_each_neighbor(i, pos, batch, n, b, rc2, cell_of, cell_start, cell_atoms, unsorted,
-                    [&](int32_t j) { nbr[e++] = j; });
-}
-
-__global__ void k_row_sort(int64_t n, const int32_t *rowptr, const int64_t *count64, int64_t max_pairs,
-                           int32_t *nbr) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n || count64[0] > max_pairs) return;
-  const int32_t a = rowptr[i], e = rowptr[i + 1];
-  for (int32_t k = a + 1; k < e; ++k) {
-    const int32_t v = nbr[k];
-    int32_t q = k - 1;
-    while (q >= a && nbr[q] > v) {
-      nbr[q + 1] = nbr[q];
-      --q;
-    }
-    nbr[q + 1] = v;
-  }
-}
-
-// Pair id of every directed edge; the public list gets (i, j) for j > i.
-__global__ void k_pair_ids(int64_t n, const int32_t *rowptr, const int32_t *pbase,
-                           const int32_t *nbr, const int64_t *count64, int64_t max_pairs, int32_t *pid,
-                           int32_t *pairs) {
+// Pair id of every directed edge (rows are sorted by neighbour); the internal pair list
+// gets (s, t) for t > s, so it is ordered by (s, t).
+__global__ void k_pair_ids(int64_t n, const int32_t *rowptr, const int32_t *pbase, const int32_t *nbr,
+                           const int64_t *count64, int64_t max_pairs, int32_t *pid, int32_t *pairs) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n || count64[0] > max_pairs) return;
   const int32_t a = rowptr[i], e = rowptr[i + 1];
@@ -429,25 +509,51 @@ __global__ void k_pair_ids(int64_t n, const int32_t *rowptr, const int32_t *pbas
   }
 }
 
-__global__ void k_pad_pairs(const int64_t *count64, int64_t max_pairs, int32_t *pairs) {
+// Public pair list in original atom indices, (min, max) per pair; padding -1.
+__global__ void k_pairs_public(const int64_t *count64, int64_t max_pairs, const int32_t *perm, const int32_t *ipairs,
+                               int32_t *pairs) {
   const int64_t P = count64[0];
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < max_pairs;
        p += (int64_t)gridDim.x * blockDim.x) {
-    if (p >= P || P > max_pairs) {
-      pairs[p] = -1;
-      pairs[max_pairs + p] = -1;
+    int32_t a = -1, c = -1;
+    if (p < P && P <= max_pairs) {
+      a = ipairs[p];
+      c = ipairs[max_pairs + p];
+      if (perm) {
+        a = perm[a];
+        c = perm[c];
+      }
+      if (a > c) {
+        const int32_t t = a;
+        a = c;
+        c = t;
+      }
     }
+    pairs[p] = a;
+    pairs[max_pairs + p] = c;
   }
 }
 
 template <class T>
-int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *batch, const BoxInfo &bi, double cutoff,
-                    int64_t max_pairs, int32_t *pairs, int64_t *n_pairs, int32_t *status, const NbrWs &w) {
+int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, const int32_t *batch,
+                    const BoxInfo &bi, double cutoff, int64_t max_pairs, int32_t *public_pairs, int64_t *n_pairs,
+                    int32_t *status, const NbrWs &w, NbrGraph<T> *graph) {
   const BoxDev b = to_dev(bi);
   const double rc2 = cutoff * cutoff;
   const int blk = 128;
   const unsigned g = grid_for(n > 0 ? n : 1, blk);
+  const unsigned gw = grid_for(n > 0 ? n * 64 : 64, kNbrBlock);   // one wavefront per atom
   int rc;
+  NbrGraph<T> out;
+  out.pos = pos;
+  out.z = z;
+  out.batch = batch;
+  out.perm = nullptr;
+  if ((rc = fill_i32(s, w.flags, 4, 0))) return rc;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_batch_sorted, dim3(g), dim3(blk), 0, s, batch, n, w.flags, status);
+    TN_LAUNCH_CHECK();
+  }
   if (bi.periodic) {
     const int64_t ncell = (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2];
     if ((rc = fill_i32(s, w.cell_count, ncell + 1, 0))) return rc;
@@ -461,14 +567,25 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *batch
       hipLaunchKernelGGL(k_cell_scatter, dim3(g), dim3(blk), 0, s, n, w.cell_of, w.cell_start, w.cell_fill,
                          w.cell_atoms);
       TN_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(ncell, blk)), dim3(blk), 0, s, ncell, w.cell_start,
+                         w.cell_atoms);
+      TN_LAUNCH_CHECK();
+      T *spos = static_cast<T *>(w.spos);
+      hipLaunchKernelGGL(k_permute<T>, dim3(g), dim3(blk), 0, s, n, w.cell_atoms, pos, z, batch, w.cell_of, spos,
+                         w.sz, w.sbatch, w.scell);
+      TN_LAUNCH_CHECK();
+      out.pos = spos;
+      out.z = z ? w.sz : nullptr;
+      out.batch = w.sbatch;
+      out.perm = w.cell_atoms;
     }
-  }
-  if ((rc = fill_i32(s, w.flags, 4, 0))) return rc;
-  if (n > 0) {
-    hipLaunchKernelGGL(k_batch_sorted, dim3(g), dim3(blk), 0, s, batch, n, w.flags, status);
+  } else if (n > 0) {
+    hipLaunchKernelGGL(k_check_finite<T>, dim3(g), dim3(blk), 0, s, pos, n, status);
     TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_nbr_count<T>, dim3(g), dim3(blk), 0, s, pos, batch, n, b, rc2, w.cell_of, w.cell_start,
-                       w.cell_atoms, w.flags, w.deg, w.nup, status);
+  }
+  if (n > 0) {
+    hipLaunchKernelGGL(k_nbr_count<T>, dim3(gw), dim3(kNbrBlock), 0, s, out.pos, out.batch, n, b, rc2, w.scell,
+                       w.cell_start, w.flags, w.deg, w.nup);
     TN_LAUNCH_CHECK();
   }
   if ((rc = exclusive_scan_i32(s, w.deg, n, w.scan_tmp, w.count64 + 1))) return rc;
@@ -476,27 +593,31 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *batch
   hipLaunchKernelGGL(k_nbr_total, dim3(1), dim3(64), 0, s, w.count64, max_pairs, n_pairs, status);
   TN_LAUNCH_CHECK();
   if (n > 0) {
-    hipLaunchKernelGGL(k_nbr_write<T>, dim3(g), dim3(blk), 0, s, pos, batch, n, b, rc2, w.cell_of, w.cell_start,
-                       w.cell_atoms, w.flags, w.deg, w.count64, max_pairs, w.nbr);
+    hipLaunchKernelGGL(k_nbr_write<T>, dim3(gw), dim3(kNbrBlock), 0, s, out.pos, out.batch, n, b, rc2, w.scell,
+                       w.cell_start, w.flags, w.deg, w.count64, max_pairs, w.nbr);
     TN_LAUNCH_CHECK();
-    if (bi.periodic) {
-      hipLaunchKernelGGL(k_row_sort, dim3(g), dim3(blk), 0, s, n, w.deg, w.count64, max_pairs, w.nbr);
-      TN_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(k_pair_ids, dim3(g), dim3(blk), 0, s, n, w.deg, w.nup, w.nbr, w.count64, max_pairs,
-                       w.pid, pairs);
+    hipLaunchKernelGGL(k_pair_ids, dim3(g), dim3(blk), 0, s, n, w.deg, w.nup, w.nbr, w.count64, max_pairs, w.pid,
+                       w.ipairs);
     TN_LAUNCH_CHECK();
   }
-  if (max_pairs > 0) {
-    hipLaunchKernelGGL(k_pad_pairs, dim3(fill_grid(max_pairs)), dim3(256), 0, s, w.count64, max_pairs, pairs);
+  if (public_pairs && max_pairs > 0) {
+    hipLaunchKernelGGL(k_pairs_public, dim3(fill_grid(max_pairs)), dim3(256), 0, s, w.count64, max_pairs, out.perm,
+                       w.ipairs, public_pairs);
     TN_LAUNCH_CHECK();
   }
+  out.rowptr = w.deg;
+  out.nbr = w.nbr;
+  out.pid = w.pid;
+  out.pairs = w.ipairs;
+  if (graph) *graph = out;
   return TN_OK;
 }
 
-template int build_neighbors<float>(hipStream_t, int64_t, const float *, const int32_t *, const BoxInfo &, double,
-                                    int64_t, int32_t *, int64_t *, int32_t *, const NbrWs &);
-template int build_neighbors<double>(hipStream_t, int64_t, const double *, const int32_t *, const BoxInfo &, double,
-                                     int64_t, int32_t *, int64_t *, int32_t *, const NbrWs &);
+template int build_neighbors<float>(hipStream_t, int64_t, const float *, const int32_t *, const int32_t *,
+                                    const BoxInfo &, double, int64_t, int32_t *, int64_t *, int32_t *, const NbrWs &,
+                                    NbrGraph<float> *);
+template int build_neighbors<double>(hipStream_t, int64_t, const double *, const int32_t *, const int32_t *,
+                                     const BoxInfo &, double, int64_t, int32_t *, int64_t *, int32_t *,
+                                     const NbrWs &, NbrGraph<double> *);
 
 }  // namespace tn

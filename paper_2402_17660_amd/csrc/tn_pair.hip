@@ -1,0 +1,362 @@
+// Fused per-pair kernels on MFMA (FP32, v_mfma_f32_16x16x4f32).
+//
+// The edge filters of TensorNet (Sec. 2.1.1; exp-normal basis and SiLU of Sec. 2.4) depend
+// on the pair distance only, so every layer's filter and the embedding's K -> 3F map are
+// evaluated once per unordered pair, in one pass over pair tiles:
+//   forward   geometry + basis (FP64) -> f0 = W0 e + b0 -> per layer
+//             z1 = Wa e + ba, z2 = Wb silu(z1) + bb, z3 = Wc silu(z2) + bc, h = phi silu(z3)
+//   reverse   per layer dz3 = dh phi silu'(z3), dz2 = (dz3 Wc) silu'(z2), dz1 = (dz2 Wb) silu'(z1),
+//             de += dz1 Wa;  de += df0 W0;  then dE/dv from de, dE/dphi, dE/dvhat (FP64)
+// Tiles hold 32 pairs; the four waves of a workgroup split the output columns, each wave
+// covering all 32 rows in two 16-row MFMA blocks.  Activations live in LDS (row padding of
+// 4 floats), weights stream from L2 as 16-byte loads.  The K index inside each 16-wide
+// chunk is permuted (lane group q takes k = 4q..4q+3) so that one 16-byte load feeds four
+// consecutive MFMAs for both operands.
+#include "tn_internal.h"
+#include "tn_device.h"
+
+namespace tn {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 32;   // pairs per tile
+constexpr int kPad = 4;     // LDS row padding (floats)
+
+bool pair_kernels_support(int F, int K, int L) {
+  return (F == 64 || F == 128) && (K == 16 || K == 32 || K == 48 || K == 64) && L >= 0 && L <= kMaxLayers;
+}
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// acc[rb][cb] += act[32 x Kin] (LDS, row stride ld) * Bt^T, where Bt is [ncol][Kin] in global
+// memory (row stride Kin) and this wave covers columns col0 .. col0 + 16*NB - 1.
+// acc element t of lane l is D[rb*16 + 4*(l/16) + t][col0 + cb*16 + l%16].
+template <int NB>
+__device__ __forceinline__ void wave_mm(const float *act, int ld, int Kin, const float *__restrict__ Bt, int col0,
+                                        floatx4 (&acc)[2][NB]) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  const float *a0p = act + r * ld + 4 * q;
+  const float *a1p = act + (r + 16) * ld + 4 * q;
+  const float *bp = Bt + (size_t)(col0 + r) * Kin + 4 * q;
+  const size_t bstride = (size_t)16 * Kin;
+#pragma unroll 2
+  for (int k0 = 0; k0 < Kin; k0 += 16) {
+    float4 b[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) b[cb] = *reinterpret_cast<const float4 *>(bp + cb * bstride + k0);
+    const float4 a0 = *reinterpret_cast<const float4 *>(a0p + k0);
+    const float4 a1 = *reinterpret_cast<const float4 *>(a1p + k0);
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      acc[0][cb] = mfma4(a0.x, b[cb].x, acc[0][cb]);
+      acc[1][cb] = mfma4(a1.x, b[cb].x, acc[1][cb]);
+      acc[0][cb] = mfma4(a0.y, b[cb].y, acc[0][cb]);
+      acc[1][cb] = mfma4(a1.y, b[cb].y, acc[1][cb]);
+      acc[0][cb] = mfma4(a0.z, b[cb].z, acc[0][cb]);
+      acc[1][cb] = mfma4(a1.z, b[cb].z, acc[1][cb]);
+      acc[0][cb] = mfma4(a0.w, b[cb].w, acc[0][cb]);
+      acc[1][cb] = mfma4(a1.w, b[cb].w, acc[1][cb]);
+    }
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void zero_acc(floatx4 (&acc)[2][NB]) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Visit the accumulator entries of this lane: f(row, col, value).
+template <int NB, class Fn>
+__device__ __forceinline__ void for_acc(const floatx4 (&acc)[2][NB], int col0, Fn &&f) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) f(rb * 16 + 4 * (lane >> 4) + t, col0 + cb * 16 + (lane & 15), acc[rb][cb][t]);
+}
+
+// Pair geometry in FP64 from the FP32 positions: unit vector, distance, cutoff and its derivative.
+struct PairGeo {
+  double u[3], d, phi, dphi;
+};
+
+__device__ inline PairGeo pair_geometry(const float *pos, int64_t i, int64_t j, int periodic, const double *box,
+                                        double r_c) {
+  PairGeo g;
+  double v[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double dl = (double)pos[3 * j + a] - (double)pos[3 * i + a];
+    if (periodic) dl -= box[a] * rint(dl / box[a]);
+    v[a] = dl;
+  }
+  g.d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const double inv = 1.0 / g.d;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) g.u[a] = v[a] * inv;
+  const double arg = M_PI * g.d / r_c;
+  g.phi = 0.5 * (cos(arg) + 1.0);
+  g.dphi = -0.5 * M_PI / r_c * sin(arg);
+  return g;
+}
+
+// ============================================================================ forward
+template <int F, int K>
+__global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
+  constexpr int LE = K + kPad, L1 = F + kPad, L2 = 2 * F + kPad;
+  __shared__ __attribute__((aligned(16))) float sE[kTile * LE];
+  __shared__ __attribute__((aligned(16))) float sA1[kTile * L1];
+  __shared__ __attribute__((aligned(16))) float sA2[kTile * L2];
+  __shared__ double sD[kTile], sPhi[kTile];
+  const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
+  const int64_t p0 = (int64_t)blockIdx.x * kTile;
+  if (p0 >= P) return;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int nvalid = (int)((P - p0) < kTile ? (P - p0) : kTile);
+
+  if (tid < kTile) {
+    double d = a.r_c, ph = 0.0;
+    if (tid < nvalid) {
+      const int64_t p = p0 + tid;
+      const int64_t i = a.pairs[p], j = a.pairs[a.max_pairs + p];
+      const PairGeo g = pair_geometry(a.pos, i, j, a.periodic, a.box, a.r_c);
+      d = g.d;
+      ph = g.phi;
+      a.geo[4 * p + 0] = (float)g.u[0];
+      a.geo[4 * p + 1] = (float)g.u[1];
+      a.geo[4 * p + 2] = (float)g.u[2];
+      a.geo[4 * p + 3] = (float)g.d;
+      a.phi[p] = (float)g.phi;
+    }
+    sD[tid] = d;
+    sPhi[tid] = ph;
+  }
+  __syncthreads();
+  for (int t = tid; t < kTile * K; t += 256) {
+    const int row = t / K, k = t % K;
+    const double u = exp(-a.alpha * (sD[row] - a.r_lo));
+    const double x = u - a.mu[k];
+    sE[row * LE + k] = (float)(sPhi[row] * exp(-a.beta[k] * x * x));
+  }
+  __syncthreads();
+
+  // embedding map f0 = W0 e + b0  (3F outputs; wave covers 3F/4 columns)
+  {
+    constexpr int NB = 3 * F / 64;
+    floatx4 acc[2][NB];
+    zero_acc(acc);
+    const int col0 = wave * (3 * F / 4);
+    wave_mm<NB>(sE, LE, K, a.W0, col0, acc);
+    for_acc(acc, col0, [&](int row, int col, float v) {
+      if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = v + a.b0[col];
+    });
+  }
+  for (int l = 0; l < a.L; ++l) {
+    {  // z1 = Wa e + ba
+      constexpr int NB = F / 64;
+      floatx4 acc[2][NB];
+      zero_acc(acc);
+      const int col0 = wave * (F / 4);
+      wave_mm<NB>(sE, LE, K, a.Wa[l], col0, acc);
+      float *z1 = a.z1[l];
+      const float *bias = a.ba[l];
+      for_acc(acc, col0, [&](int row, int col, float v) {
+        const float z = v + bias[col];
+        if (row < nvalid) z1[(p0 + row) * F + col] = z;
+        sA1[row * L1 + col] = silu(z);
+      });
+    }
+    __syncthreads();
+    {  // z2 = Wb silu(z1) + bb
+      constexpr int NB = F / 32;
+      floatx4 acc[2][NB];
+      zero_acc(acc);
+      const int col0 = wave * (F / 2);
+      wave_mm<NB>(sA1, L1, F, a.Wb[l], col0, acc);
+      float *z2 = a.z2[l];
+      const float *bias = a.bb[l];
+      for_acc(acc, col0, [&](int row, int col, float v) {
+        const float z = v + bias[col];
+        if (row < nvalid) z2[(p0 + row) * 2 * F + col] = z;
+        sA2[row * L2 + col] = silu(z);
+      });
+    }
+    __syncthreads();
+    {  // z3 = Wc silu(z2) + bc, h = phi silu(z3)
+      constexpr int NB = 3 * F / 64;
+      floatx4 acc[2][NB];
+      zero_acc(acc);
+      const int col0 = wave * (3 * F / 4);
+      wave_mm<NB>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
+      float *z3 = a.z3[l], *h = a.h[l];
+      const float *bias = a.bc[l];
+      for_acc(acc, col0, [&](int row, int col, float v) {
+        const float z = v + bias[col];
+        if (row < nvalid) {
+          z3[(p0 + row) * 3 * F + col] = z;
+          h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * silu(z);
+        }
+      });
+    }
+  }
+}
+
+// ============================================================================ reverse
+template <int F, int K>
+__global__ void __launch_bounds__(256, 1) k_pair_bwd(PairBwdArgs a) {
+  constexpr int L3 = 3 * F + kPad, L2 = 2 * F + kPad, L1 = F + kPad, LE = K + kPad;
+  __shared__ __attribute__((aligned(16))) float sG3[kTile * L3];   // dz3, then dz1 / df0
+  __shared__ __attribute__((aligned(16))) float sG2[kTile * L2];   // dz2
+  __shared__ float sPhi[kTile];
+  __shared__ float sDphi[kTile];
+  const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
+  const int64_t p0 = (int64_t)blockIdx.x * kTile;
+  if (p0 >= P) return;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int nvalid = (int)((P - p0) < kTile ? (P - p0) : kTile);
+  constexpr int NWDE = K / 16;   // waves that own the dE/de accumulator (16 columns each)
+
+  PairGeo g{};
+  if (tid < kTile) {
+    float ph = 0.f, dp = 0.f;
+    if (tid < nvalid) {
+      const int64_t p = p0 + tid;
+      g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.periodic, a.box, a.r_c);
+      ph = (float)g.phi;
+      dp = a.dphi0[p];
+    }
+    sPhi[tid] = ph;
+    sDphi[tid] = dp;
+  }
+  // embedding adjoint df0 (3F per pair) -> LDS
+  for (int t = tid; t < kTile * 3 * F; t += 256) {
+    const int row = t / (3 * F), c = t % (3 * F);
+    sG3[row * L3 + c] = row < nvalid ? a.df0[(p0 + row) * 3 * F + c] : 0.f;
+  }
+  __syncthreads();
+  floatx4 de[2][1];
+  zero_acc(de);
+  if (wave < NWDE) wave_mm<1>(sG3, L3, 3 * F, a.W0T, wave * 16, de);
+  __syncthreads();
+
+  for (int l = 0; l < a.L; ++l) {
+    const float *z1 = a.z1[l], *z2 = a.z2[l], *z3 = a.z3[l], *dh = a.dh[l];
+    // dz3 = dh phi silu'(z3); dE/dphi += sum dh silu(z3).  Each wave owns 8 rows; the lanes
+    // sweep a row's 3F columns and the per-row sum is reduced across the wave.
+    {
+      const int lane = tid & 63;
+      for (int rr = 0; rr < kTile / 4; ++rr) {
+        const int row = wave * (kTile / 4) + rr;
+        float part = 0.f;
+        for (int c = lane; c < 3 * F; c += 64) {
+          float v = 0.f;
+          if (row < nvalid) {
+            const int64_t o = (p0 + row) * 3 * F + c;
+            const float z = z3[o], gh = dh[o];
+            v = gh * sPhi[row] * silu_grad(z);
+            part += gh * silu(z);
+          }
+          sG3[row * L3 + c] = v;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+        if (lane == 0) sDphi[row] += part;
+      }
+    }
+    __syncthreads();
+    {  // dz2 = (dz3 Wc) silu'(z2)
+      constexpr int NB = F / 32;
+      floatx4 acc[2][NB];
+      zero_acc(acc);
+      const int col0 = wave * (F / 2);
+      wave_mm<NB>(sG3, L3, 3 * F, a.WcT[l], col0, acc);
+      for_acc(acc, col0, [&](int row, int col, float v) {
+        sG2[row * L2 + col] = row < nvalid ? v * silu_grad(z2[(p0 + row) * 2 * F + col]) : 0.f;
+      });
+    }
+    __syncthreads();
+    {  // dz1 = (dz2 Wb) silu'(z1)  (stored over the dz3 buffer)
+      constexpr int NB = F / 64;
+      floatx4 acc[2][NB];
+      zero_acc(acc);
+      const int col0 = wave * (F / 4);
+      wave_mm<NB>(sG2, L2, 2 * F, a.WbT[l], col0, acc);
+      for_acc(acc, col0, [&](int row, int col, float v) {
+        sG3[row * L1 + col] = row < nvalid ? v * silu_grad(z1[(p0 + row) * F + col]) : 0.f;
+      });
+    }
+    __syncthreads();
+    if (wave < NWDE) wave_mm<1>(sG3, L1, F, a.WaT[l], wave * 16, de);   // de += dz1 Wa
+    __syncthreads();
+  }
+
+  // dE/de to LDS (reuse sG2 as [32][K+4]), then the geometry adjoint per pair in FP64
+  float *sDE = sG2;
+  if (wave < NWDE)
+    for_acc(de, wave * 16, [&](int row, int col, float v) { sDE[row * LE + col] = v; });
+  __syncthreads();
+  if (tid < nvalid) {
+    const int64_t p = p0 + tid;
+    const double u = exp(-a.alpha * (g.d - a.r_lo));
+    double dd = (double)sDphi[tid] * g.dphi;
+    for (int k = 0; k < K; ++k) {
+      const double x = u - a.mu[k];
+      const double gk = exp(-a.beta[k] * x * x);
+      const double dek = g.dphi * gk + g.phi * gk * 2.0 * a.alpha * a.beta[k] * u * x;
+      dd += (double)sDE[tid * LE + k] * dek;
+    }
+    const double gx = a.dvhat[3 * p], gy = a.dvhat[3 * p + 1], gz = a.dvhat[3 * p + 2];
+    const double proj = gx * g.u[0] + gy * g.u[1] + gz * g.u[2];
+    const double inv = 1.0 / g.d;
+    a.gpair[3 * p + 0] = (float)(dd * g.u[0] + (gx - proj * g.u[0]) * inv);
+    a.gpair[3 * p + 1] = (float)(dd * g.u[1] + (gy - proj * g.u[1]) * inv);
+    a.gpair[3 * p + 2] = (float)(dd * g.u[2] + (gz - proj * g.u[2]) * inv);
+  }
+}
+
+// ============================================================================ launchers
+template <int F, int K>
+static int launch_fwd(hipStream_t s, const PairFwdArgs &a) {
+  const unsigned grid = (unsigned)((a.max_pairs + kTile - 1) / kTile);
+  if (grid == 0) return TN_OK;
+  TimedScope ts("edge_fwd", s);
+  hipLaunchKernelGGL((k_pair_fwd<F, K>), dim3(grid), dim3(256), 0, s, a);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+template <int F, int K>
+static int launch_bwd(hipStream_t s, const PairBwdArgs &a) {
+  const unsigned grid = (unsigned)((a.max_pairs + kTile - 1) / kTile);
+  if (grid == 0) return TN_OK;
+  TimedScope ts("edge_bwd", s);
+  hipLaunchKernelGGL((k_pair_bwd<F, K>), dim3(grid), dim3(256), 0, s, a);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+#define TN_PAIR_DISPATCH(FN, ARGS)                                   \
+  switch (F * 1000 + K) {                                            \
+    case 64016: return FN<64, 16>(s, ARGS);                          \
+    case 64032: return FN<64, 32>(s, ARGS);                          \
+    case 64048: return FN<64, 48>(s, ARGS);                          \
+    case 64064: return FN<64, 64>(s, ARGS);                          \
+    case 128016: return FN<128, 16>(s, ARGS);                        \
+    case 128032: return FN<128, 32>(s, ARGS);                        \
+    case 128048: return FN<128, 48>(s, ARGS);                        \
+    case 128064: return FN<128, 64>(s, ARGS);                        \
+    default: return TN_E_UNSUPPORTED;                                \
+  }
+
+int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a) { TN_PAIR_DISPATCH(launch_fwd, a) }
+int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a) { TN_PAIR_DISPATCH(launch_bwd, a) }
+
+}  // namespace tn

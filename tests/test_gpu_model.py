@@ -59,7 +59,7 @@ def cfg0():
     return c, blob, E, F
 
 
-@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp32", "plain")])
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp32", "plain"), ("fp32", "fused")])
 def test_molecule48(dev, cfg0, precision, path):
     c, blob, E_ref, F_ref = cfg0
     m = TensorNet(blob, dev)
@@ -67,10 +67,11 @@ def test_molecule48(dev, cfg0, precision, path):
     assert_close(E, F, E_ref, F_ref, precision, f"cfg0 {precision} {path}")
 
 
-@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp32", "plain")])
-def test_small_periodic_box(dev, precision, path):
+@pytest.mark.parametrize("precision,path,F,K", [("fp64", "plain", 16, 8), ("fp32", "plain", 16, 8),
+                                                ("fp32", "fused", 64, 16), ("fp32", "fused", 128, 48)])
+def test_small_periodic_box(dev, precision, path, F, K):
     pos, z, box = random_box(100, 12, 10.0)
-    blob = small_blob(F=16, K=8, L=2, seed=13)
+    blob = small_blob(F=F, K=K, L=2, seed=13)
     E_ref, F_ref = TensorNetOracle(blob).energy_forces(pos.astype(np.float32), z, np.zeros(100, np.int32), box, 1)
     E, F = gpu_ef(dev, TensorNet(blob, dev), pos.astype(np.float32), z, np.zeros(100, np.int32), box, 1,
                   precision, path)
@@ -97,15 +98,26 @@ def test_batch_of_molecules_fp64(dev):
     assert_close(E, F, E_ref, F_ref, "fp64", "batch4")
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_workloads_fp32_plain(dev, cfg):
+@pytest.mark.parametrize("cfg,path", [(1, "plain"), (2, "plain"), (1, "fused"), (2, "fused")])
+def test_workloads_fp32(dev, cfg, path):
     c = make_config(cfg)
     g = np.load(os.path.join(GOLDEN, f"oracle_cfg{cfg}.npz"))
     m = TensorNet(cfg_blob(c), dev)
-    E, F = gpu_ef(dev, m, c["pos"], c["z"], c["batch"], c["box"], c["n_systems"], "fp32", "plain",
+    E, F = gpu_ef(dev, m, c["pos"], c["z"], c["batch"], c["box"], c["n_systems"], "fp32", path,
                   max_pairs=int(g["n_pairs"]) + 4096)
     assert int(m.n_pairs.item()) == int(g["n_pairs"])
-    assert_close(E, F, g["E"], g["F"], "fp32", f"cfg{cfg} fp32 plain")
+    assert_close(E, F, g["E"], g["F"], "fp32", f"cfg{cfg} fp32 {path}")
+
+
+@pytest.mark.parametrize("L_layers", [0, 1, 3])
+def test_fused_layer_counts(dev, L_layers):
+    # weight seed chosen so the molecule's energy is not a near-cancelling sum of atom terms
+    pos, z = random_molecule(40, 60 + L_layers)
+    blob = small_blob(F=64, K=32, L=L_layers, seed=71)
+    E_ref, F_ref = TensorNetOracle(blob).energy_forces(pos.astype(np.float32), z, np.zeros(40, np.int32), None, 1)
+    E, F = gpu_ef(dev, TensorNet(blob, dev), pos.astype(np.float32), z, np.zeros(40, np.int32), None, 1, "fp32",
+                  "fused")
+    assert_close(E, F, E_ref, F_ref, "fp32", f"fused L={L_layers}")
 
 
 def test_energy_only_matches(dev, cfg0):
