@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-atoms", type=int, default=1000)
     ap.add_argument("--budget", type=float, default=1.05, help="max_pairs = budget * true pair count")
+    ap.add_argument("--extra", default="batch,md", help="extra workloads: batch (512 molecules, captured), "
+                                                        "md (100 captured velocity-Verlet steps, 100k atoms); '' = none")
+    ap.add_argument("--md-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); run it with --gpus 1",
@@ -172,6 +175,13 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         cpu = cpu_baseline(args.cpu_atoms, F, K, L, r_c, c["weight_seed"])
+    extra = {}
+    for name in [e for e in args.extra.split(",") if e]:
+        try:
+            extra[name] = EXTRA[name](args, dev)
+        except Exception as e:   # an extra workload never hides the headline line
+            log(f"extra workload {name} failed: {e!r}")
+            extra[name] = dict(error=repr(e))
     out = dict(metric=METRIC, value=head["value"], unit="atom-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32" if head["precision"] == "fp32" else head["precision"],
@@ -184,8 +194,102 @@ def main():
                step_algorithmic_tflop=step_flop / 1e12,
                step_tflops=step_flop / (head["ms_per_step"] * 1e-3) / 1e12,
                errors=dict(energy_rel=head["energy_rel_err"], force_rel_rms=head["force_rel_rms"]),
-               variants=results)
+               variants=results, extra=extra)
     print(json.dumps(out), flush=True)
+
+
+def _blob_for(c):
+    from synth import make_weights, write_blob
+    return write_blob(make_weights(c["F"], c["K"], c["L"], c["max_z"], seed=c["weight_seed"]),
+                      c["F"], c["K"], c["L"], c["max_z"], c["r_c"])
+
+
+def extra_batch(args, dev):
+    """512 isolated molecules of 8-64 atoms: one captured graph per evaluation, FP32 vs BF16."""
+    import numpy as np
+    import torch
+    from paper_2402_17660_amd import TensorNet, capture
+    from synth import make_config
+    c = make_config(2)
+    N = len(c["pos"])
+    golden = np.load(os.path.join(ROOT, "tests", "golden", "oracle_cfg2.npz"))
+    model = TensorNet(_blob_for(c), dev)
+    pos = torch.tensor(c["pos"], device=dev)
+    z = torch.tensor(c["z"], device=dev)
+    batch = torch.tensor(c["batch"], device=dev)
+    mp = int(math.ceil(1.05 * int(golden["n_pairs"]) / 1024.0) * 1024)
+    out = dict(workload="512 isolated molecules, sizes uniform 8-64 atoms (centred at the origin), hidden 128, "
+                        "2 layers, cutoff 5 A; one captured HIP graph per energy+forces call",
+               n_atoms=N, n_pairs=int(golden["n_pairs"]), max_pairs=mp)
+    for prec in ("fp32", "bf16"):
+        g, E, Fo, n_pairs, status = capture(model, pos, z, batch, c["n_systems"], max_pairs=mp, precision=prec)
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        start.record()
+        for _ in range(reps):
+            g.replay()
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / reps
+        Ev = E.cpu().numpy()
+        Fv = Fo.double().cpu().numpy()
+        out[prec] = dict(ms_per_step=ms, value=N / (ms * 1e-3), status=int(status.item()),
+                         energy_rel_err=float(np.max(np.abs(Ev - golden["E"]) / np.abs(golden["E"]))),
+                         force_rel_rms=float(np.linalg.norm(Fv - golden["F"]) / np.linalg.norm(golden["F"])))
+        log(f"batch/{prec}: {ms:.3f} ms/step, {out[prec]['value']:.3e} atom-steps/s, "
+            f"E err {out[prec]['energy_rel_err']:.2e}, F err {out[prec]['force_rel_rms']:.2e}")
+        g.close()
+    return out
+
+
+def extra_md(args, dev):
+    """100k-atom periodic box: n captured velocity-Verlet steps (dt 1 fs), neighbours rebuilt every step."""
+    import numpy as np
+    import torch
+    from paper_2402_17660_amd import TensorNet, capture
+    from synth import make_config, maxwell_boltzmann
+    from synth.generators import masses
+    c = make_config(3)
+    N = len(c["pos"])
+    model = TensorNet(_blob_for(c), dev)
+    z = torch.tensor(c["z"], device=dev)
+    batch = torch.tensor(c["batch"], device=dev)
+    m_amu = masses(c["z"])
+    inv_m = torch.tensor((1.0 / m_amu).astype(np.float32), device=dev)
+    out = dict(workload=f"periodic cubic box of 100000 atoms (100 A), hidden 128, 2 layers, cutoff 5 A; "
+                        f"{args.md_steps} velocity-Verlet steps (dt 1 fs) in one HIP graph, neighbour search every "
+                        f"step; Maxwell-Boltzmann velocities at 300 K", n_atoms=N, steps=args.md_steps)
+    for prec in ("fp32", "bf16"):
+        pos = torch.tensor(c["pos"], device=dev)
+        vel = torch.tensor(maxwell_boltzmann(c["z"]), device=dev)
+        E0, F0 = model.energy_forces(pos, z, batch, 1, box=c["box"], max_pairs=32 * N, precision=prec)
+        n0 = int(model.n_pairs.item())
+        mp = int(math.ceil(1.10 * n0 / 1024.0) * 1024)
+        rms_f0 = float(torch.sqrt((F0.double() ** 2).mean()))
+        g, E, Fo, n_pairs, status = capture(model, pos, z, batch, 1, box=c["box"], max_pairs=mp, precision=prec,
+                                            n_steps=args.md_steps, vel=vel, inv_mass=inv_m, dt_fs=1.0,
+                                            forces_out=F0)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        g.replay()
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop)
+        st = int(status.item())
+        out[prec] = dict(ms_per_replay=ms, ms_per_step=ms / args.md_steps,
+                         value=N * args.md_steps / (ms * 1e-3), status=st, initial_pairs=n0, max_pairs=mp,
+                         final_pairs=int(n_pairs.item()), initial_rms_force=rms_f0,
+                         energy_start=float(E0[0]), energy_end=float(E[0]))
+        log(f"md/{prec}: {args.md_steps} steps in {ms:.1f} ms ({ms / args.md_steps:.3f} ms/step, "
+            f"{out[prec]['value']:.3e} atom-steps/s), status {st}, pairs {n0} -> {int(n_pairs.item())}")
+        g.close()
+    return out
+
+
+EXTRA = {"batch": extra_batch, "md": extra_md}
 
 
 if __name__ == "__main__":

@@ -127,6 +127,32 @@ int tn_energy_forces(const tn_model *m, void *stream, int64_t n_atoms, int64_t n
                      int precision, int path, double *energy, void *forces, int64_t *n_pairs, int32_t *status,
                      void *ws, size_t ws_bytes);
 
+/* ------------------------------------------------------- graphs and MD ---
+ * tn_md_capture records work on `stream` into a HIP graph and instantiates
+ * it; nothing runs until tn_graph_replay.  The arguments of tn_energy_forces
+ * plus:
+ *   vel       [n_atoms, 3] float32 velocities (angstrom/fs), updated in place
+ *   inv_mass  [n_atoms] float32 inverse masses (1/amu)
+ *   dt_fs     time step (fs)
+ *   n_steps   0: the graph is one energy+forces evaluation (forces written to
+ *             `forces`); >= 1: n_steps velocity-Verlet steps, each
+ *               v += dt/2 * F/m;  x += dt * v;  x wrapped into [0, L) (box only);
+ *               neighbour search + energy + forces;  v += dt/2 * F/m
+ *             with F/m in eV/(angstrom amu) converted to angstrom/fs^2.  On entry
+ *             `forces` must hold the forces of the current positions (call
+ *             tn_energy_forces once before the first replay); pos is float32.
+ *   status    device word; in MD graphs it accumulates (OR) the status bits of
+ *             every step of a replay, cleared at the start of each replay.
+ * Every buffer must stay allocated, at the same address, while the graph
+ * exists.  Returns TN_OK or an error; *graph_out receives an opaque handle
+ * freed by tn_graph_destroy.  Replays are ordered on the replay stream. */
+int tn_md_capture(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, void *pos, float *vel,
+                  const float *inv_mass, const int32_t *z, const int32_t *batch, const double *box, double dt_fs,
+                  int n_steps, int64_t max_pairs, int precision, int path, double *energy, void *forces,
+                  int64_t *n_pairs, int32_t *status, void *ws, size_t ws_bytes, void **graph_out);
+int tn_graph_replay(void *graph, void *stream);
+int tn_graph_destroy(void *graph);
+
 /* ------------------------------------------------------------ diagnostics ---
  * Kernel timing for measurement tools.  While enabled, the library records a
  * HIP event pair on the launch stream around every launch of a timed kernel

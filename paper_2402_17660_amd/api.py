@@ -185,6 +185,69 @@ class TensorNet:
                          energy_out=energy_out, forces_out=forces_out)
 
 
+class Graph:
+    """An instantiated HIP graph (tn_md_capture); keeps every buffer it uses alive."""
+
+    def __init__(self, handle, device, keep):
+        self._h = handle
+        self.device = device
+        self._keep = keep
+
+    def replay(self):
+        _check(L.lib().tn_graph_replay(self._h, _stream(self.device)), "tn_graph_replay")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().tn_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture(model: "TensorNet", pos, z, batch, n_systems, box=None, max_pairs=None, precision="fp32",
+            path="fused", n_steps=0, vel=None, inv_mass=None, dt_fs=1.0, energy_out=None, forces_out=None):
+    """Record one energy+forces evaluation (n_steps=0) or n_steps velocity-Verlet steps into a graph.
+
+    Returns (graph, energy, forces, n_pairs, status); the tensors are the graph's outputs.
+    """
+    dev = model.device
+    pdt = torch.float64 if precision == "fp64" else torch.float32
+    _require_device(pos, "pos", pdt, dev)
+    _require_device(z, "z", torch.int32, dev)
+    _require_device(batch, "batch", torch.int32, dev)
+    n = pos.shape[0]
+    if max_pairs is None:
+        max_pairs = max(64 * n, 1)
+    boxarr, boxp = _box_arg(box)
+    need = L.lib().tn_workspace_bytes(model._h, n, n_systems, max_pairs, boxp, _PREC[precision], _PATH[path], 1)
+    if need == 0:
+        raise TensorNetError("invalid capture request")
+    ws = torch.empty(int(need) + 4096, dtype=torch.uint8, device=dev)
+    E = energy_out if energy_out is not None else torch.empty(n_systems, dtype=torch.float64, device=dev)
+    Fo = forces_out if forces_out is not None else torch.zeros((n, 3), dtype=pdt, device=dev)
+    n_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    if n_steps > 0:
+        _require_device(vel, "vel", torch.float32, dev)
+        _require_device(inv_mass, "inv_mass", torch.float32, dev)
+    h = ctypes.c_void_p()
+    torch.cuda.synchronize(dev)
+    # capture on a side stream (the legacy default stream cannot be captured)
+    side = torch.cuda.Stream(dev)
+    with torch.cuda.stream(side):
+        rc = L.lib().tn_md_capture(model._h, _stream(dev), n, n_systems, _ptr(pos), _ptr(vel), _ptr(inv_mass),
+                                   _ptr(z), _ptr(batch), boxp, float(dt_fs), int(n_steps), max_pairs,
+                                   _PREC[precision], _PATH[path], _ptr(E), _ptr(Fo), _ptr(n_pairs), _ptr(status),
+                                   _ptr(ws), ws.numel(), ctypes.byref(h))
+    _check(rc, "tn_md_capture")
+    keep = (pos, z, batch, vel, inv_mass, ws, E, Fo, n_pairs, status, side)
+    return Graph(h, dev, keep), E, Fo, n_pairs, status
+
+
 class TensorNetEF(torch.autograd.Function):
     """E = TensorNetEF.apply(model, pos, z, batch, n_systems, box, max_pairs, precision, path).
 

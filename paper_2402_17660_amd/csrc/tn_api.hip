@@ -254,16 +254,16 @@ int tn_model_create(const void *blob, size_t blob_bytes, int device, tn_model **
   }
   const size_t n = packed.size();
   std::vector<float> f32(n);
-  std::vector<__hip_bfloat16> f16(n);
+  std::vector<__bf16> f16(n);
   for (size_t i = 0; i < n; ++i) {
     f32[i] = (float)packed[i];
-    f16[i] = __float2bfloat16((float)packed[i]);
+    f16[i] = (__bf16)f32[i];
   }
   if (hipMalloc(&m->w64, n * sizeof(double)) != hipSuccess || hipMalloc(&m->w32, n * sizeof(float)) != hipSuccess ||
-      hipMalloc(&m->w16, n * sizeof(__hip_bfloat16)) != hipSuccess ||
+      hipMalloc(&m->w16, n * sizeof(__bf16)) != hipSuccess ||
       hipMemcpy(m->w64, packed.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->w32, f32.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(m->w16, f16.data(), n * sizeof(__hip_bfloat16), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(m->w16, f16.data(), n * sizeof(__bf16), hipMemcpyHostToDevice) != hipSuccess) {
     tn_model_destroy(m);
     return TN_E_HIP;
   }

@@ -2,7 +2,8 @@
 // and every layer's edge filter, forward and reverse) runs in two MFMA pair-tile kernels;
 // the node-level steps use the shared node kernels.  Precision plan as in the plain path:
 // FP32 arithmetic, with the geometry/basis, the embedding's node stage and the output
-// network in FP64, the per-system energy sum and the per-atom force sum in FP64.
+// network in FP64, the per-system energy sum and the per-atom force sum in FP64.  The BF16
+// variant feeds the pair kernels' GEMMs BF16 operands (FP32 accumulation).
 #include "tn_nodeops.h"
 
 namespace tn {
@@ -95,7 +96,8 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   w->gpair = p.take<float>(3 * MP);
 }
 
-int run_fused_f32(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, size_t ws_bytes) {
+template <bool BF16>
+int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, size_t ws_bytes) {
   const int64_t N = pb.n, MP = pb.max_pairs, F = m->F, K = m->K, L = m->L;
   WsPlan plan(ws);
   FusedWs w;
@@ -123,38 +125,66 @@ int run_fused_f32(const tn_model *m, hipStream_t s, const Problem &pb, void *ws,
   pos = gr.pos;
 
   // ---- all per-pair work of the forward pass in one MFMA kernel
-  PairFwdArgs pf;
-  pf.pairs = gr.pairs;
-  pf.max_pairs = MP;
-  pf.n_pairs = np;
-  pf.pos = pos;
-  pf.periodic = pb.box.periodic;
-  for (int a = 0; a < 3; ++a) pf.box[a] = pb.box.len[a];
-  pf.r_c = m->r_c;
-  pf.r_lo = m->r_lo;
-  pf.alpha = m->alpha;
-  pf.mu = WA(o.mu);
-  pf.beta = WA(o.beta);
-  pf.W0 = W(o.W0f);
-  pf.b0 = W(o.b0);
-  pf.L = (int)L;
-  for (int64_t l = 0; l < L; ++l) {
-    const LayerOff &lo = o.layer[l];
-    pf.Wa[l] = W(lo.Waf);
-    pf.ba[l] = W(lo.ba);
-    pf.Wb[l] = W(lo.Wbf);
-    pf.bb[l] = W(lo.bb);
-    pf.Wc[l] = W(lo.Wcf);
-    pf.bc[l] = W(lo.bc);
-    pf.z1[l] = w.z1[l];
-    pf.z2[l] = w.z2[l];
-    pf.z3[l] = w.z3[l];
-    pf.h[l] = w.h[l];
+  auto WB = [&](size_t off) { return static_cast<const __bf16 *>(m->w16 + off); };
+  auto fill_common = [&](auto &pf) {
+    pf.pairs = gr.pairs;
+    pf.max_pairs = MP;
+    pf.n_pairs = np;
+    pf.pos = pos;
+    pf.periodic = pb.box.periodic;
+    for (int a = 0; a < 3; ++a) pf.box[a] = pb.box.len[a];
+    pf.r_c = m->r_c;
+    pf.r_lo = m->r_lo;
+    pf.alpha = m->alpha;
+    pf.mu = WA(o.mu);
+    pf.beta = WA(o.beta);
+    pf.L = (int)L;
+  };
+  if (BF16) {
+    PairFwdArgsB pf;
+    fill_common(pf);
+    pf.W0 = WB(o.W0f);
+    pf.b0 = W(o.b0);
+    for (int64_t l = 0; l < L; ++l) {
+      const LayerOff &lo = o.layer[l];
+      pf.Wa[l] = WB(lo.Waf);
+      pf.Wb[l] = WB(lo.Wbf);
+      pf.Wc[l] = WB(lo.Wcf);
+      pf.ba[l] = W(lo.ba);
+      pf.bb[l] = W(lo.bb);
+      pf.bc[l] = W(lo.bc);
+      pf.z1[l] = reinterpret_cast<__bf16 *>(w.z1[l]);
+      pf.z2[l] = reinterpret_cast<__bf16 *>(w.z2[l]);
+      pf.z3[l] = reinterpret_cast<__bf16 *>(w.z3[l]);
+      pf.h[l] = w.h[l];
+    }
+    pf.geo = w.geo;
+    pf.phi = w.phi;
+    pf.f0 = w.f0;
+    if ((rc = launch_pair_fwd_bf16(s, (int)F, (int)K, pf))) return rc;
+  } else {
+    PairFwdArgs pf;
+    fill_common(pf);
+    pf.W0 = W(o.W0f);
+    pf.b0 = W(o.b0);
+    for (int64_t l = 0; l < L; ++l) {
+      const LayerOff &lo = o.layer[l];
+      pf.Wa[l] = W(lo.Waf);
+      pf.ba[l] = W(lo.ba);
+      pf.Wb[l] = W(lo.Wbf);
+      pf.bb[l] = W(lo.bb);
+      pf.Wc[l] = W(lo.Wcf);
+      pf.bc[l] = W(lo.bc);
+      pf.z1[l] = w.z1[l];
+      pf.z2[l] = w.z2[l];
+      pf.z3[l] = w.z3[l];
+      pf.h[l] = w.h[l];
+    }
+    pf.geo = w.geo;
+    pf.phi = w.phi;
+    pf.f0 = w.f0;
+    if ((rc = launch_pair_fwd(s, (int)F, (int)K, pf))) return rc;
   }
-  pf.geo = w.geo;
-  pf.phi = w.phi;
-  pf.f0 = w.f0;
-  if ((rc = launch_pair_fwd(s, (int)F, (int)K, pf))) return rc;
 
   // ---- embedding node stage (FP64)
   const unsigned gNF = grid_for(N * F, bs);
@@ -307,35 +337,45 @@ int run_fused_f32(const tn_model *m, hipStream_t s, const Problem &pb, void *ws,
     TN_LAUNCH_CHECK();
   }
   // ---- all per-pair work of the reverse sweep in one MFMA kernel
-  PairBwdArgs pbw;
-  pbw.pairs = gr.pairs;
-  pbw.max_pairs = MP;
-  pbw.n_pairs = np;
-  pbw.pos = pos;
-  pbw.periodic = pb.box.periodic;
-  for (int a = 0; a < 3; ++a) pbw.box[a] = pb.box.len[a];
-  pbw.r_c = m->r_c;
-  pbw.r_lo = m->r_lo;
-  pbw.alpha = m->alpha;
-  pbw.mu = WA(o.mu);
-  pbw.beta = WA(o.beta);
-  pbw.W0T = W(o.W0T);
-  pbw.L = (int)L;
-  for (int64_t l = 0; l < L; ++l) {
-    const LayerOff &lo = o.layer[l];
-    pbw.WaT[l] = W(lo.WaT);
-    pbw.WbT[l] = W(lo.WbT);
-    pbw.WcT[l] = W(lo.WcT);
-    pbw.z1[l] = w.z1[l];
-    pbw.z2[l] = w.z2[l];
-    pbw.z3[l] = w.z3[l];
-    pbw.dh[l] = w.dh[l];
+  if (BF16) {
+    PairBwdArgsB pbw;
+    fill_common(pbw);
+    pbw.W0T = WB(o.W0T);
+    for (int64_t l = 0; l < L; ++l) {
+      const LayerOff &lo = o.layer[l];
+      pbw.WaT[l] = WB(lo.WaT);
+      pbw.WbT[l] = WB(lo.WbT);
+      pbw.WcT[l] = WB(lo.WcT);
+      pbw.z1[l] = reinterpret_cast<const __bf16 *>(w.z1[l]);
+      pbw.z2[l] = reinterpret_cast<const __bf16 *>(w.z2[l]);
+      pbw.z3[l] = reinterpret_cast<const __bf16 *>(w.z3[l]);
+      pbw.dh[l] = w.dh[l];
+    }
+    pbw.df0 = w.df0;
+    pbw.dphi0 = w.dphi;
+    pbw.dvhat = w.dvhat;
+    pbw.gpair = w.gpair;
+    if ((rc = launch_pair_bwd_bf16(s, (int)F, (int)K, pbw))) return rc;
+  } else {
+    PairBwdArgs pbw;
+    fill_common(pbw);
+    pbw.W0T = W(o.W0T);
+    for (int64_t l = 0; l < L; ++l) {
+      const LayerOff &lo = o.layer[l];
+      pbw.WaT[l] = W(lo.WaT);
+      pbw.WbT[l] = W(lo.WbT);
+      pbw.WcT[l] = W(lo.WcT);
+      pbw.z1[l] = w.z1[l];
+      pbw.z2[l] = w.z2[l];
+      pbw.z3[l] = w.z3[l];
+      pbw.dh[l] = w.dh[l];
+    }
+    pbw.df0 = w.df0;
+    pbw.dphi0 = w.dphi;
+    pbw.dvhat = w.dvhat;
+    pbw.gpair = w.gpair;
+    if ((rc = launch_pair_bwd(s, (int)F, (int)K, pbw))) return rc;
   }
-  pbw.df0 = w.df0;
-  pbw.dphi0 = w.dphi;
-  pbw.dvhat = w.dvhat;
-  pbw.gpair = w.gpair;
-  if ((rc = launch_pair_bwd(s, (int)F, (int)K, pbw))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL((k_force_gather<float, float>), dim3(grid_for(N, bs)), dim3(bs), 0, s, N, rowptr, nbr, pid,
                        np, MP, w.gpair, gr.perm, static_cast<float *>(pb.forces));
@@ -349,7 +389,7 @@ int run_fused_f32(const tn_model *m, hipStream_t s, const Problem &pb, void *ws,
 size_t fused_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t max_pairs, const BoxInfo &bi, int prec,
                              int want_forces) {
   (void)S;
-  if (prec != TN_FP32 || !pair_kernels_support(m->F, m->K, m->L)) return 0;
+  if ((prec != TN_FP32 && prec != TN_BF16) || !pair_kernels_support(m->F, m->K, m->L, prec == TN_BF16)) return 0;
   WsPlan p(nullptr);
   FusedWs w;
   plan_fused(p, m, n, max_pairs, bi, want_forces != 0, &w);
@@ -357,8 +397,9 @@ size_t fused_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t ma
 }
 
 int fused_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, void *ws, size_t ws_bytes) {
-  if (!pair_kernels_support(m->F, m->K, m->L)) return TN_E_UNSUPPORTED;
-  if (prec == TN_FP32) return run_fused_f32(m, s, pb, ws, ws_bytes);
+  if (!pair_kernels_support(m->F, m->K, m->L, prec == TN_BF16)) return TN_E_UNSUPPORTED;
+  if (prec == TN_FP32) return run_fused<false>(m, s, pb, ws, ws_bytes);
+  if (prec == TN_BF16) return run_fused<true>(m, s, pb, ws, ws_bytes);
   return TN_E_UNSUPPORTED;
 }
 

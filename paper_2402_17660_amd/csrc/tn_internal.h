@@ -53,7 +53,7 @@ struct tn_model {
   tn::WeightOff off;
   double *w64 = nullptr;           // packed FP64 weights (device)
   float *w32 = nullptr;            // packed FP32 weights (device)
-  __hip_bfloat16 *w16 = nullptr;   // packed BF16 weights (device)
+  __bf16 *w16 = nullptr;           // packed BF16 weights (device)
 };
 
 namespace tn {
@@ -150,7 +150,7 @@ int fused_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, voi
 constexpr int kMaxLayers = 16;
 
 // Whether the fused pair kernels support these sizes.
-bool pair_kernels_support(int F, int K, int L);
+bool pair_kernels_support(int F, int K, int L, bool bf16);
 
 struct PairFwdArgs {
   const int32_t *pairs = nullptr;   // [2, max_pairs]
@@ -187,6 +187,48 @@ struct PairBwdArgs {
 
 int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a);
 int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a);
+
+// BF16-operand variants: weights and stored pre-activations in BF16, biases, basis
+// constants, h and every other stored quantity in FP32/FP64 as above.
+struct PairFwdArgsB {
+  const int32_t *pairs = nullptr;
+  int64_t max_pairs = 0;
+  const int64_t *n_pairs = nullptr;
+  const float *pos = nullptr;
+  int periodic = 0;
+  double box[3] = {0, 0, 0};
+  double r_c = 0, r_lo = 0, alpha = 0;
+  const double *mu = nullptr, *beta = nullptr;
+  const __bf16 *W0 = nullptr;
+  const float *b0 = nullptr;
+  const __bf16 *Wa[kMaxLayers], *Wb[kMaxLayers], *Wc[kMaxLayers];
+  const float *ba[kMaxLayers], *bb[kMaxLayers], *bc[kMaxLayers];
+  int L = 0;
+  float *geo = nullptr, *phi = nullptr, *f0 = nullptr;
+  __bf16 *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers];
+  float *h[kMaxLayers];
+};
+
+struct PairBwdArgsB {
+  const int32_t *pairs = nullptr;
+  int64_t max_pairs = 0;
+  const int64_t *n_pairs = nullptr;
+  const float *pos = nullptr;
+  int periodic = 0;
+  double box[3] = {0, 0, 0};
+  double r_c = 0, r_lo = 0, alpha = 0;
+  const double *mu = nullptr, *beta = nullptr;
+  const __bf16 *W0T = nullptr;
+  const __bf16 *WaT[kMaxLayers], *WbT[kMaxLayers], *WcT[kMaxLayers];
+  int L = 0;
+  const __bf16 *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers];
+  const float *dh[kMaxLayers];
+  const float *df0 = nullptr, *dphi0 = nullptr, *dvhat = nullptr;
+  float *gpair = nullptr;
+};
+
+int launch_pair_fwd_bf16(hipStream_t s, int F, int K, const PairFwdArgsB &a);
+int launch_pair_bwd_bf16(hipStream_t s, int F, int K, const PairBwdArgsB &a);
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 

@@ -104,11 +104,97 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
   }
 }
 
+// The same product on matrix cores: 64x64 block tiles, each of the four waves computes a
+// 32x32 quarter as 2x2 MFMA 16x16x4 tiles (f32 or f64); A and B chunks of 16 along K are
+// staged through LDS.  Lane l of an MFMA holds D[4(l/16)+t][l%16].
+typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
+typedef double mf_f64x4 __attribute__((ext_vector_type(4)));
+template <class T> struct MfmaVec;
+template <> struct MfmaVec<float> { using type = mf_f32x4; };
+template <> struct MfmaVec<double> { using type = mf_f64x4; };
+__device__ __forceinline__ mf_f32x4 mfma_16x16x4(float a, float b, mf_f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mf_f64x4 mfma_16x16x4(double a, double b, mf_f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
+  using V = typename MfmaVec<T>::type;
+  __shared__ T As[GBM][GBK + 1];
+  __shared__ T Bs[GBN][GBK + 1];
+  int64_t Mrows = g.M;
+  if (g.Mdev) {
+    const int64_t md = *g.Mdev;
+    if (md < Mrows) Mrows = md;
+  }
+  const int64_t m0 = (int64_t)blockIdx.y * GBM;
+  const int64_t n0 = (int64_t)blockIdx.x * GBN;
+  if (m0 >= Mrows) return;
+  const int z = blockIdx.z;
+  const T *A = g.A + z * g.zoff;
+  const T *B = g.zpart ? g.Bz[coord_part(z)] : g.B;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int r16 = lane & 15, q = lane >> 4;
+  V acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = V{T(0), T(0), T(0), T(0)};
+  for (int64_t k0 = 0; k0 < g.K; k0 += GBK) {
+    for (int t = tid; t < GBM * GBK; t += 256) {
+      const int mm_ = t / GBK, kk = t % GBK;
+      const int64_t m = m0 + mm_, k = k0 + kk;
+      As[mm_][kk] = (m < Mrows && k < g.K) ? A[m * g.lda + k] : T(0);
+    }
+    for (int t = tid; t < GBK * GBN; t += 256) {
+      int kk, nn;
+      if (g.transB) { nn = t / GBK; kk = t % GBK; } else { kk = t / GBN; nn = t % GBN; }
+      const int64_t n = n0 + nn, k = k0 + kk;
+      T v = T(0);
+      if (n < g.N && k < g.K) v = g.transB ? B[n * g.ldb + k] : B[k * g.ldb + n];
+      Bs[nn][kk] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < GBK; s4 += 4) {
+      const T a0 = As[wr + r16][s4 + q], a1 = As[wr + 16 + r16][s4 + q];
+      const T b0 = Bs[wc + r16][s4 + q], b1 = Bs[wc + 16 + r16][s4 + q];
+      acc[0][0] = mfma_16x16x4(a0, b0, acc[0][0]);
+      acc[0][1] = mfma_16x16x4(a0, b1, acc[0][1]);
+      acc[1][0] = mfma_16x16x4(a1, b0, acc[1][0]);
+      acc[1][1] = mfma_16x16x4(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  T *C = g.C + z * g.zoff;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t m = m0 + wr + rb * 16 + 4 * q + t;
+        const int64_t n = n0 + wc + cb * 16 + r16;
+        if (m >= Mrows || n >= g.N) continue;
+        T v = acc[rb][cb][t];
+        if (g.bias) v += g.bias[n];
+        if (g.Z) g.Z[z * g.zoff + m * g.ldz + n] = v;
+        if (g.act == 1) v = silu(v);
+        if (g.rowscale) v *= g.rowscale[m];
+        if (g.gate) v *= silu_grad(g.gate[z * g.zoff + m * g.ldg + n]);
+        T *dst = C + m * g.ldc + n;
+        if (g.accumulate) *dst += v; else *dst = v;
+      }
+}
+
 template <class T>
 inline int gemm(hipStream_t s, const GemmArgs<T> &g, int zdim = 1) {
   if (g.M <= 0 || g.N <= 0) return TN_OK;
   dim3 grid((unsigned)((g.N + GBN - 1) / GBN), (unsigned)((g.M + GBM - 1) / GBM), (unsigned)zdim);
-  hipLaunchKernelGGL(k_gemm<T>, grid, dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_gemm_mfma<T>, grid, dim3(256), 0, s, g);
   TN_LAUNCH_CHECK();
   return TN_OK;
 }

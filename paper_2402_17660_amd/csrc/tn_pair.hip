@@ -22,8 +22,9 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kTile = 32;   // pairs per tile
 constexpr int kPad = 4;     // LDS row padding (floats)
 
-bool pair_kernels_support(int F, int K, int L) {
-  return (F == 64 || F == 128) && (K == 16 || K == 32 || K == 48 || K == 64) && L >= 0 && L <= kMaxLayers;
+bool pair_kernels_support(int F, int K, int L, bool bf16) {
+  const bool k_ok = bf16 ? (K == 32 || K == 64) : (K == 16 || K == 32 || K == 48 || K == 64);
+  return (F == 64 || F == 128) && k_ok && L >= 0 && L <= kMaxLayers;
 }
 
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
@@ -322,6 +323,262 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd(PairBwdArgs a) {
   }
 }
 
+// ============================================================================ BF16 variant
+// GEMM operands (basis, activations, adjoints and weights) in BF16, FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..8(l/16)+7] and
+// B[8(l/16)..+7][l%16]).  64-pair tiles (four 16-row blocks) so every weight fragment read
+// from L2 feeds four MFMAs.  Pre-activations are stored in BF16, the filter h in FP32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kTileB = 64;
+constexpr int kPadB = 8;   // LDS row padding (bf16 elements)
+
+__device__ __forceinline__ floatx4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int NB>
+__device__ __forceinline__ void zero_acc4(floatx4 (&acc)[4][NB]) {
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
+// acc[rb][cb] += act[64 x Kin] (LDS bf16, row stride ld) * Bt^T (Bt [ncol][Kin] bf16 in global memory).
+template <int NB>
+__device__ __forceinline__ void wave_mm_bf16(const __bf16 *act, int ld, int Kin, const __bf16 *__restrict__ Bt,
+                                             int col0, floatx4 (&acc)[4][NB]) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  const __bf16 *ap = act + r * ld + 8 * q;
+  const __bf16 *bp = Bt + (size_t)(col0 + r) * Kin + 8 * q;
+  const size_t bstride = (size_t)16 * Kin;
+  const int astride = 16 * ld;
+#pragma unroll 2
+  for (int k0 = 0; k0 < Kin; k0 += 32) {
+    bf16x8 b[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) b[cb] = *reinterpret_cast<const bf16x8 *>(bp + cb * bstride + k0);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(ap + rb * astride + k0);
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = mfma_bf16(a, b[cb], acc[rb][cb]);
+    }
+  }
+}
+
+template <int NB, class Fn>
+__device__ __forceinline__ void for_acc4(const floatx4 (&acc)[4][NB], int col0, Fn &&f) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) f(rb * 16 + 4 * (lane >> 4) + t, col0 + cb * 16 + (lane & 15), acc[rb][cb][t]);
+}
+
+template <int F, int K>
+__global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
+  constexpr int LE = K + kPadB, L1 = F + kPadB, L2 = 2 * F + kPadB;
+  __shared__ __attribute__((aligned(16))) __bf16 sE[kTileB * LE];
+  __shared__ __attribute__((aligned(16))) __bf16 sA1[kTileB * L1];
+  __shared__ __attribute__((aligned(16))) __bf16 sA2[kTileB * L2];
+  __shared__ double sD[kTileB], sPhi[kTileB];
+  const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
+  const int64_t p0 = (int64_t)blockIdx.x * kTileB;
+  if (p0 >= P) return;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int nvalid = (int)((P - p0) < kTileB ? (P - p0) : kTileB);
+  if (tid < kTileB) {
+    double d = a.r_c, ph = 0.0;
+    if (tid < nvalid) {
+      const int64_t p = p0 + tid;
+      const PairGeo g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.periodic, a.box, a.r_c);
+      d = g.d;
+      ph = g.phi;
+      a.geo[4 * p + 0] = (float)g.u[0];
+      a.geo[4 * p + 1] = (float)g.u[1];
+      a.geo[4 * p + 2] = (float)g.u[2];
+      a.geo[4 * p + 3] = (float)g.d;
+      a.phi[p] = (float)g.phi;
+    }
+    sD[tid] = d;
+    sPhi[tid] = ph;
+  }
+  __syncthreads();
+  for (int t = tid; t < kTileB * K; t += 256) {
+    const int row = t / K, k = t % K;
+    const double u = exp(-a.alpha * (sD[row] - a.r_lo));
+    const double x = u - a.mu[k];
+    sE[row * LE + k] = (__bf16)(float)(sPhi[row] * exp(-a.beta[k] * x * x));
+  }
+  __syncthreads();
+  {
+    constexpr int NB = 3 * F / 64;
+    floatx4 acc[4][NB];
+    zero_acc4(acc);
+    const int col0 = wave * (3 * F / 4);
+    wave_mm_bf16<NB>(sE, LE, K, a.W0, col0, acc);
+    for_acc4(acc, col0, [&](int row, int col, float v) {
+      if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = v + a.b0[col];
+    });
+  }
+  for (int l = 0; l < a.L; ++l) {
+    {
+      constexpr int NB = F / 64;
+      floatx4 acc[4][NB];
+      zero_acc4(acc);
+      const int col0 = wave * (F / 4);
+      wave_mm_bf16<NB>(sE, LE, K, a.Wa[l], col0, acc);
+      __bf16 *z1 = a.z1[l];
+      const float *bias = a.ba[l];
+      for_acc4(acc, col0, [&](int row, int col, float v) {
+        const float z = v + bias[col];
+        if (row < nvalid) z1[(p0 + row) * F + col] = (__bf16)z;
+        sA1[row * L1 + col] = (__bf16)silu(z);
+      });
+    }
+    __syncthreads();
+    {
+      constexpr int NB = F / 32;
+      floatx4 acc[4][NB];
+      zero_acc4(acc);
+      const int col0 = wave * (F / 2);
+      wave_mm_bf16<NB>(sA1, L1, F, a.Wb[l], col0, acc);
+      __bf16 *z2 = a.z2[l];
+      const float *bias = a.bb[l];
+      for_acc4(acc, col0, [&](int row, int col, float v) {
+        const float z = v + bias[col];
+        if (row < nvalid) z2[(p0 + row) * 2 * F + col] = (__bf16)z;
+        sA2[row * L2 + col] = (__bf16)silu(z);
+      });
+    }
+    __syncthreads();
+    {
+      constexpr int NB = 3 * F / 64;
+      floatx4 acc[4][NB];
+      zero_acc4(acc);
+      const int col0 = wave * (3 * F / 4);
+      wave_mm_bf16<NB>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
+      __bf16 *z3 = a.z3[l];
+      float *h = a.h[l];
+      const float *bias = a.bc[l];
+      for_acc4(acc, col0, [&](int row, int col, float v) {
+        const float z = v + bias[col];
+        if (row < nvalid) {
+          z3[(p0 + row) * 3 * F + col] = (__bf16)z;
+          h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * silu(z);
+        }
+      });
+    }
+  }
+}
+
+template <int F, int K>
+__global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
+  constexpr int L3 = 3 * F + kPadB, L2 = 2 * F + kPadB, L1 = F + kPadB, LE = K + 4;
+  __shared__ __attribute__((aligned(16))) __bf16 sG3[kTileB * L3];   // dz3, then dz1 / df0
+  __shared__ __attribute__((aligned(16))) __bf16 sG2[kTileB * L2];   // dz2
+  __shared__ __attribute__((aligned(16))) float sDE[kTileB * LE];
+  __shared__ float sPhi[kTileB];
+  __shared__ float sDphi[kTileB];
+  const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
+  const int64_t p0 = (int64_t)blockIdx.x * kTileB;
+  if (p0 >= P) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nvalid = (int)((P - p0) < kTileB ? (P - p0) : kTileB);
+  constexpr int NWDE = K / 16;
+  PairGeo g{};
+  if (tid < kTileB) {
+    float ph = 0.f, dp = 0.f;
+    if (tid < nvalid) {
+      const int64_t p = p0 + tid;
+      g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.periodic, a.box, a.r_c);
+      ph = (float)g.phi;
+      dp = a.dphi0[p];
+    }
+    sPhi[tid] = ph;
+    sDphi[tid] = dp;
+  }
+  for (int t = tid; t < kTileB * 3 * F; t += 256) {
+    const int row = t / (3 * F), c = t % (3 * F);
+    sG3[row * L3 + c] = (__bf16)(row < nvalid ? a.df0[(p0 + row) * 3 * F + c] : 0.f);
+  }
+  __syncthreads();
+  floatx4 de[4][1];
+  zero_acc4(de);
+  if (wave < NWDE) wave_mm_bf16<1>(sG3, L3, 3 * F, a.W0T, wave * 16, de);
+  __syncthreads();
+  for (int l = 0; l < a.L; ++l) {
+    const __bf16 *z1 = a.z1[l], *z2 = a.z2[l], *z3 = a.z3[l];
+    const float *dh = a.dh[l];
+    for (int rr = 0; rr < kTileB / 4; ++rr) {
+      const int row = wave * (kTileB / 4) + rr;
+      float part = 0.f;
+      for (int c = lane; c < 3 * F; c += 64) {
+        float v = 0.f;
+        if (row < nvalid) {
+          const int64_t o = (p0 + row) * 3 * F + c;
+          const float z = (float)z3[o], gh = dh[o];
+          v = gh * sPhi[row] * silu_grad(z);
+          part += gh * silu(z);
+        }
+        sG3[row * L3 + c] = (__bf16)v;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+      if (lane == 0) sDphi[row] += part;
+    }
+    __syncthreads();
+    {
+      constexpr int NB = F / 32;
+      floatx4 acc[4][NB];
+      zero_acc4(acc);
+      const int col0 = wave * (F / 2);
+      wave_mm_bf16<NB>(sG3, L3, 3 * F, a.WcT[l], col0, acc);
+      for_acc4(acc, col0, [&](int row, int col, float v) {
+        sG2[row * L2 + col] = (__bf16)(row < nvalid ? v * silu_grad((float)z2[(p0 + row) * 2 * F + col]) : 0.f);
+      });
+    }
+    __syncthreads();
+    {
+      constexpr int NB = F / 64;
+      floatx4 acc[4][NB];
+      zero_acc4(acc);
+      const int col0 = wave * (F / 4);
+      wave_mm_bf16<NB>(sG2, L2, 2 * F, a.WbT[l], col0, acc);
+      for_acc4(acc, col0, [&](int row, int col, float v) {
+        sG3[row * L1 + col] = (__bf16)(row < nvalid ? v * silu_grad((float)z1[(p0 + row) * F + col]) : 0.f);
+      });
+    }
+    __syncthreads();
+    if (wave < NWDE) wave_mm_bf16<1>(sG3, L1, F, a.WaT[l], wave * 16, de);
+    __syncthreads();
+  }
+  if (wave < NWDE)
+    for_acc4(de, wave * 16, [&](int row, int col, float v) { sDE[row * LE + col] = v; });
+  __syncthreads();
+  if (tid < nvalid) {
+    const int64_t p = p0 + tid;
+    const double u = exp(-a.alpha * (g.d - a.r_lo));
+    double dd = (double)sDphi[tid] * g.dphi;
+    for (int k = 0; k < K; ++k) {
+      const double x = u - a.mu[k];
+      const double gk = exp(-a.beta[k] * x * x);
+      const double dek = g.dphi * gk + g.phi * gk * 2.0 * a.alpha * a.beta[k] * u * x;
+      dd += (double)sDE[tid * LE + k] * dek;
+    }
+    const double gx = a.dvhat[3 * p], gy = a.dvhat[3 * p + 1], gz = a.dvhat[3 * p + 2];
+    const double proj = gx * g.u[0] + gy * g.u[1] + gz * g.u[2];
+    const double inv = 1.0 / g.d;
+    a.gpair[3 * p + 0] = (float)(dd * g.u[0] + (gx - proj * g.u[0]) * inv);
+    a.gpair[3 * p + 1] = (float)(dd * g.u[1] + (gy - proj * g.u[1]) * inv);
+    a.gpair[3 * p + 2] = (float)(dd * g.u[2] + (gz - proj * g.u[2]) * inv);
+  }
+}
+
 // ============================================================================ launchers
 template <int F, int K>
 static int launch_fwd(hipStream_t s, const PairFwdArgs &a) {
@@ -356,7 +613,29 @@ static int launch_bwd(hipStream_t s, const PairBwdArgs &a) {
     default: return TN_E_UNSUPPORTED;                                \
   }
 
+template <int F, int K>
+static int launch_fwd_bf16(hipStream_t s, const PairFwdArgsB &a) {
+  const unsigned grid = (unsigned)((a.max_pairs + kTileB - 1) / kTileB);
+  if (grid == 0) return TN_OK;
+  TimedScope ts("edge_fwd", s);
+  hipLaunchKernelGGL((k_pair_fwd_bf16<F, K>), dim3(grid), dim3(256), 0, s, a);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+template <int F, int K>
+static int launch_bwd_bf16(hipStream_t s, const PairBwdArgsB &a) {
+  const unsigned grid = (unsigned)((a.max_pairs + kTileB - 1) / kTileB);
+  if (grid == 0) return TN_OK;
+  TimedScope ts("edge_bwd", s);
+  hipLaunchKernelGGL((k_pair_bwd_bf16<F, K>), dim3(grid), dim3(256), 0, s, a);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
 int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a) { TN_PAIR_DISPATCH(launch_fwd, a) }
 int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a) { TN_PAIR_DISPATCH(launch_bwd, a) }
+int launch_pair_fwd_bf16(hipStream_t s, int F, int K, const PairFwdArgsB &a) { TN_PAIR_DISPATCH(launch_fwd_bf16, a) }
+int launch_pair_bwd_bf16(hipStream_t s, int F, int K, const PairBwdArgsB &a) { TN_PAIR_DISPATCH(launch_bwd_bf16, a) }
 
 }  // namespace tn

@@ -29,6 +29,7 @@ def cfg_blob(c):
 
 
 def gpu_ef(dev, model, pos, z, batch, box, S, precision, path, max_pairs=None, forces=True):
+    """Energies and forces from the library; float64 numpy arrays."""
     pdt = torch.float64 if precision == "fp64" else torch.float32
     p = torch.tensor(np.asarray(pos), dtype=pdt, device=dev)
     zt = torch.tensor(np.asarray(z), dtype=torch.int32, device=dev)
@@ -59,7 +60,8 @@ def cfg0():
     return c, blob, E, F
 
 
-@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp32", "plain"), ("fp32", "fused")])
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp32", "plain"), ("fp32", "fused"),
+                                            ("bf16", "fused")])
 def test_molecule48(dev, cfg0, precision, path):
     c, blob, E_ref, F_ref = cfg0
     m = TensorNet(blob, dev)
@@ -68,7 +70,8 @@ def test_molecule48(dev, cfg0, precision, path):
 
 
 @pytest.mark.parametrize("precision,path,F,K", [("fp64", "plain", 16, 8), ("fp32", "plain", 16, 8),
-                                                ("fp32", "fused", 64, 16), ("fp32", "fused", 128, 48)])
+                                                ("fp32", "fused", 64, 16), ("fp32", "fused", 128, 48),
+                                                ("bf16", "fused", 128, 32), ("bf16", "fused", 64, 64)])
 def test_small_periodic_box(dev, precision, path, F, K):
     pos, z, box = random_box(100, 12, 10.0)
     blob = small_blob(F=F, K=K, L=2, seed=13)
@@ -98,15 +101,16 @@ def test_batch_of_molecules_fp64(dev):
     assert_close(E, F, E_ref, F_ref, "fp64", "batch4")
 
 
-@pytest.mark.parametrize("cfg,path", [(1, "plain"), (2, "plain"), (1, "fused"), (2, "fused")])
-def test_workloads_fp32(dev, cfg, path):
+@pytest.mark.parametrize("cfg,path,precision", [(1, "plain", "fp32"), (2, "plain", "fp32"), (1, "fused", "fp32"),
+                                               (2, "fused", "fp32"), (1, "fused", "bf16"), (2, "fused", "bf16")])
+def test_workloads(dev, cfg, path, precision):
     c = make_config(cfg)
     g = np.load(os.path.join(GOLDEN, f"oracle_cfg{cfg}.npz"))
     m = TensorNet(cfg_blob(c), dev)
-    E, F = gpu_ef(dev, m, c["pos"], c["z"], c["batch"], c["box"], c["n_systems"], "fp32", path,
+    E, F = gpu_ef(dev, m, c["pos"], c["z"], c["batch"], c["box"], c["n_systems"], precision, path,
                   max_pairs=int(g["n_pairs"]) + 4096)
     assert int(m.n_pairs.item()) == int(g["n_pairs"])
-    assert_close(E, F, g["E"], g["F"], "fp32", f"cfg{cfg} fp32 {path}")
+    assert_close(E, F, g["E"], g["F"], precision, f"cfg{cfg} {precision} {path}")
 
 
 @pytest.mark.parametrize("L_layers", [0, 1, 3])
