@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--variants", default="fused:fp32,fused:bf16,plain:fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-atoms", type=int, default=1000)
+    ap.add_argument("--cpu-atoms", type=int, default=3000)
     ap.add_argument("--budget", type=float, default=1.05, help="max_pairs = budget * true pair count")
     ap.add_argument("--extra", default="batch,md", help="extra workloads: batch (512 molecules, captured), "
                                                         "md (100 captured velocity-Verlet steps, 100k atoms); '' = none")

@@ -16,11 +16,11 @@ struct FusedWs {
   NbrWs nb;
   float *geo, *phi, *f0, *Xr;
   TA *XrA, *T0, *nrm0, *xhat0, *rstd0, *n0, *ez1, *ea1, *ez2, *g, *X0A;
-  std::vector<float *> X, nX, Xb, Y, z1, z2, z3, h, M, P, nP, Pb, D, dh;
+  std::vector<float *> X, nX, Xb, Y, z1, z2, z3, h, M, P, nP, Pb, D, dM;
   TA *XLA, *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps, *eps_orig;
-  float *dX = nullptr, *dD, *dPb, *dY, *dM, *dXr;
+  float *dX = nullptr, *dD, *dPb, *dY, *dXr;
   TA *dXA, *dT0, *dXrA, *dg, *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
-  float *df0, *dphi, *dvhat, *gpair;
+  float *gpair;
 };
 
 void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxInfo &bi, bool fw, FusedWs *w) {
@@ -71,12 +71,11 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   w->eps = p.take<TA>(N);
   w->eps_orig = p.take<TA>(N);
   if (!fw) return;
-  per_layer(w->dh, MP * 3 * F);
+  per_layer(w->dM, N * 9 * F);
   w->dX = p.take<float>(N * 9 * F);
   w->dD = p.take<float>(N * 9 * F);
   w->dPb = p.take<float>(N * 9 * F);
   w->dY = p.take<float>(N * 9 * F);
-  w->dM = p.take<float>(N * 9 * F);
   w->dXr = p.take<float>(N * 9 * F);
   w->dXA = p.take<TA>(N * 9 * F);
   w->dT0 = p.take<TA>(N * 9 * F);
@@ -90,9 +89,6 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   w->dox = p.take<TA>(N * F);
   w->dq = p.take<TA>(N * 3 * F);
   w->don = p.take<TA>(N * 3 * F);
-  w->df0 = p.take<float>(MP * 3 * F);
-  w->dphi = p.take<float>(MP);
-  w->dvhat = p.take<float>(3 * MP);
   w->gpair = p.take<float>(3 * MP);
 }
 
@@ -210,27 +206,29 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     TN_LAUNCH_CHECK();
   }
   if ((rc = convert<TA, float>(s, w.X0A, w.X[0], N * 9 * F))) return rc;
-  // ---- interaction layers
+  // ---- interaction layers: normalise (first layer), mix, message+product, mix, residual(+normalise)
+  if (N > 0 && L > 0) {
+    hipLaunchKernelGGL(k_normalize<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[0], w.nX[0], w.Xb[0]);
+    TN_LAUNCH_CHECK();
+  }
   for (int64_t l = 0; l < L; ++l) {
     const LayerOff &lo = o.layer[l];
-    if (N > 0) {
-      hipLaunchKernelGGL(k_normalize<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[l], w.nX[l], w.Xb[l]);
-      TN_LAUNCH_CHECK();
-    }
     const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
     if ((rc = mix<float>(s, w.Xb[l], w.Y[l], N, F, W1, 0, 0))) return rc;
     if (N > 0) {
-      hipLaunchKernelGGL(k_message<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, w.h[l],
-                         w.Y[l], w.M[l], 0);
-      TN_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_product<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Y[l], w.M[l], w.P[l], w.nP[l],
-                         w.Pb[l]);
+      hipLaunchKernelGGL(k_message_product<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP,
+                         w.h[l], w.Y[l], w.M[l], w.P[l], w.nP[l], w.Pb[l]);
       TN_LAUNCH_CHECK();
     }
     const float *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
     if ((rc = mix<float>(s, w.Pb[l], w.D[l], N, F, W2, 0, 0))) return rc;
     if (N > 0) {
-      hipLaunchKernelGGL(k_residual<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xb[l], w.D[l], w.X[l + 1]);
+      if (l + 1 < L) {
+        hipLaunchKernelGGL(k_residual_normalize<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xb[l], w.D[l],
+                           w.X[l + 1], w.nX[l + 1], w.Xb[l + 1]);
+      } else {
+        hipLaunchKernelGGL(k_residual<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xb[l], w.D[l], w.X[l + 1]);
+      }
       TN_LAUNCH_CHECK();
     }
   }
@@ -280,7 +278,6 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     TN_LAUNCH_CHECK();
   }
   if ((rc = convert<TA, float>(s, w.dXA, w.dX, N * 9 * F))) return rc;
-  if (MP > 0 && (rc = fill_bytes_zero(s, w.dphi, MP * sizeof(float)))) return rc;
   for (int64_t l = L - 1; l >= 0; --l) {
     const LayerOff &lo = o.layer[l];
     const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
@@ -292,15 +289,10 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     if ((rc = mix<float>(s, w.dD, w.dPb, N, F, W2, 1, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_product_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dPb, w.P[l], w.nP[l], w.Y[l],
-                         w.M[l], w.dY, w.dM);
+                         w.M[l], w.dY, w.dM[l]);
       TN_LAUNCH_CHECK();
       hipLaunchKernelGGL(k_message<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, w.h[l],
-                         w.dM, w.dY, 1);
-      TN_LAUNCH_CHECK();
-    }
-    if (MP > 0) {
-      hipLaunchKernelGGL(k_message_bwd_pair<float>, dim3(grid_for(MP * F, bs)), dim3(bs), 0, s, gr.pairs, MP, np,
-                         (int)F, w.Y[l], w.dM, w.dh[l]);
+                         w.dM[l], w.dY, 1);
       TN_LAUNCH_CHECK();
     }
     if ((rc = mix<float>(s, w.dY, w.dX, N, F, W1, 1, 1))) return rc;
@@ -331,16 +323,17 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     TN_LAUNCH_CHECK();
   }
   if ((rc = convert<TA, float>(s, w.dXrA, w.dXr, N * 9 * F))) return rc;
-  if (MP > 0) {
-    hipLaunchKernelGGL(k_embed_bwd_pair<float>, dim3((unsigned)MP), dim3(128), 0, s, gr.pairs, MP, np, (int)F, zz,
-                       m->max_z, W(o.U), W(o.V), w.geo, w.phi, w.f0, w.dXr, w.df0, w.dphi, w.dvhat);
-    TN_LAUNCH_CHECK();
-  }
   // ---- all per-pair work of the reverse sweep in one MFMA kernel
   if (BF16) {
     PairBwdArgsB pbw;
     fill_common(pbw);
     pbw.W0T = WB(o.W0T);
+    pbw.g.z = zz;
+    pbw.g.U = W(o.U);
+    pbw.g.V = W(o.V);
+    pbw.g.max_z = m->max_z;
+    pbw.g.f0 = w.f0;
+    pbw.g.dXr = w.dXr;
     for (int64_t l = 0; l < L; ++l) {
       const LayerOff &lo = o.layer[l];
       pbw.WaT[l] = WB(lo.WaT);
@@ -349,17 +342,21 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
       pbw.z1[l] = reinterpret_cast<const __bf16 *>(w.z1[l]);
       pbw.z2[l] = reinterpret_cast<const __bf16 *>(w.z2[l]);
       pbw.z3[l] = reinterpret_cast<const __bf16 *>(w.z3[l]);
-      pbw.dh[l] = w.dh[l];
+      pbw.g.Y[l] = w.Y[l];
+      pbw.g.dM[l] = w.dM[l];
     }
-    pbw.df0 = w.df0;
-    pbw.dphi0 = w.dphi;
-    pbw.dvhat = w.dvhat;
     pbw.gpair = w.gpair;
     if ((rc = launch_pair_bwd_bf16(s, (int)F, (int)K, pbw))) return rc;
   } else {
     PairBwdArgs pbw;
     fill_common(pbw);
     pbw.W0T = W(o.W0T);
+    pbw.g.z = zz;
+    pbw.g.U = W(o.U);
+    pbw.g.V = W(o.V);
+    pbw.g.max_z = m->max_z;
+    pbw.g.f0 = w.f0;
+    pbw.g.dXr = w.dXr;
     for (int64_t l = 0; l < L; ++l) {
       const LayerOff &lo = o.layer[l];
       pbw.WaT[l] = W(lo.WaT);
@@ -368,11 +365,9 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
       pbw.z1[l] = w.z1[l];
       pbw.z2[l] = w.z2[l];
       pbw.z3[l] = w.z3[l];
-      pbw.dh[l] = w.dh[l];
+      pbw.g.Y[l] = w.Y[l];
+      pbw.g.dM[l] = w.dM[l];
     }
-    pbw.df0 = w.df0;
-    pbw.dphi0 = w.dphi;
-    pbw.dvhat = w.dvhat;
     pbw.gpair = w.gpair;
     if ((rc = launch_pair_bwd(s, (int)F, (int)K, pbw))) return rc;
   }

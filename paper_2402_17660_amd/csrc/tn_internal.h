@@ -168,6 +168,16 @@ struct PairFwdArgs {
   float *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers], *h[kMaxLayers];
 };
 
+// Per-atom rows the reverse pair kernels gather (internal atom order, [N][9][F] coordinates).
+struct BwdGather {
+  const int32_t *z = nullptr;
+  const float *U = nullptr, *V = nullptr;
+  int max_z = 0;
+  const float *f0 = nullptr;
+  const float *dXr = nullptr;
+  const float *Y[kMaxLayers], *dM[kMaxLayers];
+};
+
 struct PairBwdArgs {
   const int32_t *pairs = nullptr;
   int64_t max_pairs = 0;
@@ -180,8 +190,8 @@ struct PairBwdArgs {
   const float *W0T = nullptr;
   const float *WaT[kMaxLayers], *WbT[kMaxLayers], *WcT[kMaxLayers];
   int L = 0;
-  const float *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers], *dh[kMaxLayers];
-  const float *df0 = nullptr, *dphi0 = nullptr, *dvhat = nullptr;
+  const float *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers];
+  BwdGather g;
   float *gpair = nullptr;
 };
 
@@ -222,8 +232,7 @@ struct PairBwdArgsB {
   const __bf16 *WaT[kMaxLayers], *WbT[kMaxLayers], *WcT[kMaxLayers];
   int L = 0;
   const __bf16 *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers];
-  const float *dh[kMaxLayers];
-  const float *df0 = nullptr, *dphi0 = nullptr, *dvhat = nullptr;
+  BwdGather g;
   float *gpair = nullptr;
 };
 

@@ -485,6 +485,71 @@ __global__ void k_product(int64_t n, int F, const T *Y, const T *M, T *P, T *nP,
   store9(Pb, i, F, f, pc);
 }
 
+// Message and product in one pass: M_i = sum_j h_part(c) * Y_j[c] over the CSR row of i,
+// then P = Y M + M Y and Pb = P / (||P|| + 1).  Writes M, P, ||P|| and Pb.
+template <class T>
+__global__ void k_message_product(int64_t n, int F, const int32_t *rowptr, const int32_t *nbr, const int32_t *pid,
+                                  const int64_t *n_pairs, int64_t max_pairs, const T *h, const T *Y, T *M, T *P,
+                                  T *nP, T *Pb) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F || !pairs_ok(n_pairs, max_pairs)) return;
+  const int64_t i = t / F;
+  const int f = (int)(t % F);
+  T mc[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const int64_t j = nbr[e];
+    const int64_t p = pid[e];
+    const T hI = h[p * 3 * F + f], hA = h[p * 3 * F + F + f], hS = h[p * 3 * F + 2 * F + f];
+    const T *y = Y + j * 9 * F + f;
+    mc[0] += hI * y[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) mc[q] += hA * y[q * F];
+#pragma unroll
+    for (int q = 4; q < 9; ++q) mc[q] += hS * y[q * F];
+  }
+  store9(M, i, F, f, mc);
+  T yc[9], Ym[9], Mm[9], A1[9], A2[9], pc[9];
+  load9(Y, i, F, f, yc);
+  rec(yc, Ym);
+  rec(mc, Mm);
+  mm(Ym, Mm, A1);
+  mm(Mm, Ym, A2);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) A1[q] += A2[q];
+  dec(A1, pc);
+  store9(P, i, F, f, pc);
+  const T nn = norm9(pc);
+  nP[i * F + f] = nn;
+  const T sc = T(1) / (nn + T(1));
+#pragma unroll
+  for (int q = 0; q < 9; ++q) pc[q] *= sc;
+  store9(Pb, i, F, f, pc);
+}
+
+// X_out = Xb + D + D D, and for the next layer ||X_out|| and X_out / (||X_out|| + 1).
+template <class T>
+__global__ void k_residual_normalize(int64_t n, int F, const T *Xb, const T *D, T *Xo, T *nXo, T *Xbo) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  const int64_t i = t / F;
+  const int f = (int)(t % F);
+  T dc[9], Dm[9], Q[9], qc[9], xb[9];
+  load9(D, i, F, f, dc);
+  load9(Xb, i, F, f, xb);
+  rec(dc, Dm);
+  mm(Dm, Dm, Q);
+  dec(Q, qc);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) xb[q] += dc[q] + qc[q];
+  store9(Xo, i, F, f, xb);
+  const T nn = norm9(xb);
+  nXo[i * F + f] = nn;
+  const T sc = T(1) / (nn + T(1));
+#pragma unroll
+  for (int q = 0; q < 9; ++q) xb[q] *= sc;
+  store9(Xbo, i, F, f, xb);
+}
+
 // X_out = Xb + D + D D
 template <class T>
 __global__ void k_residual(int64_t n, int F, const T *Xb, const T *D, T *Xo) {

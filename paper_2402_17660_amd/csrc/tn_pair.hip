@@ -5,7 +5,9 @@
 // evaluated once per unordered pair, in one pass over pair tiles:
 //   forward   geometry + basis (FP64) -> f0 = W0 e + b0 -> per layer
 //             z1 = Wa e + ba, z2 = Wb silu(z1) + bb, z3 = Wc silu(z2) + bc, h = phi silu(z3)
-//   reverse   per layer dz3 = dh phi silu'(z3), dz2 = (dz3 Wc) silu'(z2), dz1 = (dz2 Wb) silu'(z1),
+//   reverse   dE/df0, dE/dphi, dE/dvhat of the embedding and, per layer, dh from the two
+//             atoms' adjoint rows (gathered in the tile's prologue), then per layer
+//             dz3 = dh phi silu'(z3), dz2 = (dz3 Wc) silu'(z2), dz1 = (dz2 Wb) silu'(z1),
 //             de += dz1 Wa;  de += df0 W0;  then dE/dv from de, dE/dphi, dE/dvhat (FP64)
 // Tiles hold 32 pairs; the four waves of a workgroup split the output columns, each wave
 // covering all 32 rows in two 16-row MFMA blocks.  Activations live in LDS (row padding of
@@ -43,11 +45,19 @@ __device__ __forceinline__ void wave_mm(const float *act, int ld, int Kin, const
   const float *a1p = act + (r + 16) * ld + 4 * q;
   const float *bp = Bt + (size_t)(col0 + r) * Kin + 4 * q;
   const size_t bstride = (size_t)16 * Kin;
-#pragma unroll 2
+  // weight fragments are double-buffered in registers: the loads for chunk k0+16 are in
+  // flight while the MFMAs of chunk k0 run
+  float4 bn[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) bn[cb] = *reinterpret_cast<const float4 *>(bp + cb * bstride);
   for (int k0 = 0; k0 < Kin; k0 += 16) {
     float4 b[NB];
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) b[cb] = *reinterpret_cast<const float4 *>(bp + cb * bstride + k0);
+    for (int cb = 0; cb < NB; ++cb) b[cb] = bn[cb];
+    if (k0 + 16 < Kin) {
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) bn[cb] = *reinterpret_cast<const float4 *>(bp + cb * bstride + k0 + 16);
+    }
     const float4 a0 = *reinterpret_cast<const float4 *>(a0p + k0);
     const float4 a1 = *reinterpret_cast<const float4 *>(a1p + k0);
 #pragma unroll
@@ -210,14 +220,150 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
   }
 }
 
+// ============================================================================ reverse-sweep prologues
+// Both directions of a pair meet in the pair tile, so the pair-level adjoints are formed
+// here from the two atoms' rows (coordinates layout [N, 9, F]) and written straight into
+// LDS as the A operand of the MFMA backprop.  Each wave owns R/4 rows; its lanes sweep the
+// F channels and per-row scalars are reduced across the wave.
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// dE/df0 = (da, db, dc) for both directions of the pair -> lds[row][0..3F); returns the pair's
+// dE/dphi and dE/dvhat (embedding part) through the per-row LDS arrays.
+template <int F, class TL>
+__device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const int32_t *pairs, int64_t max_pairs,
+                                                   int64_t p0, int R, int nvalid, const float (*sU)[3],
+                                                   const float *sPhi, TL *lds, int ld, float *sDphi,
+                                                   float (*sDv)[3]) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rows = R / 4;
+  for (int rr = 0; rr < rows; ++rr) {
+    const int row = wave * rows + rr;
+    float aphi = 0.f, av0 = 0.f, av1 = 0.f, av2 = 0.f;
+    if (row < nvalid) {
+      const int64_t p = p0 + row;
+      const int64_t i = pairs[p], j = pairs[max_pairs + p];
+      int zi = bg.z[i], zj = bg.z[j];
+      zi = zi < 0 ? 0 : (zi >= bg.max_z ? bg.max_z - 1 : zi);
+      zj = zj < 0 ? 0 : (zj >= bg.max_z ? bg.max_z - 1 : zj);
+      const float ux = sU[row][0], uy = sU[row][1], uz = sU[row][2];
+      const float ph = sPhi[row];
+      float s5[5];
+      s0_coords(ux, uy, uz, s5);
+      const float *di = bg.dXr + i * 9 * F, *dj = bg.dXr + j * 9 * F;
+      for (int f = lane; f < F; f += 64) {
+        const float Zij = bg.U[zi * F + f] + bg.V[zj * F + f];
+        const float Zji = bg.U[zj * F + f] + bg.V[zi * F + f];
+        const float a = bg.f0[p * 3 * F + f], b = bg.f0[p * 3 * F + F + f], c = bg.f0[p * 3 * F + 2 * F + f];
+        float ci[9], cj[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          ci[q] = di[q * F + f];
+          cj[q] = dj[q * F + f];
+        }
+        const float giA = ci[1] * ux + ci[2] * uy + ci[3] * uz;
+        const float gjA = -(cj[1] * ux + cj[2] * uy + cj[3] * uz);
+        float giS = 0.f, gjS = 0.f;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          giS += ci[4 + q] * s5[q];
+          gjS += cj[4 + q] * s5[q];
+        }
+        lds[row * ld + f] = (TL)(ph * (Zij * ci[0] + Zji * cj[0]));
+        lds[row * ld + F + f] = (TL)(ph * (Zij * giA + Zji * gjA));
+        lds[row * ld + 2 * F + f] = (TL)(ph * (Zij * giS + Zji * gjS));
+        aphi += Zij * (a * ci[0] + b * giA + c * giS) + Zji * (a * cj[0] + b * gjA + c * gjS);
+        float gsi[3], gsj[3];
+        s0_dot_grad(ci + 4, ux, uy, uz, gsi);
+        s0_dot_grad(cj + 4, ux, uy, uz, gsj);
+        av0 += ph * (b * (Zij * ci[1] - Zji * cj[1]) + c * (Zij * gsi[0] + Zji * gsj[0]));
+        av1 += ph * (b * (Zij * ci[2] - Zji * cj[2]) + c * (Zij * gsi[1] + Zji * gsj[1]));
+        av2 += ph * (b * (Zij * ci[3] - Zji * cj[3]) + c * (Zij * gsi[2] + Zji * gsj[2]));
+      }
+    } else {
+      for (int f = lane; f < 3 * F; f += 64) lds[row * ld + f] = (TL)0.f;
+    }
+    aphi = wave_sum(aphi);
+    av0 = wave_sum(av0);
+    av1 = wave_sum(av1);
+    av2 = wave_sum(av2);
+    if (lane == 0) {
+      sDphi[row] = aphi;
+      sDv[row][0] = av0;
+      sDv[row][1] = av1;
+      sDv[row][2] = av2;
+    }
+  }
+}
+
+// Layer l: dh = <part(Y_j), dM_i> + <part(Y_i), dM_j> per channel; then
+// lds[row][c] = dh phi silu'(z3) and dE/dphi += sum_c dh silu(z3).
+template <int F, class TL, class TZ>
+__device__ __forceinline__ void filter_adjoint_rows(const float *Y, const float *dM, const TZ *z3,
+                                                    const int32_t *pairs, int64_t max_pairs, int64_t p0, int R,
+                                                    int nvalid, const float *sPhi, TL *lds, int ld, float *sDphi) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rows = R / 4;
+  for (int rr = 0; rr < rows; ++rr) {
+    const int row = wave * rows + rr;
+    float part = 0.f;
+    if (row < nvalid) {
+      const int64_t p = p0 + row;
+      const int64_t i = pairs[p], j = pairs[max_pairs + p];
+      const float *yi = Y + i * 9 * F, *yj = Y + j * 9 * F, *gi = dM + i * 9 * F, *gj = dM + j * 9 * F;
+      const float ph = sPhi[row];
+      for (int f = lane; f < F; f += 64) {
+        float dh[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dh[coord_part(q)] += yj[q * F + f] * gi[q * F + f] + yi[q * F + f] * gj[q * F + f];
+#pragma unroll
+        for (int pt = 0; pt < 3; ++pt) {
+          const int c = pt * F + f;
+          const float zz = (float)z3[p * 3 * F + c];
+          lds[row * ld + c] = (TL)(dh[pt] * ph * silu_grad(zz));
+          part += dh[pt] * silu(zz);
+        }
+      }
+    } else {
+      for (int c = lane; c < 3 * F; c += 64) lds[row * ld + c] = (TL)0.f;
+    }
+    part = wave_sum(part);
+    if (lane == 0) sDphi[row] += part;
+  }
+}
+
+// dE/dv for the tile's pairs from dE/de (LDS [R][ldE]), dE/dphi and dE/dvhat (per-row LDS).
+template <int K>
+__device__ __forceinline__ void geometry_adjoint_rows(const PairGeo &g, const float *sDE, int ldE, float dphi,
+                                                      const float *dv, double alpha, double r_lo, const double *mu,
+                                                      const double *beta, float *gout) {
+  const double u = exp(-alpha * (g.d - r_lo));
+  double dd = (double)dphi * g.dphi;
+  for (int k = 0; k < K; ++k) {
+    const double x = u - mu[k];
+    const double gk = exp(-beta[k] * x * x);
+    const double dek = g.dphi * gk + g.phi * gk * 2.0 * alpha * beta[k] * u * x;
+    dd += (double)sDE[k] * dek;
+  }
+  const double gx = dv[0], gy = dv[1], gz = dv[2];
+  const double proj = gx * g.u[0] + gy * g.u[1] + gz * g.u[2];
+  const double inv = 1.0 / g.d;
+  gout[0] = (float)(dd * g.u[0] + (gx - proj * g.u[0]) * inv);
+  gout[1] = (float)(dd * g.u[1] + (gy - proj * g.u[1]) * inv);
+  gout[2] = (float)(dd * g.u[2] + (gz - proj * g.u[2]) * inv);
+}
+
 // ============================================================================ reverse
 template <int F, int K>
 __global__ void __launch_bounds__(256, 1) k_pair_bwd(PairBwdArgs a) {
   constexpr int L3 = 3 * F + kPad, L2 = 2 * F + kPad, L1 = F + kPad, LE = K + kPad;
-  __shared__ __attribute__((aligned(16))) float sG3[kTile * L3];   // dz3, then dz1 / df0
-  __shared__ __attribute__((aligned(16))) float sG2[kTile * L2];   // dz2
-  __shared__ float sPhi[kTile];
-  __shared__ float sDphi[kTile];
+  __shared__ __attribute__((aligned(16))) float sG3[kTile * L3];   // df0, dz3, then dz1
+  __shared__ __attribute__((aligned(16))) float sG2[kTile * L2];   // dz2, finally dE/de
+  __shared__ float sPhi[kTile], sDphi[kTile], sU[kTile][3], sDv[kTile][3];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
   const int64_t p0 = (int64_t)blockIdx.x * kTile;
   if (p0 >= P) return;
@@ -227,21 +373,20 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd(PairBwdArgs a) {
 
   PairGeo g{};
   if (tid < kTile) {
-    float ph = 0.f, dp = 0.f;
+    float ph = 0.f;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
       g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.periodic, a.box, a.r_c);
       ph = (float)g.phi;
-      dp = a.dphi0[p];
     }
     sPhi[tid] = ph;
-    sDphi[tid] = dp;
+    sU[tid][0] = (float)g.u[0];
+    sU[tid][1] = (float)g.u[1];
+    sU[tid][2] = (float)g.u[2];
   }
-  // embedding adjoint df0 (3F per pair) -> LDS
-  for (int t = tid; t < kTile * 3 * F; t += 256) {
-    const int row = t / (3 * F), c = t % (3 * F);
-    sG3[row * L3 + c] = row < nvalid ? a.df0[(p0 + row) * 3 * F + c] : 0.f;
-  }
+  __syncthreads();
+  // embedding adjoint: dE/df0 -> sG3, dE/dphi and dE/dvhat per pair
+  embed_adjoint_rows<F>(a.g, a.pairs, a.max_pairs, p0, kTile, nvalid, sU, sPhi, sG3, L3, sDphi, sDv);
   __syncthreads();
   floatx4 de[2][1];
   zero_acc(de);
@@ -249,29 +394,9 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd(PairBwdArgs a) {
   __syncthreads();
 
   for (int l = 0; l < a.L; ++l) {
-    const float *z1 = a.z1[l], *z2 = a.z2[l], *z3 = a.z3[l], *dh = a.dh[l];
-    // dz3 = dh phi silu'(z3); dE/dphi += sum dh silu(z3).  Each wave owns 8 rows; the lanes
-    // sweep a row's 3F columns and the per-row sum is reduced across the wave.
-    {
-      const int lane = tid & 63;
-      for (int rr = 0; rr < kTile / 4; ++rr) {
-        const int row = wave * (kTile / 4) + rr;
-        float part = 0.f;
-        for (int c = lane; c < 3 * F; c += 64) {
-          float v = 0.f;
-          if (row < nvalid) {
-            const int64_t o = (p0 + row) * 3 * F + c;
-            const float z = z3[o], gh = dh[o];
-            v = gh * sPhi[row] * silu_grad(z);
-            part += gh * silu(z);
-          }
-          sG3[row * L3 + c] = v;
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-        if (lane == 0) sDphi[row] += part;
-      }
-    }
+    const float *z1 = a.z1[l], *z2 = a.z2[l];
+    filter_adjoint_rows<F>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, kTile, nvalid, sPhi, sG3, L3,
+                           sDphi);
     __syncthreads();
     {  // dz2 = (dz3 Wc) silu'(z2)
       constexpr int NB = F / 32;
@@ -299,28 +424,13 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd(PairBwdArgs a) {
     __syncthreads();
   }
 
-  // dE/de to LDS (reuse sG2 as [32][K+4]), then the geometry adjoint per pair in FP64
-  float *sDE = sG2;
+  float *sDE = sG2;   // [32][K+4]
   if (wave < NWDE)
     for_acc(de, wave * 16, [&](int row, int col, float v) { sDE[row * LE + col] = v; });
   __syncthreads();
-  if (tid < nvalid) {
-    const int64_t p = p0 + tid;
-    const double u = exp(-a.alpha * (g.d - a.r_lo));
-    double dd = (double)sDphi[tid] * g.dphi;
-    for (int k = 0; k < K; ++k) {
-      const double x = u - a.mu[k];
-      const double gk = exp(-a.beta[k] * x * x);
-      const double dek = g.dphi * gk + g.phi * gk * 2.0 * a.alpha * a.beta[k] * u * x;
-      dd += (double)sDE[tid * LE + k] * dek;
-    }
-    const double gx = a.dvhat[3 * p], gy = a.dvhat[3 * p + 1], gz = a.dvhat[3 * p + 2];
-    const double proj = gx * g.u[0] + gy * g.u[1] + gz * g.u[2];
-    const double inv = 1.0 / g.d;
-    a.gpair[3 * p + 0] = (float)(dd * g.u[0] + (gx - proj * g.u[0]) * inv);
-    a.gpair[3 * p + 1] = (float)(dd * g.u[1] + (gy - proj * g.u[1]) * inv);
-    a.gpair[3 * p + 2] = (float)(dd * g.u[2] + (gz - proj * g.u[2]) * inv);
-  }
+  if (tid < nvalid)
+    geometry_adjoint_rows<K>(g, sDE + tid * LE, 0, sDphi[tid], sDv[tid], a.alpha, a.r_lo, a.mu, a.beta,
+                             a.gpair + 3 * (p0 + tid));
 }
 
 // ============================================================================ BF16 variant
@@ -354,11 +464,17 @@ __device__ __forceinline__ void wave_mm_bf16(const __bf16 *act, int ld, int Kin,
   const __bf16 *bp = Bt + (size_t)(col0 + r) * Kin + 8 * q;
   const size_t bstride = (size_t)16 * Kin;
   const int astride = 16 * ld;
-#pragma unroll 2
+  bf16x8 bn[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) bn[cb] = *reinterpret_cast<const bf16x8 *>(bp + cb * bstride);
   for (int k0 = 0; k0 < Kin; k0 += 32) {
     bf16x8 b[NB];
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) b[cb] = *reinterpret_cast<const bf16x8 *>(bp + cb * bstride + k0);
+    for (int cb = 0; cb < NB; ++cb) b[cb] = bn[cb];
+    if (k0 + 32 < Kin) {
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) bn[cb] = *reinterpret_cast<const bf16x8 *>(bp + cb * bstride + k0 + 32);
+    }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const bf16x8 a = *reinterpret_cast<const bf16x8 *>(ap + rb * astride + k0);
@@ -479,58 +595,40 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
 template <int F, int K>
 __global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
   constexpr int L3 = 3 * F + kPadB, L2 = 2 * F + kPadB, L1 = F + kPadB, LE = K + 4;
-  __shared__ __attribute__((aligned(16))) __bf16 sG3[kTileB * L3];   // dz3, then dz1 / df0
+  __shared__ __attribute__((aligned(16))) __bf16 sG3[kTileB * L3];   // df0, dz3, then dz1
   __shared__ __attribute__((aligned(16))) __bf16 sG2[kTileB * L2];   // dz2
   __shared__ __attribute__((aligned(16))) float sDE[kTileB * LE];
-  __shared__ float sPhi[kTileB];
-  __shared__ float sDphi[kTileB];
+  __shared__ float sPhi[kTileB], sDphi[kTileB], sU[kTileB][3], sDv[kTileB][3];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
   const int64_t p0 = (int64_t)blockIdx.x * kTileB;
   if (p0 >= P) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < kTileB ? (P - p0) : kTileB);
   constexpr int NWDE = K / 16;
   PairGeo g{};
   if (tid < kTileB) {
-    float ph = 0.f, dp = 0.f;
+    float ph = 0.f;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
       g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.periodic, a.box, a.r_c);
       ph = (float)g.phi;
-      dp = a.dphi0[p];
     }
     sPhi[tid] = ph;
-    sDphi[tid] = dp;
+    sU[tid][0] = (float)g.u[0];
+    sU[tid][1] = (float)g.u[1];
+    sU[tid][2] = (float)g.u[2];
   }
-  for (int t = tid; t < kTileB * 3 * F; t += 256) {
-    const int row = t / (3 * F), c = t % (3 * F);
-    sG3[row * L3 + c] = (__bf16)(row < nvalid ? a.df0[(p0 + row) * 3 * F + c] : 0.f);
-  }
+  __syncthreads();
+  embed_adjoint_rows<F>(a.g, a.pairs, a.max_pairs, p0, kTileB, nvalid, sU, sPhi, sG3, L3, sDphi, sDv);
   __syncthreads();
   floatx4 de[4][1];
   zero_acc4(de);
   if (wave < NWDE) wave_mm_bf16<1>(sG3, L3, 3 * F, a.W0T, wave * 16, de);
   __syncthreads();
   for (int l = 0; l < a.L; ++l) {
-    const __bf16 *z1 = a.z1[l], *z2 = a.z2[l], *z3 = a.z3[l];
-    const float *dh = a.dh[l];
-    for (int rr = 0; rr < kTileB / 4; ++rr) {
-      const int row = wave * (kTileB / 4) + rr;
-      float part = 0.f;
-      for (int c = lane; c < 3 * F; c += 64) {
-        float v = 0.f;
-        if (row < nvalid) {
-          const int64_t o = (p0 + row) * 3 * F + c;
-          const float z = (float)z3[o], gh = dh[o];
-          v = gh * sPhi[row] * silu_grad(z);
-          part += gh * silu(z);
-        }
-        sG3[row * L3 + c] = (__bf16)v;
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-      if (lane == 0) sDphi[row] += part;
-    }
+    const __bf16 *z1 = a.z1[l], *z2 = a.z2[l];
+    filter_adjoint_rows<F>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, kTileB, nvalid, sPhi, sG3, L3,
+                           sDphi);
     __syncthreads();
     {
       constexpr int NB = F / 32;
@@ -560,23 +658,9 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
   if (wave < NWDE)
     for_acc4(de, wave * 16, [&](int row, int col, float v) { sDE[row * LE + col] = v; });
   __syncthreads();
-  if (tid < nvalid) {
-    const int64_t p = p0 + tid;
-    const double u = exp(-a.alpha * (g.d - a.r_lo));
-    double dd = (double)sDphi[tid] * g.dphi;
-    for (int k = 0; k < K; ++k) {
-      const double x = u - a.mu[k];
-      const double gk = exp(-a.beta[k] * x * x);
-      const double dek = g.dphi * gk + g.phi * gk * 2.0 * a.alpha * a.beta[k] * u * x;
-      dd += (double)sDE[tid * LE + k] * dek;
-    }
-    const double gx = a.dvhat[3 * p], gy = a.dvhat[3 * p + 1], gz = a.dvhat[3 * p + 2];
-    const double proj = gx * g.u[0] + gy * g.u[1] + gz * g.u[2];
-    const double inv = 1.0 / g.d;
-    a.gpair[3 * p + 0] = (float)(dd * g.u[0] + (gx - proj * g.u[0]) * inv);
-    a.gpair[3 * p + 1] = (float)(dd * g.u[1] + (gy - proj * g.u[1]) * inv);
-    a.gpair[3 * p + 2] = (float)(dd * g.u[2] + (gz - proj * g.u[2]) * inv);
-  }
+  if (tid < nvalid)
+    geometry_adjoint_rows<K>(g, sDE + tid * LE, 0, sDphi[tid], sDv[tid], a.alpha, a.r_lo, a.mu, a.beta,
+                             a.gpair + 3 * (p0 + tid));
 }
 
 // ============================================================================ launchers

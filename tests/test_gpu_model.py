@@ -124,6 +124,23 @@ def test_fused_layer_counts(dev, L_layers):
     assert_close(E, F, E_ref, F_ref, "fp32", f"fused L={L_layers}")
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_100k_box_full_size(dev, precision):
+    """The MD workload at full size with the bench's pair budget (1.10 x the true count):
+    exact oracle forces of ~100 atoms (isolated clusters large enough to contain every atom
+    those forces depend on), and the zero net force of the whole box."""
+    g = np.load(os.path.join(GOLDEN, "oracle_cfg3_sampled.npz"))
+    c = make_config(3)
+    mp = int(np.ceil(1.10 * int(g["n_pairs"]) / 1024.0) * 1024)
+    m = TensorNet(cfg_blob(c), dev)
+    E, F = gpu_ef(dev, m, c["pos"], c["z"], c["batch"], c["box"], 1, precision, "fused", max_pairs=mp)
+    assert int(m.n_pairs.item()) == int(g["n_pairs"])
+    fe = rel_rms(F[g["idx"]], g["F"])
+    print(f"cfg3 {precision} fused: force rel RMS on {len(g['idx'])} sampled atoms {fe:.3e}", flush=True)
+    assert fe <= TOL[precision][1]
+    assert np.abs(F.sum(0)).max() < 1e-3 * np.abs(F).max()
+
+
 def test_energy_only_matches(dev, cfg0):
     c, blob, E_ref, _ = cfg0
     m = TensorNet(blob, dev)
@@ -132,10 +149,11 @@ def test_energy_only_matches(dev, cfg0):
     assert abs(E1[0] - E2[0]) <= 1e-13 * abs(E2[0])
 
 
-def test_max_pairs_independence_and_determinism(dev, cfg0):
+@pytest.mark.parametrize("precision,path", [("fp32", "plain"), ("fp32", "fused"), ("bf16", "fused")])
+def test_max_pairs_independence_and_determinism(dev, cfg0, precision, path):
     c, blob, _, _ = cfg0
     m = TensorNet(blob, dev)
-    outs = [gpu_ef(dev, m, c["pos"], c["z"], c["batch"], None, 1, "fp32", "plain", max_pairs=mp)
+    outs = [gpu_ef(dev, m, c["pos"], c["z"], c["batch"], None, 1, precision, path, max_pairs=mp)
             for mp in (600, 600, 5000)]
     for E, F in outs[1:]:
         assert np.array_equal(E, outs[0][0]) and np.array_equal(F, outs[0][1])
