@@ -75,8 +75,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-atoms", type=int, default=3000)
     ap.add_argument("--budget", type=float, default=1.05, help="max_pairs = budget * true pair count")
-    ap.add_argument("--extra", default="batch,md", help="extra workloads: batch (512 molecules, captured), "
-                                                        "md (100 captured velocity-Verlet steps, 100k atoms); '' = none")
+    ap.add_argument("--extra", default="batch,md,table2",
+                    help="extra workloads: batch (512 molecules, captured), md (100 captured velocity-Verlet steps, "
+                         "100k atoms), table2 (the paper's Table 2 sizes, captured); 'none' = none")
     ap.add_argument("--md-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -176,7 +177,7 @@ def main():
         log("timing the FP64 oracle on the host ...")
         cpu = cpu_baseline(args.cpu_atoms, F, K, L, r_c, c["weight_seed"])
     extra = {}
-    for name in [e for e in args.extra.split(",") if e]:
+    for name in [e for e in args.extra.split(",") if e and e != "none"]:
         try:
             extra[name] = EXTRA[name](args, dev)
         except Exception as e:   # an extra workload never hides the headline line
@@ -289,7 +290,51 @@ def extra_md(args, dev):
     return out
 
 
-EXTRA = {"batch": extra_batch, "md": extra_md}
+# Table 2 of the paper: TensorNet E+F, one molecule per call, cutoff 4.5 A, hidden 128, 32 RBF,
+# pair budget 32 N; the paper's "Graph" column (RTX 4090, Msteps/day) for 0/1/2 layers.
+TABLE2 = [("alanine dipeptide", 22, (172.80, 84.71, 56.47)), ("testosterone", 49, (154.29, 63.53, 39.82)),
+          ("chignolin", 166, (77.14, 26.02, 15.57)), ("DHFR", 2489, (5.65, 1.69, 1.00)),
+          ("factor IX", 5807, (2.33, 0.70, 0.42))]
+
+
+def extra_table2(args, dev):
+    """Synthetic molecules of the Table 2 sizes (random H/C/N/O, 0.1 atoms/A^3), captured graphs, FP32 fused."""
+    import torch
+    from paper_2402_17660_amd import TensorNet, capture
+    from synth import make_weights, single_molecule, write_blob
+    rows = []
+    for name, n, paper_g in TABLE2:
+        mol = single_molecule(n, seed=7000 + n)
+        pos = torch.tensor(mol["pos"], device=dev)
+        z = torch.tensor(mol["z"], device=dev)
+        batch = torch.tensor(mol["batch"], device=dev)
+        for L in (0, 1, 2):
+            model = TensorNet(write_blob(make_weights(128, 32, L, 100, seed=8000 + L), 128, 32, L, 100, 4.5), dev)
+            g, E, Fo, n_pairs, status = capture(model, pos, z, batch, 1, max_pairs=32 * n, precision="fp32")
+            for _ in range(10):
+                g.replay()
+            torch.cuda.synchronize()
+            reps = 50 if n < 1000 else 20
+            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record()
+            for _ in range(reps):
+                g.replay()
+            stop.record()
+            torch.cuda.synchronize()
+            ms = start.elapsed_time(stop) / reps
+            msteps_day = 86400.0 / (ms * 1e-3) / 1e6
+            rows.append(dict(molecule=name, atoms=n, layers=L, ms_per_step=ms, msteps_per_day=msteps_day,
+                             atom_steps_per_s=n / (ms * 1e-3), status=int(status.item()),
+                             paper_graph_msteps_per_day_rtx4090=paper_g[L]))
+            log(f"table2 {name} ({n} atoms) {L}L: {ms * 1e3:.1f} us/step, {msteps_day:.2f} Msteps/day "
+                f"(paper RTX 4090 Graph: {paper_g[L]})")
+            g.close()
+    return dict(workload="synthetic stand-ins for the Table 2 molecules (sizes 22-5807 atoms), cutoff 4.5 A, "
+                         "hidden 128, 32 RBF, max_pairs 32 N, fused FP32, one captured HIP graph per step",
+                rows=rows)
+
+
+EXTRA = {"batch": extra_batch, "md": extra_md, "table2": extra_table2}
 
 
 if __name__ == "__main__":

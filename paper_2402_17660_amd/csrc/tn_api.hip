@@ -79,7 +79,7 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
   // room for the derived tables: species tables, basis constants, aligned and transposed
   // copies of the per-pair weights (each start aligned to 64 elements)
   const size_t extra = 2 * Z * F + 2 * K + 2 * (3 * F * K) + (size_t)m->L * 2 * (F * K + 2 * F * F + 6 * F * F) +
-                       64 * (8 + 6 * (size_t)m->L);
+                       (size_t)m->L * 6 * F * F + 64 * (8 + 12 * (size_t)m->L);
   packed.assign(total + extra, 0.0);
   size_t off = 0;
   const unsigned char *src = b + kHeaderBytes;
@@ -122,6 +122,10 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
     lo.WbT = copy(lo.Wb, 2 * F, F, true);
     lo.Wcf = copy(lo.Wc, 3 * F, 2 * F, false);
     lo.WcT = copy(lo.Wc, 3 * F, 2 * F, true);
+    for (int q = 0; q < 3; ++q) {
+      lo.W1T[q] = copy(lo.W1[q], F, F, true);
+      lo.W2T[q] = copy(lo.W2[q], F, F, true);
+    }
   }
   o.total = off;
   if (o.total > packed.size()) return TN_E_BLOB;

@@ -200,7 +200,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   if ((rc = linear_fwd<TA>(s, w.n0, N, F, WA(o.W1), WA(o.b1), 2 * F, w.ea1, w.ez1, 1))) return rc;
   if ((rc = linear_fwd<TA>(s, w.ea1, N, 2 * F, WA(o.W2), WA(o.b2), 3 * F, w.g, w.ez2, 1))) return rc;
   const TA *Wemb[3] = {WA(o.Wmix[0]), WA(o.Wmix[1]), WA(o.Wmix[2])};
-  if ((rc = mix<TA>(s, w.XrA, w.T0, N, F, Wemb, 0, 0))) return rc;
+  if ((rc = mix<TA>(s, w.XrA, w.T0, N, F, Wemb, nullptr, 0, 0))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_gate<TA>, dim3(grid_for(N * 9 * F, bs)), dim3(bs), 0, s, N, (int)F, w.g, w.T0, w.X0A);
     TN_LAUNCH_CHECK();
@@ -214,14 +214,16 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   for (int64_t l = 0; l < L; ++l) {
     const LayerOff &lo = o.layer[l];
     const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
-    if ((rc = mix<float>(s, w.Xb[l], w.Y[l], N, F, W1, 0, 0))) return rc;
+    const float *W1T[3] = {W(lo.W1T[0]), W(lo.W1T[1]), W(lo.W1T[2])};
+    if ((rc = mix<float>(s, w.Xb[l], w.Y[l], N, F, W1, W1T, 0, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_message_product<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP,
                          w.h[l], w.Y[l], w.M[l], w.P[l], w.nP[l], w.Pb[l]);
       TN_LAUNCH_CHECK();
     }
     const float *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
-    if ((rc = mix<float>(s, w.Pb[l], w.D[l], N, F, W2, 0, 0))) return rc;
+    const float *W2T[3] = {W(lo.W2T[0]), W(lo.W2T[1]), W(lo.W2T[2])};
+    if ((rc = mix<float>(s, w.Pb[l], w.D[l], N, F, W2, W2T, 0, 0))) return rc;
     if (N > 0) {
       if (l + 1 < L) {
         hipLaunchKernelGGL(k_residual_normalize<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xb[l], w.D[l],
@@ -281,12 +283,14 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   for (int64_t l = L - 1; l >= 0; --l) {
     const LayerOff &lo = o.layer[l];
     const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
+    const float *W1T[3] = {W(lo.W1T[0]), W(lo.W1T[1]), W(lo.W1T[2])};
     const float *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
+    const float *W2T[3] = {W(lo.W2T[0]), W(lo.W2T[1]), W(lo.W2T[2])};
     if (N > 0) {
       hipLaunchKernelGGL(k_residual_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.D[l], w.dX, w.dD);
       TN_LAUNCH_CHECK();
     }
-    if ((rc = mix<float>(s, w.dD, w.dPb, N, F, W2, 1, 0))) return rc;
+    if ((rc = mix<float>(s, w.dD, w.dPb, N, F, W2, W2T, 1, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_product_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dPb, w.P[l], w.nP[l], w.Y[l],
                          w.M[l], w.dY, w.dM[l]);
@@ -295,7 +299,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
                          w.dM[l], w.dY, 1);
       TN_LAUNCH_CHECK();
     }
-    if ((rc = mix<float>(s, w.dY, w.dX, N, F, W1, 1, 1))) return rc;
+    if ((rc = mix<float>(s, w.dY, w.dX, N, F, W1, W1T, 1, 1))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_normalize_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[l], w.nX[l], w.dX);
       TN_LAUNCH_CHECK();
@@ -307,7 +311,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     hipLaunchKernelGGL(k_gate_bwd<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dXA, w.T0, w.g, w.dg, w.dT0);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = mix<TA>(s, w.dT0, w.dXrA, N, F, Wemb, 1, 0))) return rc;
+  if ((rc = mix<TA>(s, w.dT0, w.dXrA, N, F, Wemb, nullptr, 1, 0))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_mul_silu_grad<TA>, dim3(grid_for(N * 3 * F, bs)), dim3(bs), 0, s, N * 3 * F, w.dg, w.ez2,
                        w.dez2);

@@ -32,6 +32,7 @@ struct LayerOff {
   size_t Wa, ba, Wb, bb, Wc, bc, W1[3], W2[3];
   size_t WaT, WbT, WcT;   // transposed copies [K][F], [F][2F], [2F][3F] (fused reverse sweep)
   size_t Waf, Wbf, Wcf;   // 64-element aligned copies of Wa, Wb, Wc (fused forward)
+  size_t W1T[3], W2T[3];  // transposed mixing matrices, 64-element aligned (adjoint mixing)
 };
 
 struct WeightOff {

@@ -1,0 +1,68 @@
+// Wave-level MFMA tile products shared by the pair kernels and the node mixing kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tn {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// acc[rb][cb] += act_rb[16 x Kin] * Bt^T for rb < RB, where row i of block rb starts at
+// act + rb*rbs + i*ld (LDS) and Bt is [ncol][Kin] in global memory (row stride Kin); this wave
+// covers columns col0 .. col0 + 16*NB - 1 (v_mfma_f32_16x16x4f32).  Inside each 16-wide K
+// chunk, lane group q takes k = 4q..4q+3, so one 16-byte load feeds four MFMAs for both
+// operands; the weight fragments of the next chunk are loaded while the current chunk's MFMAs
+// run.  Element t of acc[rb][cb] in lane l is D_rb[4*(l/16) + t][col0 + cb*16 + l%16].
+template <int RB, int NB>
+__device__ __forceinline__ void wave_mm_rows(const float *act, int ld, int rbs, int Kin, const float *__restrict__ Bt,
+                                             int col0, floatx4 (&acc)[RB][NB]) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  const float *ap = act + r * ld + 4 * q;
+  const float *bp = Bt + (size_t)(col0 + r) * Kin + 4 * q;
+  const size_t bstride = (size_t)16 * Kin;
+  float4 bn[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) bn[cb] = *reinterpret_cast<const float4 *>(bp + cb * bstride);
+  for (int k0 = 0; k0 < Kin; k0 += 16) {
+    float4 b[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) b[cb] = bn[cb];
+    if (k0 + 16 < Kin) {
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) bn[cb] = *reinterpret_cast<const float4 *>(bp + cb * bstride + k0 + 16);
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const float4 a = *reinterpret_cast<const float4 *>(ap + rb * rbs + k0);
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        acc[rb][cb] = mfma4(a.x, b[cb].x, acc[rb][cb]);
+        acc[rb][cb] = mfma4(a.y, b[cb].y, acc[rb][cb]);
+        acc[rb][cb] = mfma4(a.z, b[cb].z, acc[rb][cb]);
+        acc[rb][cb] = mfma4(a.w, b[cb].w, acc[rb][cb]);
+      }
+    }
+  }
+}
+
+// Row blocks stacked contiguously: block rb starts 16 rows after block rb - 1.
+template <int RB, int NB>
+__device__ __forceinline__ void wave_mm_rb(const float *act, int ld, int Kin, const float *__restrict__ Bt, int col0,
+                                           floatx4 (&acc)[RB][NB]) {
+  wave_mm_rows<RB, NB>(act, ld, 16 * ld, Kin, Bt, col0, acc);
+}
+
+template <int RB, int NB>
+__device__ __forceinline__ void zero_acc_rb(floatx4 (&acc)[RB][NB]) {
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
+}  // namespace tn

@@ -476,14 +476,18 @@ __global__ void k_nbr_total(const int64_t *count64, int64_t max_pairs, int64_t *
 }
 
 // Pair id of every directed edge (rows are sorted by neighbour); the internal pair list
-// gets (s, t) for t > s, so it is ordered by (s, t).
-__global__ void k_pair_ids(int64_t n, const int32_t *rowptr, const int32_t *pbase, const int32_t *nbr,
-                           const int64_t *count64, int64_t max_pairs, int32_t *pid, int32_t *pairs) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// gets (s, t) for t > s, so it is ordered by (s, t).  One wavefront per atom, one lane per
+// edge of its row; a lower edge finds its pair in the partner's row by binary search.
+__global__ void __launch_bounds__(kNbrBlock) k_pair_ids(int64_t n, const int32_t *rowptr, const int32_t *pbase,
+                                                        const int32_t *nbr, const int64_t *count64, int64_t max_pairs,
+                                                        int32_t *pid, int32_t *pairs) {
+  const int64_t i = (blockIdx.x * (int64_t)kNbrBlock + threadIdx.x) >> 6;
   if (i >= n || count64[0] > max_pairs) return;
+  const int lane = threadIdx.x & 63;
   const int32_t a = rowptr[i], e = rowptr[i + 1];
   const int32_t nlow_i = (e - a) - (pbase[i + 1] - pbase[i]);
-  for (int32_t k = a; k < e; ++k) {
+  const int32_t P = (int32_t)count64[0];
+  for (int32_t k = a + lane; k < e; k += 64) {
     const int32_t j = nbr[k];
     int32_t p;
     if (j > i) {
@@ -491,7 +495,6 @@ __global__ void k_pair_ids(int64_t n, const int32_t *rowptr, const int32_t *pbas
       pairs[p] = (int32_t)i;
       pairs[max_pairs + p] = j;
     } else {
-      // find i in row j (sorted), rank it among row j's upper neighbours
       const int32_t aj = rowptr[j], ej = rowptr[j + 1];
       int32_t lo = aj, hi = ej;
       while (lo < hi) {
@@ -501,7 +504,6 @@ __global__ void k_pair_ids(int64_t n, const int32_t *rowptr, const int32_t *pbas
       const int32_t nlow_j = (ej - aj) - (pbase[j + 1] - pbase[j]);
       p = pbase[j] + (lo - aj - nlow_j);
       // the relation is symmetric, so i is always found; clamp defensively anyway
-      const int32_t P = (int32_t)count64[0];
       if (p < 0) p = 0;
       if (p > P - 1) p = P - 1;
     }
@@ -596,8 +598,8 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, co
     hipLaunchKernelGGL(k_nbr_write<T>, dim3(gw), dim3(kNbrBlock), 0, s, out.pos, out.batch, n, b, rc2, w.scell,
                        w.cell_start, w.flags, w.deg, w.count64, max_pairs, w.nbr);
     TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_pair_ids, dim3(g), dim3(blk), 0, s, n, w.deg, w.nup, w.nbr, w.count64, max_pairs, w.pid,
-                       w.ipairs);
+    hipLaunchKernelGGL(k_pair_ids, dim3(gw), dim3(kNbrBlock), 0, s, n, w.deg, w.nup, w.nbr, w.count64, max_pairs,
+                       w.pid, w.ipairs);
     TN_LAUNCH_CHECK();
   }
   if (public_pairs && max_pairs > 0) {

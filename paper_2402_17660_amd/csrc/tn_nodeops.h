@@ -4,6 +4,9 @@
 
 #include "tn_internal.h"
 #include "tn_device.h"
+#include "tn_mfma.h"
+
+#include <type_traits>
 
 namespace tn {
 
@@ -32,81 +35,10 @@ struct GemmArgs {
 
 constexpr int GBM = 64, GBN = 64, GBK = 16;
 
-template <class T>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
-  __shared__ T As[GBK][GBM + 1];
-  __shared__ T Bs[GBK][GBN + 1];
-  int64_t Mrows = g.M;
-  if (g.Mdev) {
-    const int64_t md = *g.Mdev;
-    if (md < Mrows) Mrows = md;
-  }
-  const int64_t m0 = (int64_t)blockIdx.y * GBM;
-  const int64_t n0 = (int64_t)blockIdx.x * GBN;
-  if (m0 >= Mrows) return;
-  const int z = blockIdx.z;
-  const T *A = g.A + z * g.zoff;
-  const T *B = g.zpart ? g.Bz[coord_part(z)] : g.B;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  T acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = T(0);
-  for (int64_t k0 = 0; k0 < g.K; k0 += GBK) {
-    // A tile: GBM x GBK
-    for (int t = threadIdx.x; t < GBM * GBK; t += 256) {
-      const int mm_ = t / GBK, kk = t % GBK;
-      const int64_t m = m0 + mm_, k = k0 + kk;
-      As[kk][mm_] = (m < Mrows && k < g.K) ? A[m * g.lda + k] : T(0);
-    }
-    for (int t = threadIdx.x; t < GBK * GBN; t += 256) {
-      int kk, nn;
-      if (g.transB) { nn = t / GBK; kk = t % GBK; } else { kk = t / GBN; nn = t % GBN; }
-      const int64_t n = n0 + nn, k = k0 + kk;
-      T v = T(0);
-      if (n < g.N && k < g.K) v = g.transB ? B[n * g.ldb + k] : B[k * g.ldb + n];
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GBK; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
-    }
-    __syncthreads();
-  }
-  T *C = g.C + z * g.zoff;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t m = m0 + ty + 16 * r;
-    if (m >= Mrows) continue;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t n = n0 + tx + 16 * c;
-      if (n >= g.N) continue;
-      T v = acc[r][c];
-      if (g.bias) v += g.bias[n];
-      if (g.Z) g.Z[z * g.zoff + m * g.ldz + n] = v;
-      if (g.act == 1) v = silu(v);
-      if (g.rowscale) v *= g.rowscale[m];
-      if (g.gate) v *= silu_grad(g.gate[z * g.zoff + m * g.ldg + n]);
-      T *dst = C + m * g.ldc + n;
-      if (g.accumulate) *dst += v; else *dst = v;
-    }
-  }
-}
-
-// The same product on matrix cores: 64x64 block tiles, each of the four waves computes a
+// The product runs on the matrix cores: 64x64 block tiles, each of the four waves computes a
 // 32x32 quarter as 2x2 MFMA 16x16x4 tiles (f32 or f64); A and B chunks of 16 along K are
-// staged through LDS.  Lane l of an MFMA holds D[4(l/16)+t][l%16].
+// staged through LDS.  Both instructions take A[l%16][l/16] and B[l/16][l%16] from lane l;
+// element t of the result in lane l is D[4(l/16)+t][l%16] for f32 and D[4t+l/16][l%16] for f64.
 typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
 typedef double mf_f64x4 __attribute__((ext_vector_type(4)));
 template <class T> struct MfmaVec;
@@ -176,7 +108,7 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int64_t m = m0 + wr + rb * 16 + 4 * q + t;
+        const int64_t m = m0 + wr + rb * 16 + (sizeof(T) == 4 ? 4 * q + t : 4 * t + q);
         const int64_t n = n0 + wc + cb * 16 + r16;
         if (m >= Mrows || n >= g.N) continue;
         T v = acc[rb][cb][t];
@@ -221,11 +153,88 @@ inline int linear_bwd(hipStream_t s, const T *dy, int64_t M, int64_t Nout, const
   return gemm(s, g);
 }
 
+// FP32 channel mixing on the matrix cores.  A block stages 16 atoms x 9 coordinates x F
+// channels (contiguous in memory) in LDS with padded rows and computes 64*NB output channels;
+// each of the four waves takes 16*NB of them for the 1 + 3 + 5 coordinate rows of the I, A and S
+// parts, so one weight fragment feeds every coordinate of its part.  Bt[p] is the [F][F] matrix
+// whose row n holds the input weights of output channel n (W_p itself for the forward mixing,
+// its transpose for the adjoint).  Tiles are numbered so that consecutive tiles, which share
+// the same 16 atoms, are dispatched to the same XCD.
+template <int F, int NB>
+__global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float *__restrict__ out, int64_t N,
+                                             const float *__restrict__ B0, const float *__restrict__ B1,
+                                             const float *__restrict__ B2, int accumulate, int ncb,
+                                             int64_t ntiles) {
+  constexpr int LD = F + 4;
+  __shared__ __attribute__((aligned(16))) float sA[16 * 9 * LD];
+  const int64_t per_xcd = (int64_t)gridDim.x / 8;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= ntiles) return;
+  const int64_t a0 = (t / ncb) * 16;
+  const int cblk = (int)(t % ncb);
+  const int64_t navail = N - a0 < 16 ? N - a0 : 16;
+  const float4 *src = reinterpret_cast<const float4 *>(in + a0 * 9 * F);
+  for (int e = threadIdx.x; e < 16 * 9 * (F / 4); e += 256) {
+    const int row = e / (F / 4), c4 = e % (F / 4);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row / 9 < navail) v = src[e];
+    *reinterpret_cast<float4 *>(sA + row * LD + 4 * c4) = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col0 = cblk * 64 * NB + wave * 16 * NB;
+  const int r16 = lane & 15, q = lane >> 4;
+  auto part = [&](auto c0_tag, auto nc_tag, const float *Bt) {
+    constexpr int C0 = decltype(c0_tag)::value, NC = decltype(nc_tag)::value;
+    floatx4 acc[NC][NB];
+    zero_acc_rb<NC, NB>(acc);
+    wave_mm_rows<NC, NB>(sA + C0 * LD, 9 * LD, LD, F, Bt, col0, acc);
+#pragma unroll
+    for (int rb = 0; rb < NC; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int a = 4 * q + e;
+          if (a >= navail) continue;
+          float *dst = out + ((a0 + a) * 9 + C0 + rb) * F + col0 + cb * 16 + r16;
+          if (accumulate) *dst += acc[rb][cb][e]; else *dst = acc[rb][cb][e];
+        }
+  };
+  part(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}, B0);
+  part(std::integral_constant<int, 1>{}, std::integral_constant<int, 3>{}, B1);
+  part(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2);
+}
+
+template <int F, int NB>
+inline int launch_mix(hipStream_t s, const float *in, float *out, int64_t N, const float *const Bt[3],
+                      int accumulate) {
+  constexpr int ncb = F / (64 * NB);
+  const int64_t ntiles = (N + 15) / 16 * ncb;
+  const int64_t grid = (ntiles + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_mix<F, NB>), dim3((unsigned)grid), dim3(256), 0, s, in, out, N, Bt[0], Bt[1], Bt[2],
+                     accumulate, ncb, ntiles);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 // Per-part channel mixing of [N, 9, F] features: out[n,c,:] = W_part(c) in[n,c,:] (forward)
-// or out[n,c,:] (+)= in[n,c,:] W_part(c) (adjoint).
+// or out[n,c,:] (+)= in[n,c,:] W_part(c) (adjoint).  WT holds the transposed matrices (used by
+// the FP32 matrix-core kernel for the adjoint; may be null otherwise).
 template <class T>
-inline int mix(hipStream_t s, const T *in, T *out, int64_t N, int64_t F, const T *W[3], int adjoint,
+inline int mix(hipStream_t s, const T *in, T *out, int64_t N, int64_t F, const T *W[3], const T *WT[3], int adjoint,
                int accumulate) {
+  if (N <= 0) return TN_OK;
+  if constexpr (sizeof(T) == 4) {
+    const T *const *Bt = adjoint ? WT : W;
+    bool ok = Bt != nullptr && aligned16(in) && aligned16(out);
+    for (int q = 0; ok && q < 3; ++q) ok = Bt[q] != nullptr && aligned16(Bt[q]);
+    if (ok && F == 64) return launch_mix<64, 1>(s, in, out, N, Bt, accumulate);
+    if (ok && F == 128) return launch_mix<128, 1>(s, in, out, N, Bt, accumulate);
+    if (ok && F == 256) return launch_mix<256, 2>(s, in, out, N, Bt, accumulate);
+  }
   GemmArgs<T> g;
   g.A = in; g.lda = 9 * F; g.C = out; g.ldc = 9 * F; g.transB = adjoint ? 0 : 1; g.ldb = F;
   g.M = N; g.N = F; g.K = F; g.zoff = F; g.zpart = 1; g.accumulate = accumulate;

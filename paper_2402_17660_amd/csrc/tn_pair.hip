@@ -16,10 +16,9 @@
 // consecutive MFMAs for both operands.
 #include "tn_internal.h"
 #include "tn_device.h"
+#include "tn_mfma.h"
 
 namespace tn {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 32;   // pairs per tile
 constexpr int kPad = 4;     // LDS row padding (floats)
@@ -29,49 +28,11 @@ bool pair_kernels_support(int F, int K, int L, bool bf16) {
   return (F == 64 || F == 128) && k_ok && L >= 0 && L <= kMaxLayers;
 }
 
-__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// acc[rb][cb] += act[32 x Kin] (LDS, row stride ld) * Bt^T, where Bt is [ncol][Kin] in global
-// memory (row stride Kin) and this wave covers columns col0 .. col0 + 16*NB - 1.
-// acc element t of lane l is D[rb*16 + 4*(l/16) + t][col0 + cb*16 + l%16].
+// 32-row tile product (two 16-row MFMA blocks), see wave_mm_rb.
 template <int NB>
 __device__ __forceinline__ void wave_mm(const float *act, int ld, int Kin, const float *__restrict__ Bt, int col0,
                                         floatx4 (&acc)[2][NB]) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15, q = lane >> 4;
-  const float *a0p = act + r * ld + 4 * q;
-  const float *a1p = act + (r + 16) * ld + 4 * q;
-  const float *bp = Bt + (size_t)(col0 + r) * Kin + 4 * q;
-  const size_t bstride = (size_t)16 * Kin;
-  // weight fragments are double-buffered in registers: the loads for chunk k0+16 are in
-  // flight while the MFMAs of chunk k0 run
-  float4 bn[NB];
-#pragma unroll
-  for (int cb = 0; cb < NB; ++cb) bn[cb] = *reinterpret_cast<const float4 *>(bp + cb * bstride);
-  for (int k0 = 0; k0 < Kin; k0 += 16) {
-    float4 b[NB];
-#pragma unroll
-    for (int cb = 0; cb < NB; ++cb) b[cb] = bn[cb];
-    if (k0 + 16 < Kin) {
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb) bn[cb] = *reinterpret_cast<const float4 *>(bp + cb * bstride + k0 + 16);
-    }
-    const float4 a0 = *reinterpret_cast<const float4 *>(a0p + k0);
-    const float4 a1 = *reinterpret_cast<const float4 *>(a1p + k0);
-#pragma unroll
-    for (int cb = 0; cb < NB; ++cb) {
-      acc[0][cb] = mfma4(a0.x, b[cb].x, acc[0][cb]);
-      acc[1][cb] = mfma4(a1.x, b[cb].x, acc[1][cb]);
-      acc[0][cb] = mfma4(a0.y, b[cb].y, acc[0][cb]);
-      acc[1][cb] = mfma4(a1.y, b[cb].y, acc[1][cb]);
-      acc[0][cb] = mfma4(a0.z, b[cb].z, acc[0][cb]);
-      acc[1][cb] = mfma4(a1.z, b[cb].z, acc[1][cb]);
-      acc[0][cb] = mfma4(a0.w, b[cb].w, acc[0][cb]);
-      acc[1][cb] = mfma4(a1.w, b[cb].w, acc[1][cb]);
-    }
-  }
+  wave_mm_rb<2, NB>(act, ld, Kin, Bt, col0, acc);
 }
 
 template <int NB>

@@ -187,7 +187,7 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
   if ((rc = linear_fwd<TA>(s, w.n0, N, F, WA(o.W1), WA(o.b1), 2 * F, w.ea1, w.ez1, 1))) return rc;
   if ((rc = linear_fwd<TA>(s, w.ea1, N, 2 * F, WA(o.W2), WA(o.b2), 3 * F, w.g, w.ez2, 1))) return rc;
   const TA *Wemb[3] = {WA(o.Wmix[0]), WA(o.Wmix[1]), WA(o.Wmix[2])};
-  if ((rc = mix<TA>(s, w.XrA, w.T0, N, F, Wemb, 0, 0))) return rc;
+  if ((rc = mix<TA>(s, w.XrA, w.T0, N, F, Wemb, nullptr, 0, 0))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_gate<TA>, dim3(grid_for(N * 9 * F, bs)), dim3(bs), 0, s, N, (int)F, w.g, w.T0, w.X0A);
     TN_LAUNCH_CHECK();
@@ -201,7 +201,8 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
       TN_LAUNCH_CHECK();
     }
     const T *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
-    if ((rc = mix<T>(s, w.Xb[l], w.Y[l], N, F, W1, 0, 0))) return rc;
+    const T *W1T[3] = {W(lo.W1T[0]), W(lo.W1T[1]), W(lo.W1T[2])};
+    if ((rc = mix<T>(s, w.Xb[l], w.Y[l], N, F, W1, W1T, 0, 0))) return rc;
     if ((rc = linear_fwd<T>(s, w.rbf, MP, K, W(lo.Wa), W(lo.ba), F, w.a1[l], w.z1[l], 1, nullptr, np))) return rc;
     if ((rc = linear_fwd<T>(s, w.a1[l], MP, F, W(lo.Wb), W(lo.bb), 2 * F, w.a2[l], w.z2[l], 1, nullptr, np))) return rc;
     {
@@ -217,7 +218,8 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
       TN_LAUNCH_CHECK();
     }
     const T *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
-    if ((rc = mix<T>(s, w.Pb[l], w.D[l], N, F, W2, 0, 0))) return rc;
+    const T *W2T[3] = {W(lo.W2T[0]), W(lo.W2T[1]), W(lo.W2T[2])};
+    if ((rc = mix<T>(s, w.Pb[l], w.D[l], N, F, W2, W2T, 0, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_residual<T>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xb[l], w.D[l], w.X[l + 1]);
       TN_LAUNCH_CHECK();
@@ -276,12 +278,14 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
   for (int64_t l = L - 1; l >= 0; --l) {
     const LayerOff &lo = o.layer[l];
     const T *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
+    const T *W1T[3] = {W(lo.W1T[0]), W(lo.W1T[1]), W(lo.W1T[2])};
     const T *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
+    const T *W2T[3] = {W(lo.W2T[0]), W(lo.W2T[1]), W(lo.W2T[2])};
     if (N > 0) {
       hipLaunchKernelGGL(k_residual_bwd<T>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.D[l], w.dX, w.dD);
       TN_LAUNCH_CHECK();
     }
-    if ((rc = mix<T>(s, w.dD, w.dPb, N, F, W2, 1, 0))) return rc;
+    if ((rc = mix<T>(s, w.dD, w.dPb, N, F, W2, W2T, 1, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_product_bwd<T>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dPb, w.P[l], w.nP[l], w.Y[l],
                          w.M[l], w.dY, w.dM);
@@ -296,7 +300,7 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
       TN_LAUNCH_CHECK();
     }
     // dXb = dX (identity branch) + mix^T(W1, dY), accumulated in place
-    if ((rc = mix<T>(s, w.dY, w.dX, N, F, W1, 1, 1))) return rc;
+    if ((rc = mix<T>(s, w.dY, w.dX, N, F, W1, W1T, 1, 1))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_normalize_bwd<T>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[l], w.nX[l], w.dX);
       TN_LAUNCH_CHECK();
@@ -317,7 +321,7 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
     hipLaunchKernelGGL(k_gate_bwd<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dXA, w.T0, w.g, w.dg, w.dT0);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = mix<TA>(s, w.dT0, w.dXrA, N, F, Wemb, 1, 0))) return rc;
+  if ((rc = mix<TA>(s, w.dT0, w.dXrA, N, F, Wemb, nullptr, 1, 0))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_mul_silu_grad<TA>, dim3(grid_for(N * 3 * F, bs)), dim3(bs), 0, s, N * 3 * F, w.dg, w.ez2,
                        w.dez2);
