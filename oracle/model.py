@@ -49,7 +49,7 @@ import torch
 from torch.utils.checkpoint import checkpoint
 
 from .blob import read_blob
-from .neighbors import neighbor_pairs
+from .neighbors import lattice, neighbor_pairs
 
 DT = torch.float64
 _EYE = torch.eye(3, dtype=DT)
@@ -205,8 +205,11 @@ class TensorNetOracle:
 
         v = pos[send] - pos[recv]
         if box is not None:
-            lengths = torch.as_tensor(np.diag(np.asarray(box, dtype=np.float64).reshape(3, 3)).copy(), dtype=DT)
-            v = v - lengths * torch.round(v / lengths)       # minimum image; round = half to even
+            # minimum image in the reduced cell: along c, then b, then a (round = half to even)
+            H = torch.as_tensor(lattice(box), dtype=DT)
+            v = v - torch.round(v[:, 2:3] / H[2, 2]) * H[2]
+            v = v - torch.round(v[:, 1:2] / H[1, 1]) * H[1]
+            v = v - torch.round(v[:, 0:1] / H[0, 0]) * H[0]
         d = torch.sqrt((v * v).sum(-1))
         vhat = v / d[:, None]
         phi = cosine_cutoff(d, r_c)

@@ -307,3 +307,50 @@ def test_p15_lattice_shift_invariance():
     E2, F2 = o.energy_forces(pos + 10.0 * k, z, np.zeros(100, np.int32), box, 1)
     assert abs(E2[0] - E[0]) <= 1e-12 * abs(E[0])
     assert np.allclose(F2, Fv, atol=1e-12 * np.abs(Fv).max())
+
+
+# ---------------------------------------------------------------- triclinic cells
+from tests.util import random_in_cell, random_triclinic_cell  # noqa: E402
+
+
+def test_p14_supercell_triclinic():
+    r_c = 3.0
+    o = TensorNetOracle(small_blob(F=16, K=8, L=2, seed=51, r_c=r_c))
+    H = random_triclinic_cell(52, r_c, (2.1, 2.6))
+    pos, z = random_in_cell(30, 52, H)
+    E, Fv = o.energy_forces(pos, z, np.zeros(30, np.int32), H, 1)
+    shifts = np.array([(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)], dtype=np.float64) @ H
+    pos8 = np.concatenate([pos + s for s in shifts])
+    z8 = np.tile(z, 8)
+    E8, F8 = o.energy_forces(pos8, z8, np.zeros(240, np.int32), 2 * H, 1)
+    assert abs(E8[0] - 8 * E[0]) <= 1e-11 * abs(8 * E[0])
+    assert np.allclose(F8, np.tile(Fv, (8, 1)), atol=1e-11 * np.abs(Fv).max())
+
+
+def test_p15_lattice_shift_invariance_triclinic():
+    o = TensorNetOracle(small_blob(F=16, K=8, L=2, seed=53))
+    H = random_triclinic_cell(54, 4.5)
+    pos, z = random_in_cell(80, 54, H)
+    E, Fv = o.energy_forces(pos, z, np.zeros(80, np.int32), H, 1)
+    k = np.random.default_rng(55).integers(-2, 3, size=pos.shape)
+    E2, F2 = o.energy_forces(pos + k @ H, z, np.zeros(80, np.int32), H, 1)
+    assert abs(E2[0] - E[0]) <= 1e-12 * abs(E[0])
+    assert np.allclose(F2, Fv, atol=1e-12 * np.abs(Fv).max())
+
+
+def test_p11_finite_differences_triclinic():
+    o = TensorNetOracle(small_blob(F=16, K=8, L=2, seed=56))
+    H = random_triclinic_cell(57, 4.5)
+    pos, z = random_in_cell(40, 57, H)
+    batch = np.zeros(40, np.int32)
+    _, Fv = o.energy_forces(pos, z, batch, H, 1)
+    pairs = o.pairs(pos, batch, H)
+    h = 1e-5
+    rng = np.random.default_rng(58)
+    for a in rng.choice(40, size=4, replace=False):
+        for ax in range(3):
+            p1, p2 = pos.copy(), pos.copy()
+            p1[a, ax] += h
+            p2[a, ax] -= h
+            fd = -(o.energy(p1, z, batch, H, 1, pairs=pairs)[0] - o.energy(p2, z, batch, H, 1, pairs=pairs)[0]) / (2 * h)
+            assert abs(fd - Fv[a, ax]) <= 1e-7 * max(1.0, np.abs(Fv).max())

@@ -133,3 +133,77 @@ def test_rint_half_to_even():
     got = brute_force_pairs(pos, np.zeros(4, np.int32), np.diag([box_len] * 3), 5.01)
     # (1,3) are 10 apart = one full box: distance 0 after the image shift
     assert {tuple(p) for p in got} == {(0, 1), (0, 2), (0, 3), (1, 3)}
+
+
+# ---------------------------------------------------------------- triclinic cells
+from oracle.neighbors import lattice, nearest_image_d2  # noqa: E402
+from tests.util import random_in_cell, random_triclinic_cell  # noqa: E402
+
+
+def enumeration_pairs_cell(pos, batch, H, cutoff):
+    """Independent definition for any cell: nearest image by enumerating lattice translations."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = len(pos)
+    i, j = np.triu_indices(n, 1)
+    keep = batch[i] == batch[j]
+    i, j = i[keep], j[keep]
+    d2 = nearest_image_d2(pos[i], pos[j], H, reach=3)
+    m = d2 < cutoff * cutoff
+    return np.stack([i[m], j[m]], 1).astype(np.int64), d2
+
+
+@pytest.mark.parametrize("seed,n", [(31, 60), (32, 120), (33, 200), (34, 300)])
+def test_p1_triclinic_sequential_image_is_nearest(seed, n):
+    cutoff = 4.5
+    H = random_triclinic_cell(seed, cutoff)
+    pos, _ = random_in_cell(n, seed, H)
+    rng = np.random.default_rng(seed)
+    # unwrapped input: shift atoms by random lattice vectors
+    pos = (pos + rng.integers(-2, 3, size=(n, 3)) @ H).astype(np.float32)
+    batch = np.zeros(n, dtype=np.int32)
+    ref, _ = enumeration_pairs_cell(pos, batch, H, cutoff)
+    got = brute_force_pairs(pos, batch, H, cutoff)
+    assert len(ref) > 0
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("seed,n,scale", [(41, 60, (2.0, 2.3)), (42, 150, (2.5, 3.5)), (43, 400, (3.0, 4.5)),
+                                          (44, 1200, (5.0, 6.0))])
+def test_p1_triclinic_cell_list_matches_brute_force(seed, n, scale):
+    cutoff = 4.5
+    H = random_triclinic_cell(seed, cutoff, scale)
+    pos, _ = random_in_cell(n, seed, H, dmin=0.5)
+    pos = pos.astype(np.float32)
+    batch = np.zeros(n, dtype=np.int32)
+    a = brute_force_pairs(pos, batch, H, cutoff)
+    b = cell_list_pairs(pos, batch, H, cutoff)
+    assert len(a) > 0
+    assert np.array_equal(a, b)
+
+
+def test_p2_triclinic_lattice_shift():
+    cutoff = 4.5
+    H = random_triclinic_cell(45, cutoff)
+    pos, _ = random_in_cell(150, 45, H)
+    batch = np.zeros(150, dtype=np.int32)
+    a = brute_force_pairs(pos, batch, H, cutoff)
+    k = np.random.default_rng(46).integers(-1, 2, size=(150, 3))
+    b = brute_force_pairs(pos + k @ H, batch, H, cutoff)
+    assert np.array_equal(a, b)
+
+
+def test_triclinic_cell_validation():
+    with pytest.raises(ValueError):
+        lattice(np.array([[10.0, 1.0, 0.0], [0.0, 10.0, 0.0], [0.0, 0.0, 10.0]]))   # not lower triangular
+    with pytest.raises(ValueError):
+        lattice(np.array([[10.0, 0.0, 0.0], [6.0, 10.0, 0.0], [0.0, 0.0, 10.0]]))   # not reduced
+    H = lattice(np.array([[10.0, 0.0, 0.0], [5.0, 10.0, 0.0], [-5.0, 5.0, 10.0]]))
+    assert H.shape == (3, 3)
+
+
+def test_zero_tilt_cell_is_the_rectangular_box():
+    pos, _, box = random_box(200, 47, 13.0)
+    batch = np.zeros(200, dtype=np.int32)
+    a = brute_force_pairs(pos.astype(np.float32), batch, box, 4.5)
+    ref = image_enumeration_pairs(pos.astype(np.float32), batch, 13.0, 4.5)
+    assert np.array_equal(a, ref)

@@ -51,3 +51,32 @@ def rel_rms(Fv, F_ref):
     Fv = np.asarray(Fv, dtype=np.float64)
     F_ref = np.asarray(F_ref, dtype=np.float64)
     return float(np.linalg.norm(Fv - F_ref) / np.linalg.norm(F_ref))
+
+
+def random_triclinic_cell(seed, cutoff, scale=(2.1, 3.2)):
+    """A reduced triclinic cell (rows a, b, c; lower triangular) with random tilts and every
+    height between scale[0] and scale[1] times the cutoff (scaled up if a draw is too flat)."""
+    from oracle.neighbors import cell_heights
+    rng = np.random.default_rng(seed)
+    ax, by, cz = cutoff * rng.uniform(scale[0], scale[1], size=3)
+    H = np.array([[ax, 0.0, 0.0],
+                  [rng.uniform(-0.5, 0.5) * ax, by, 0.0],
+                  [rng.uniform(-0.5, 0.5) * ax, rng.uniform(-0.5, 0.5) * by, cz]])
+    h = cell_heights(H)
+    if h.min() < 2.0 * cutoff:
+        H = H * (2.0 * cutoff / h.min()) * 1.01
+    return H
+
+
+def random_in_cell(n, seed, H, dmin=0.9):
+    """n points in the cell H (rows), no two closer than dmin under the nearest image."""
+    from oracle.neighbors import nearest_image_d2
+    rng = np.random.default_rng(seed)
+    pts = np.zeros((0, 3))
+    while len(pts) < n:
+        p = rng.uniform(0.0, 1.0, size=(1, 3)) @ H
+        if len(pts) and nearest_image_d2(np.repeat(p, len(pts), 0), pts, H, reach=1).min() < dmin * dmin:
+            continue
+        pts = np.concatenate([pts, p])
+    z = SPECIES[rng.integers(0, 4, size=n)].astype(np.int32)
+    return pts, z
