@@ -75,10 +75,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-atoms", type=int, default=3000)
     ap.add_argument("--budget", type=float, default=1.05, help="max_pairs = budget * true pair count")
-    ap.add_argument("--extra", default="batch,md,table2",
+    ap.add_argument("--extra", default="batch,md,table2,nbr",
                     help="extra workloads: batch (512 molecules, captured), md (100 captured velocity-Verlet steps, "
-                         "100k atoms), table2 (the paper's Table 2 sizes, captured); 'none' = none")
+                         "100k atoms), table2 (the paper's Table 2 sizes and 0/1/2 layers, captured), nbr "
+                         "(neighbour-search study on random clouds); 'none' = none")
     ap.add_argument("--md-steps", type=int, default=100)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after the timed variants, copy this many MiB device-to-device once (a reference "
+                         "dispatch of known size for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); run it with --gpus 1",
@@ -163,6 +167,16 @@ def main():
             f"F err {f_err:.2e}, " + ", ".join(f"{k['name']} {k['avg_ms']:.3f} ms/launch "
                                                f"({k['achieved_tflops'] or 0:.1f} TFLOP/s)" for k in kernels))
         results.append(res)
+
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written in one dispatch")
+        del src, dst
 
     avail = [r for r in results if r.get("available")]
     head = next((r for r in avail if r["path"] == "fused" and r["precision"] == "fp32"), None) or avail[0]
@@ -297,8 +311,24 @@ TABLE2 = [("alanine dipeptide", 22, (172.80, 84.71, 56.47)), ("testosterone", 49
           ("factor IX", 5807, (2.33, 0.70, 0.42))]
 
 
+def _time_replays(g, reps):
+    import torch
+    for _ in range(10):
+        g.replay()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        g.replay()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
 def extra_table2(args, dev):
-    """Synthetic molecules of the Table 2 sizes (random H/C/N/O, 0.1 atoms/A^3), captured graphs, FP32 fused."""
+    """Synthetic molecules of the Table 2 sizes (random H/C/N/O, 0.1 atoms/A^3), 0/1/2 interaction layers,
+    captured graphs, FP32 fused; plus the cost of the static pair budget (32 N, as in the paper) against an
+    exact one, in workspace bytes and in time."""
     import torch
     from paper_2402_17660_amd import TensorNet, capture
     from synth import make_weights, single_molecule, write_blob
@@ -310,31 +340,87 @@ def extra_table2(args, dev):
         batch = torch.tensor(mol["batch"], device=dev)
         for L in (0, 1, 2):
             model = TensorNet(write_blob(make_weights(128, 32, L, 100, seed=8000 + L), 128, 32, L, 100, 4.5), dev)
-            g, E, Fo, n_pairs, status = capture(model, pos, z, batch, 1, max_pairs=32 * n, precision="fp32")
-            for _ in range(10):
-                g.replay()
-            torch.cuda.synchronize()
             reps = 50 if n < 1000 else 20
-            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            start.record()
-            for _ in range(reps):
-                g.replay()
-            stop.record()
-            torch.cuda.synchronize()
-            ms = start.elapsed_time(stop) / reps
-            msteps_day = 86400.0 / (ms * 1e-3) / 1e6
-            rows.append(dict(molecule=name, atoms=n, layers=L, ms_per_step=ms, msteps_per_day=msteps_day,
-                             atom_steps_per_s=n / (ms * 1e-3), status=int(status.item()),
-                             paper_graph_msteps_per_day_rtx4090=paper_g[L]))
-            log(f"table2 {name} ({n} atoms) {L}L: {ms * 1e3:.1f} us/step, {msteps_day:.2f} Msteps/day "
-                f"(paper RTX 4090 Graph: {paper_g[L]})")
+            g, E, Fo, n_pairs, status = capture(model, pos, z, batch, 1, max_pairs=32 * n, precision="fp32")
+            ms = _time_replays(g, reps)
+            st = int(status.item())
+            np_true = int(n_pairs.item())
             g.close()
+            g, E, Fo, n_pairs, status = capture(model, pos, z, batch, 1, max_pairs=max(np_true, 1),
+                                                precision="fp32")
+            ms_exact = _time_replays(g, reps)
+            st |= int(status.item())
+            g.close()
+            ws_static = model.workspace_bytes(n, 1, 32 * n)
+            ws_exact = model.workspace_bytes(n, 1, max(np_true, 1))
+            msteps_day = 86400.0 / (ms * 1e-3) / 1e6
+            rows.append(dict(molecule=name, atoms=n, layers=L, pairs=np_true, ms_per_step=ms,
+                             msteps_per_day=msteps_day, atom_steps_per_s=n / (ms * 1e-3), status=st,
+                             ms_per_step_exact_budget=ms_exact, workspace_mb_static=ws_static / 2**20,
+                             workspace_mb_exact=ws_exact / 2**20,
+                             paper_graph_msteps_per_day_rtx4090=paper_g[L]))
+            log(f"table2 {name} ({n} atoms, {np_true} pairs) {L}L: {ms * 1e3:.1f} us/step "
+                f"({ms_exact * 1e3:.1f} with an exact pair budget), {msteps_day:.2f} Msteps/day "
+                f"(paper RTX 4090 Graph: {paper_g[L]}); workspace {ws_static / 2**20:.1f} MB static vs "
+                f"{ws_exact / 2**20:.1f} MB exact")
+            model.close()
     return dict(workload="synthetic stand-ins for the Table 2 molecules (sizes 22-5807 atoms), cutoff 4.5 A, "
-                         "hidden 128, 32 RBF, max_pairs 32 N, fused FP32, one captured HIP graph per step",
+                         "hidden 128, 32 RBF, 0/1/2 layers, max_pairs 32 N (and the exact pair count), fused FP32, "
+                         "one captured HIP graph per step",
                 rows=rows)
 
 
-EXTRA = {"batch": extra_batch, "md": extra_md, "table2": extra_table2}
+def extra_nbr(args, dev):
+    """Neighbour-search study, cell list vs brute force, on uniform random clouds with 64 neighbours per
+    point (cutoff 5 A, periodic cube): an N sweep at 1, 2 and 64 systems, and 32768 points split into
+    1..1024 systems.  Times eager calls (all launches of one search) with preallocated outputs."""
+    import torch
+    from paper_2402_17660_amd import Workspace, build_neighbors
+    from synth import random_cloud
+
+    def time_search(c, method, reps):
+        n = len(c["pos"])
+        pos = torch.tensor(c["pos"], device=dev)
+        batch = torch.tensor(c["batch"], device=dev)
+        mp = 40 * n
+        ws = Workspace(dev)
+        out = (torch.empty((2, mp), dtype=torch.int32, device=dev), torch.zeros(1, dtype=torch.int64, device=dev),
+               torch.zeros(1, dtype=torch.int32, device=dev))
+        call = lambda: build_neighbors(pos, batch, 5.0, mp, box=c["box"], check=False, ws=ws, method=method,
+                                       out=out)
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            call()
+        stop.record()
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / reps, int(out[1].item()), int(out[2].item())
+
+    def row(n, nb, seed):
+        c = random_cloud(n, nb, seed)
+        r = dict(points=n, systems=nb)
+        for method in ("cell", "brute"):
+            if method == "brute" and n // nb > 65536:
+                continue
+            ms, pairs, st = time_search(c, method, 20)
+            r[f"{method}_ms"] = ms
+            r[f"{method}_pairs"] = pairs
+            r[f"{method}_status"] = st
+        log(f"nbr {n} points / {nb} systems: cell {r['cell_ms']:.3f} ms"
+            + (f", brute {r['brute_ms']:.3f} ms" if "brute_ms" in r else "") + f", {r['cell_pairs']} pairs")
+        return r
+
+    sweep = [row(1 << k, nb, 9000 + 100 * nb + k) for nb in (1, 2, 64) for k in range(8, 21) if (1 << k) >= 4 * nb]
+    split = [row(32768, 1 << b, 9500 + b) for b in range(0, 11)]
+    return dict(workload="uniform random clouds, 64 neighbours per point on average within 5 A, periodic cube; "
+                         "points split into systems by index range; cell list vs brute force (brute force up to "
+                         "65536 points per system)", sweep=sweep, batch_split=split)
+
+
+EXTRA = {"batch": extra_batch, "md": extra_md, "table2": extra_table2, "nbr": extra_nbr}
 
 
 if __name__ == "__main__":

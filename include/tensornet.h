@@ -2,8 +2,8 @@
  * tensornet.h - C ABI of the MI355X TensorNet energy-and-forces library.
  *
  * One TensorNet evaluation (TorchMD-Net 2.0, arXiv 2402.17660): the neighbour
- * search of Sec. 2.5.1 (cell list with rectangular periodic boundaries, or a
- * brute-force search inside each isolated system), the TensorNet network of
+ * search of Sec. 2.5.1 (cell list with rectangular or triclinic periodic
+ * boundaries, or a brute-force search inside each system), the TensorNet network of
  * Sec. 2.1.1 with the hyper-parameters of Sec. 2.4, and forces as the negative
  * position gradient of the per-system energy (Sec. 2, model composition).
  *
@@ -22,9 +22,14 @@
  *     read it after your own synchronisation.  Outputs are undefined whenever
  *     the return value or *status is non-zero.
  *   - Positions are angstrom, energies eV, forces eV/angstrom.  `box` is a
- *     row-major 3x3 of lattice vectors; only rectangular boxes (zero
- *     off-diagonal entries) are accepted, each side at least twice the cutoff
- *     (the minimum image is then unique).  box == NULL means isolated systems.
+ *     row-major 3x3 whose rows are the lattice vectors a, b, c of a periodic
+ *     cell (Sec. 2.5.1: rectangular and triclinic).  It must be lower
+ *     triangular (a = (a_x,0,0), b = (b_x,b_y,0), c = (c_x,c_y,c_z), positive
+ *     diagonal) and reduced (|b_x|, |c_x| <= a_x/2, |c_y| <= b_y/2), else
+ *     TN_E_ARG; every cell height (distance between opposite faces) must be
+ *     at least twice the cutoff, else TN_E_BOX, so the minimum image is
+ *     unique.  A rectangular box is the case of zero tilts.  box == NULL
+ *     means isolated systems.
  *   - `batch[i]` is the system index of atom i.  It must be sorted ascending
  *     (systems contiguous) with values in [0, n_systems); violations set
  *     TN_STATUS_BATCH.  Systems never interact (Sec. 2.5.1).
@@ -43,10 +48,10 @@ typedef struct tn_model tn_model;
 
 typedef enum {
   TN_OK = 0,
-  TN_E_ARG = -1,        /* invalid argument (null pointer, size, enum, non-rectangular box) */
+  TN_E_ARG = -1,        /* invalid argument (null pointer, size, enum, box not lower triangular/reduced) */
   TN_E_BLOB = -2,       /* weight blob: bad magic, version, size or hyper-parameters */
   TN_E_HIP = -3,        /* a HIP runtime call or kernel launch failed */
-  TN_E_BOX = -4,        /* a box side is shorter than twice the cutoff */
+  TN_E_BOX = -4,        /* a cell height is less than twice the cutoff */
   TN_E_WORKSPACE = -5,  /* ws_bytes smaller than the workspace query returned */
   TN_E_UNSUPPORTED = -6 /* valid request this build does not implement (e.g. precision/path pair) */
 } tn_status;
@@ -81,10 +86,13 @@ int tn_model_info(const tn_model *m, int32_t *F, int32_t *K, int32_t *L, int32_t
 /* ------------------------------------------------------ neighbour search ---
  * The unordered pair set {(i,j) : i<j, batch_i == batch_j, d_ij^2 < cutoff^2}
  * (Sec. 2.5.1), d by the minimum image when `box` is given.  The decision is
- * taken in FP64 on the positions promoted to FP64:
- *   v_a = D_a - L_a * rint(D_a / L_a),  D_a = x_ja - x_ia  (box only)
+ * taken in FP64 on the positions promoted to FP64, D = r_j - r_i reduced
+ * along c, then b, then a (box only):
+ *   v = D - c rint(D_z / c_z);  v -= b rint(v_y / b_y);  v -= a rint(v_x / a_x)
  *   d^2 = (v_x*v_x + v_y*v_y) + v_z*v_z  (each product rounded, no FMA)
- * box != NULL: one cell list over all systems (cells of side >= cutoff).
+ * (for a rectangular box, v_a = D_a - L_a rint(D_a / L_a)).
+ * box != NULL: one cell list over all systems (cells binned in fractional
+ * coordinates, at least as high as the cutoff).
  * box == NULL: brute force over the atoms of each system.
  * Output: pairs[0][p] < pairs[1][p] (int32, layout [2, max_pairs]) for
  * p < *n_pairs, in a deterministic order (by (i, j) for isolated systems, by
@@ -96,6 +104,24 @@ size_t tn_neighbor_workspace_bytes(int64_t n_atoms, int64_t max_pairs, const dou
 int tn_build_neighbors(void *stream, int64_t n_atoms, const void *pos, int pos_f64, const int32_t *batch,
                        const double *box, double cutoff, int64_t max_pairs, int32_t *pairs, int64_t *n_pairs,
                        int32_t *status, void *ws, size_t ws_bytes);
+
+/* The same search with an explicit candidate strategy (Sec. 2.5.1 offers a
+ * brute-force O(N^2) search for small inputs and a cell list for large ones):
+ *   TN_NBR_AUTO   cell list in a periodic box, brute force for isolated systems
+ *                 (what tn_build_neighbors and the model calls use)
+ *   TN_NBR_CELL   cell list; needs a box (TN_E_UNSUPPORTED without one)
+ *   TN_NBR_BRUTE  every atom of the same system is a candidate (system ranges
+ *                 from the sorted batch vector); minimum image in a box
+ * The pair set is the same for every strategy; the pair order is deterministic
+ * per strategy (cell order with the cell list, by (i, j) with the brute force).
+ * tn_neighbor_workspace_bytes covers every strategy.  Other arguments, outputs
+ * and errors as for tn_build_neighbors; an unknown method is TN_E_ARG. */
+#define TN_NBR_AUTO 0
+#define TN_NBR_CELL 1
+#define TN_NBR_BRUTE 2
+int tn_build_neighbors_method(void *stream, int64_t n_atoms, const void *pos, int pos_f64, const int32_t *batch,
+                              const double *box, double cutoff, int64_t max_pairs, int32_t *pairs,
+                              int64_t *n_pairs, int32_t *status, void *ws, size_t ws_bytes, int method);
 
 /* -------------------------------------------------------------- energies ---
  * tn_workspace_bytes returns the ws size needed by tn_energy (want_forces 0)
@@ -136,7 +162,8 @@ int tn_energy_forces(const tn_model *m, void *stream, int64_t n_atoms, int64_t n
  *   dt_fs     time step (fs)
  *   n_steps   0: the graph is one energy+forces evaluation (forces written to
  *             `forces`); >= 1: n_steps velocity-Verlet steps, each
- *               v += dt/2 * F/m;  x += dt * v;  x wrapped into [0, L) (box only);
+ *               v += dt/2 * F/m;  x += dt * v;  x wrapped into the cell
+ *               (fractional coordinates in [0, 1); box only);
  *               neighbour search + energy + forces;  v += dt/2 * F/m
  *             with F/m in eV/(angstrom amu) converted to angstrom/fs^2.  On entry
  *             `forces` must hold the forces of the current positions (call

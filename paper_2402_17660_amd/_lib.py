@@ -13,6 +13,7 @@ TN_E_ARG, TN_E_BLOB, TN_E_HIP, TN_E_BOX, TN_E_WORKSPACE, TN_E_UNSUPPORTED = -1, 
 TN_STATUS_OVERFLOW, TN_STATUS_BATCH, TN_STATUS_Z, TN_STATUS_NONFINITE = 1, 2, 4, 8
 TN_FP32, TN_BF16, TN_FP64 = 0, 1, 2
 TN_FUSED, TN_PLAIN = 0, 1
+TN_NBR_AUTO, TN_NBR_CELL, TN_NBR_BRUTE = 0, 1, 2
 
 _c = ctypes
 _vp, _i32, _i64, _sz, _dbl = _c.c_void_p, _c.c_int, _c.c_int64, _c.c_size_t, _c.c_double
@@ -26,6 +27,7 @@ PROTOTYPES = {
                              _c.POINTER(_c.c_int32), _c.POINTER(_dbl), _c.POINTER(_dbl)]),
     "tn_neighbor_workspace_bytes": (_sz, [_i64, _i64, _vp, _dbl]),
     "tn_build_neighbors": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp, _dbl, _i64, _vp, _vp, _vp, _vp, _sz]),
+    "tn_build_neighbors_method": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp, _dbl, _i64, _vp, _vp, _vp, _vp, _sz, _i32]),
     "tn_workspace_bytes": (_sz, [_vp, _i64, _i64, _i64, _vp, _i32, _i32, _i32]),
     "tn_energy": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz]),
     "tn_energy_forces": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp,

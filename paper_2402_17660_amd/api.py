@@ -70,9 +70,13 @@ class Workspace:
         return self.buf
 
 
+_NBR = {"auto": L.TN_NBR_AUTO, "cell": L.TN_NBR_CELL, "brute": L.TN_NBR_BRUTE}
+
+
 def build_neighbors(pos: torch.Tensor, batch: torch.Tensor, cutoff: float, max_pairs: int, box=None,
-                    check: bool = True, ws: Workspace | None = None):
-    """Unordered neighbour pairs (tn_build_neighbors): returns (pairs [2, max_pairs] int32, n_pairs, status)."""
+                    check: bool = True, ws: Workspace | None = None, method: str = "auto", out=None):
+    """Unordered neighbour pairs (tn_build_neighbors_method): returns (pairs [2, max_pairs] int32, n_pairs,
+    status).  method: "auto", "cell" or "brute"; out: optional (pairs, n_pairs, status) tensors to fill."""
     device = pos.device
     pos_f64 = pos.dtype == torch.float64
     _require_device(pos, "pos", torch.float64 if pos_f64 else torch.float32, device)
@@ -84,12 +88,16 @@ def build_neighbors(pos: torch.Tensor, batch: torch.Tensor, cutoff: float, max_p
         raise TensorNetError("invalid neighbour-search request (box or sizes)")
     ws = ws or Workspace(device)
     buf = ws.get(nbytes)
-    pairs = torch.empty((2, max_pairs), dtype=torch.int32, device=device)
-    n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
-    status = torch.zeros(1, dtype=torch.int32, device=device)
-    rc = L.lib().tn_build_neighbors(_stream(device), n, _ptr(pos), int(pos_f64), _ptr(batch), boxp, float(cutoff),
-                                    max_pairs, _ptr(pairs), _ptr(n_pairs), _ptr(status), _ptr(buf), buf.numel())
-    _check(rc, "tn_build_neighbors")
+    if out is None:
+        pairs = torch.empty((2, max_pairs), dtype=torch.int32, device=device)
+        n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
+        status = torch.zeros(1, dtype=torch.int32, device=device)
+    else:
+        pairs, n_pairs, status = out
+    rc = L.lib().tn_build_neighbors_method(_stream(device), n, _ptr(pos), int(pos_f64), _ptr(batch), boxp,
+                                           float(cutoff), max_pairs, _ptr(pairs), _ptr(n_pairs), _ptr(status),
+                                           _ptr(buf), buf.numel(), _NBR[method])
+    _check(rc, "tn_build_neighbors_method")
     if check:
         word = int(status.item())
         if word & ~L.TN_STATUS_OVERFLOW:

@@ -233,7 +233,7 @@ const char *tn_status_string(int status) {
     case TN_E_ARG: return "invalid argument";
     case TN_E_BLOB: return "invalid weight blob";
     case TN_E_HIP: return "HIP runtime error";
-    case TN_E_BOX: return "box side shorter than twice the cutoff";
+    case TN_E_BOX: return "box: a cell height is less than twice the cutoff";
     case TN_E_WORKSPACE: return "workspace too small";
     case TN_E_UNSUPPORTED: return "unsupported precision/path combination";
     default: return "unknown status";
@@ -307,11 +307,21 @@ size_t tn_neighbor_workspace_bytes(int64_t n_atoms, int64_t max_pairs, const dou
 int tn_build_neighbors(void *stream, int64_t n_atoms, const void *pos, int pos_f64, const int32_t *batch,
                        const double *box, double cutoff, int64_t max_pairs, int32_t *pairs, int64_t *n_pairs,
                        int32_t *status, void *ws, size_t ws_bytes) {
+  return tn_build_neighbors_method(stream, n_atoms, pos, pos_f64, batch, box, cutoff, max_pairs, pairs, n_pairs,
+                                   status, ws, ws_bytes, TN_NBR_AUTO);
+}
+
+int tn_build_neighbors_method(void *stream, int64_t n_atoms, const void *pos, int pos_f64, const int32_t *batch,
+                              const double *box, double cutoff, int64_t max_pairs, int32_t *pairs,
+                              int64_t *n_pairs, int32_t *status, void *ws, size_t ws_bytes, int method) {
   if (n_atoms < 0 || max_pairs < 0 || max_pairs > (int64_t(1) << 30) || n_atoms >= (int64_t(1) << 31)) return TN_E_ARG;
   if (!n_pairs || !status || (n_atoms > 0 && (!pos || !batch)) || (max_pairs > 0 && !pairs)) return TN_E_ARG;
+  if (method != TN_NBR_AUTO && method != TN_NBR_CELL && method != TN_NBR_BRUTE) return TN_E_ARG;
   BoxInfo bi;
   int rc = box_info(box, cutoff, &bi);
   if (rc) return rc;
+  if (method == TN_NBR_CELL && !bi.periodic) return TN_E_UNSUPPORTED;
+  if (method == TN_NBR_BRUTE) bi.cells = 0;
   WsPlan p(ws);
   NbrWs w;
   plan_neighbors(p, n_atoms, max_pairs, bi, &w);

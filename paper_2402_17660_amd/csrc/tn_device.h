@@ -18,6 +18,39 @@ constexpr int kCoord = 9;
 
 __host__ __device__ inline int coord_part(int c) { return c == 0 ? 0 : (c < 4 ? 1 : 2); }
 
+// A periodic cell given by its rows a = (ax, 0, 0), b = (bx, by, 0), c = (cx, cy, cz), lower
+// triangular and reduced (|bx|, |cx| <= ax/2, |cy| <= by/2); a rectangular box has zero tilts.
+struct Lattice {
+  int periodic = 0;
+  double ax = 0, bx = 0, by = 0, cx = 0, cy = 0, cz = 0;
+};
+
+// Minimum image of a displacement d = r_j - r_i (Sec. 2.5.1, rectangular and triclinic
+// boundaries): reduce along c, then b, then a.  In a reduced cell whose heights are at least
+// twice the distance of interest this is the nearest image.  Every product is rounded before
+// its subtraction (no contraction), so the neighbour predicate is reproducible bit for bit.
+__host__ __device__ inline void min_image(const Lattice &L, double &dx, double &dy, double &dz) {
+#pragma clang fp contract(off)
+  if (!L.periodic) return;
+  const double kz = rint(dz / L.cz);
+  dx = dx - L.cx * kz;
+  dy = dy - L.cy * kz;
+  dz = dz - L.cz * kz;
+  const double ky = rint(dy / L.by);
+  dx = dx - L.bx * ky;
+  dy = dy - L.by * ky;
+  const double kx = rint(dx / L.ax);
+  dx = dx - L.ax * kx;
+}
+
+// Fractional coordinates s = r H^-1 (H has the rows a, b, c).
+__host__ __device__ inline void fractional(const Lattice &L, double x, double y, double z, double &s0, double &s1,
+                                           double &s2) {
+  s2 = z / L.cz;
+  s1 = (y - L.cy * s2) / L.by;
+  s0 = (x - L.cx * s2 - L.bx * s1) / L.ax;
+}
+
 __device__ inline float dexp(float x) { return expf(x); }
 __device__ inline double dexp(double x) { return exp(x); }
 __device__ inline float dsqrt(float x) { return sqrtf(x); }
@@ -145,6 +178,41 @@ template <class T> __device__ inline void s0_dot_grad(const T w[5], T ux, T uy, 
   g[0] = T(2) * w[0] * ux + w[2] * uy + w[3] * uz;
   g[1] = T(2) * w[1] * uy + w[2] * ux + w[4] * uz;
   g[2] = w[3] * ux + w[4] * uy;
+}
+
+// V consecutive floats through one vector access (V = 1, 2 or 4; p aligned to 4V bytes).
+template <int V>
+__device__ __forceinline__ void ldv(const float *p, float (&o)[V]) {
+  if constexpr (V == 4) {
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+  } else if constexpr (V == 2) {
+    const float2 t = *reinterpret_cast<const float2 *>(p);
+    o[0] = t.x; o[1] = t.y;
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = p[v];
+  }
+}
+template <int V>
+__device__ __forceinline__ void stv(float *p, const float (&o)[V]) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<float2 *>(p) = make_float2(o[0], o[1]);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) p[v] = o[v];
+  }
+}
+
+// Workgroups are dispatched round-robin over the eight XCDs, each with its own L2.  This
+// renumbering gives every XCD one contiguous range of logical blocks, so that blocks working
+// on neighbouring atoms or pairs (both are kept in spatial cell order) share an L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  const int64_t q = G / 8, r = G % 8, x = b % 8;
+  return x * q + (x < r ? x : r) + b / 8;
 }
 
 // Flag a bit in the device status word.

@@ -127,8 +127,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     pf.max_pairs = MP;
     pf.n_pairs = np;
     pf.pos = pos;
-    pf.periodic = pb.box.periodic;
-    for (int a = 0; a < 3; ++a) pf.box[a] = pb.box.len[a];
+    pf.lat = pb.box.lat;
     pf.r_c = m->r_c;
     pf.r_lo = m->r_lo;
     pf.alpha = m->alpha;
@@ -184,11 +183,9 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
 
   // ---- embedding node stage (FP64)
   const unsigned gNF = grid_for(N * F, bs);
-  if (N > 0) {
-    hipLaunchKernelGGL(k_embed_gather<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, zz,
-                       m->max_z, W(o.U), W(o.V), w.geo, w.phi, w.f0, w.Xr);
-    TN_LAUNCH_CHECK();
-  }
+  if ((rc = embed_gather_w(s, F, N, rowptr, nbr, pid, np, MP, zz, m->max_z, W(o.U), W(o.V), w.geo, w.phi, w.f0,
+                           w.Xr)))
+    return rc;
   if ((rc = convert<float, TA>(s, w.Xr, w.XrA, N * 9 * F))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_node_norm<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XrA, w.nrm0);
@@ -216,11 +213,9 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
     const float *W1T[3] = {W(lo.W1T[0]), W(lo.W1T[1]), W(lo.W1T[2])};
     if ((rc = mix<float>(s, w.Xb[l], w.Y[l], N, F, W1, W1T, 0, 0))) return rc;
-    if (N > 0) {
-      hipLaunchKernelGGL(k_message_product<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP,
-                         w.h[l], w.Y[l], w.M[l], w.P[l], w.nP[l], w.Pb[l]);
-      TN_LAUNCH_CHECK();
-    }
+    if ((rc = message_product_w(s, F, N, rowptr, nbr, pid, np, MP, w.h[l], w.Y[l], w.M[l], w.P[l], w.nP[l],
+                                w.Pb[l])))
+      return rc;
     const float *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
     const float *W2T[3] = {W(lo.W2T[0]), W(lo.W2T[1]), W(lo.W2T[2])};
     if ((rc = mix<float>(s, w.Pb[l], w.D[l], N, F, W2, W2T, 0, 0))) return rc;
@@ -295,10 +290,8 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
       hipLaunchKernelGGL(k_product_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dPb, w.P[l], w.nP[l], w.Y[l],
                          w.M[l], w.dY, w.dM[l]);
       TN_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_message<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, w.h[l],
-                         w.dM[l], w.dY, 1);
-      TN_LAUNCH_CHECK();
     }
+    if ((rc = message_w(s, F, N, rowptr, nbr, pid, np, MP, w.h[l], w.dM[l], w.dY, 1))) return rc;
     if ((rc = mix<float>(s, w.dY, w.dX, N, F, W1, W1T, 1, 1))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_normalize_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[l], w.nX[l], w.dX);
@@ -376,8 +369,8 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     if ((rc = launch_pair_bwd(s, (int)F, (int)K, pbw))) return rc;
   }
   if (N > 0) {
-    hipLaunchKernelGGL((k_force_gather<float, float>), dim3(grid_for(N, bs)), dim3(bs), 0, s, N, rowptr, nbr, pid,
-                       np, MP, w.gpair, gr.perm, static_cast<float *>(pb.forces));
+    hipLaunchKernelGGL((k_force_gather_w<float, float>), dim3(wave_atom_grid(N)), dim3(256), 0, s, N, rowptr, nbr,
+                       pid, np, MP, w.gpair, gr.perm, static_cast<float *>(pb.forces));
     TN_LAUNCH_CHECK();
   }
   return TN_OK;

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "tensornet.h"
+#include "tn_device.h"
 
 #define TN_HIP(call)                                                   \
   do {                                                                 \
@@ -81,7 +82,10 @@ struct WsPlan {
 // ------------------------------------------------------------------ neighbour search
 struct BoxInfo {
   int periodic = 0;
-  double len[3] = {0, 0, 0};
+  int cells = 0;   // candidates from the cell list (periodic box) rather than the system's atom range
+  int tri = 0;     // nonzero tilt: cells are binned in fractional coordinates
+  Lattice lat;
+  double len[3] = {0, 0, 0};   // ax, by, cz
   int nc[3] = {1, 1, 1};
   double side[3] = {0, 0, 0};
 };
@@ -158,8 +162,7 @@ struct PairFwdArgs {
   int64_t max_pairs = 0;
   const int64_t *n_pairs = nullptr;
   const float *pos = nullptr;
-  int periodic = 0;
-  double box[3] = {0, 0, 0};
+  Lattice lat;   // periodic cell (lat.periodic == 0: isolated systems)
   double r_c = 0, r_lo = 0, alpha = 0;
   const double *mu = nullptr, *beta = nullptr;
   const float *W0 = nullptr, *b0 = nullptr;
@@ -184,8 +187,7 @@ struct PairBwdArgs {
   int64_t max_pairs = 0;
   const int64_t *n_pairs = nullptr;
   const float *pos = nullptr;
-  int periodic = 0;
-  double box[3] = {0, 0, 0};
+  Lattice lat;   // periodic cell (lat.periodic == 0: isolated systems)
   double r_c = 0, r_lo = 0, alpha = 0;
   const double *mu = nullptr, *beta = nullptr;
   const float *W0T = nullptr;
@@ -206,8 +208,7 @@ struct PairFwdArgsB {
   int64_t max_pairs = 0;
   const int64_t *n_pairs = nullptr;
   const float *pos = nullptr;
-  int periodic = 0;
-  double box[3] = {0, 0, 0};
+  Lattice lat;   // periodic cell (lat.periodic == 0: isolated systems)
   double r_c = 0, r_lo = 0, alpha = 0;
   const double *mu = nullptr, *beta = nullptr;
   const __bf16 *W0 = nullptr;
@@ -225,8 +226,7 @@ struct PairBwdArgsB {
   int64_t max_pairs = 0;
   const int64_t *n_pairs = nullptr;
   const float *pos = nullptr;
-  int periodic = 0;
-  double box[3] = {0, 0, 0};
+  Lattice lat;   // periodic cell (lat.periodic == 0: isolated systems)
   double r_c = 0, r_lo = 0, alpha = 0;
   const double *mu = nullptr, *beta = nullptr;
   const __bf16 *W0T = nullptr;

@@ -22,21 +22,34 @@ __global__ void k_md_kick(int64_t n, float *vel, const float *forces, const floa
   vel[3 * i + 2] += s * forces[3 * i + 2];
 }
 
-__global__ void k_md_drift(int64_t n, float *pos, const float *vel, float dt, int periodic, float Lx, float Ly,
-                           float Lz) {
+// x += dt v, then wrap into the cell: [0, L) per axis for a rectangular box, fractional
+// coordinates in [0, 1) for a triclinic cell.
+__global__ void k_md_drift(int64_t n, float *pos, const float *vel, float dt, Lattice lat, int tri) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float L[3] = {Lx, Ly, Lz};
+  float x[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float x = pos[3 * i + a] + dt * vel[3 * i + a];
-    if (periodic) {
-      x -= L[a] * floorf(x / L[a]);
-      if (x >= L[a]) x -= L[a];   // rounding can land exactly on L
-      if (x < 0.f) x = 0.f;
+  for (int a = 0; a < 3; ++a) x[a] = pos[3 * i + a] + dt * vel[3 * i + a];
+  if (lat.periodic && tri) {
+    double s0, s1, s2;
+    fractional(lat, x[0], x[1], x[2], s0, s1, s2);
+    s0 -= floor(s0);
+    s1 -= floor(s1);
+    s2 -= floor(s2);
+    x[0] = (float)(s0 * lat.ax + s1 * lat.bx + s2 * lat.cx);
+    x[1] = (float)(s1 * lat.by + s2 * lat.cy);
+    x[2] = (float)(s2 * lat.cz);
+  } else if (lat.periodic) {
+    const float L[3] = {(float)lat.ax, (float)lat.by, (float)lat.cz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      x[a] -= L[a] * floorf(x[a] / L[a]);
+      if (x[a] >= L[a]) x[a] -= L[a];   // rounding can land exactly on L
+      if (x[a] < 0.f) x[a] = 0.f;
     }
-    pos[3 * i + a] = x;
   }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) pos[3 * i + a] = x[a];
 }
 
 __global__ void k_status_or(const int32_t *step_status, int32_t *acc) {
@@ -93,8 +106,8 @@ int tn_md_capture(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_sy
     for (int st = 0; st < n_steps && rc == TN_OK; ++st) {
       if (n_atoms > 0) {
         hipLaunchKernelGGL(k_md_kick, dim3(blocks), dim3(256), 0, s, n_atoms, vel, f32, inv_mass, half);
-        hipLaunchKernelGGL(k_md_drift, dim3(blocks), dim3(256), 0, s, n_atoms, p32, vel, (float)dt_fs, bi.periodic,
-                           (float)bi.len[0], (float)bi.len[1], (float)bi.len[2]);
+        hipLaunchKernelGGL(k_md_drift, dim3(blocks), dim3(256), 0, s, n_atoms, p32, vel, (float)dt_fs, bi.lat,
+                           bi.tri);
         if (hipGetLastError() != hipSuccess) { rc = TN_E_HIP; break; }
       }
       rc = tn_energy_forces(m, stream, n_atoms, n_systems, pos, z, batch, box, max_pairs, precision, path, energy,

@@ -1,24 +1,28 @@
 // Neighbour search (Sec. 2.5.1 of the paper): unordered pairs of atoms of the
-// same system closer than the cutoff, minimum image in a rectangular box.
+// same system closer than the cutoff, minimum image in a rectangular or triclinic cell.
 //
 // MI355X design.  The output is a receiver-major CSR graph that the model
 // kernels consume directly, plus the public [2, max_pairs] pair list:
-//   1. periodic boxes: bin atoms into cells of side >= cutoff (counting sort:
-//      atomic histogram, device scan, scatter); isolated systems: each atom
-//      binary-searches its system's atom range in the sorted batch vector
-//      (no system count or offsets are ever needed on the host);
-//   2. one thread per atom counts its neighbours (full and j > i), two device
+//   1. candidates: with the cell list (periodic boxes by default), atoms are
+//      binned into cells of side >= cutoff (counting sort: atomic histogram,
+//      device scan, scatter) and each atom sweeps its 27 stencil cells; with the
+//      brute force (isolated systems by default, periodic boxes on request) each
+//      atom binary-searches its system's atom range in the sorted batch vector
+//      and sweeps all of it (no system count or offsets are ever needed on the
+//      host).  A shared cell list with a batch test, as in the paper, lets one
+//      launch serve any number of systems;
+//   2. one wavefront per atom counts its neighbours (full and j > i), two device
 //      scans turn the counts into CSR row offsets and pair offsets; the pair
 //      budget is checked on the device (no host round trip);
 //   3. the rows are written, sorted by neighbour index, and every directed edge
 //      gets the id of its unordered pair (binary search in the partner's row).
-// In a periodic box the atoms are renumbered in cell order (counting sort, each
+// With the cell list the atoms are renumbered in cell order (counting sort, each
 // cell's atoms by original index), so that spatial neighbours are close in
-// index; the model kernels work in that order and map results back.  One
-// wavefront handles one atom and sweeps the candidates of its stencil cells as
-// one flattened list; ballots place the neighbours, already sorted.  Pair
-// writes use scanned offsets instead of one global atomic counter per pair.
-// The cutoff decision is an FP64 predicate with contraction disabled.
+// index; the model kernels work in that order and map results back.  The
+// wavefront of an atom sweeps its candidates as one flattened list; ballots
+// place the neighbours, already sorted.  Pair writes use scanned offsets instead
+// of one global atomic counter per pair.  The cutoff decision is an FP64
+// predicate with contraction disabled.
 #include "tn_internal.h"
 #include "tn_device.h"
 
@@ -154,36 +158,59 @@ int box_info(const double *box, double cutoff, BoxInfo *bi) {
   *bi = BoxInfo{};
   if (!(cutoff > 0.0) || !std::isfinite(cutoff)) return TN_E_ARG;
   if (!box) return TN_OK;
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c)
-      if (r != c && box[r * 3 + c] != 0.0) return TN_E_ARG;   // rectangular boxes only
+  for (int e = 0; e < 9; ++e)
+    if (!std::isfinite(box[e])) return TN_E_ARG;
+  // rows a, b, c, lower triangular (a along x, b in the xy plane)
+  if (box[1] != 0.0 || box[2] != 0.0 || box[5] != 0.0) return TN_E_ARG;
+  Lattice &L = bi->lat;
+  L.periodic = 1;
+  L.ax = box[0];
+  L.bx = box[3];
+  L.by = box[4];
+  L.cx = box[6];
+  L.cy = box[7];
+  L.cz = box[8];
+  if (!(L.ax > 0.0 && L.by > 0.0 && L.cz > 0.0)) return TN_E_ARG;
+  // reduced form, which makes the sequential minimum image the nearest image
+  if (std::fabs(L.bx) > 0.5 * L.ax || std::fabs(L.cx) > 0.5 * L.ax || std::fabs(L.cy) > 0.5 * L.by) return TN_E_ARG;
   bi->periodic = 1;
+  bi->cells = 1;
+  bi->tri = (L.bx != 0.0 || L.cx != 0.0 || L.cy != 0.0);
+  bi->len[0] = L.ax;
+  bi->len[1] = L.by;
+  bi->len[2] = L.cz;
+  // cell heights (distances between opposite faces) = 1 / |columns of H^-1|
+  double h[3] = {L.ax, L.by, L.cz};
+  if (bi->tri) {
+    const double c0[3] = {1.0 / L.ax, -L.bx / (L.ax * L.by), (L.bx * L.cy - L.by * L.cx) / (L.ax * L.by * L.cz)};
+    const double c1[2] = {1.0 / L.by, -L.cy / (L.by * L.cz)};
+    h[0] = 1.0 / std::sqrt(c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]);
+    h[1] = 1.0 / std::sqrt(c1[0] * c1[0] + c1[1] * c1[1]);
+  }
   for (int a = 0; a < 3; ++a) {
-    const double L = box[a * 4];
-    if (!(L > 0.0) || !std::isfinite(L)) return TN_E_ARG;
-    if (L < 2.0 * cutoff) return TN_E_BOX;
-    // cells of side >= cutoff with a relative margin: rounding in the binning
-    // can then never put two atoms closer than the cutoff two cells apart
-    int nc = (int)std::floor(L / (cutoff * (1.0 + 1e-6)));
+    if (h[a] < 2.0 * cutoff) return TN_E_BOX;
+    // cells at least as high as the cutoff with a relative margin: rounding in the binning
+    // can then never put two atoms closer than the cutoff two cells apart (along each
+    // fractional axis two such atoms differ by at most one cell)
+    int nc = (int)std::floor(h[a] / (cutoff * (1.0 + 1e-6)));
     if (nc < 1) nc = 1;
     if (nc > 512) nc = 512;
-    bi->len[a] = L;
     bi->nc[a] = nc;
-    bi->side[a] = L / nc;
+    bi->side[a] = bi->len[a] / nc;
   }
   return TN_OK;
 }
 
 void plan_neighbors(WsPlan &p, int64_t n, int64_t max_pairs, const BoxInfo &bi, NbrWs *w) {
-  const int64_t ncell = bi.periodic ? (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2] : 0;
-  if (bi.periodic) {
+  const int64_t ncell = bi.cells ? (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2] : 0;
+  if (bi.cells) {
     w->cell_of = p.take<int32_t>(n);
     w->cell_count = p.take<int32_t>(ncell + 1);
     w->cell_fill = p.take<int32_t>(ncell);
     w->cell_atoms = p.take<int32_t>(n);
     w->cell_start = w->cell_count;   // scanned in place
   }
-  if (bi.periodic) {
+  if (bi.cells) {
     w->spos = p.take<double>(3 * n);
     w->sz = p.take<int32_t>(n);
     w->sbatch = p.take<int32_t>(n);
@@ -200,7 +227,8 @@ void plan_neighbors(WsPlan &p, int64_t n, int64_t max_pairs, const BoxInfo &bi, 
 }
 
 struct BoxDev {
-  int periodic;
+  int periodic, cells, tri;
+  Lattice lat;
   double len[3];
   double side[3];
   int nc[3];
@@ -209,6 +237,9 @@ struct BoxDev {
 static BoxDev to_dev(const BoxInfo &bi) {
   BoxDev b;
   b.periodic = bi.periodic;
+  b.cells = bi.cells;
+  b.tri = bi.tri;
+  b.lat = bi.lat;
   for (int a = 0; a < 3; ++a) {
     b.len[a] = bi.len[a];
     b.side[a] = bi.side[a];
@@ -222,14 +253,7 @@ __device__ inline bool pair_within(double xi, double yi, double zi, double xj, d
                                          const BoxDev &b, double rc2) {
 #pragma clang fp contract(off)
   double dx = xj - xi, dy = yj - yi, dz = zj - zi;
-  if (b.periodic) {
-    double sx = b.len[0] * rint(dx / b.len[0]);
-    double sy = b.len[1] * rint(dy / b.len[1]);
-    double sz = b.len[2] * rint(dz / b.len[2]);
-    dx = dx - sx;
-    dy = dy - sy;
-    dz = dz - sz;
-  }
+  min_image(b.lat, dx, dy, dz);
   double xx = dx * dx;
   double yy = dy * dy;
   double zz = dz * dz;
@@ -252,6 +276,15 @@ __device__ inline int cell_coord(double x, double L, double side, int nc) {
   return c;
 }
 
+// The same from a fractional coordinate (triclinic cells).
+__device__ inline int frac_cell(double s, int nc) {
+  const double w = s - floor(s);
+  int c = (int)floor(w * nc);
+  if (!(c >= 0)) c = 0;
+  if (c > nc - 1) c = nc - 1;
+  return c;
+}
+
 template <class T>
 __global__ void k_cell_assign(const T *pos, int64_t n, BoxDev b, int32_t *cell_of, int32_t *cell_count,
                               int32_t *status) {
@@ -260,9 +293,18 @@ __global__ void k_cell_assign(const T *pos, int64_t n, BoxDev b, int32_t *cell_o
   double x, y, z;
   load_pos(pos, i, x, y, z);
   if (!isfinite(x) || !isfinite(y) || !isfinite(z)) set_status(status, TN_STATUS_NONFINITE);
-  const int cx = cell_coord(x, b.len[0], b.side[0], b.nc[0]);
-  const int cy = cell_coord(y, b.len[1], b.side[1], b.nc[1]);
-  const int cz = cell_coord(z, b.len[2], b.side[2], b.nc[2]);
+  int cx, cy, cz;
+  if (b.tri) {
+    double s0, s1, s2;
+    fractional(b.lat, x, y, z, s0, s1, s2);
+    cx = frac_cell(s0, b.nc[0]);
+    cy = frac_cell(s1, b.nc[1]);
+    cz = frac_cell(s2, b.nc[2]);
+  } else {
+    cx = cell_coord(x, b.len[0], b.side[0], b.nc[0]);
+    cy = cell_coord(y, b.len[1], b.side[1], b.nc[1]);
+    cz = cell_coord(z, b.len[2], b.side[2], b.nc[2]);
+  }
   const int c = (cx * b.nc[1] + cy) * b.nc[2] + cz;
   cell_of[i] = c;
   atomicAdd(&cell_count[c], 1);
@@ -342,9 +384,9 @@ __global__ void k_permute(int64_t n, const int32_t *perm, const T *pos, const in
   scell[s] = cell_of[o];
 }
 
-// One wavefront per (cell-ordered) atom visits its candidates in ascending index order:
-// the distinct stencil cells in ascending linear order (periodic box) or the atom's system
-// range (isolated systems), flattened into one list that the 64 lanes sweep together.
+// One wavefront per atom visits its candidates in ascending index order: the distinct
+// stencil cells in ascending linear order (cell list) or the atom's system range (brute
+// force), flattened into one list that the 64 lanes sweep together.
 // f(pred, j) is called by every lane with its candidate; neighbours come out sorted.
 constexpr int kNbrBlock = 256;
 
@@ -356,7 +398,7 @@ __device__ inline void wave_candidates(int64_t s, const T *pos, const int32_t *b
   double xi, yi, zi;
   load_pos(pos, s, xi, yi, zi);
   const int32_t bs = batch[s];
-  if (b.periodic) {
+  if (b.cells) {
     const int c = scell[s];
     const int cz = c % b.nc[2];
     const int cy = (c / b.nc[2]) % b.nc[1];
@@ -556,7 +598,7 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, co
     hipLaunchKernelGGL(k_batch_sorted, dim3(g), dim3(blk), 0, s, batch, n, w.flags, status);
     TN_LAUNCH_CHECK();
   }
-  if (bi.periodic) {
+  if (bi.cells) {
     const int64_t ncell = (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2];
     if ((rc = fill_i32(s, w.cell_count, ncell + 1, 0))) return rc;
     if ((rc = fill_i32(s, w.cell_fill, ncell, 0))) return rc;

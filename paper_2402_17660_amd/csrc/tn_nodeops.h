@@ -33,12 +33,14 @@ struct GemmArgs {
   const T *Bz[3] = {nullptr, nullptr, nullptr};
 };
 
-constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int GBM = 64, GBN = 64, GBK = 32;
 
 // The product runs on the matrix cores: 64x64 block tiles, each of the four waves computes a
-// 32x32 quarter as 2x2 MFMA 16x16x4 tiles (f32 or f64); A and B chunks of 16 along K are
-// staged through LDS.  Both instructions take A[l%16][l/16] and B[l/16][l%16] from lane l;
-// element t of the result in lane l is D[4(l/16)+t][l%16] for f32 and D[4t+l/16][l%16] for f64.
+// 32x32 quarter as 2x2 MFMA 16x16x4 tiles (f32 or f64).  A and B chunks of 32 along K are
+// staged through LDS; the next chunk's global loads are issued into registers before the
+// current chunk's MFMAs, so their latency overlaps the products.  Both instructions take
+// A[l%16][l/16] and B[l/16][l%16] from lane l; element t of the result in lane l is
+// D[4(l/16)+t][l%16] for f32 and D[4t+l/16][l%16] for f64.
 typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
 typedef double mf_f64x4 __attribute__((ext_vector_type(4)));
 template <class T> struct MfmaVec;
@@ -54,6 +56,7 @@ __device__ __forceinline__ mf_f64x4 mfma_16x16x4(double a, double b, mf_f64x4 c)
 template <class T>
 __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
   using V = typename MfmaVec<T>::type;
+  constexpr int PER = GBM * GBK / 256;   // elements of each operand chunk per thread
   __shared__ T As[GBM][GBK + 1];
   __shared__ T Bs[GBN][GBK + 1];
   int64_t Mrows = g.M;
@@ -65,31 +68,57 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
   const int64_t n0 = (int64_t)blockIdx.x * GBN;
   if (m0 >= Mrows) return;
   const int z = blockIdx.z;
-  const T *A = g.A + z * g.zoff;
-  const T *B = g.zpart ? g.Bz[coord_part(z)] : g.B;
+  const T *__restrict__ A = g.A + z * g.zoff;
+  const T *__restrict__ B = g.zpart ? g.Bz[coord_part(z)] : g.B;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int r16 = lane & 15, q = lane >> 4;
+  // element e of this thread's share: A tile row/col, B tile row (n) / col (k)
+  auto a_at = [&](int e, int &mm_, int &kk) {
+    const int t = tid + 256 * e;
+    mm_ = t / GBK;
+    kk = t % GBK;
+  };
+  auto b_at = [&](int e, int &nn, int &kk) {
+    const int t = tid + 256 * e;
+    if (g.transB) { nn = t / GBK; kk = t % GBK; } else { kk = t / GBN; nn = t % GBN; }
+  };
+  T ra[PER], rb[PER];
+  auto load_chunk = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      int mm_, kk;
+      a_at(e, mm_, kk);
+      const int64_t m = m0 + mm_, k = k0 + kk;
+      ra[e] = (m < Mrows && k < g.K) ? A[m * g.lda + k] : T(0);
+      int nn;
+      b_at(e, nn, kk);
+      const int64_t n = n0 + nn, k2 = k0 + kk;
+      T v = T(0);
+      if (n < g.N && k2 < g.K) v = g.transB ? B[n * g.ldb + k2] : B[k2 * g.ldb + n];
+      rb[e] = v;
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      int mm_, kk, nn;
+      a_at(e, mm_, kk);
+      As[mm_][kk] = ra[e];
+      b_at(e, nn, kk);
+      Bs[nn][kk] = rb[e];
+    }
+  };
   V acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = V{T(0), T(0), T(0), T(0)};
+  load_chunk(0);
   for (int64_t k0 = 0; k0 < g.K; k0 += GBK) {
-    for (int t = tid; t < GBM * GBK; t += 256) {
-      const int mm_ = t / GBK, kk = t % GBK;
-      const int64_t m = m0 + mm_, k = k0 + kk;
-      As[mm_][kk] = (m < Mrows && k < g.K) ? A[m * g.lda + k] : T(0);
-    }
-    for (int t = tid; t < GBK * GBN; t += 256) {
-      int kk, nn;
-      if (g.transB) { nn = t / GBK; kk = t % GBK; } else { kk = t / GBN; nn = t % GBN; }
-      const int64_t n = n0 + nn, k = k0 + kk;
-      T v = T(0);
-      if (n < g.N && k < g.K) v = g.transB ? B[n * g.ldb + k] : B[k * g.ldb + n];
-      Bs[nn][kk] = v;
-    }
+    store_chunk();
     __syncthreads();
+    if (k0 + GBK < g.K) load_chunk(k0 + GBK);
 #pragma unroll
     for (int s4 = 0; s4 < GBK; s4 += 4) {
       const T a0 = As[wr + r16][s4 + q], a1 = As[wr + 16 + r16][s4 + q];
@@ -102,17 +131,22 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
     __syncthreads();
   }
   T *C = g.C + z * g.zoff;
+  T bias[2] = {T(0), T(0)};
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int cb = 0; cb < 2; ++cb) {
+    const int64_t n = n0 + wc + cb * 16 + r16;
+    if (g.bias && n < g.N) bias[cb] = g.bias[n];
+  }
+#pragma unroll
+  for (int rb_ = 0; rb_ < 2; ++rb_)
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int64_t m = m0 + wr + rb * 16 + (sizeof(T) == 4 ? 4 * q + t : 4 * t + q);
+        const int64_t m = m0 + wr + rb_ * 16 + (sizeof(T) == 4 ? 4 * q + t : 4 * t + q);
         const int64_t n = n0 + wc + cb * 16 + r16;
         if (m >= Mrows || n >= g.N) continue;
-        T v = acc[rb][cb][t];
-        if (g.bias) v += g.bias[n];
+        T v = acc[rb_][cb][t] + bias[cb];
         if (g.Z) g.Z[z * g.zoff + m * g.ldz + n] = v;
         if (g.act == 1) v = silu(v);
         if (g.rowscale) v *= g.rowscale[m];
@@ -250,11 +284,6 @@ __device__ inline int64_t pair_bound(const int64_t *n_pairs, int64_t max_pairs) 
   return P < max_pairs ? P : max_pairs;
 }
 
-struct BoxLen {
-  int periodic;
-  double len[3];
-};
-
 template <class T>
 __global__ void k_check_inputs(const int32_t *z, const int32_t *batch, int64_t n, int64_t S, int max_z,
                                int32_t *status) {
@@ -270,7 +299,7 @@ __device__ inline int clamp_z(int32_t z, int max_z) { return z < 0 ? 0 : (z >= m
 // FP64 from the (promoted) input positions and rounded once to T: the narrow Gaussians of
 // the exp-normal basis amplify rounding in d by up to 2*alpha*beta*u*|u - mu_k|.
 template <class T>
-__global__ void k_geom(const int32_t *pairs, int64_t max_pairs, const int64_t *n_pairs, const T *pos, BoxLen box,
+__global__ void k_geom(const int32_t *pairs, int64_t max_pairs, const int64_t *n_pairs, const T *pos, Lattice box,
                        double r_c, double r_lo, double alpha, const double *mu, const double *beta, int K, T *geo,
                        T *phi, T *rbf) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -278,11 +307,8 @@ __global__ void k_geom(const int32_t *pairs, int64_t max_pairs, const int64_t *n
   const int64_t i = pairs[p], j = pairs[max_pairs + p];
   double v[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double dlt = (double)pos[3 * j + a] - (double)pos[3 * i + a];
-    if (box.periodic) dlt -= box.len[a] * rint(dlt / box.len[a]);
-    v[a] = dlt;
-  }
+  for (int a = 0; a < 3; ++a) v[a] = (double)pos[3 * j + a] - (double)pos[3 * i + a];
+  min_image(box, v[0], v[1], v[2]);
   const double d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   const double inv = 1.0 / d;
   geo[4 * p + 0] = (T)(v[0] * inv);
@@ -922,6 +948,236 @@ __global__ void k_unpermute(int64_t n, const int32_t *perm, const T *in, T *out)
   if (i < n) out[perm[i]] = in[i];
 }
 
+
+// ============================================================================ wave-per-atom gathers
+// FP32 gathers over the CSR rows with one wave per atom: the row is wave-uniform, so its
+// indices and per-pair scalars come through scalar loads, and lane l owns the V channels
+// V*l .. V*l+V-1 (F = 64 V), read with one vector access per coordinate.  Four atoms per
+// 256-thread block, numbered per XCD.
+__device__ __forceinline__ int32_t wave_atom() {
+  return __builtin_amdgcn_readfirstlane((int32_t)(xcd_block() * 4 + (threadIdx.x >> 6)));
+}
+
+inline unsigned wave_atom_grid(int64_t n) { return (unsigned)((n + 3) / 4); }
+
+// X_i = sum_j phi Z_ij (a 1 + b A0(u_ij) + c S0(u_ij))
+template <int V>
+__global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ nbr,
+                                                        const int32_t *__restrict__ pid, const int64_t *n_pairs,
+                                                        int64_t max_pairs, const int32_t *__restrict__ z, int max_z,
+                                                        const float *__restrict__ U, const float *__restrict__ Vt,
+                                                        const float *__restrict__ geo, const float *__restrict__ phi,
+                                                        const float *__restrict__ f0, float *__restrict__ X) {
+  constexpr int F = 64 * V;
+  const int32_t i = wave_atom();
+  if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
+  const int f = (threadIdx.x & 63) * V;
+  float ui[V];
+  ldv<V>(U + (int64_t)clamp_z(z[i], max_z) * F + f, ui);
+  float c[9][V];
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int v = 0; v < V; ++v) c[q][v] = 0.f;
+  const int32_t e1 = rowptr[i + 1];
+  for (int32_t e = rowptr[i]; e < e1; ++e) {
+    const int32_t j = nbr[e];
+    const int64_t p = pid[e];
+    const float sg = (j > i) ? 1.f : -1.f;
+    const float ux = sg * geo[4 * p], uy = sg * geo[4 * p + 1], uz = sg * geo[4 * p + 2];
+    const float ph = phi[p];
+    float vj[V], a[V], b[V], cc[V];
+    ldv<V>(Vt + (int64_t)clamp_z(z[j], max_z) * F + f, vj);
+    ldv<V>(f0 + p * 3 * F + f, a);
+    ldv<V>(f0 + p * 3 * F + F + f, b);
+    ldv<V>(f0 + p * 3 * F + 2 * F + f, cc);
+    float s5[5];
+    s0_coords(ux, uy, uz, s5);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const float w = ph * (ui[v] + vj[v]);
+      const float wb = w * b[v], wc = w * cc[v];
+      c[0][v] += w * a[v];
+      c[1][v] += wb * ux;
+      c[2][v] += wb * uy;
+      c[3][v] += wb * uz;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) c[4 + q][v] += wc * s5[q];
+    }
+  }
+  float *x = X + (int64_t)i * 9 * F + f;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) stv<V>(x + q * F, c[q]);
+}
+
+// c[q] = sum over the CSR row of i of h_part(q)(pair) * Y_j[q]
+template <int V>
+__device__ __forceinline__ void gather_message(int32_t i, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
+                                               const float *__restrict__ h, const float *__restrict__ Y, int f,
+                                               float (&c)[9][V]) {
+  constexpr int F = 64 * V;
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int v = 0; v < V; ++v) c[q][v] = 0.f;
+  const int32_t e1 = rowptr[i + 1];
+  for (int32_t e = rowptr[i]; e < e1; ++e) {
+    const int64_t j = nbr[e];
+    const int64_t p = pid[e];
+    float hh[3][V], y[9][V];
+#pragma unroll
+    for (int pt = 0; pt < 3; ++pt) ldv<V>(h + p * 3 * F + pt * F + f, hh[pt]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ldv<V>(Y + j * 9 * F + q * F + f, y[q]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+#pragma unroll
+      for (int v = 0; v < V; ++v) c[q][v] += hh[coord_part(q)][v] * y[q][v];
+  }
+}
+
+// M_i (+)= sum_j h_part(c)(d_ij) * Y_j[c]
+template <int V>
+__global__ void __launch_bounds__(256) k_message_w(int64_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
+                                                   const int64_t *n_pairs, int64_t max_pairs,
+                                                   const float *__restrict__ h, const float *__restrict__ Y,
+                                                   float *__restrict__ M, int accumulate) {
+  constexpr int F = 64 * V;
+  const int32_t i = wave_atom();
+  if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
+  const int f = (threadIdx.x & 63) * V;
+  float c[9][V];
+  gather_message<V>(i, rowptr, nbr, pid, h, Y, f, c);
+  float *m = M + (int64_t)i * 9 * F + f;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    if (accumulate) {
+      float old[V];
+      ldv<V>(m + q * F, old);
+#pragma unroll
+      for (int v = 0; v < V; ++v) c[q][v] += old[v];
+    }
+    stv<V>(m + q * F, c[q]);
+  }
+}
+
+// M_i = sum_j h_part(c) * Y_j[c]; P = Y M + M Y; Pb = P / (||P|| + 1).  Writes M, P, ||P||, Pb.
+template <int V>
+__global__ void __launch_bounds__(256) k_message_product_w(int64_t n, const int32_t *__restrict__ rowptr,
+                                                           const int32_t *__restrict__ nbr,
+                                                           const int32_t *__restrict__ pid, const int64_t *n_pairs,
+                                                           int64_t max_pairs, const float *__restrict__ h,
+                                                           const float *__restrict__ Y, float *__restrict__ M,
+                                                           float *__restrict__ P, float *__restrict__ nP,
+                                                           float *__restrict__ Pb) {
+  constexpr int F = 64 * V;
+  const int32_t i = wave_atom();
+  if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
+  const int f = (threadIdx.x & 63) * V;
+  float mc[9][V], yc[9][V];
+  gather_message<V>(i, rowptr, nbr, pid, h, Y, f, mc);
+  const int64_t base = (int64_t)i * 9 * F + f;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    stv<V>(M + base + q * F, mc[q]);
+    ldv<V>(Y + base + q * F, yc[q]);
+  }
+  float pc[9][V], nn[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    float y9[9], m9[9], Ym[9], Mm[9], A1[9], A2[9], p9[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      y9[q] = yc[q][v];
+      m9[q] = mc[q][v];
+    }
+    rec(y9, Ym);
+    rec(m9, Mm);
+    mm(Ym, Mm, A1);
+    mm(Mm, Ym, A2);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) A1[q] += A2[q];
+    dec(A1, p9);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) pc[q][v] = p9[q];
+    nn[v] = norm9(p9);
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) stv<V>(P + base + q * F, pc[q]);
+  stv<V>(nP + (int64_t)i * F + f, nn);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const float sc = 1.f / (nn[v] + 1.f);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) pc[q][v] *= sc;
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) stv<V>(Pb + base + q * F, pc[q]);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// F_i = sum over the CSR row of i of +-g_pair in FP64: lanes stride over the row, then a fixed
+// butterfly sums the lanes (deterministic).
+template <class T, class TO>
+__global__ void __launch_bounds__(256) k_force_gather_w(int64_t n, const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ nbr,
+                                                        const int32_t *__restrict__ pid, const int64_t *n_pairs,
+                                                        int64_t max_pairs, const T *__restrict__ gpair,
+                                                        const int32_t *__restrict__ perm, TO *__restrict__ forces) {
+  const int32_t i = wave_atom();
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  if (pairs_ok(n_pairs, max_pairs)) {
+    const int32_t e1 = rowptr[i + 1];
+    for (int32_t e = rowptr[i] + lane; e < e1; e += 64) {
+      const int64_t p = pid[e];
+      const double sg = (nbr[e] > i) ? 1.0 : -1.0;
+      fx += sg * (double)gpair[3 * p];
+      fy += sg * (double)gpair[3 * p + 1];
+      fz += sg * (double)gpair[3 * p + 2];
+    }
+  }
+  fx = wave_sum_d(fx);
+  fy = wave_sum_d(fy);
+  fz = wave_sum_d(fz);
+  if (lane == 0) {
+    const int64_t o = perm ? perm[i] : i;
+    forces[3 * o] = (TO)fx;
+    forces[3 * o + 1] = (TO)fy;
+    forces[3 * o + 2] = (TO)fz;
+  }
+}
+
+// Launch one of the wave-per-atom kernels above for F = 64 V (V = 1, 2, 4).
+#define TN_WAVE_GATHER_LAUNCHER(NAME, KERNEL)                                                   \
+  template <class... A>                                                                         \
+  inline int NAME(hipStream_t s, int64_t F, int64_t n, A... a) {                                \
+    if (n <= 0) return TN_OK;                                                                   \
+    const dim3 g(wave_atom_grid(n)), b(256);                                                    \
+    if (F == 64)                                                                                \
+      hipLaunchKernelGGL(KERNEL<1>, g, b, 0, s, n, a...);                                       \
+    else if (F == 128)                                                                          \
+      hipLaunchKernelGGL(KERNEL<2>, g, b, 0, s, n, a...);                                       \
+    else if (F == 256)                                                                          \
+      hipLaunchKernelGGL(KERNEL<4>, g, b, 0, s, n, a...);                                       \
+    else                                                                                        \
+      return TN_E_UNSUPPORTED;                                                                  \
+    TN_LAUNCH_CHECK();                                                                          \
+    return TN_OK;                                                                               \
+  }
+TN_WAVE_GATHER_LAUNCHER(embed_gather_w, k_embed_gather_w)
+TN_WAVE_GATHER_LAUNCHER(message_w, k_message_w)
+TN_WAVE_GATHER_LAUNCHER(message_product_w, k_message_product_w)
+#undef TN_WAVE_GATHER_LAUNCHER
 
 template <class TI, class TO>
 inline int convert(hipStream_t s, const TI *in, TO *out, int64_t n) {

@@ -18,6 +18,8 @@
 #include "tn_device.h"
 #include "tn_mfma.h"
 
+#include <type_traits>
+
 namespace tn {
 
 constexpr int kTile = 32;   // pairs per tile
@@ -37,22 +39,46 @@ __device__ __forceinline__ void wave_mm(const float *act, int ld, int Kin, const
 
 template <int NB>
 __device__ __forceinline__ void zero_acc(floatx4 (&acc)[2][NB]) {
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  zero_acc_rb<2, NB>(acc);
 }
 
-// Visit the accumulator entries of this lane: f(row, col, value).
-template <int NB, class Fn>
-__device__ __forceinline__ void for_acc(const floatx4 (&acc)[2][NB], int col0, Fn &&f) {
+// Visit this lane's accumulator entries: f(rb, cb, t, row, col, value).  Entry t of block
+// (rb, cb) sits at row rb*16 + 4(l/16) + t and column col0 + cb*16 + l%16 (lane l).
+template <int RB, int NB, class Fn>
+__device__ __forceinline__ void for_acc_rc(const floatx4 (&acc)[RB][NB], int col0, Fn &&f) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) f(rb * 16 + 4 * (lane >> 4) + t, col0 + cb * 16 + (lane & 15), acc[rb][cb][t]);
+      for (int t = 0; t < 4; ++t)
+        f(rb, cb, t, rb * 16 + 4 * (lane >> 4) + t, col0 + cb * 16 + (lane & 15), acc[rb][cb][t]);
+}
+
+// This lane's columns of a per-column vector (bias), loaded once before the products.
+template <int NB>
+__device__ __forceinline__ void load_cols(const float *v, int col0, float (&o)[NB]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) o[cb] = v[col0 + cb * 16 + (lane & 15)];
+}
+
+// The stored pre-activations at this lane's accumulator positions (rows past nvalid read
+// row 0), issued before the product so that their latency overlaps the MFMAs.
+template <int RB, int NB, class TZ>
+__device__ __forceinline__ void load_acc_rows(const TZ *z, int ldz, int64_t p0, int nvalid, int col0,
+                                              float (&o)[RB][NB][4]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int row = rb * 16 + 4 * (lane >> 4) + t;
+      const int64_t base = (p0 + (row < nvalid ? row : 0)) * ldz + col0 + (lane & 15);
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) o[rb][cb][t] = (float)z[base + cb * 16];
+    }
 }
 
 // Pair geometry in FP64 from the FP32 positions: unit vector, distance, cutoff and its derivative.
@@ -60,16 +86,12 @@ struct PairGeo {
   double u[3], d, phi, dphi;
 };
 
-__device__ inline PairGeo pair_geometry(const float *pos, int64_t i, int64_t j, int periodic, const double *box,
-                                        double r_c) {
+__device__ inline PairGeo pair_geometry(const float *pos, int64_t i, int64_t j, const Lattice &lat, double r_c) {
   PairGeo g;
   double v[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double dl = (double)pos[3 * j + a] - (double)pos[3 * i + a];
-    if (periodic) dl -= box[a] * rint(dl / box[a]);
-    v[a] = dl;
-  }
+  for (int a = 0; a < 3; ++a) v[a] = (double)pos[3 * j + a] - (double)pos[3 * i + a];
+  min_image(lat, v[0], v[1], v[2]);
   g.d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   const double inv = 1.0 / g.d;
 #pragma unroll
@@ -89,7 +111,7 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
   __shared__ __attribute__((aligned(16))) float sA2[kTile * L2];
   __shared__ double sD[kTile], sPhi[kTile];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = (int64_t)blockIdx.x * kTile;
+  const int64_t p0 = xcd_block() * kTile;
   if (p0 >= P) return;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < kTile ? (P - p0) : kTile);
@@ -99,7 +121,7 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
       const int64_t i = a.pairs[p], j = a.pairs[a.max_pairs + p];
-      const PairGeo g = pair_geometry(a.pos, i, j, a.periodic, a.box, a.r_c);
+      const PairGeo g = pair_geometry(a.pos, i, j, a.lat, a.r_c);
       d = g.d;
       ph = g.phi;
       a.geo[4 * p + 0] = (float)g.u[0];
@@ -126,9 +148,11 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
     floatx4 acc[2][NB];
     zero_acc(acc);
     const int col0 = wave * (3 * F / 4);
+    float br[NB];
+    load_cols<NB>(a.b0, col0, br);
     wave_mm<NB>(sE, LE, K, a.W0, col0, acc);
-    for_acc(acc, col0, [&](int row, int col, float v) {
-      if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = v + a.b0[col];
+    for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+      if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = v + br[cb];
     });
   }
   for (int l = 0; l < a.L; ++l) {
@@ -137,11 +161,12 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
       floatx4 acc[2][NB];
       zero_acc(acc);
       const int col0 = wave * (F / 4);
+      float br[NB];
+      load_cols<NB>(a.ba[l], col0, br);
       wave_mm<NB>(sE, LE, K, a.Wa[l], col0, acc);
       float *z1 = a.z1[l];
-      const float *bias = a.ba[l];
-      for_acc(acc, col0, [&](int row, int col, float v) {
-        const float z = v + bias[col];
+      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+        const float z = v + br[cb];
         if (row < nvalid) z1[(p0 + row) * F + col] = z;
         sA1[row * L1 + col] = silu(z);
       });
@@ -152,11 +177,12 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
       floatx4 acc[2][NB];
       zero_acc(acc);
       const int col0 = wave * (F / 2);
+      float br[NB];
+      load_cols<NB>(a.bb[l], col0, br);
       wave_mm<NB>(sA1, L1, F, a.Wb[l], col0, acc);
       float *z2 = a.z2[l];
-      const float *bias = a.bb[l];
-      for_acc(acc, col0, [&](int row, int col, float v) {
-        const float z = v + bias[col];
+      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+        const float z = v + br[cb];
         if (row < nvalid) z2[(p0 + row) * 2 * F + col] = z;
         sA2[row * L2 + col] = silu(z);
       });
@@ -167,11 +193,12 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
       floatx4 acc[2][NB];
       zero_acc(acc);
       const int col0 = wave * (3 * F / 4);
+      float br[NB];
+      load_cols<NB>(a.bc[l], col0, br);
       wave_mm<NB>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
       float *z3 = a.z3[l], *h = a.h[l];
-      const float *bias = a.bc[l];
-      for_acc(acc, col0, [&](int row, int col, float v) {
-        const float z = v + bias[col];
+      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+        const float z = v + br[cb];
         if (row < nvalid) {
           z3[(p0 + row) * 3 * F + col] = z;
           h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * silu(z);
@@ -184,8 +211,10 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
 // ============================================================================ reverse-sweep prologues
 // Both directions of a pair meet in the pair tile, so the pair-level adjoints are formed
 // here from the two atoms' rows (coordinates layout [N, 9, F]) and written straight into
-// LDS as the A operand of the MFMA backprop.  Each wave owns R/4 rows; its lanes sweep the
-// F channels and per-row scalars are reduced across the wave.
+// LDS as the A operand of the MFMA backprop.  Each wave owns R/4 rows; lane l holds the
+// V = F/64 channels V*l .. V*l+V-1 (one vector access per coordinate), and per-row scalars
+// are reduced across the wave.  Rows past the tile's valid count read the tile's first pair
+// and store zeros, so the row loop has no branches and its loads can overlap.
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -193,65 +222,99 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+template <class TL, int V>
+__device__ __forceinline__ void st_row(TL *p, const float (&o)[V]) {
+  if constexpr (std::is_same<TL, float>::value) {
+    stv<V>(p, o);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) p[v] = (TL)o[v];
+  }
+}
+
+template <class TZ, int V>
+__device__ __forceinline__ void ld_row(const TZ *p, float (&o)[V]) {
+  if constexpr (std::is_same<TZ, float>::value) {
+    ldv<V>(p, o);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = (float)p[v];
+  }
+}
+
 // dE/df0 = (da, db, dc) for both directions of the pair -> lds[row][0..3F); returns the pair's
 // dE/dphi and dE/dvhat (embedding part) through the per-row LDS arrays.
-template <int F, class TL>
+template <int F, int R, class TL>
 __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const int32_t *pairs, int64_t max_pairs,
-                                                   int64_t p0, int R, int nvalid, const float (*sU)[3],
-                                                   const float *sPhi, TL *lds, int ld, float *sDphi,
-                                                   float (*sDv)[3]) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int rows = R / 4;
+                                                   int64_t p0, int nvalid, const float (*sU)[3], const float *sPhi,
+                                                   TL *lds, int ld, float *sDphi, float (*sDv)[3]) {
+  constexpr int V = F / 64, rows = R / 4;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int f = lane * V;
+#pragma unroll
   for (int rr = 0; rr < rows; ++rr) {
     const int row = wave * rows + rr;
-    float aphi = 0.f, av0 = 0.f, av1 = 0.f, av2 = 0.f;
-    if (row < nvalid) {
-      const int64_t p = p0 + row;
-      const int64_t i = pairs[p], j = pairs[max_pairs + p];
-      int zi = bg.z[i], zj = bg.z[j];
-      zi = zi < 0 ? 0 : (zi >= bg.max_z ? bg.max_z - 1 : zi);
-      zj = zj < 0 ? 0 : (zj >= bg.max_z ? bg.max_z - 1 : zj);
-      const float ux = sU[row][0], uy = sU[row][1], uz = sU[row][2];
-      const float ph = sPhi[row];
-      float s5[5];
-      s0_coords(ux, uy, uz, s5);
-      const float *di = bg.dXr + i * 9 * F, *dj = bg.dXr + j * 9 * F;
-      for (int f = lane; f < F; f += 64) {
-        const float Zij = bg.U[zi * F + f] + bg.V[zj * F + f];
-        const float Zji = bg.U[zj * F + f] + bg.V[zi * F + f];
-        const float a = bg.f0[p * 3 * F + f], b = bg.f0[p * 3 * F + F + f], c = bg.f0[p * 3 * F + 2 * F + f];
-        float ci[9], cj[9];
+    const bool valid = row < nvalid;
+    const int64_t p = p0 + (valid ? row : 0);
+    const int64_t i = pairs[p], j = pairs[max_pairs + p];
+    int zi = bg.z[i], zj = bg.z[j];
+    zi = zi < 0 ? 0 : (zi >= bg.max_z ? bg.max_z - 1 : zi);
+    zj = zj < 0 ? 0 : (zj >= bg.max_z ? bg.max_z - 1 : zj);
+    const float ux = sU[row][0], uy = sU[row][1], uz = sU[row][2];
+    const float ph = sPhi[row];
+    float s5[5];
+    s0_coords(ux, uy, uz, s5);
+    const float *di = bg.dXr + i * 9 * F + f, *dj = bg.dXr + j * 9 * F + f;
+    float ci[9][V], cj[9][V], Ui[V], Uj[V], Vi[V], Vj[V], a[V], b[V], c[V];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          ci[q] = di[q * F + f];
-          cj[q] = dj[q * F + f];
-        }
-        const float giA = ci[1] * ux + ci[2] * uy + ci[3] * uz;
-        const float gjA = -(cj[1] * ux + cj[2] * uy + cj[3] * uz);
-        float giS = 0.f, gjS = 0.f;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          giS += ci[4 + q] * s5[q];
-          gjS += cj[4 + q] * s5[q];
-        }
-        lds[row * ld + f] = (TL)(ph * (Zij * ci[0] + Zji * cj[0]));
-        lds[row * ld + F + f] = (TL)(ph * (Zij * giA + Zji * gjA));
-        lds[row * ld + 2 * F + f] = (TL)(ph * (Zij * giS + Zji * gjS));
-        aphi += Zij * (a * ci[0] + b * giA + c * giS) + Zji * (a * cj[0] + b * gjA + c * gjS);
-        float gsi[3], gsj[3];
-        s0_dot_grad(ci + 4, ux, uy, uz, gsi);
-        s0_dot_grad(cj + 4, ux, uy, uz, gsj);
-        av0 += ph * (b * (Zij * ci[1] - Zji * cj[1]) + c * (Zij * gsi[0] + Zji * gsj[0]));
-        av1 += ph * (b * (Zij * ci[2] - Zji * cj[2]) + c * (Zij * gsi[1] + Zji * gsj[1]));
-        av2 += ph * (b * (Zij * ci[3] - Zji * cj[3]) + c * (Zij * gsi[2] + Zji * gsj[2]));
-      }
-    } else {
-      for (int f = lane; f < 3 * F; f += 64) lds[row * ld + f] = (TL)0.f;
+    for (int q = 0; q < 9; ++q) {
+      ldv<V>(di + q * F, ci[q]);
+      ldv<V>(dj + q * F, cj[q]);
     }
-    aphi = wave_sum(aphi);
-    av0 = wave_sum(av0);
-    av1 = wave_sum(av1);
-    av2 = wave_sum(av2);
+    ldv<V>(bg.U + zi * F + f, Ui);
+    ldv<V>(bg.U + zj * F + f, Uj);
+    ldv<V>(bg.V + zi * F + f, Vi);
+    ldv<V>(bg.V + zj * F + f, Vj);
+    ldv<V>(bg.f0 + p * 3 * F + f, a);
+    ldv<V>(bg.f0 + p * 3 * F + F + f, b);
+    ldv<V>(bg.f0 + p * 3 * F + 2 * F + f, c);
+    float oI[V], oA[V], oS[V];
+    float aphi = 0.f, av0 = 0.f, av1 = 0.f, av2 = 0.f;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const float Zij = Ui[v] + Vj[v], Zji = Uj[v] + Vi[v];
+      float xi[9], xj[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        xi[q] = ci[q][v];
+        xj[q] = cj[q][v];
+      }
+      const float giA = xi[1] * ux + xi[2] * uy + xi[3] * uz;
+      const float gjA = -(xj[1] * ux + xj[2] * uy + xj[3] * uz);
+      float giS = 0.f, gjS = 0.f;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        giS += xi[4 + q] * s5[q];
+        gjS += xj[4 + q] * s5[q];
+      }
+      oI[v] = valid ? ph * (Zij * xi[0] + Zji * xj[0]) : 0.f;
+      oA[v] = valid ? ph * (Zij * giA + Zji * gjA) : 0.f;
+      oS[v] = valid ? ph * (Zij * giS + Zji * gjS) : 0.f;
+      aphi += Zij * (a[v] * xi[0] + b[v] * giA + c[v] * giS) + Zji * (a[v] * xj[0] + b[v] * gjA + c[v] * gjS);
+      float gsi[3], gsj[3];
+      s0_dot_grad(xi + 4, ux, uy, uz, gsi);
+      s0_dot_grad(xj + 4, ux, uy, uz, gsj);
+      av0 += ph * (b[v] * (Zij * xi[1] - Zji * xj[1]) + c[v] * (Zij * gsi[0] + Zji * gsj[0]));
+      av1 += ph * (b[v] * (Zij * xi[2] - Zji * xj[2]) + c[v] * (Zij * gsi[1] + Zji * gsj[1]));
+      av2 += ph * (b[v] * (Zij * xi[3] - Zji * xj[3]) + c[v] * (Zij * gsi[2] + Zji * gsj[2]));
+    }
+    st_row<TL, V>(lds + row * ld + f, oI);
+    st_row<TL, V>(lds + row * ld + F + f, oA);
+    st_row<TL, V>(lds + row * ld + 2 * F + f, oS);
+    aphi = wave_sum(valid ? aphi : 0.f);
+    av0 = wave_sum(valid ? av0 : 0.f);
+    av1 = wave_sum(valid ? av1 : 0.f);
+    av2 = wave_sum(valid ? av2 : 0.f);
     if (lane == 0) {
       sDphi[row] = aphi;
       sDv[row][0] = av0;
@@ -263,36 +326,51 @@ __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const in
 
 // Layer l: dh = <part(Y_j), dM_i> + <part(Y_i), dM_j> per channel; then
 // lds[row][c] = dh phi silu'(z3) and dE/dphi += sum_c dh silu(z3).
-template <int F, class TL, class TZ>
+template <int F, int R, class TL, class TZ>
 __device__ __forceinline__ void filter_adjoint_rows(const float *Y, const float *dM, const TZ *z3,
-                                                    const int32_t *pairs, int64_t max_pairs, int64_t p0, int R,
-                                                    int nvalid, const float *sPhi, TL *lds, int ld, float *sDphi) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int rows = R / 4;
+                                                    const int32_t *pairs, int64_t max_pairs, int64_t p0, int nvalid,
+                                                    const float *sPhi, TL *lds, int ld, float *sDphi) {
+  constexpr int V = F / 64, rows = R / 4;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int f = lane * V;
+#pragma unroll
   for (int rr = 0; rr < rows; ++rr) {
     const int row = wave * rows + rr;
-    float part = 0.f;
-    if (row < nvalid) {
-      const int64_t p = p0 + row;
-      const int64_t i = pairs[p], j = pairs[max_pairs + p];
-      const float *yi = Y + i * 9 * F, *yj = Y + j * 9 * F, *gi = dM + i * 9 * F, *gj = dM + j * 9 * F;
-      const float ph = sPhi[row];
-      for (int f = lane; f < F; f += 64) {
-        float dh[3] = {0.f, 0.f, 0.f};
+    const bool valid = row < nvalid;
+    const int64_t p = p0 + (valid ? row : 0);
+    const int64_t i = pairs[p], j = pairs[max_pairs + p];
+    const float *yi = Y + i * 9 * F + f, *yj = Y + j * 9 * F + f, *gi = dM + i * 9 * F + f,
+                *gj = dM + j * 9 * F + f;
+    const float ph = sPhi[row];
+    float dh[3][V], zz[3][V];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) dh[coord_part(q)] += yj[q * F + f] * gi[q * F + f] + yi[q * F + f] * gj[q * F + f];
+    for (int pt = 0; pt < 3; ++pt) {
+      ld_row<TZ, V>(z3 + p * 3 * F + pt * F + f, zz[pt]);
 #pragma unroll
-        for (int pt = 0; pt < 3; ++pt) {
-          const int c = pt * F + f;
-          const float zz = (float)z3[p * 3 * F + c];
-          lds[row * ld + c] = (TL)(dh[pt] * ph * silu_grad(zz));
-          part += dh[pt] * silu(zz);
-        }
-      }
-    } else {
-      for (int c = lane; c < 3 * F; c += 64) lds[row * ld + c] = (TL)0.f;
+      for (int v = 0; v < V; ++v) dh[pt][v] = 0.f;
     }
-    part = wave_sum(part);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      float a[V], b[V], c[V], d[V];
+      ldv<V>(yj + q * F, a);
+      ldv<V>(gi + q * F, b);
+      ldv<V>(yi + q * F, c);
+      ldv<V>(gj + q * F, d);
+#pragma unroll
+      for (int v = 0; v < V; ++v) dh[coord_part(q)][v] += a[v] * b[v] + c[v] * d[v];
+    }
+    float part = 0.f;
+#pragma unroll
+    for (int pt = 0; pt < 3; ++pt) {
+      float o[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        o[v] = valid ? dh[pt][v] * ph * silu_grad(zz[pt][v]) : 0.f;
+        part += dh[pt][v] * silu(zz[pt][v]);
+      }
+      st_row<TL, V>(lds + row * ld + pt * F + f, o);
+    }
+    part = wave_sum(valid ? part : 0.f);
     if (lane == 0) sDphi[row] += part;
   }
 }
@@ -319,14 +397,16 @@ __device__ __forceinline__ void geometry_adjoint_rows(const PairGeo &g, const fl
 }
 
 // ============================================================================ reverse
+// One LDS buffer holds the tile's current adjoint: dE/df0, then per layer dz3, dz2, dz1, and
+// finally dE/de.  Each product keeps its result in registers until every wave has finished
+// reading the buffer, so the tile needs ~50 KB of LDS and two blocks share a CU.
 template <int F, int K>
-__global__ void __launch_bounds__(256, 1) k_pair_bwd(PairBwdArgs a) {
+__global__ void __launch_bounds__(256, 2) k_pair_bwd(PairBwdArgs a) {
   constexpr int L3 = 3 * F + kPad, L2 = 2 * F + kPad, L1 = F + kPad, LE = K + kPad;
-  __shared__ __attribute__((aligned(16))) float sG3[kTile * L3];   // df0, dz3, then dz1
-  __shared__ __attribute__((aligned(16))) float sG2[kTile * L2];   // dz2, finally dE/de
+  __shared__ __attribute__((aligned(16))) float sG[kTile * L3];
   __shared__ float sPhi[kTile], sDphi[kTile], sU[kTile][3], sDv[kTile][3];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = (int64_t)blockIdx.x * kTile;
+  const int64_t p0 = xcd_block() * kTile;
   if (p0 >= P) return;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < kTile ? (P - p0) : kTile);
@@ -337,7 +417,7 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd(PairBwdArgs a) {
     float ph = 0.f;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
-      g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.periodic, a.box, a.r_c);
+      g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.lat, a.r_c);
       ph = (float)g.phi;
     }
     sPhi[tid] = ph;
@@ -346,48 +426,54 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd(PairBwdArgs a) {
     sU[tid][2] = (float)g.u[2];
   }
   __syncthreads();
-  // embedding adjoint: dE/df0 -> sG3, dE/dphi and dE/dvhat per pair
-  embed_adjoint_rows<F>(a.g, a.pairs, a.max_pairs, p0, kTile, nvalid, sU, sPhi, sG3, L3, sDphi, sDv);
+  // embedding adjoint: dE/df0 -> sG, dE/dphi and dE/dvhat per pair
+  embed_adjoint_rows<F, kTile>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
   __syncthreads();
   floatx4 de[2][1];
   zero_acc(de);
-  if (wave < NWDE) wave_mm<1>(sG3, L3, 3 * F, a.W0T, wave * 16, de);
+  if (wave < NWDE) wave_mm<1>(sG, L3, 3 * F, a.W0T, wave * 16, de);
   __syncthreads();
 
   for (int l = 0; l < a.L; ++l) {
     const float *z1 = a.z1[l], *z2 = a.z2[l];
-    filter_adjoint_rows<F>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, kTile, nvalid, sPhi, sG3, L3,
-                           sDphi);
+    filter_adjoint_rows<F, kTile>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
+                                  sDphi);
     __syncthreads();
     {  // dz2 = (dz3 Wc) silu'(z2)
       constexpr int NB = F / 32;
       floatx4 acc[2][NB];
       zero_acc(acc);
       const int col0 = wave * (F / 2);
-      wave_mm<NB>(sG3, L3, 3 * F, a.WcT[l], col0, acc);
-      for_acc(acc, col0, [&](int row, int col, float v) {
-        sG2[row * L2 + col] = row < nvalid ? v * silu_grad(z2[(p0 + row) * 2 * F + col]) : 0.f;
+      float zp[2][NB][4];
+      load_acc_rows<2, NB>(z2, 2 * F, p0, nvalid, col0, zp);
+      wave_mm<NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
+      __syncthreads();
+      for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
+        sG[row * L2 + col] = row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f;
       });
     }
     __syncthreads();
-    {  // dz1 = (dz2 Wb) silu'(z1)  (stored over the dz3 buffer)
+    {  // dz1 = (dz2 Wb) silu'(z1)
       constexpr int NB = F / 64;
       floatx4 acc[2][NB];
       zero_acc(acc);
       const int col0 = wave * (F / 4);
-      wave_mm<NB>(sG2, L2, 2 * F, a.WbT[l], col0, acc);
-      for_acc(acc, col0, [&](int row, int col, float v) {
-        sG3[row * L1 + col] = row < nvalid ? v * silu_grad(z1[(p0 + row) * F + col]) : 0.f;
+      float zp[2][NB][4];
+      load_acc_rows<2, NB>(z1, F, p0, nvalid, col0, zp);
+      wave_mm<NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
+      __syncthreads();
+      for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
+        sG[row * L1 + col] = row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f;
       });
     }
     __syncthreads();
-    if (wave < NWDE) wave_mm<1>(sG3, L1, F, a.WaT[l], wave * 16, de);   // de += dz1 Wa
+    if (wave < NWDE) wave_mm<1>(sG, L1, F, a.WaT[l], wave * 16, de);   // de += dz1 Wa
     __syncthreads();
   }
 
-  float *sDE = sG2;   // [32][K+4]
+  float *sDE = sG;   // [32][K+4]
   if (wave < NWDE)
-    for_acc(de, wave * 16, [&](int row, int col, float v) { sDE[row * LE + col] = v; });
+    for_acc_rc(de, wave * 16, [&](int, int, int, int row, int col, float v) { sDE[row * LE + col] = v; });
   __syncthreads();
   if (tid < nvalid)
     geometry_adjoint_rows<K>(g, sDE + tid * LE, 0, sDphi[tid], sDv[tid], a.alpha, a.r_lo, a.mu, a.beta,
@@ -405,14 +491,6 @@ constexpr int kPadB = 8;   // LDS row padding (bf16 elements)
 
 __device__ __forceinline__ floatx4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-template <int NB>
-__device__ __forceinline__ void zero_acc4(floatx4 (&acc)[4][NB]) {
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 }
 
 // acc[rb][cb] += act[64 x Kin] (LDS bf16, row stride ld) * Bt^T (Bt [ncol][Kin] bf16 in global memory).
@@ -445,17 +523,6 @@ __device__ __forceinline__ void wave_mm_bf16(const __bf16 *act, int ld, int Kin,
   }
 }
 
-template <int NB, class Fn>
-__device__ __forceinline__ void for_acc4(const floatx4 (&acc)[4][NB], int col0, Fn &&f) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) f(rb * 16 + 4 * (lane >> 4) + t, col0 + cb * 16 + (lane & 15), acc[rb][cb][t]);
-}
-
 template <int F, int K>
 __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
   constexpr int LE = K + kPadB, L1 = F + kPadB, L2 = 2 * F + kPadB;
@@ -464,7 +531,7 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
   __shared__ __attribute__((aligned(16))) __bf16 sA2[kTileB * L2];
   __shared__ double sD[kTileB], sPhi[kTileB];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = (int64_t)blockIdx.x * kTileB;
+  const int64_t p0 = xcd_block() * kTileB;
   if (p0 >= P) return;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < kTileB ? (P - p0) : kTileB);
@@ -472,7 +539,7 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
     double d = a.r_c, ph = 0.0;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
-      const PairGeo g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.periodic, a.box, a.r_c);
+      const PairGeo g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.lat, a.r_c);
       d = g.d;
       ph = g.phi;
       a.geo[4 * p + 0] = (float)g.u[0];
@@ -495,24 +562,27 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
   {
     constexpr int NB = 3 * F / 64;
     floatx4 acc[4][NB];
-    zero_acc4(acc);
+    zero_acc_rb<4, NB>(acc);
     const int col0 = wave * (3 * F / 4);
+    float br[NB];
+    load_cols<NB>(a.b0, col0, br);
     wave_mm_bf16<NB>(sE, LE, K, a.W0, col0, acc);
-    for_acc4(acc, col0, [&](int row, int col, float v) {
-      if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = v + a.b0[col];
+    for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+      if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = v + br[cb];
     });
   }
   for (int l = 0; l < a.L; ++l) {
     {
       constexpr int NB = F / 64;
       floatx4 acc[4][NB];
-      zero_acc4(acc);
+      zero_acc_rb<4, NB>(acc);
       const int col0 = wave * (F / 4);
+      float br[NB];
+      load_cols<NB>(a.ba[l], col0, br);
       wave_mm_bf16<NB>(sE, LE, K, a.Wa[l], col0, acc);
       __bf16 *z1 = a.z1[l];
-      const float *bias = a.ba[l];
-      for_acc4(acc, col0, [&](int row, int col, float v) {
-        const float z = v + bias[col];
+      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+        const float z = v + br[cb];
         if (row < nvalid) z1[(p0 + row) * F + col] = (__bf16)z;
         sA1[row * L1 + col] = (__bf16)silu(z);
       });
@@ -521,13 +591,14 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
     {
       constexpr int NB = F / 32;
       floatx4 acc[4][NB];
-      zero_acc4(acc);
+      zero_acc_rb<4, NB>(acc);
       const int col0 = wave * (F / 2);
+      float br[NB];
+      load_cols<NB>(a.bb[l], col0, br);
       wave_mm_bf16<NB>(sA1, L1, F, a.Wb[l], col0, acc);
       __bf16 *z2 = a.z2[l];
-      const float *bias = a.bb[l];
-      for_acc4(acc, col0, [&](int row, int col, float v) {
-        const float z = v + bias[col];
+      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+        const float z = v + br[cb];
         if (row < nvalid) z2[(p0 + row) * 2 * F + col] = (__bf16)z;
         sA2[row * L2 + col] = (__bf16)silu(z);
       });
@@ -536,14 +607,15 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
     {
       constexpr int NB = 3 * F / 64;
       floatx4 acc[4][NB];
-      zero_acc4(acc);
+      zero_acc_rb<4, NB>(acc);
       const int col0 = wave * (3 * F / 4);
+      float br[NB];
+      load_cols<NB>(a.bc[l], col0, br);
       wave_mm_bf16<NB>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
       __bf16 *z3 = a.z3[l];
       float *h = a.h[l];
-      const float *bias = a.bc[l];
-      for_acc4(acc, col0, [&](int row, int col, float v) {
-        const float z = v + bias[col];
+      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+        const float z = v + br[cb];
         if (row < nvalid) {
           z3[(p0 + row) * 3 * F + col] = (__bf16)z;
           h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * silu(z);
@@ -556,12 +628,11 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
 template <int F, int K>
 __global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
   constexpr int L3 = 3 * F + kPadB, L2 = 2 * F + kPadB, L1 = F + kPadB, LE = K + 4;
-  __shared__ __attribute__((aligned(16))) __bf16 sG3[kTileB * L3];   // df0, dz3, then dz1
-  __shared__ __attribute__((aligned(16))) __bf16 sG2[kTileB * L2];   // dz2
-  __shared__ __attribute__((aligned(16))) float sDE[kTileB * LE];
+  static_assert(kTileB * LE * 4 <= kTileB * L3 * 2, "dE/de must fit in the adjoint buffer");
+  __shared__ __attribute__((aligned(16))) __bf16 sG[kTileB * L3];   // df0, dz3, dz2, dz1; finally dE/de (f32)
   __shared__ float sPhi[kTileB], sDphi[kTileB], sU[kTileB][3], sDv[kTileB][3];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = (int64_t)blockIdx.x * kTileB;
+  const int64_t p0 = xcd_block() * kTileB;
   if (p0 >= P) return;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < kTileB ? (P - p0) : kTileB);
@@ -571,7 +642,7 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
     float ph = 0.f;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
-      g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.periodic, a.box, a.r_c);
+      g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.lat, a.r_c);
       ph = (float)g.phi;
     }
     sPhi[tid] = ph;
@@ -580,44 +651,51 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
     sU[tid][2] = (float)g.u[2];
   }
   __syncthreads();
-  embed_adjoint_rows<F>(a.g, a.pairs, a.max_pairs, p0, kTileB, nvalid, sU, sPhi, sG3, L3, sDphi, sDv);
+  embed_adjoint_rows<F, kTileB>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
   __syncthreads();
   floatx4 de[4][1];
-  zero_acc4(de);
-  if (wave < NWDE) wave_mm_bf16<1>(sG3, L3, 3 * F, a.W0T, wave * 16, de);
+  zero_acc_rb<4, 1>(de);
+  if (wave < NWDE) wave_mm_bf16<1>(sG, L3, 3 * F, a.W0T, wave * 16, de);
   __syncthreads();
   for (int l = 0; l < a.L; ++l) {
     const __bf16 *z1 = a.z1[l], *z2 = a.z2[l];
-    filter_adjoint_rows<F>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, kTileB, nvalid, sPhi, sG3, L3,
-                           sDphi);
+    filter_adjoint_rows<F, kTileB>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
+                                   sDphi);
     __syncthreads();
     {
       constexpr int NB = F / 32;
       floatx4 acc[4][NB];
-      zero_acc4(acc);
+      zero_acc_rb<4, NB>(acc);
       const int col0 = wave * (F / 2);
-      wave_mm_bf16<NB>(sG3, L3, 3 * F, a.WcT[l], col0, acc);
-      for_acc4(acc, col0, [&](int row, int col, float v) {
-        sG2[row * L2 + col] = (__bf16)(row < nvalid ? v * silu_grad((float)z2[(p0 + row) * 2 * F + col]) : 0.f);
+      float zp[4][NB][4];
+      load_acc_rows<4, NB>(z2, 2 * F, p0, nvalid, col0, zp);
+      wave_mm_bf16<NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
+      __syncthreads();
+      for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
+        sG[row * L2 + col] = (__bf16)(row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f);
       });
     }
     __syncthreads();
     {
       constexpr int NB = F / 64;
       floatx4 acc[4][NB];
-      zero_acc4(acc);
+      zero_acc_rb<4, NB>(acc);
       const int col0 = wave * (F / 4);
-      wave_mm_bf16<NB>(sG2, L2, 2 * F, a.WbT[l], col0, acc);
-      for_acc4(acc, col0, [&](int row, int col, float v) {
-        sG3[row * L1 + col] = (__bf16)(row < nvalid ? v * silu_grad((float)z1[(p0 + row) * F + col]) : 0.f);
+      float zp[4][NB][4];
+      load_acc_rows<4, NB>(z1, F, p0, nvalid, col0, zp);
+      wave_mm_bf16<NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
+      __syncthreads();
+      for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
+        sG[row * L1 + col] = (__bf16)(row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f);
       });
     }
     __syncthreads();
-    if (wave < NWDE) wave_mm_bf16<1>(sG3, L1, F, a.WaT[l], wave * 16, de);
+    if (wave < NWDE) wave_mm_bf16<1>(sG, L1, F, a.WaT[l], wave * 16, de);
     __syncthreads();
   }
+  float *sDE = reinterpret_cast<float *>(sG);
   if (wave < NWDE)
-    for_acc4(de, wave * 16, [&](int row, int col, float v) { sDE[row * LE + col] = v; });
+    for_acc_rc(de, wave * 16, [&](int, int, int, int row, int col, float v) { sDE[row * LE + col] = v; });
   __syncthreads();
   if (tid < nvalid)
     geometry_adjoint_rows<K>(g, sDE + tid * LE, 0, sDphi[tid], sDv[tid], a.alpha, a.r_lo, a.mu, a.beta,

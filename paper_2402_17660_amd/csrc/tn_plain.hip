@@ -160,9 +160,7 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
   const int32_t *zz = gr.z;
   pos = gr.pos;
 
-  BoxLen bl;
-  bl.periodic = pb.box.periodic;
-  for (int a = 0; a < 3; ++a) bl.len[a] = pb.box.len[a];
+  const Lattice bl = pb.box.lat;
   if (MP > 0) {
     hipLaunchKernelGGL(k_geom<T>, dim3(grid_for(MP, bs)), dim3(bs), 0, s, gr.pairs, MP, np, pos, bl, m->r_c, m->r_lo,
                        m->alpha, WA(o.mu), WA(o.beta), (int)K, w.geo, w.phi, w.rbf);

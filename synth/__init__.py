@@ -16,6 +16,7 @@ from .generators import (  # noqa: F401
     make_weights,
     maxwell_boltzmann,
     periodic_box,
+    random_cloud,
     molecule_batch,
     single_molecule,
 )

@@ -137,6 +137,20 @@ def periodic_box(n: int, seed: int, box_len: float | None = None, density: float
                 batch=np.zeros(n, dtype=np.int32), box=box, n_systems=1)
 
 
+def random_cloud(n: int, n_batches: int, seed: int, neighbors: float = 64.0, cutoff: float = 5.0):
+    """Neighbour-search benchmark shape: n points iid uniform in a periodic cube whose density puts
+    `neighbors` points within `cutoff` of a point on average, split into n_batches systems of
+    (nearly) equal size by contiguous index ranges (sorted batch vector), so every system is spread
+    over the whole box."""
+    rng = np.random.default_rng(seed)
+    density = neighbors / (4.0 / 3.0 * math.pi * cutoff ** 3)
+    box_len = (n / density) ** (1.0 / 3.0)
+    pos = rng.uniform(0.0, box_len, size=(n, 3))
+    batch = (np.arange(n, dtype=np.int64) * n_batches // max(n, 1)).astype(np.int32)
+    box = np.diag([box_len, box_len, box_len]).astype(np.float64)
+    return dict(pos=pos.astype(np.float32), batch=batch, box=box, n_systems=int(n_batches))
+
+
 @functools.lru_cache(maxsize=8)
 def _config_cached(cfg: int):
     c = CONFIGS[cfg]

@@ -82,3 +82,35 @@ def test_md_graph_consistency_and_conservation(dev):
     drift = abs((e1 + ke_end) - (es + ks))
     print(f"MD: E_pot {es:.6f} -> {e1:.6f}, E_kin {ks:.6f} -> {ke_end:.6f}, total drift {drift:.3e}", flush=True)
     assert drift < 1e-3 * max(1.0, abs(es))
+
+
+def test_md_triclinic_cell_wraps_and_conserves(dev):
+    from tests.util import random_in_cell, random_triclinic_cell
+    H = random_triclinic_cell(81, 4.5, (2.6, 3.0))
+    pos0, z = random_in_cell(200, 81, H)
+    rng = np.random.default_rng(82)
+    m_amu = np.array([MASS_BY_Z[int(a)] for a in z])
+    vel0 = rng.normal(0.0, 0.01, size=(200, 3))
+    vel0 -= (m_amu[:, None] * vel0).sum(0) / m_amu.sum()
+    model = TensorNet(small_blob(F=64, K=32, L=2, seed=83, r_c=4.5), dev)
+    batch = np.zeros(200, np.int32)
+    pos, zt, bt = _inputs(dev, pos0, z, batch)
+    vel = torch.tensor(vel0.astype(np.float32), device=dev)
+    im = torch.tensor((1.0 / m_amu).astype(np.float32), device=dev)
+    E, Fo = model.energy_forces(pos, zt, bt, 1, box=H, max_pairs=20000, precision="fp32")
+    es = float(E[0])
+    ks = 0.5 * float((m_amu[:, None] * vel0 ** 2).sum()) / 9.648533212e-3
+    g, E_out, F_out, n_pairs, status = capture(model, pos, zt, bt, 1, box=H, max_pairs=20000, precision="fp32",
+                                               n_steps=20, vel=vel, inv_mass=im, dt_fs=0.1, forces_out=Fo)
+    g.replay()
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    p = pos.cpu().numpy().astype(np.float64)
+    frac = p @ np.linalg.inv(H)
+    assert frac.min() >= -1e-5 and frac.max() <= 1.0 + 1e-5      # wrapped into the cell
+    v1 = vel.cpu().numpy().astype(np.float64)
+    ke = 0.5 * float((m_amu[:, None] * v1 ** 2).sum()) / 9.648533212e-3
+    drift = abs((float(E_out[0]) + ke) - (es + ks))
+    print(f"triclinic MD: E_pot {es:.6f} -> {float(E_out[0]):.6f}, total drift {drift:.3e}", flush=True)
+    assert drift < 1e-3 * max(1.0, abs(es))
+    g.close()

@@ -187,3 +187,23 @@ def test_autograd_function(dev, cfg0):
     E = TensorNetEF.apply(m, p, zt, bt, 1, None, None, "fp64", "plain")
     (2.0 * E.sum()).backward()
     assert rel_rms(-p.grad.cpu().numpy() / 2.0, F_ref) <= 1e-10
+
+
+# ---------------------------------------------------------------- triclinic cells
+from tests.util import random_in_cell, random_triclinic_cell  # noqa: E402
+
+
+@pytest.mark.parametrize("precision,path,F,K", [("fp64", "plain", 16, 8), ("fp32", "plain", 32, 16),
+                                                ("fp32", "fused", 64, 16), ("fp32", "fused", 128, 32),
+                                                ("bf16", "fused", 128, 32)])
+def test_triclinic_cell(dev, precision, path, F, K):
+    H = random_triclinic_cell(61, 4.5, (2.2, 3.0))
+    pos, z = random_in_cell(150, 61, H)
+    # unwrapped input: atoms shifted by lattice vectors
+    pos = (pos + np.random.default_rng(62).integers(-1, 2, size=pos.shape) @ H).astype(np.float32)
+    batch = np.zeros(150, np.int32)
+    blob = small_blob(F=F, K=K, L=2, seed=63)
+    print(f"triclinic {precision} {path} F={F} K={K} cell rows {H.tolist()}", flush=True)
+    E_ref, F_ref = TensorNetOracle(blob).energy_forces(pos, z, batch, H, 1)
+    E, Fv = gpu_ef(dev, TensorNet(blob, dev), pos, z, batch, H, 1, precision, path)
+    assert_close(E, Fv, E_ref, F_ref, precision, f"triclinic150 {precision} {path}")

@@ -9,24 +9,24 @@ import torch
 from oracle.neighbors import brute_force_pairs, neighbor_pairs
 from paper_2402_17660_amd import _lib as L
 from paper_2402_17660_amd import build_neighbors
-from synth import make_config
+from synth import make_config, random_cloud
 from tests.util import random_box, random_molecule
 
 pytestmark = pytest.mark.gpu
 
 
-def gpu_pairs(dev, pos, batch, box, cutoff, max_pairs, f64=False):
+def gpu_pairs(dev, pos, batch, box, cutoff, max_pairs, f64=False, method="auto"):
     p = torch.tensor(np.asarray(pos), dtype=torch.float64 if f64 else torch.float32, device=dev)
     b = torch.tensor(np.asarray(batch), dtype=torch.int32, device=dev)
-    pairs, n_pairs, status = build_neighbors(p, b, cutoff, max_pairs, box=box, check=False)
+    pairs, n_pairs, status = build_neighbors(p, b, cutoff, max_pairs, box=box, check=False, method=method)
     torch.cuda.synchronize()
     return pairs.cpu().numpy(), int(n_pairs.item()), int(status.item())
 
 
-def check_against_oracle(dev, pos, batch, box, cutoff, slack=1000, f64=False):
+def check_against_oracle(dev, pos, batch, box, cutoff, slack=1000, f64=False, method="auto"):
     ref = neighbor_pairs(np.asarray(pos, dtype=np.float64 if f64 else np.float32), batch, box, cutoff)
     max_pairs = len(ref) + slack
-    pr, n, st = gpu_pairs(dev, pos, batch, box, cutoff, max_pairs, f64=f64)
+    pr, n, st = gpu_pairs(dev, pos, batch, box, cutoff, max_pairs, f64=f64, method=method)
     assert st == 0, st
     assert n == len(ref)
     got = pr[:, :n].T.astype(np.int64)
@@ -130,3 +130,71 @@ def test_nonfinite_position_flagged(dev):
     pr, n, st = gpu_pairs(dev, pos, np.zeros(50, np.int32), box, 4.5, 4000)
     assert st & L.TN_STATUS_NONFINITE
     assert not np.any(pr[:, :n] == 3)
+
+
+# ---------------------------------------------------------------- search strategies
+# The benchmark shape of the neighbour-search study: a uniform random cloud with 64
+# neighbours per point on average in a periodic cube, split into systems by index range.
+@pytest.mark.parametrize("method", ["cell", "brute"])
+@pytest.mark.parametrize("n,n_batches,seed", [(2000, 1, 11), (2000, 2, 12), (3000, 64, 13), (777, 5, 14),
+                                              (130, 1, 15)])
+def test_random_cloud_strategies(dev, method, n, n_batches, seed):
+    c = random_cloud(n, n_batches, seed)
+    print(f"random cloud n={n} batches={n_batches} method={method}", flush=True)
+    ref = check_against_oracle(dev, c["pos"], c["batch"], c["box"], 5.0, method=method)
+    assert np.all(c["batch"][ref[:, 0]] == c["batch"][ref[:, 1]])
+
+
+def test_strategy_order_is_deterministic(dev):
+    c = random_cloud(1500, 3, 16)
+    mp = 60_000
+    for method in ("cell", "brute"):
+        a = gpu_pairs(dev, c["pos"], c["batch"], c["box"], 5.0, mp, method=method)
+        b = gpu_pairs(dev, c["pos"], c["batch"], c["box"], 5.0, mp, method=method)
+        assert a[2] == 0 and a[1] == b[1]
+        assert np.array_equal(a[0], b[0])
+    # the brute force keeps the caller's order: pairs come sorted by (i, j)
+    pr, n, _ = gpu_pairs(dev, c["pos"], c["batch"], c["box"], 5.0, mp, method="brute")
+    got = pr[:, :n].T.astype(np.int64)
+    assert np.array_equal(got, got[np.lexsort((got[:, 1], got[:, 0]))])
+
+
+def test_strategy_overflow_reports_true_count(dev):
+    c = random_cloud(1000, 1, 17)
+    ref = neighbor_pairs(c["pos"], c["batch"], c["box"], 5.0)
+    for method in ("cell", "brute"):
+        pr, n, st = gpu_pairs(dev, c["pos"], c["batch"], c["box"], 5.0, len(ref) - 10, method=method)
+        assert n == len(ref)
+        assert st & L.TN_STATUS_OVERFLOW
+        assert np.all(pr == -1)
+
+
+def test_cell_strategy_needs_a_box(dev):
+    mol, _ = random_molecule(20, 18)
+    with pytest.raises(Exception):
+        gpu_pairs(dev, mol, np.zeros(20, np.int32), None, 5.0, 1000, method="cell")
+
+
+# ---------------------------------------------------------------- triclinic cells
+from tests.util import random_in_cell, random_triclinic_cell  # noqa: E402
+
+
+@pytest.mark.parametrize("method", ["auto", "brute"])
+@pytest.mark.parametrize("seed,n,scale", [(71, 60, (2.0, 2.3)), (72, 150, (2.4, 3.4)), (73, 400, (3.0, 4.5)),
+                                          (74, 1500, (5.0, 7.0))])
+def test_triclinic_pair_sets(dev, method, seed, n, scale):
+    H = random_triclinic_cell(seed, 4.5, scale)
+    pos, _ = random_in_cell(n, seed, H, dmin=0.5)
+    pos = (pos + np.random.default_rng(seed).integers(-2, 3, size=pos.shape) @ H).astype(np.float32)
+    print(f"triclinic pairs n={n} seed={seed} method={method}", flush=True)
+    check_against_oracle(dev, pos, np.zeros(n, np.int32), H, 4.5, method=method)
+
+
+def test_triclinic_two_systems_one_cell(dev):
+    H = random_triclinic_cell(75, 4.5, (3.0, 3.5))
+    p1, _ = random_in_cell(200, 75, H)
+    p2, _ = random_in_cell(150, 76, H)
+    pos = np.concatenate([p1, p2]).astype(np.float32)
+    batch = np.array([0] * 200 + [1] * 150, np.int32)
+    ref = check_against_oracle(dev, pos, batch, H, 4.5)
+    assert np.all(batch[ref[:, 0]] == batch[ref[:, 1]])

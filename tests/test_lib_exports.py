@@ -59,11 +59,17 @@ def test_blob_rejected_on_host():
 def test_box_validation_on_host():
     lib = L.lib()
     small = (ctypes.c_double * 9)(8.0, 0, 0, 0, 8.0, 0, 0, 0, 8.0)
-    tilted = (ctypes.c_double * 9)(20.0, 0, 0, 1.0, 20.0, 0, 0, 0, 20.0)
+    tilted = (ctypes.c_double * 9)(20.0, 1.0, 0, 0, 20.0, 0, 0, 0, 20.0)      # not lower triangular
+    unreduced = (ctypes.c_double * 9)(20.0, 0, 0, 12.0, 20.0, 0, 0, 0, 20.0)  # |b_x| > a_x / 2
+    flat = (ctypes.c_double * 9)(20.0, 0, 0, 0, 20.0, 0, 10.0, 10.0, 8.5)     # height c_z < 2 r_c
+    triclinic = (ctypes.c_double * 9)(20.0, 0, 0, 5.0, 19.0, 0, -4.0, 6.0, 18.0)
     ok = (ctypes.c_double * 9)(20.0, 0, 0, 0, 20.0, 0, 0, 0, 20.0)
     cast = lambda a: ctypes.cast(a, ctypes.c_void_p)
     assert lib.tn_neighbor_workspace_bytes(100, 1000, cast(small), 4.5) == 0
     assert lib.tn_neighbor_workspace_bytes(100, 1000, cast(tilted), 4.5) == 0
+    assert lib.tn_neighbor_workspace_bytes(100, 1000, cast(unreduced), 4.5) == 0
+    assert lib.tn_neighbor_workspace_bytes(100, 1000, cast(flat), 4.5) == 0
+    assert lib.tn_neighbor_workspace_bytes(100, 1000, cast(triclinic), 4.5) > 0
     assert lib.tn_neighbor_workspace_bytes(100, 1000, cast(ok), 4.5) > 0
     assert lib.tn_neighbor_workspace_bytes(100, 1000, None, 4.5) > 0
     one = ctypes.c_void_p(1)   # never dereferenced: the call fails validation first
@@ -71,5 +77,27 @@ def test_box_validation_on_host():
     assert rc == L.TN_E_BOX
     rc = lib.tn_build_neighbors(None, 10, one, 0, one, cast(tilted), 4.5, 100, one, one, one, one, 1 << 20)
     assert rc == L.TN_E_ARG
+    rc = lib.tn_build_neighbors(None, 10, one, 0, one, cast(unreduced), 4.5, 100, one, one, one, one, 1 << 20)
+    assert rc == L.TN_E_ARG
+    rc = lib.tn_build_neighbors(None, 10, one, 0, one, cast(flat), 4.5, 100, one, one, one, one, 1 << 20)
+    assert rc == L.TN_E_BOX
     rc = lib.tn_build_neighbors(None, 10, one, 0, one, cast(ok), 4.5, 100, one, one, one, one, 16)
+    assert rc == L.TN_E_WORKSPACE
+
+
+def test_neighbor_method_validation_on_host():
+    lib = L.lib()
+    ok = (ctypes.c_double * 9)(20.0, 0, 0, 0, 20.0, 0, 0, 0, 20.0)
+    cast = lambda a: ctypes.cast(a, ctypes.c_void_p)
+    one = ctypes.c_void_p(1)   # never dereferenced: the call fails validation first
+    args = (None, 10, one, 0, one)
+    rc = lib.tn_build_neighbors_method(*args, cast(ok), 4.5, 100, one, one, one, one, 1 << 20, 7)
+    assert rc == L.TN_E_ARG
+    rc = lib.tn_build_neighbors_method(*args, None, 4.5, 100, one, one, one, one, 1 << 20, L.TN_NBR_CELL)
+    assert rc == L.TN_E_UNSUPPORTED
+    # the brute force in a box still validates the box and the workspace
+    small = (ctypes.c_double * 9)(8.0, 0, 0, 0, 8.0, 0, 0, 0, 8.0)
+    rc = lib.tn_build_neighbors_method(*args, cast(small), 4.5, 100, one, one, one, one, 1 << 20, L.TN_NBR_BRUTE)
+    assert rc == L.TN_E_BOX
+    rc = lib.tn_build_neighbors_method(*args, cast(ok), 4.5, 100, one, one, one, one, 16, L.TN_NBR_BRUTE)
     assert rc == L.TN_E_WORKSPACE
