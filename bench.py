@@ -50,6 +50,28 @@ def timed_kernels(path, F, K, L):
     return {"edge_fwd": per_pair, "edge_bwd": per_pair}
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "edge_kernels_fp32_box6000_hbm_counters.md")
+
+
+def measured_traffic(kernel, precision):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, or None when
+    there is none for it or the kernel sources changed since the counters were taken."""
+    import hashlib
+    if kernel != "edge_bwd" or precision != "fp32" or not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_SUMMARY):
+        k, _, v = line.strip().partition(": ")
+        if k in ("edge_bwd_traffic_bytes", "kernel_sources_sha256"):
+            fields[k] = v
+    csrc = os.path.join(ROOT, "paper_2402_17660_amd", "csrc")
+    h = hashlib.sha256(b"".join(open(os.path.join(csrc, n), "rb").read()
+                                for n in ("tn_pair.hip", "tn_mfma.h", "tn_device.h", "tn_internal.h"))).hexdigest()
+    if fields.get("kernel_sources_sha256") != h or "edge_bwd_traffic_bytes" not in fields:
+        return None
+    return float(fields["edge_bwd_traffic_bytes"])
+
+
 def cpu_baseline(n_atoms, F, K, L, r_c, seed):
     import numpy as np
     import torch
@@ -182,7 +204,8 @@ def main():
     head = next((r for r in avail if r["path"] == "fused" and r["precision"] == "fp32"), None) or avail[0]
     k = head["kernel"]
     roofline = dict(bound="mfma", achieved=k["achieved_tflops"], peak=k["peak_tflops"], unit="TFLOP/s",
-                    frac=(k["achieved_tflops"] / k["peak_tflops"]) if k["achieved_tflops"] else None, traffic=None,
+                    frac=(k["achieved_tflops"] / k["peak_tflops"]) if k["achieved_tflops"] else None,
+                    traffic=measured_traffic(k["name"], head["precision"]),
                     kernel=k["name"], avg_launch_ms=k["avg_ms"], flop_per_launch=k["flop_per_launch"])
     p_atom = n_pairs / N
     step_flop = algorithmic_flops_per_atom_step(F, K, L, p_atom) * N
