@@ -23,6 +23,12 @@
 namespace tn {
 
 constexpr int kTile = 32;   // pairs per tile
+#ifndef PAIR_FWD_BLOCKS
+#define PAIR_FWD_BLOCKS 3
+#endif
+#ifndef PAIR_BWD_BLOCKS
+#define PAIR_BWD_BLOCKS 3
+#endif
 constexpr int kPad = 4;     // LDS row padding (floats)
 
 bool pair_kernels_support(int F, int K, int L, bool bf16) {
@@ -103,12 +109,13 @@ __device__ inline PairGeo pair_geometry(const float *pos, int64_t i, int64_t j, 
 }
 
 // ============================================================================ forward
+// One LDS buffer holds the tile's current activation, silu(z1) and then silu(z2); each product
+// keeps its result in registers until every wave has finished reading the buffer.
 template <int F, int K>
-__global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
+__global__ void __launch_bounds__(256, PAIR_FWD_BLOCKS) k_pair_fwd(PairFwdArgs a) {
   constexpr int LE = K + kPad, L1 = F + kPad, L2 = 2 * F + kPad;
   __shared__ __attribute__((aligned(16))) float sE[kTile * LE];
-  __shared__ __attribute__((aligned(16))) float sA1[kTile * L1];
-  __shared__ __attribute__((aligned(16))) float sA2[kTile * L2];
+  __shared__ __attribute__((aligned(16))) float sA[kTile * L2];
   __shared__ double sD[kTile], sPhi[kTile];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
   const int64_t p0 = xcd_block() * kTile;
@@ -164,11 +171,12 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
       float br[NB];
       load_cols<NB>(a.ba[l], col0, br);
       wave_mm<NB>(sE, LE, K, a.Wa[l], col0, acc);
+      __syncthreads();   // the previous layer's last product has finished reading sA
       float *z1 = a.z1[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
         if (row < nvalid) z1[(p0 + row) * F + col] = z;
-        sA1[row * L1 + col] = silu(z);
+        sA[row * L1 + col] = silu(z);
       });
     }
     __syncthreads();
@@ -179,12 +187,13 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
       const int col0 = wave * (F / 2);
       float br[NB];
       load_cols<NB>(a.bb[l], col0, br);
-      wave_mm<NB>(sA1, L1, F, a.Wb[l], col0, acc);
+      wave_mm<NB>(sA, L1, F, a.Wb[l], col0, acc);
+      __syncthreads();
       float *z2 = a.z2[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
         if (row < nvalid) z2[(p0 + row) * 2 * F + col] = z;
-        sA2[row * L2 + col] = silu(z);
+        sA[row * L2 + col] = silu(z);
       });
     }
     __syncthreads();
@@ -195,7 +204,7 @@ __global__ void __launch_bounds__(256, 2) k_pair_fwd(PairFwdArgs a) {
       const int col0 = wave * (3 * F / 4);
       float br[NB];
       load_cols<NB>(a.bc[l], col0, br);
-      wave_mm<NB>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
+      wave_mm<NB>(sA, L2, 2 * F, a.Wc[l], col0, acc);
       float *z3 = a.z3[l], *h = a.h[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
@@ -401,7 +410,7 @@ __device__ __forceinline__ void geometry_adjoint_rows(const PairGeo &g, const fl
 // finally dE/de.  Each product keeps its result in registers until every wave has finished
 // reading the buffer, so the tile needs ~50 KB of LDS and two blocks share a CU.
 template <int F, int K>
-__global__ void __launch_bounds__(256, 2) k_pair_bwd(PairBwdArgs a) {
+__global__ void __launch_bounds__(256, PAIR_BWD_BLOCKS) k_pair_bwd(PairBwdArgs a) {
   constexpr int L3 = 3 * F + kPad, L2 = 2 * F + kPad, L1 = F + kPad, LE = K + kPad;
   __shared__ __attribute__((aligned(16))) float sG[kTile * L3];
   __shared__ float sPhi[kTile], sDphi[kTile], sU[kTile][3], sDv[kTile][3];
