@@ -146,6 +146,9 @@ def main():
                                               path=path, check=False, energy_out=E_out, forces_out=F_out)
             run()
             model.check()
+            # pick the pair-tile shapes for this workload (setup, outside the timed region)
+            shapes = (model.autotune(pos, z, batch, 1, box=box, max_pairs=max_pairs, precision=prec, reps=5)
+                      if path == "fused" else None)
         except TensorNetError as e:
             log(f"{path}/{prec}: unavailable ({e})")
             results.append(dict(path=path, precision=prec, available=False))
@@ -184,8 +187,10 @@ def main():
         f_err = float(np.linalg.norm(Fo - golden["F"]) / np.linalg.norm(golden["F"]))
         dom = max(kernels, key=lambda k: k["ms_per_step"])
         res = dict(path=path, precision=prec, available=True, ms_per_step=ms, value=N / (ms * 1e-3),
-                   energy_rel_err=e_err, force_rel_rms=f_err, kernel=dom, kernels=kernels)
+                   energy_rel_err=e_err, force_rel_rms=f_err, kernel=dom, kernels=kernels,
+                   pair_tile_shapes=dict(forward=shapes[0], reverse=shapes[1]) if shapes else None)
         log(f"{path}/{prec}: {ms:.3f} ms/step, {res['value']:.3e} atom-steps/s, E err {e_err:.2e}, "
+            + (f"tile shapes {shapes}, " if shapes else "") +
             f"F err {f_err:.2e}, " + ", ".join(f"{k['name']} {k['avg_ms']:.3f} ms/launch "
                                                f"({k['achieved_tflops'] or 0:.1f} TFLOP/s)" for k in kernels))
         results.append(res)
@@ -260,6 +265,7 @@ def extra_batch(args, dev):
                         "2 layers, cutoff 5 A; one captured HIP graph per energy+forces call",
                n_atoms=N, n_pairs=int(golden["n_pairs"]), max_pairs=mp)
     for prec in ("fp32", "bf16"):
+        shapes = model.autotune(pos, z, batch, c["n_systems"], max_pairs=mp, precision=prec, reps=3)
         g, E, Fo, n_pairs, status = capture(model, pos, z, batch, c["n_systems"], max_pairs=mp, precision=prec)
         for _ in range(3):
             g.replay()
@@ -274,7 +280,7 @@ def extra_batch(args, dev):
         ms = start.elapsed_time(stop) / reps
         Ev = E.cpu().numpy()
         Fv = Fo.double().cpu().numpy()
-        out[prec] = dict(ms_per_step=ms, value=N / (ms * 1e-3), status=int(status.item()),
+        out[prec] = dict(ms_per_step=ms, value=N / (ms * 1e-3), status=int(status.item()), pair_tile_shapes=shapes,
                          energy_rel_err=float(np.max(np.abs(Ev - golden["E"]) / np.abs(golden["E"]))),
                          force_rel_rms=float(np.linalg.norm(Fv - golden["F"]) / np.linalg.norm(golden["F"])))
         log(f"batch/{prec}: {ms:.3f} ms/step, {out[prec]['value']:.3e} atom-steps/s, "
@@ -307,6 +313,7 @@ def extra_md(args, dev):
         n0 = int(model.n_pairs.item())
         mp = int(math.ceil(1.10 * n0 / 1024.0) * 1024)
         rms_f0 = float(torch.sqrt((F0.double() ** 2).mean()))
+        shapes = model.autotune(pos, z, batch, 1, box=c["box"], max_pairs=mp, precision=prec, reps=2)
         g, E, Fo, n_pairs, status = capture(model, pos, z, batch, 1, box=c["box"], max_pairs=mp, precision=prec,
                                             n_steps=args.md_steps, vel=vel, inv_mass=inv_m, dt_fs=1.0,
                                             forces_out=F0)
@@ -317,7 +324,7 @@ def extra_md(args, dev):
         torch.cuda.synchronize()
         ms = start.elapsed_time(stop)
         st = int(status.item())
-        out[prec] = dict(ms_per_replay=ms, ms_per_step=ms / args.md_steps,
+        out[prec] = dict(ms_per_replay=ms, ms_per_step=ms / args.md_steps, pair_tile_shapes=shapes,
                          value=N * args.md_steps / (ms * 1e-3), status=st, initial_pairs=n0, max_pairs=mp,
                          final_pairs=int(n_pairs.item()), initial_rms_force=rms_f0,
                          energy_start=float(E0[0]), energy_end=float(E[0]))

@@ -153,6 +153,32 @@ int tn_energy_forces(const tn_model *m, void *stream, int64_t n_atoms, int64_t n
                      int precision, int path, double *energy, void *forces, int64_t *n_pairs, int32_t *status,
                      void *ws, size_t ws_bytes);
 
+/* ------------------------------------------------------ pair-tile tuning ---
+ * The fused path evaluates every layer's edge filter once per unordered pair
+ * in MFMA tiles (Sec. 2.5: per-pair work dominates; the paper picks kernel
+ * variants by input size).  The tiles come in several shapes (pairs per tile,
+ * workgroups per compute unit); each pair is computed with the same arithmetic
+ * in the same order in every shape, so results are bitwise independent of it.
+ *   tn_pair_variant_count(precision): number of shapes for TN_FP32 / TN_BF16
+ *     (0 for other precisions).
+ *   tn_model_set_pair_variant: forces a shape for the forward and the reverse
+ *     pair kernel (-1 = the tuned choice, else shape 0).  TN_E_ARG for an
+ *     out-of-range shape or precision.
+ *   tn_autotune: runs tn_energy_forces (TN_FUSED) on the given inputs with
+ *     every shape, `reps` timed calls each (1..1000), and records the fastest
+ *     forward and reverse shapes in the model for calls whose max_pairs has the
+ *     same bit length; `chosen` (host int32[2], may be NULL) receives them.
+ *     It leaves energy/forces/n_pairs/status as one call would, resets the
+ *     tn_timing_* registry and synchronises on its own timing events, so it must
+ *     not be captured: call it before tn_md_capture.
+ * Not thread-safe against other calls on the same model. */
+int tn_pair_variant_count(int precision);
+int tn_model_set_pair_variant(tn_model *m, int precision, int forward, int reverse);
+int tn_autotune(tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, const void *pos, const int32_t *z,
+                const int32_t *batch, const double *box, int64_t max_pairs, int precision, double *energy,
+                void *forces, int64_t *n_pairs, int32_t *status, void *ws, size_t ws_bytes, int reps,
+                int32_t *chosen);
+
 /* ------------------------------------------------------- graphs and MD ---
  * tn_md_capture records work on `stream` into a HIP graph and instantiates
  * it; nothing runs until tn_graph_replay.  The arguments of tn_energy_forces

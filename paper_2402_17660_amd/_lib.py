@@ -36,6 +36,10 @@ PROTOTYPES = {
                              _vp, _vp, _vp, _vp, _sz, _c.POINTER(_vp)]),
     "tn_graph_replay": (_i32, [_vp, _vp]),
     "tn_graph_destroy": (_i32, [_vp]),
+    "tn_pair_variant_count": (_i32, [_i32]),
+    "tn_model_set_pair_variant": (_i32, [_vp, _i32, _i32, _i32]),
+    "tn_autotune": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
+                           _vp]),
     "tn_timing_enable": (_i32, [_i32]),
     "tn_timing_reset": (_i32, []),
     "tn_timing_read": (_i32, [_c.c_char_p, _c.POINTER(_dbl), _c.POINTER(_i64)]),

@@ -192,6 +192,42 @@ class TensorNet:
         return self._run(pos, z, batch, n_systems, box, max_pairs, precision, path, True, check,
                          energy_out=energy_out, forces_out=forces_out)
 
+    @staticmethod
+    def pair_variant_count(precision="fp32") -> int:
+        return int(L.lib().tn_pair_variant_count(_PREC[precision]))
+
+    def set_pair_variant(self, precision="fp32", forward=-1, reverse=-1):
+        """Force the fused pair kernels' tile shapes (tn_model_set_pair_variant); -1 = tuned/default."""
+        _check(L.lib().tn_model_set_pair_variant(self._h, _PREC[precision], int(forward), int(reverse)),
+               "tn_model_set_pair_variant")
+
+    def autotune(self, pos, z, batch, n_systems, box=None, max_pairs=None, precision="fp32", reps=10):
+        """Time every pair-tile shape on these inputs (tn_autotune) and keep the fastest for this pair-budget
+        class; returns (forward shape, reverse shape).  Synchronises; never call it under capture."""
+        dev = self.device
+        _require_device(pos, "pos", torch.float32, dev)
+        _require_device(z, "z", torch.int32, dev)
+        _require_device(batch, "batch", torch.int32, dev)
+        n = pos.shape[0]
+        if max_pairs is None:
+            max_pairs = max(64 * n, 1)
+        boxarr, boxp = _box_arg(box)
+        nbytes = L.lib().tn_workspace_bytes(self._h, n, n_systems, max_pairs, boxp, _PREC[precision],
+                                            _PATH["fused"], 1)
+        if nbytes == 0:
+            raise TensorNetError(f"invalid request (precision={precision}, box, sizes)")
+        buf = self.ws.get(nbytes)
+        E = torch.empty(n_systems, dtype=torch.float64, device=dev)
+        Fo = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        chosen = (ctypes.c_int32 * 2)()
+        rc = L.lib().tn_autotune(self._h, _stream(dev), n, n_systems, _ptr(pos), _ptr(z), _ptr(batch), boxp,
+                                 max_pairs, _PREC[precision], _ptr(E), _ptr(Fo), _ptr(self.n_pairs),
+                                 _ptr(self.status), _ptr(buf), buf.numel(), int(reps),
+                                 ctypes.cast(chosen, ctypes.c_void_p))
+        _check(rc, "tn_autotune")
+        self.check()
+        return int(chosen[0]), int(chosen[1])
+
 
 class Graph:
     """An instantiated HIP graph (tn_md_capture); keeps every buffer it uses alive."""

@@ -192,6 +192,13 @@ TimedScope::~TimedScope() {
   (void)hipEventRecord(g_events[slot].b, stream);
 }
 
+bool timing_swap(bool on) {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  const bool was = g_timing_on;
+  g_timing_on = on;
+  return was;
+}
+
 }  // namespace tn
 
 extern "C" {
@@ -226,6 +233,68 @@ int tn_timing_read(const char *name, double *total_ms, int64_t *launches) {
   return TN_OK;
 }
 
+
+int tn_pair_variant_count(int precision) {
+  if (precision == TN_FP32) return pair_variant_count(false);
+  if (precision == TN_BF16) return pair_variant_count(true);
+  return 0;
+}
+
+int tn_model_set_pair_variant(tn_model *m, int precision, int forward, int reverse) {
+  if (!m || (precision != TN_FP32 && precision != TN_BF16)) return TN_E_ARG;
+  const int n = tn_pair_variant_count(precision);
+  if (forward < -1 || forward >= n || reverse < -1 || reverse >= n) return TN_E_ARG;
+  const int p = precision == TN_BF16 ? 1 : 0;
+  m->pair_force[p][0] = forward;
+  m->pair_force[p][1] = reverse;
+  return TN_OK;
+}
+
+int tn_autotune(tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, const void *pos, const int32_t *z,
+                const int32_t *batch, const double *box, int64_t max_pairs, int precision, double *energy,
+                void *forces, int64_t *n_pairs, int32_t *status, void *ws, size_t ws_bytes, int reps,
+                int32_t *chosen) {
+  if (!m || (precision != TN_FP32 && precision != TN_BF16) || reps < 1 || reps > 1000) return TN_E_ARG;
+  const int p = precision == TN_BF16 ? 1 : 0;
+  const int nv = tn_pair_variant_count(precision);
+  const int saved[2] = {m->pair_force[p][0], m->pair_force[p][1]};
+  const bool was_timing = timing_swap(true);
+  std::vector<double> tf(nv, 1e30), tb(nv, 1e30);
+  int rc = TN_OK;
+  for (int v = 0; v < nv && rc == TN_OK; ++v) {
+    m->pair_force[p][0] = m->pair_force[p][1] = v;
+    rc = tn_energy_forces(m, stream, n_atoms, n_systems, pos, z, batch, box, max_pairs, precision, TN_FUSED,
+                          energy, forces, n_pairs, status, ws, ws_bytes);   // warm-up
+    if (rc) break;
+    tn_timing_reset();
+    for (int r = 0; r < reps && rc == TN_OK; ++r)
+      rc = tn_energy_forces(m, stream, n_atoms, n_systems, pos, z, batch, box, max_pairs, precision, TN_FUSED,
+                            energy, forces, n_pairs, status, ws, ws_bytes);
+    if (rc) break;
+    double tot = 0.0;
+    int64_t cnt = 0;
+    if ((rc = tn_timing_read("edge_fwd", &tot, &cnt))) break;
+    if (cnt) tf[v] = tot / cnt;
+    if ((rc = tn_timing_read("edge_bwd", &tot, &cnt))) break;
+    if (cnt) tb[v] = tot / cnt;
+  }
+  tn_timing_reset();
+  timing_swap(was_timing);
+  m->pair_force[p][0] = saved[0];
+  m->pair_force[p][1] = saved[1];
+  if (rc) return rc;
+  int bf = 0, bb = 0;
+  for (int v = 1; v < nv; ++v) {
+    if (tf[v] < tf[bf]) bf = v;
+    if (tb[v] < tb[bb]) bb = v;
+  }
+  m->pair_tuned[p][pair_budget_class(max_pairs)] = {bf, bb};
+  if (chosen) {
+    chosen[0] = bf;
+    chosen[1] = bb;
+  }
+  return TN_OK;
+}
 
 const char *tn_status_string(int status) {
   switch (status) {

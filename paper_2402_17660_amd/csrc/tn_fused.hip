@@ -8,6 +8,25 @@
 
 namespace tn {
 
+int pair_budget_class(int64_t max_pairs) {
+  int c = 0;
+  while (max_pairs > 0) {
+    ++c;
+    max_pairs >>= 1;
+  }
+  return c;
+}
+
+int pair_variant(const tn_model *m, bool bf16, int64_t max_pairs, bool reverse) {
+  const int prec = bf16 ? 1 : 0, dir = reverse ? 1 : 0;
+  int v = m->pair_force[prec][dir];
+  if (v < 0) {
+    auto it = m->pair_tuned[prec].find(pair_budget_class(max_pairs));
+    v = it != m->pair_tuned[prec].end() ? it->second[dir] : 0;
+  }
+  return (v >= 0 && v < pair_variant_count(bf16)) ? v : 0;
+}
+
 namespace {
 
 using TA = double;
@@ -156,7 +175,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     pf.geo = w.geo;
     pf.phi = w.phi;
     pf.f0 = w.f0;
-    if ((rc = launch_pair_fwd_bf16(s, (int)F, (int)K, pf))) return rc;
+    if ((rc = launch_pair_fwd_bf16(s, (int)F, (int)K, pf, pair_variant(m, true, MP, false)))) return rc;
   } else {
     PairFwdArgs pf;
     fill_common(pf);
@@ -178,7 +197,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     pf.geo = w.geo;
     pf.phi = w.phi;
     pf.f0 = w.f0;
-    if ((rc = launch_pair_fwd(s, (int)F, (int)K, pf))) return rc;
+    if ((rc = launch_pair_fwd(s, (int)F, (int)K, pf, pair_variant(m, false, MP, false)))) return rc;
   }
 
   // ---- embedding node stage (FP64)
@@ -343,7 +362,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
       pbw.g.dM[l] = w.dM[l];
     }
     pbw.gpair = w.gpair;
-    if ((rc = launch_pair_bwd_bf16(s, (int)F, (int)K, pbw))) return rc;
+    if ((rc = launch_pair_bwd_bf16(s, (int)F, (int)K, pbw, pair_variant(m, true, MP, true)))) return rc;
   } else {
     PairBwdArgs pbw;
     fill_common(pbw);
@@ -366,7 +385,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
       pbw.g.dM[l] = w.dM[l];
     }
     pbw.gpair = w.gpair;
-    if ((rc = launch_pair_bwd(s, (int)F, (int)K, pbw))) return rc;
+    if ((rc = launch_pair_bwd(s, (int)F, (int)K, pbw, pair_variant(m, false, MP, true)))) return rc;
   }
   if (N > 0) {
     hipLaunchKernelGGL((k_force_gather_w<float, float>), dim3(wave_atom_grid(N)), dim3(256), 0, s, N, rowptr, nbr,

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <array>
+#include <map>
 #include <vector>
 
 #include "tensornet.h"
@@ -49,6 +51,11 @@ struct WeightOff {
 }  // namespace tn
 
 struct tn_model {
+  // Pair-kernel tile shapes [precision: 0 FP32, 1 BF16][0 forward, 1 reverse]: `pair_force`
+  // (>= 0) overrides; otherwise `pair_tuned` by pair-budget class (bit length of max_pairs),
+  // filled by tn_autotune; otherwise shape 0.
+  int pair_force[2][2] = {{-1, -1}, {-1, -1}};
+  std::map<int, std::array<int, 2>> pair_tuned[2];
   int device = 0;
   int F = 0, K = 0, L = 0, max_z = 0;
   double r_lo = 0.0, r_c = 0.0, alpha = 0.0;
@@ -156,6 +163,12 @@ constexpr int kMaxLayers = 16;
 
 // Whether the fused pair kernels support these sizes.
 bool pair_kernels_support(int F, int K, int L, bool bf16);
+// Number of tile shapes of the fused pair kernels (see tn_pair.hip).
+int pair_variant_count(bool bf16);
+// Pair-budget class of the tuning table: the bit length of max_pairs.
+int pair_budget_class(int64_t max_pairs);
+// The tile shape a fused call uses for this model, precision, budget and direction.
+int pair_variant(const tn_model *m, bool bf16, int64_t max_pairs, bool reverse);
 
 struct PairFwdArgs {
   const int32_t *pairs = nullptr;   // [2, max_pairs]
@@ -198,8 +211,8 @@ struct PairBwdArgs {
   float *gpair = nullptr;
 };
 
-int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a);
-int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a);
+int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a, int variant);
+int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a, int variant);
 
 // BF16-operand variants: weights and stored pre-activations in BF16, biases, basis
 // constants, h and every other stored quantity in FP32/FP64 as above.
@@ -237,12 +250,15 @@ struct PairBwdArgsB {
   float *gpair = nullptr;
 };
 
-int launch_pair_fwd_bf16(hipStream_t s, int F, int K, const PairFwdArgsB &a);
-int launch_pair_bwd_bf16(hipStream_t s, int F, int K, const PairBwdArgsB &a);
+int launch_pair_fwd_bf16(hipStream_t s, int F, int K, const PairFwdArgsB &a, int variant);
+int launch_pair_bwd_bf16(hipStream_t s, int F, int K, const PairBwdArgsB &a, int variant);
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // Event pair around the launches of a named kernel while timing is enabled.
+// Turns the timing registry on or off; returns the previous state.
+bool timing_swap(bool on);
+
 struct TimedScope {
   TimedScope(const char *name, hipStream_t s);
   ~TimedScope();

@@ -87,9 +87,9 @@ int tn_md_capture(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_sy
   hipStream_t s = static_cast<hipStream_t>(stream);
   Graph *g = new (std::nothrow) Graph();
   if (!g) return TN_E_ARG;
-  const int was_timing = tn_timing_enable(0) == TN_OK;   // no event records inside a graph
-  (void)was_timing;
+  const bool was_timing = timing_swap(false);   // no event records inside a graph
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    timing_swap(was_timing);
     delete g;
     return TN_E_HIP;
   }
@@ -121,6 +121,7 @@ int tn_md_capture(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_sy
   }
   hipGraph_t graph = nullptr;
   const hipError_t e_end = hipStreamEndCapture(s, &graph);
+  timing_swap(was_timing);
   if (rc != TN_OK || e_end != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     delete g;

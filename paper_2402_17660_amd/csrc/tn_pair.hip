@@ -9,8 +9,9 @@
 //             atoms' adjoint rows (gathered in the tile's prologue), then per layer
 //             dz3 = dh phi silu'(z3), dz2 = (dz3 Wc) silu'(z2), dz1 = (dz2 Wb) silu'(z1),
 //             de += dz1 Wa;  de += df0 W0;  then dE/dv from de, dE/dphi, dE/dvhat (FP64)
-// Tiles hold 32 pairs; the four waves of a workgroup split the output columns, each wave
-// covering all 32 rows in two 16-row MFMA blocks.  Activations live in LDS (row padding of
+// Tiles hold 16 RB pairs (RB = 1, 2, 4; see the launchers); the four waves of a workgroup
+// split the output columns, each wave covering all rows in RB 16-row MFMA blocks.
+// Activations live in LDS (row padding of
 // 4 floats), weights stream from L2 as 16-byte loads.  The K index inside each 16-wide
 // chunk is permuted (lane group q takes k = 4q..4q+3) so that one 16-byte load feeds four
 // consecutive MFMAs for both operands.
@@ -22,30 +23,11 @@
 
 namespace tn {
 
-constexpr int kTile = 32;   // pairs per tile
-#ifndef PAIR_FWD_BLOCKS
-#define PAIR_FWD_BLOCKS 3
-#endif
-#ifndef PAIR_BWD_BLOCKS
-#define PAIR_BWD_BLOCKS 3
-#endif
 constexpr int kPad = 4;     // LDS row padding (floats)
 
 bool pair_kernels_support(int F, int K, int L, bool bf16) {
   const bool k_ok = bf16 ? (K == 32 || K == 64) : (K == 16 || K == 32 || K == 48 || K == 64);
   return (F == 64 || F == 128) && k_ok && L >= 0 && L <= kMaxLayers;
-}
-
-// 32-row tile product (two 16-row MFMA blocks), see wave_mm_rb.
-template <int NB>
-__device__ __forceinline__ void wave_mm(const float *act, int ld, int Kin, const float *__restrict__ Bt, int col0,
-                                        floatx4 (&acc)[2][NB]) {
-  wave_mm_rb<2, NB>(act, ld, Kin, Bt, col0, acc);
-}
-
-template <int NB>
-__device__ __forceinline__ void zero_acc(floatx4 (&acc)[2][NB]) {
-  zero_acc_rb<2, NB>(acc);
 }
 
 // Visit this lane's accumulator entries: f(rb, cb, t, row, col, value).  Entry t of block
@@ -111,19 +93,20 @@ __device__ inline PairGeo pair_geometry(const float *pos, int64_t i, int64_t j, 
 // ============================================================================ forward
 // One LDS buffer holds the tile's current activation, silu(z1) and then silu(z2); each product
 // keeps its result in registers until every wave has finished reading the buffer.
-template <int F, int K>
-__global__ void __launch_bounds__(256, PAIR_FWD_BLOCKS) k_pair_fwd(PairFwdArgs a) {
+template <int F, int K, int RB, int MINB>
+__global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
+  constexpr int TILE = 16 * RB;
   constexpr int LE = K + kPad, L1 = F + kPad, L2 = 2 * F + kPad;
-  __shared__ __attribute__((aligned(16))) float sE[kTile * LE];
-  __shared__ __attribute__((aligned(16))) float sA[kTile * L2];
-  __shared__ double sD[kTile], sPhi[kTile];
+  __shared__ __attribute__((aligned(16))) float sE[TILE * LE];
+  __shared__ __attribute__((aligned(16))) float sA[TILE * L2];
+  __shared__ double sD[TILE], sPhi[TILE];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = xcd_block() * kTile;
+  const int64_t p0 = xcd_block() * TILE;
   if (p0 >= P) return;
   const int tid = threadIdx.x, wave = tid >> 6;
-  const int nvalid = (int)((P - p0) < kTile ? (P - p0) : kTile);
+  const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
 
-  if (tid < kTile) {
+  if (tid < TILE) {
     double d = a.r_c, ph = 0.0;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
@@ -141,7 +124,7 @@ __global__ void __launch_bounds__(256, PAIR_FWD_BLOCKS) k_pair_fwd(PairFwdArgs a
     sPhi[tid] = ph;
   }
   __syncthreads();
-  for (int t = tid; t < kTile * K; t += 256) {
+  for (int t = tid; t < TILE * K; t += 256) {
     const int row = t / K, k = t % K;
     const double u = exp(-a.alpha * (sD[row] - a.r_lo));
     const double x = u - a.mu[k];
@@ -152,12 +135,12 @@ __global__ void __launch_bounds__(256, PAIR_FWD_BLOCKS) k_pair_fwd(PairFwdArgs a
   // embedding map f0 = W0 e + b0  (3F outputs; wave covers 3F/4 columns)
   {
     constexpr int NB = 3 * F / 64;
-    floatx4 acc[2][NB];
-    zero_acc(acc);
+    floatx4 acc[RB][NB];
+    zero_acc_rb<RB, NB>(acc);
     const int col0 = wave * (3 * F / 4);
     float br[NB];
     load_cols<NB>(a.b0, col0, br);
-    wave_mm<NB>(sE, LE, K, a.W0, col0, acc);
+    wave_mm_rb<RB, NB>(sE, LE, K, a.W0, col0, acc);
     for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
       if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = v + br[cb];
     });
@@ -165,12 +148,12 @@ __global__ void __launch_bounds__(256, PAIR_FWD_BLOCKS) k_pair_fwd(PairFwdArgs a
   for (int l = 0; l < a.L; ++l) {
     {  // z1 = Wa e + ba
       constexpr int NB = F / 64;
-      floatx4 acc[2][NB];
-      zero_acc(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 4);
       float br[NB];
       load_cols<NB>(a.ba[l], col0, br);
-      wave_mm<NB>(sE, LE, K, a.Wa[l], col0, acc);
+      wave_mm_rb<RB, NB>(sE, LE, K, a.Wa[l], col0, acc);
       __syncthreads();   // the previous layer's last product has finished reading sA
       float *z1 = a.z1[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
@@ -182,12 +165,12 @@ __global__ void __launch_bounds__(256, PAIR_FWD_BLOCKS) k_pair_fwd(PairFwdArgs a
     __syncthreads();
     {  // z2 = Wb silu(z1) + bb
       constexpr int NB = F / 32;
-      floatx4 acc[2][NB];
-      zero_acc(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 2);
       float br[NB];
       load_cols<NB>(a.bb[l], col0, br);
-      wave_mm<NB>(sA, L1, F, a.Wb[l], col0, acc);
+      wave_mm_rb<RB, NB>(sA, L1, F, a.Wb[l], col0, acc);
       __syncthreads();
       float *z2 = a.z2[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
@@ -199,12 +182,12 @@ __global__ void __launch_bounds__(256, PAIR_FWD_BLOCKS) k_pair_fwd(PairFwdArgs a
     __syncthreads();
     {  // z3 = Wc silu(z2) + bc, h = phi silu(z3)
       constexpr int NB = 3 * F / 64;
-      floatx4 acc[2][NB];
-      zero_acc(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (3 * F / 4);
       float br[NB];
       load_cols<NB>(a.bc[l], col0, br);
-      wave_mm<NB>(sA, L2, 2 * F, a.Wc[l], col0, acc);
+      wave_mm_rb<RB, NB>(sA, L2, 2 * F, a.Wc[l], col0, acc);
       float *z3 = a.z3[l], *h = a.h[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
@@ -409,20 +392,21 @@ __device__ __forceinline__ void geometry_adjoint_rows(const PairGeo &g, const fl
 // One LDS buffer holds the tile's current adjoint: dE/df0, then per layer dz3, dz2, dz1, and
 // finally dE/de.  Each product keeps its result in registers until every wave has finished
 // reading the buffer, so the tile needs ~50 KB of LDS and two blocks share a CU.
-template <int F, int K>
-__global__ void __launch_bounds__(256, PAIR_BWD_BLOCKS) k_pair_bwd(PairBwdArgs a) {
+template <int F, int K, int RB, int MINB>
+__global__ void __launch_bounds__(256, MINB) k_pair_bwd(PairBwdArgs a) {
+  constexpr int TILE = 16 * RB;
   constexpr int L3 = 3 * F + kPad, L2 = 2 * F + kPad, L1 = F + kPad, LE = K + kPad;
-  __shared__ __attribute__((aligned(16))) float sG[kTile * L3];
-  __shared__ float sPhi[kTile], sDphi[kTile], sU[kTile][3], sDv[kTile][3];
+  __shared__ __attribute__((aligned(16))) float sG[TILE * L3];
+  __shared__ float sPhi[TILE], sDphi[TILE], sU[TILE][3], sDv[TILE][3];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = xcd_block() * kTile;
+  const int64_t p0 = xcd_block() * TILE;
   if (p0 >= P) return;
   const int tid = threadIdx.x, wave = tid >> 6;
-  const int nvalid = (int)((P - p0) < kTile ? (P - p0) : kTile);
+  const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
   constexpr int NWDE = K / 16;   // waves that own the dE/de accumulator (16 columns each)
 
   PairGeo g{};
-  if (tid < kTile) {
+  if (tid < TILE) {
     float ph = 0.f;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
@@ -436,26 +420,26 @@ __global__ void __launch_bounds__(256, PAIR_BWD_BLOCKS) k_pair_bwd(PairBwdArgs a
   }
   __syncthreads();
   // embedding adjoint: dE/df0 -> sG, dE/dphi and dE/dvhat per pair
-  embed_adjoint_rows<F, kTile>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
+  embed_adjoint_rows<F, TILE>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
   __syncthreads();
-  floatx4 de[2][1];
-  zero_acc(de);
-  if (wave < NWDE) wave_mm<1>(sG, L3, 3 * F, a.W0T, wave * 16, de);
+  floatx4 de[RB][1];
+  zero_acc_rb<RB, 1>(de);
+  if (wave < NWDE) wave_mm_rb<RB, 1>(sG, L3, 3 * F, a.W0T, wave * 16, de);
   __syncthreads();
 
   for (int l = 0; l < a.L; ++l) {
     const float *z1 = a.z1[l], *z2 = a.z2[l];
-    filter_adjoint_rows<F, kTile>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
+    filter_adjoint_rows<F, TILE>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
                                   sDphi);
     __syncthreads();
     {  // dz2 = (dz3 Wc) silu'(z2)
       constexpr int NB = F / 32;
-      floatx4 acc[2][NB];
-      zero_acc(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 2);
-      float zp[2][NB][4];
-      load_acc_rows<2, NB>(z2, 2 * F, p0, nvalid, col0, zp);
-      wave_mm<NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
+      float zp[RB][NB][4];
+      load_acc_rows<RB, NB>(z2, 2 * F, p0, nvalid, col0, zp);
+      wave_mm_rb<RB, NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
         sG[row * L2 + col] = row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f;
@@ -464,23 +448,23 @@ __global__ void __launch_bounds__(256, PAIR_BWD_BLOCKS) k_pair_bwd(PairBwdArgs a
     __syncthreads();
     {  // dz1 = (dz2 Wb) silu'(z1)
       constexpr int NB = F / 64;
-      floatx4 acc[2][NB];
-      zero_acc(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 4);
-      float zp[2][NB][4];
-      load_acc_rows<2, NB>(z1, F, p0, nvalid, col0, zp);
-      wave_mm<NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
+      float zp[RB][NB][4];
+      load_acc_rows<RB, NB>(z1, F, p0, nvalid, col0, zp);
+      wave_mm_rb<RB, NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
         sG[row * L1 + col] = row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f;
       });
     }
     __syncthreads();
-    if (wave < NWDE) wave_mm<1>(sG, L1, F, a.WaT[l], wave * 16, de);   // de += dz1 Wa
+    if (wave < NWDE) wave_mm_rb<RB, 1>(sG, L1, F, a.WaT[l], wave * 16, de);   // de += dz1 Wa
     __syncthreads();
   }
 
-  float *sDE = sG;   // [32][K+4]
+  float *sDE = sG;   // [TILE][K+4]
   if (wave < NWDE)
     for_acc_rc(de, wave * 16, [&](int, int, int, int row, int col, float v) { sDE[row * LE + col] = v; });
   __syncthreads();
@@ -492,20 +476,19 @@ __global__ void __launch_bounds__(256, PAIR_BWD_BLOCKS) k_pair_bwd(PairBwdArgs a
 // ============================================================================ BF16 variant
 // GEMM operands (basis, activations, adjoints and weights) in BF16, FP32 accumulation
 // (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..8(l/16)+7] and
-// B[8(l/16)..+7][l%16]).  64-pair tiles (four 16-row blocks) so every weight fragment read
-// from L2 feeds four MFMAs.  Pre-activations are stored in BF16, the filter h in FP32.
+// B[8(l/16)..+7][l%16]).  Tiles of 16 RB pairs (RB 16-row blocks), so every weight fragment
+// read from L2 feeds RB MFMAs.  Pre-activations are stored in BF16, the filter h in FP32.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int kTileB = 64;
 constexpr int kPadB = 8;   // LDS row padding (bf16 elements)
 
 __device__ __forceinline__ floatx4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// acc[rb][cb] += act[64 x Kin] (LDS bf16, row stride ld) * Bt^T (Bt [ncol][Kin] bf16 in global memory).
-template <int NB>
+// acc[rb][cb] += act[16*RB x Kin] (LDS bf16, row stride ld) * Bt^T (Bt [ncol][Kin] bf16 in global memory).
+template <int RB, int NB>
 __device__ __forceinline__ void wave_mm_bf16(const __bf16 *act, int ld, int Kin, const __bf16 *__restrict__ Bt,
-                                             int col0, floatx4 (&acc)[4][NB]) {
+                                             int col0, floatx4 (&acc)[RB][NB]) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, q = lane >> 4;
   const __bf16 *ap = act + r * ld + 8 * q;
@@ -524,7 +507,7 @@ __device__ __forceinline__ void wave_mm_bf16(const __bf16 *act, int ld, int Kin,
       for (int cb = 0; cb < NB; ++cb) bn[cb] = *reinterpret_cast<const bf16x8 *>(bp + cb * bstride + k0 + 32);
     }
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
       const bf16x8 a = *reinterpret_cast<const bf16x8 *>(ap + rb * astride + k0);
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = mfma_bf16(a, b[cb], acc[rb][cb]);
@@ -532,19 +515,20 @@ __device__ __forceinline__ void wave_mm_bf16(const __bf16 *act, int ld, int Kin,
   }
 }
 
-template <int F, int K>
-__global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
+template <int F, int K, int RB, int MINB>
+__global__ void __launch_bounds__(256, MINB) k_pair_fwd_bf16(PairFwdArgsB a) {
+  constexpr int TILE = 16 * RB;
   constexpr int LE = K + kPadB, L1 = F + kPadB, L2 = 2 * F + kPadB;
-  __shared__ __attribute__((aligned(16))) __bf16 sE[kTileB * LE];
-  __shared__ __attribute__((aligned(16))) __bf16 sA1[kTileB * L1];
-  __shared__ __attribute__((aligned(16))) __bf16 sA2[kTileB * L2];
-  __shared__ double sD[kTileB], sPhi[kTileB];
+  __shared__ __attribute__((aligned(16))) __bf16 sE[TILE * LE];
+  __shared__ __attribute__((aligned(16))) __bf16 sA1[TILE * L1];
+  __shared__ __attribute__((aligned(16))) __bf16 sA2[TILE * L2];
+  __shared__ double sD[TILE], sPhi[TILE];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = xcd_block() * kTileB;
+  const int64_t p0 = xcd_block() * TILE;
   if (p0 >= P) return;
   const int tid = threadIdx.x, wave = tid >> 6;
-  const int nvalid = (int)((P - p0) < kTileB ? (P - p0) : kTileB);
-  if (tid < kTileB) {
+  const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
+  if (tid < TILE) {
     double d = a.r_c, ph = 0.0;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
@@ -561,7 +545,7 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
     sPhi[tid] = ph;
   }
   __syncthreads();
-  for (int t = tid; t < kTileB * K; t += 256) {
+  for (int t = tid; t < TILE * K; t += 256) {
     const int row = t / K, k = t % K;
     const double u = exp(-a.alpha * (sD[row] - a.r_lo));
     const double x = u - a.mu[k];
@@ -570,12 +554,12 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
   __syncthreads();
   {
     constexpr int NB = 3 * F / 64;
-    floatx4 acc[4][NB];
-    zero_acc_rb<4, NB>(acc);
+    floatx4 acc[RB][NB];
+    zero_acc_rb<RB, NB>(acc);
     const int col0 = wave * (3 * F / 4);
     float br[NB];
     load_cols<NB>(a.b0, col0, br);
-    wave_mm_bf16<NB>(sE, LE, K, a.W0, col0, acc);
+    wave_mm_bf16<RB, NB>(sE, LE, K, a.W0, col0, acc);
     for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
       if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = v + br[cb];
     });
@@ -583,12 +567,12 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
   for (int l = 0; l < a.L; ++l) {
     {
       constexpr int NB = F / 64;
-      floatx4 acc[4][NB];
-      zero_acc_rb<4, NB>(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 4);
       float br[NB];
       load_cols<NB>(a.ba[l], col0, br);
-      wave_mm_bf16<NB>(sE, LE, K, a.Wa[l], col0, acc);
+      wave_mm_bf16<RB, NB>(sE, LE, K, a.Wa[l], col0, acc);
       __bf16 *z1 = a.z1[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
@@ -599,12 +583,12 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
     __syncthreads();
     {
       constexpr int NB = F / 32;
-      floatx4 acc[4][NB];
-      zero_acc_rb<4, NB>(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 2);
       float br[NB];
       load_cols<NB>(a.bb[l], col0, br);
-      wave_mm_bf16<NB>(sA1, L1, F, a.Wb[l], col0, acc);
+      wave_mm_bf16<RB, NB>(sA1, L1, F, a.Wb[l], col0, acc);
       __bf16 *z2 = a.z2[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
@@ -615,12 +599,12 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
     __syncthreads();
     {
       constexpr int NB = 3 * F / 64;
-      floatx4 acc[4][NB];
-      zero_acc_rb<4, NB>(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (3 * F / 4);
       float br[NB];
       load_cols<NB>(a.bc[l], col0, br);
-      wave_mm_bf16<NB>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
+      wave_mm_bf16<RB, NB>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
       __bf16 *z3 = a.z3[l];
       float *h = a.h[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
@@ -634,20 +618,21 @@ __global__ void __launch_bounds__(256, 1) k_pair_fwd_bf16(PairFwdArgsB a) {
   }
 }
 
-template <int F, int K>
-__global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
+template <int F, int K, int RB, int MINB>
+__global__ void __launch_bounds__(256, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
+  constexpr int TILE = 16 * RB;
   constexpr int L3 = 3 * F + kPadB, L2 = 2 * F + kPadB, L1 = F + kPadB, LE = K + 4;
-  static_assert(kTileB * LE * 4 <= kTileB * L3 * 2, "dE/de must fit in the adjoint buffer");
-  __shared__ __attribute__((aligned(16))) __bf16 sG[kTileB * L3];   // df0, dz3, dz2, dz1; finally dE/de (f32)
-  __shared__ float sPhi[kTileB], sDphi[kTileB], sU[kTileB][3], sDv[kTileB][3];
+  static_assert(TILE * LE * 4 <= TILE * L3 * 2, "dE/de must fit in the adjoint buffer");
+  __shared__ __attribute__((aligned(16))) __bf16 sG[TILE * L3];   // df0, dz3, dz2, dz1; finally dE/de (f32)
+  __shared__ float sPhi[TILE], sDphi[TILE], sU[TILE][3], sDv[TILE][3];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = xcd_block() * kTileB;
+  const int64_t p0 = xcd_block() * TILE;
   if (p0 >= P) return;
   const int tid = threadIdx.x, wave = tid >> 6;
-  const int nvalid = (int)((P - p0) < kTileB ? (P - p0) : kTileB);
+  const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
   constexpr int NWDE = K / 16;
   PairGeo g{};
-  if (tid < kTileB) {
+  if (tid < TILE) {
     float ph = 0.f;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
@@ -660,25 +645,25 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
     sU[tid][2] = (float)g.u[2];
   }
   __syncthreads();
-  embed_adjoint_rows<F, kTileB>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
+  embed_adjoint_rows<F, TILE>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
   __syncthreads();
-  floatx4 de[4][1];
-  zero_acc_rb<4, 1>(de);
-  if (wave < NWDE) wave_mm_bf16<1>(sG, L3, 3 * F, a.W0T, wave * 16, de);
+  floatx4 de[RB][1];
+  zero_acc_rb<RB, 1>(de);
+  if (wave < NWDE) wave_mm_bf16<RB, 1>(sG, L3, 3 * F, a.W0T, wave * 16, de);
   __syncthreads();
   for (int l = 0; l < a.L; ++l) {
     const __bf16 *z1 = a.z1[l], *z2 = a.z2[l];
-    filter_adjoint_rows<F, kTileB>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
+    filter_adjoint_rows<F, TILE>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
                                    sDphi);
     __syncthreads();
     {
       constexpr int NB = F / 32;
-      floatx4 acc[4][NB];
-      zero_acc_rb<4, NB>(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 2);
-      float zp[4][NB][4];
-      load_acc_rows<4, NB>(z2, 2 * F, p0, nvalid, col0, zp);
-      wave_mm_bf16<NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
+      float zp[RB][NB][4];
+      load_acc_rows<RB, NB>(z2, 2 * F, p0, nvalid, col0, zp);
+      wave_mm_bf16<RB, NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
         sG[row * L2 + col] = (__bf16)(row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f);
@@ -687,19 +672,19 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
     __syncthreads();
     {
       constexpr int NB = F / 64;
-      floatx4 acc[4][NB];
-      zero_acc_rb<4, NB>(acc);
+      floatx4 acc[RB][NB];
+      zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 4);
-      float zp[4][NB][4];
-      load_acc_rows<4, NB>(z1, F, p0, nvalid, col0, zp);
-      wave_mm_bf16<NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
+      float zp[RB][NB][4];
+      load_acc_rows<RB, NB>(z1, F, p0, nvalid, col0, zp);
+      wave_mm_bf16<RB, NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
         sG[row * L1 + col] = (__bf16)(row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f);
       });
     }
     __syncthreads();
-    if (wave < NWDE) wave_mm_bf16<1>(sG, L1, F, a.WaT[l], wave * 16, de);
+    if (wave < NWDE) wave_mm_bf16<RB, 1>(sG, L1, F, a.WaT[l], wave * 16, de);
     __syncthreads();
   }
   float *sDE = reinterpret_cast<float *>(sG);
@@ -712,62 +697,119 @@ __global__ void __launch_bounds__(256, 1) k_pair_bwd_bf16(PairBwdArgsB a) {
 }
 
 // ============================================================================ launchers
-template <int F, int K>
-static int launch_fwd(hipStream_t s, const PairFwdArgs &a) {
-  const unsigned grid = (unsigned)((a.max_pairs + kTile - 1) / kTile);
+// Tile shapes (pairs per tile = 16 * RB, minimum blocks per CU for the register budget).
+// Every shape computes each pair with the same arithmetic in the same order, so results do
+// not depend on the shape; tn_autotune picks the fastest per workload.
+//   FP32: 0 = 32 pairs / 3 blocks, 1 = 32 / 2, 2 = 16 / 4, 3 = 64 / 1
+//   BF16: 0 = 64 pairs / 1 block, 1 = 32 / 2
+int pair_variant_count(bool bf16) { return bf16 ? 2 : 4; }
+
+template <int TILE>
+static unsigned tile_grid(int64_t max_pairs) {
+  return (unsigned)((max_pairs + TILE - 1) / TILE);
+}
+
+template <int F, int K, int RB, int MINB>
+static int launch_fwd_v(hipStream_t s, const PairFwdArgs &a) {
+  const unsigned grid = tile_grid<16 * RB>(a.max_pairs);
   if (grid == 0) return TN_OK;
   TimedScope ts("edge_fwd", s);
-  hipLaunchKernelGGL((k_pair_fwd<F, K>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_pair_fwd<F, K, RB, MINB>), dim3(grid), dim3(256), 0, s, a);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+template <int F, int K, int RB, int MINB>
+static int launch_bwd_v(hipStream_t s, const PairBwdArgs &a) {
+  const unsigned grid = tile_grid<16 * RB>(a.max_pairs);
+  if (grid == 0) return TN_OK;
+  TimedScope ts("edge_bwd", s);
+  hipLaunchKernelGGL((k_pair_bwd<F, K, RB, MINB>), dim3(grid), dim3(256), 0, s, a);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+template <int F, int K, int RB, int MINB>
+static int launch_fwd_bf16_v(hipStream_t s, const PairFwdArgsB &a) {
+  const unsigned grid = tile_grid<16 * RB>(a.max_pairs);
+  if (grid == 0) return TN_OK;
+  TimedScope ts("edge_fwd", s);
+  hipLaunchKernelGGL((k_pair_fwd_bf16<F, K, RB, MINB>), dim3(grid), dim3(256), 0, s, a);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+template <int F, int K, int RB, int MINB>
+static int launch_bwd_bf16_v(hipStream_t s, const PairBwdArgsB &a) {
+  const unsigned grid = tile_grid<16 * RB>(a.max_pairs);
+  if (grid == 0) return TN_OK;
+  TimedScope ts("edge_bwd", s);
+  hipLaunchKernelGGL((k_pair_bwd_bf16<F, K, RB, MINB>), dim3(grid), dim3(256), 0, s, a);
   TN_LAUNCH_CHECK();
   return TN_OK;
 }
 
 template <int F, int K>
-static int launch_bwd(hipStream_t s, const PairBwdArgs &a) {
-  const unsigned grid = (unsigned)((a.max_pairs + kTile - 1) / kTile);
-  if (grid == 0) return TN_OK;
-  TimedScope ts("edge_bwd", s);
-  hipLaunchKernelGGL((k_pair_bwd<F, K>), dim3(grid), dim3(256), 0, s, a);
-  TN_LAUNCH_CHECK();
-  return TN_OK;
+static int launch_fwd(hipStream_t s, const PairFwdArgs &a, int v) {
+  switch (v) {
+    case 1: return launch_fwd_v<F, K, 2, 2>(s, a);
+    case 2: return launch_fwd_v<F, K, 1, 4>(s, a);
+    case 3: return launch_fwd_v<F, K, 4, 1>(s, a);
+    default: return launch_fwd_v<F, K, 2, 3>(s, a);
+  }
 }
 
-#define TN_PAIR_DISPATCH(FN, ARGS)                                   \
+template <int F, int K>
+static int launch_bwd(hipStream_t s, const PairBwdArgs &a, int v) {
+  switch (v) {
+    case 1: return launch_bwd_v<F, K, 2, 2>(s, a);
+    case 2: return launch_bwd_v<F, K, 1, 4>(s, a);
+    case 3: return launch_bwd_v<F, K, 4, 1>(s, a);
+    default: return launch_bwd_v<F, K, 2, 3>(s, a);
+  }
+}
+
+template <int F, int K>
+static int launch_fwd_bf16(hipStream_t s, const PairFwdArgsB &a, int v) {
+  if (v == 1) return launch_fwd_bf16_v<F, K, 2, 2>(s, a);
+  return launch_fwd_bf16_v<F, K, 4, 1>(s, a);
+}
+
+template <int F, int K>
+static int launch_bwd_bf16(hipStream_t s, const PairBwdArgsB &a, int v) {
+  if (v == 1) return launch_bwd_bf16_v<F, K, 2, 2>(s, a);
+  return launch_bwd_bf16_v<F, K, 4, 1>(s, a);
+}
+
+#define TN_PAIR_DISPATCH(FN)                                         \
   switch (F * 1000 + K) {                                            \
-    case 64016: return FN<64, 16>(s, ARGS);                          \
-    case 64032: return FN<64, 32>(s, ARGS);                          \
-    case 64048: return FN<64, 48>(s, ARGS);                          \
-    case 64064: return FN<64, 64>(s, ARGS);                          \
-    case 128016: return FN<128, 16>(s, ARGS);                        \
-    case 128032: return FN<128, 32>(s, ARGS);                        \
-    case 128048: return FN<128, 48>(s, ARGS);                        \
-    case 128064: return FN<128, 64>(s, ARGS);                        \
+    case 64016: return FN<64, 16>(s, a, v);                          \
+    case 64032: return FN<64, 32>(s, a, v);                          \
+    case 64048: return FN<64, 48>(s, a, v);                          \
+    case 64064: return FN<64, 64>(s, a, v);                          \
+    case 128016: return FN<128, 16>(s, a, v);                        \
+    case 128032: return FN<128, 32>(s, a, v);                        \
+    case 128048: return FN<128, 48>(s, a, v);                        \
+    case 128064: return FN<128, 64>(s, a, v);                        \
     default: return TN_E_UNSUPPORTED;                                \
   }
 
-template <int F, int K>
-static int launch_fwd_bf16(hipStream_t s, const PairFwdArgsB &a) {
-  const unsigned grid = (unsigned)((a.max_pairs + kTileB - 1) / kTileB);
-  if (grid == 0) return TN_OK;
-  TimedScope ts("edge_fwd", s);
-  hipLaunchKernelGGL((k_pair_fwd_bf16<F, K>), dim3(grid), dim3(256), 0, s, a);
-  TN_LAUNCH_CHECK();
-  return TN_OK;
-}
+#define TN_PAIR_DISPATCH_BF16(FN)                                    \
+  switch (F * 1000 + K) {                                            \
+    case 64032: return FN<64, 32>(s, a, v);                          \
+    case 64064: return FN<64, 64>(s, a, v);                          \
+    case 128032: return FN<128, 32>(s, a, v);                        \
+    case 128064: return FN<128, 64>(s, a, v);                        \
+    default: return TN_E_UNSUPPORTED;                                \
+  }
 
-template <int F, int K>
-static int launch_bwd_bf16(hipStream_t s, const PairBwdArgsB &a) {
-  const unsigned grid = (unsigned)((a.max_pairs + kTileB - 1) / kTileB);
-  if (grid == 0) return TN_OK;
-  TimedScope ts("edge_bwd", s);
-  hipLaunchKernelGGL((k_pair_bwd_bf16<F, K>), dim3(grid), dim3(256), 0, s, a);
-  TN_LAUNCH_CHECK();
-  return TN_OK;
+int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a, int v) { TN_PAIR_DISPATCH(launch_fwd) }
+int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a, int v) { TN_PAIR_DISPATCH(launch_bwd) }
+int launch_pair_fwd_bf16(hipStream_t s, int F, int K, const PairFwdArgsB &a, int v) {
+  TN_PAIR_DISPATCH_BF16(launch_fwd_bf16)
 }
-
-int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a) { TN_PAIR_DISPATCH(launch_fwd, a) }
-int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a) { TN_PAIR_DISPATCH(launch_bwd, a) }
-int launch_pair_fwd_bf16(hipStream_t s, int F, int K, const PairFwdArgsB &a) { TN_PAIR_DISPATCH(launch_fwd_bf16, a) }
-int launch_pair_bwd_bf16(hipStream_t s, int F, int K, const PairBwdArgsB &a) { TN_PAIR_DISPATCH(launch_bwd_bf16, a) }
+int launch_pair_bwd_bf16(hipStream_t s, int F, int K, const PairBwdArgsB &a, int v) {
+  TN_PAIR_DISPATCH_BF16(launch_bwd_bf16)
+}
 
 }  // namespace tn

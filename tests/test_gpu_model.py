@@ -207,3 +207,46 @@ def test_triclinic_cell(dev, precision, path, F, K):
     E_ref, F_ref = TensorNetOracle(blob).energy_forces(pos, z, batch, H, 1)
     E, Fv = gpu_ef(dev, TensorNet(blob, dev), pos, z, batch, H, 1, precision, path)
     assert_close(E, Fv, E_ref, F_ref, precision, f"triclinic150 {precision} {path}")
+
+
+# ---------------------------------------------------------------- pair-tile shapes
+@pytest.fixture(scope="module")
+def box600():
+    pos, z, box = random_box(600, 91, (600 / 0.1) ** (1 / 3))
+    return pos.astype(np.float32), z, box
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_pair_tile_shapes_are_bitwise_identical(dev, box600, precision):
+    pos, z, box = box600
+    blob = small_blob(F=128, K=32, L=2, seed=92)
+    m = TensorNet(blob, dev)
+    nv = TensorNet.pair_variant_count(precision)
+    assert nv >= 2
+    ref = None
+    for v in range(nv):
+        m.set_pair_variant(precision, v, v)
+        E, Fv = gpu_ef(dev, m, pos, z, np.zeros(600, np.int32), box, 1, precision, "fused")
+        print(f"pair tile shape {v} ({precision}): E={E[0]:.10f}", flush=True)
+        if ref is None:
+            ref = (E, Fv)
+            if precision == "fp32":
+                E_ref, F_ref = TensorNetOracle(blob).energy_forces(pos, z, np.zeros(600, np.int32), box, 1)
+                assert_close(E, Fv, E_ref, F_ref, precision, "box600 shape 0")
+        else:
+            assert np.array_equal(E, ref[0]) and np.array_equal(Fv, ref[1]), v
+    with pytest.raises(Exception):
+        m.set_pair_variant(precision, nv, 0)
+
+
+def test_autotune_picks_a_shape_and_keeps_results(dev, box600):
+    pos, z, box = box600
+    m = TensorNet(small_blob(F=128, K=32, L=2, seed=93), dev)
+    args = (torch.tensor(pos, device=dev), torch.tensor(z, device=dev),
+            torch.tensor(np.zeros(600, np.int32), device=dev))
+    E0, F0 = m.energy_forces(*args, 1, box=box, max_pairs=20000, precision="fp32")
+    fwd, bwd = m.autotune(*args, 1, box=box, max_pairs=20000, precision="fp32", reps=3)
+    print(f"autotune chose forward shape {fwd}, reverse shape {bwd}", flush=True)
+    assert 0 <= fwd < TensorNet.pair_variant_count("fp32") and 0 <= bwd < TensorNet.pair_variant_count("fp32")
+    E1, F1 = m.energy_forces(*args, 1, box=box, max_pairs=20000, precision="fp32")
+    assert torch.equal(E0, E1) and torch.equal(F0, F1)

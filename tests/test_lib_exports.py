@@ -101,3 +101,11 @@ def test_neighbor_method_validation_on_host():
     assert rc == L.TN_E_BOX
     rc = lib.tn_build_neighbors_method(*args, cast(ok), 4.5, 100, one, one, one, one, 16, L.TN_NBR_BRUTE)
     assert rc == L.TN_E_WORKSPACE
+
+
+def test_pair_variant_queries_on_host():
+    lib = L.lib()
+    assert lib.tn_pair_variant_count(L.TN_FP32) >= 2
+    assert lib.tn_pair_variant_count(L.TN_BF16) >= 2
+    assert lib.tn_pair_variant_count(L.TN_FP64) == 0
+    assert lib.tn_model_set_pair_variant(None, L.TN_FP32, 0, 0) == L.TN_E_ARG
