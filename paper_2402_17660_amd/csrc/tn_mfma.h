@@ -57,6 +57,41 @@ __device__ __forceinline__ void wave_mm_rb(const float *act, int ld, int Kin, co
   wave_mm_rows<RB, NB>(act, ld, 16 * ld, Kin, Bt, col0, acc);
 }
 
+// The same product with this wave's weight fragments already in registers: b[kc][cb] holds
+// Bt[col0 + cb*16 + l%16][16 kc + 4(l/16) .. +3] for the KC = Kin/16 chunks.
+template <int RB, int NB, int KC>
+__device__ __forceinline__ void wave_mm_rows_breg(const float *act, int ld, int rbs, const float4 (&b)[KC][NB],
+                                                  floatx4 (&acc)[RB][NB]) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  const float *ap = act + r * ld + 4 * q;
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const float4 a = *reinterpret_cast<const float4 *>(ap + rb * rbs + 16 * kc);
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        acc[rb][cb] = mfma4(a.x, b[kc][cb].x, acc[rb][cb]);
+        acc[rb][cb] = mfma4(a.y, b[kc][cb].y, acc[rb][cb]);
+        acc[rb][cb] = mfma4(a.z, b[kc][cb].z, acc[rb][cb]);
+        acc[rb][cb] = mfma4(a.w, b[kc][cb].w, acc[rb][cb]);
+      }
+    }
+  }
+}
+
+// Loads this wave's weight fragments for wave_mm_rows_breg.
+template <int NB, int KC>
+__device__ __forceinline__ void load_bfrag(const float *__restrict__ Bt, int Kin, int col0, float4 (&b)[KC][NB]) {
+  const int lane = threadIdx.x & 63;
+  const float *bp = Bt + (size_t)(col0 + (lane & 15)) * Kin + 4 * (lane >> 4);
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) b[kc][cb] = *reinterpret_cast<const float4 *>(bp + (size_t)cb * 16 * Kin + 16 * kc);
+}
+
 template <int RB, int NB>
 __device__ __forceinline__ void zero_acc_rb(floatx4 (&acc)[RB][NB]) {
 #pragma unroll

@@ -353,19 +353,42 @@ __global__ void k_check_finite(const T *pos, int64_t n, int32_t *status) {
   if (!isfinite(x) || !isfinite(y) || !isfinite(z)) set_status(status, TN_STATUS_NONFINITE);
 }
 
-// Deterministic order inside each cell: insertion sort of the cell's atoms by original index.
-__global__ void k_cell_sort(int64_t ncell, const int32_t *cell_start, int32_t *cell_atoms) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Deterministic order inside each cell: the cell's atoms sorted by original index.  One
+// wavefront per cell stages the (distinct) indices in LDS and gives every element its rank,
+// the number of smaller indices in the cell; cells with more than kSortCap atoms (not met at
+// physical densities) fall back to an insertion sort by one lane.
+constexpr int kSortCap = 1024;
+
+__global__ void __launch_bounds__(256) k_cell_sort(int64_t ncell, const int32_t *cell_start, int32_t *cell_atoms) {
+  __shared__ int32_t buf[4][kSortCap];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + w;
   if (c >= ncell) return;
-  const int32_t a = cell_start[c], e = cell_start[c + 1];
-  for (int32_t k = a + 1; k < e; ++k) {
-    const int32_t v = cell_atoms[k];
-    int32_t q = k - 1;
-    while (q >= a && cell_atoms[q] > v) {
-      cell_atoms[q + 1] = cell_atoms[q];
-      --q;
+  const int32_t a = cell_start[c], e = cell_start[c + 1], n = e - a;
+  if (n <= 1) return;
+  if (n > kSortCap) {
+    if (lane == 0) {
+      for (int32_t k = a + 1; k < e; ++k) {
+        const int32_t v = cell_atoms[k];
+        int32_t q = k - 1;
+        while (q >= a && cell_atoms[q] > v) {
+          cell_atoms[q + 1] = cell_atoms[q];
+          --q;
+        }
+        cell_atoms[q + 1] = v;
+      }
     }
-    cell_atoms[q + 1] = v;
+    return;
+  }
+  int32_t *b = buf[w];
+  for (int k = lane; k < n; k += 64) b[k] = cell_atoms[a + k];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  for (int k = lane; k < n; k += 64) {
+    const int32_t v = b[k];
+    int r = 0;
+    for (int m = 0; m < n; ++m) r += b[m] < v;
+    cell_atoms[a + r] = v;
   }
 }
 
@@ -611,7 +634,7 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, co
       hipLaunchKernelGGL(k_cell_scatter, dim3(g), dim3(blk), 0, s, n, w.cell_of, w.cell_start, w.cell_fill,
                          w.cell_atoms);
       TN_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(ncell, blk)), dim3(blk), 0, s, ncell, w.cell_start,
+      hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)((ncell + 3) / 4)), dim3(256), 0, s, ncell, w.cell_start,
                          w.cell_atoms);
       TN_LAUNCH_CHECK();
       T *spos = static_cast<T *>(w.spos);

@@ -33,10 +33,10 @@ struct GemmArgs {
   const T *Bz[3] = {nullptr, nullptr, nullptr};
 };
 
-constexpr int GBM = 64, GBN = 64, GBK = 32;
+constexpr int GBN = 64, GBK = 32;
 
-// The product runs on the matrix cores: 64x64 block tiles, each of the four waves computes a
-// 32x32 quarter as 2x2 MFMA 16x16x4 tiles (f32 or f64).  A and B chunks of 32 along K are
+// The product runs on the matrix cores: BMx64 block tiles (BM = 32 or 64), each of the four
+// waves computes a (BM/2)x32 part as MFMA 16x16x4 tiles (f32 or f64).  A and B chunks of 32 along K are
 // staged through LDS; the next chunk's global loads are issued into registers before the
 // current chunk's MFMAs, so their latency overlaps the products.  Both instructions take
 // A[l%16][l/16] and B[l/16][l%16] from lane l; element t of the result in lane l is
@@ -53,65 +53,63 @@ __device__ __forceinline__ mf_f64x4 mfma_16x16x4(double a, double b, mf_f64x4 c)
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <class T>
+template <class T, int BM>
 __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
   using V = typename MfmaVec<T>::type;
-  constexpr int PER = GBM * GBK / 256;   // elements of each operand chunk per thread
-  __shared__ T As[GBM][GBK + 1];
+  constexpr int RBW = BM / 32;                 // 16-row MFMA blocks per wave
+  constexpr int PERA = BM * GBK / 256, PERB = GBN * GBK / 256;   // chunk elements per thread
+  __shared__ T As[BM][GBK + 1];
   __shared__ T Bs[GBN][GBK + 1];
   int64_t Mrows = g.M;
   if (g.Mdev) {
     const int64_t md = *g.Mdev;
     if (md < Mrows) Mrows = md;
   }
-  const int64_t m0 = (int64_t)blockIdx.y * GBM;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
   const int64_t n0 = (int64_t)blockIdx.x * GBN;
   if (m0 >= Mrows) return;
   const int z = blockIdx.z;
   const T *__restrict__ A = g.A + z * g.zoff;
   const T *__restrict__ B = g.zpart ? g.Bz[coord_part(z)] : g.B;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
   const int r16 = lane & 15, q = lane >> 4;
-  // element e of this thread's share: A tile row/col, B tile row (n) / col (k)
-  auto a_at = [&](int e, int &mm_, int &kk) {
-    const int t = tid + 256 * e;
-    mm_ = t / GBK;
-    kk = t % GBK;
-  };
-  auto b_at = [&](int e, int &nn, int &kk) {
-    const int t = tid + 256 * e;
-    if (g.transB) { nn = t / GBK; kk = t % GBK; } else { kk = t / GBN; nn = t % GBN; }
-  };
-  T ra[PER], rb[PER];
+  T ra[PERA], rb[PERB];
   auto load_chunk = [&](int64_t k0) {
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      int mm_, kk;
-      a_at(e, mm_, kk);
+    for (int e = 0; e < PERA; ++e) {
+      const int t = tid + 256 * e, mm_ = t / GBK, kk = t % GBK;
       const int64_t m = m0 + mm_, k = k0 + kk;
       ra[e] = (m < Mrows && k < g.K) ? A[m * g.lda + k] : T(0);
-      int nn;
-      b_at(e, nn, kk);
-      const int64_t n = n0 + nn, k2 = k0 + kk;
+    }
+#pragma unroll
+    for (int e = 0; e < PERB; ++e) {
+      const int t = tid + 256 * e;
+      int nn, kk;
+      if (g.transB) { nn = t / GBK; kk = t % GBK; } else { kk = t / GBN; nn = t % GBN; }
+      const int64_t n = n0 + nn, k = k0 + kk;
       T v = T(0);
-      if (n < g.N && k2 < g.K) v = g.transB ? B[n * g.ldb + k2] : B[k2 * g.ldb + n];
+      if (n < g.N && k < g.K) v = g.transB ? B[n * g.ldb + k] : B[k * g.ldb + n];
       rb[e] = v;
     }
   };
   auto store_chunk = [&]() {
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      int mm_, kk, nn;
-      a_at(e, mm_, kk);
-      As[mm_][kk] = ra[e];
-      b_at(e, nn, kk);
+    for (int e = 0; e < PERA; ++e) {
+      const int t = tid + 256 * e;
+      As[t / GBK][t % GBK] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < PERB; ++e) {
+      const int t = tid + 256 * e;
+      int nn, kk;
+      if (g.transB) { nn = t / GBK; kk = t % GBK; } else { kk = t / GBN; nn = t % GBN; }
       Bs[nn][kk] = rb[e];
     }
   };
-  V acc[2][2];
+  V acc[RBW][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < RBW; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = V{T(0), T(0), T(0), T(0)};
   load_chunk(0);
@@ -121,12 +119,13 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
     if (k0 + GBK < g.K) load_chunk(k0 + GBK);
 #pragma unroll
     for (int s4 = 0; s4 < GBK; s4 += 4) {
-      const T a0 = As[wr + r16][s4 + q], a1 = As[wr + 16 + r16][s4 + q];
       const T b0 = Bs[wc + r16][s4 + q], b1 = Bs[wc + 16 + r16][s4 + q];
-      acc[0][0] = mfma_16x16x4(a0, b0, acc[0][0]);
-      acc[0][1] = mfma_16x16x4(a0, b1, acc[0][1]);
-      acc[1][0] = mfma_16x16x4(a1, b0, acc[1][0]);
-      acc[1][1] = mfma_16x16x4(a1, b1, acc[1][1]);
+#pragma unroll
+      for (int a = 0; a < RBW; ++a) {
+        const T av = As[wr + 16 * a + r16][s4 + q];
+        acc[a][0] = mfma_16x16x4(av, b0, acc[a][0]);
+        acc[a][1] = mfma_16x16x4(av, b1, acc[a][1]);
+      }
     }
     __syncthreads();
   }
@@ -138,7 +137,7 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
     if (g.bias && n < g.N) bias[cb] = g.bias[n];
   }
 #pragma unroll
-  for (int rb_ = 0; rb_ < 2; ++rb_)
+  for (int rb_ = 0; rb_ < RBW; ++rb_)
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -156,11 +155,19 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
       }
 }
 
+// Products with few 64-row tiles (fewer than two per compute unit) use 32-row tiles.
 template <class T>
 inline int gemm(hipStream_t s, const GemmArgs<T> &g, int zdim = 1) {
   if (g.M <= 0 || g.N <= 0) return TN_OK;
-  dim3 grid((unsigned)((g.N + GBN - 1) / GBN), (unsigned)((g.M + GBM - 1) / GBM), (unsigned)zdim);
-  hipLaunchKernelGGL(k_gemm_mfma<T>, grid, dim3(256), 0, s, g);
+  const int64_t nb = (g.N + GBN - 1) / GBN;
+  const int64_t tiles64 = nb * ((g.M + 63) / 64) * zdim;
+  if (tiles64 < 512) {
+    dim3 grid((unsigned)nb, (unsigned)((g.M + 31) / 32), (unsigned)zdim);
+    hipLaunchKernelGGL((k_gemm_mfma<T, 32>), grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid((unsigned)nb, (unsigned)((g.M + 63) / 64), (unsigned)zdim);
+    hipLaunchKernelGGL((k_gemm_mfma<T, 64>), grid, dim3(256), 0, s, g);
+  }
   TN_LAUNCH_CHECK();
   return TN_OK;
 }
@@ -200,12 +207,23 @@ __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float
                                              const float *__restrict__ B2, int accumulate, int ncb,
                                              int64_t ntiles) {
   constexpr int LD = F + 4;
+  constexpr int KC = F / 16;
+  // the three parts' weight fragments stay in registers when they fit (F <= 128)
+  constexpr bool kBreg = 3 * KC * NB * 4 <= 96;
   __shared__ __attribute__((aligned(16))) float sA[16 * 9 * LD];
   const int64_t per_xcd = (int64_t)gridDim.x / 8;
   const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= ntiles) return;
   const int64_t a0 = (t / ncb) * 16;
   const int cblk = (int)(t % ncb);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col0 = cblk * 64 * NB + wave * 16 * NB;
+  float4 bI[kBreg ? KC : 1][NB], bA[kBreg ? KC : 1][NB], bS[kBreg ? KC : 1][NB];
+  if constexpr (kBreg) {   // issued before the tile staging so the two overlap
+    load_bfrag<NB, KC>(B0, F, col0, bI);
+    load_bfrag<NB, KC>(B1, F, col0, bA);
+    load_bfrag<NB, KC>(B2, F, col0, bS);
+  }
   const int64_t navail = N - a0 < 16 ? N - a0 : 16;
   const float4 *src = reinterpret_cast<const float4 *>(in + a0 * 9 * F);
   for (int e = threadIdx.x; e < 16 * 9 * (F / 4); e += 256) {
@@ -215,14 +233,15 @@ __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float
     *reinterpret_cast<float4 *>(sA + row * LD + 4 * c4) = v;
   }
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col0 = cblk * 64 * NB + wave * 16 * NB;
   const int r16 = lane & 15, q = lane >> 4;
-  auto part = [&](auto c0_tag, auto nc_tag, const float *Bt) {
+  auto part = [&](auto c0_tag, auto nc_tag, const float *Bt, const auto &breg) {
     constexpr int C0 = decltype(c0_tag)::value, NC = decltype(nc_tag)::value;
     floatx4 acc[NC][NB];
     zero_acc_rb<NC, NB>(acc);
-    wave_mm_rows<NC, NB>(sA + C0 * LD, 9 * LD, LD, F, Bt, col0, acc);
+    if constexpr (kBreg)
+      wave_mm_rows_breg<NC, NB, KC>(sA + C0 * LD, 9 * LD, LD, breg, acc);
+    else
+      wave_mm_rows<NC, NB>(sA + C0 * LD, 9 * LD, LD, F, Bt, col0, acc);
 #pragma unroll
     for (int rb = 0; rb < NC; ++rb)
 #pragma unroll
@@ -235,9 +254,9 @@ __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float
           if (accumulate) *dst += acc[rb][cb][e]; else *dst = acc[rb][cb][e];
         }
   };
-  part(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}, B0);
-  part(std::integral_constant<int, 1>{}, std::integral_constant<int, 3>{}, B1);
-  part(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2);
+  part(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}, B0, bI);
+  part(std::integral_constant<int, 1>{}, std::integral_constant<int, 3>{}, B1, bA);
+  part(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2, bS);
 }
 
 template <int F, int NB>
