@@ -120,13 +120,13 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
       a.geo[4 * p + 3] = (float)g.d;
       a.phi[p] = (float)g.phi;
     }
-    sD[tid] = d;
+    sD[tid] = exp(-a.alpha * (d - a.r_lo));   // the basis argument u, once per pair
     sPhi[tid] = ph;
   }
   __syncthreads();
   for (int t = tid; t < TILE * K; t += 256) {
     const int row = t / K, k = t % K;
-    const double u = exp(-a.alpha * (sD[row] - a.r_lo));
+    const double u = sD[row];
     const double x = u - a.mu[k];
     sE[row * LE + k] = (float)(sPhi[row] * exp(-a.beta[k] * x * x));
   }
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
         if (row < nvalid) z1[(p0 + row) * F + col] = z;
-        sA[row * L1 + col] = silu(z);
+        sA[row * L1 + col] = fast_silu(z);
       });
     }
     __syncthreads();
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
         if (row < nvalid) z2[(p0 + row) * 2 * F + col] = z;
-        sA[row * L2 + col] = silu(z);
+        sA[row * L2 + col] = fast_silu(z);
       });
     }
     __syncthreads();
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
         const float z = v + br[cb];
         if (row < nvalid) {
           z3[(p0 + row) * 3 * F + col] = z;
-          h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * silu(z);
+          h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * fast_silu(z);
         }
       });
     }
@@ -357,8 +357,8 @@ __device__ __forceinline__ void filter_adjoint_rows(const float *Y, const float 
       float o[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        o[v] = valid ? dh[pt][v] * ph * silu_grad(zz[pt][v]) : 0.f;
-        part += dh[pt][v] * silu(zz[pt][v]);
+        o[v] = valid ? dh[pt][v] * ph * fast_silu_grad(zz[pt][v]) : 0.f;
+        part += dh[pt][v] * fast_silu(zz[pt][v]);
       }
       st_row<TL, V>(lds + row * ld + pt * F + f, o);
     }
@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd(PairBwdArgs a) {
       wave_mm_rb<RB, NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        sG[row * L2 + col] = row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f;
+        sG[row * L2 + col] = row < nvalid ? v * fast_silu_grad(zp[rb][cb][t]) : 0.f;
       });
     }
     __syncthreads();
@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd(PairBwdArgs a) {
       wave_mm_rb<RB, NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        sG[row * L1 + col] = row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f;
+        sG[row * L1 + col] = row < nvalid ? v * fast_silu_grad(zp[rb][cb][t]) : 0.f;
       });
     }
     __syncthreads();
@@ -541,13 +541,13 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd_bf16(PairFwdArgsB a) {
       a.geo[4 * p + 3] = (float)g.d;
       a.phi[p] = (float)g.phi;
     }
-    sD[tid] = d;
+    sD[tid] = exp(-a.alpha * (d - a.r_lo));   // the basis argument u, once per pair
     sPhi[tid] = ph;
   }
   __syncthreads();
   for (int t = tid; t < TILE * K; t += 256) {
     const int row = t / K, k = t % K;
-    const double u = exp(-a.alpha * (sD[row] - a.r_lo));
+    const double u = sD[row];
     const double x = u - a.mu[k];
     sE[row * LE + k] = (__bf16)(float)(sPhi[row] * exp(-a.beta[k] * x * x));
   }
@@ -577,7 +577,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd_bf16(PairFwdArgsB a) {
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
         if (row < nvalid) z1[(p0 + row) * F + col] = (__bf16)z;
-        sA1[row * L1 + col] = (__bf16)silu(z);
+        sA1[row * L1 + col] = (__bf16)fast_silu(z);
       });
     }
     __syncthreads();
@@ -593,7 +593,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd_bf16(PairFwdArgsB a) {
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
         if (row < nvalid) z2[(p0 + row) * 2 * F + col] = (__bf16)z;
-        sA2[row * L2 + col] = (__bf16)silu(z);
+        sA2[row * L2 + col] = (__bf16)fast_silu(z);
       });
     }
     __syncthreads();
@@ -611,7 +611,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd_bf16(PairFwdArgsB a) {
         const float z = v + br[cb];
         if (row < nvalid) {
           z3[(p0 + row) * 3 * F + col] = (__bf16)z;
-          h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * silu(z);
+          h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * fast_silu(z);
         }
       });
     }
@@ -666,7 +666,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
       wave_mm_bf16<RB, NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        sG[row * L2 + col] = (__bf16)(row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f);
+        sG[row * L2 + col] = (__bf16)(row < nvalid ? v * fast_silu_grad(zp[rb][cb][t]) : 0.f);
       });
     }
     __syncthreads();
@@ -680,7 +680,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
       wave_mm_bf16<RB, NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        sG[row * L1 + col] = (__bf16)(row < nvalid ? v * silu_grad(zp[rb][cb][t]) : 0.f);
+        sG[row * L1 + col] = (__bf16)(row < nvalid ? v * fast_silu_grad(zp[rb][cb][t]) : 0.f);
       });
     }
     __syncthreads();
