@@ -225,6 +225,17 @@ __device__ __forceinline__ int64_t xcd_block() {
   return x * q + (x < r ? x : r) + b / 8;
 }
 
+// The same renumbering when only the first T of the grid's blocks have work (the grid is
+// sized for a static bound such as max_pairs): every XCD gets an equal contiguous share of
+// the T work items, so a partly filled grid still spreads over all eight XCDs.  Returns the
+// work item of this block, or -1 for a block without one.  Needs gridDim.x >= T.
+__device__ __forceinline__ int64_t xcd_block_of(int64_t T) {
+  const int64_t b = blockIdx.x, x = b % 8, k = b / 8;
+  const int64_t q = T / 8, r = T % 8;
+  const int64_t len = q + (x < r ? 1 : 0);
+  return k < len ? x * q + (x < r ? x : r) + k : -1;
+}
+
 // Flag a bit in the device status word.
 __device__ inline void set_status(int32_t *status, int32_t bit) {
   if (status) atomicOr(reinterpret_cast<int *>(status), bit);

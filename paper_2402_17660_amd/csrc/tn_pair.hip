@@ -93,16 +93,17 @@ __device__ inline PairGeo pair_geometry(const float *pos, int64_t i, int64_t j, 
 // ============================================================================ forward
 // One LDS buffer holds the tile's current activation, silu(z1) and then silu(z2); each product
 // keeps its result in registers until every wave has finished reading the buffer.
-template <int F, int K, int RB, int MINB>
-__global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
+template <int F, int K, int RB, int NW, int MINB>
+__global__ void __launch_bounds__(64 * NW, MINB) k_pair_fwd(PairFwdArgs a) {
   constexpr int TILE = 16 * RB;
   constexpr int LE = K + kPad, L1 = F + kPad, L2 = 2 * F + kPad;
   __shared__ __attribute__((aligned(16))) float sE[TILE * LE];
   __shared__ __attribute__((aligned(16))) float sA[TILE * L2];
   __shared__ double sD[TILE], sPhi[TILE];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = xcd_block() * TILE;
-  if (p0 >= P) return;
+  const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
+  if (tile < 0) return;
+  const int64_t p0 = tile * TILE;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
 
@@ -124,7 +125,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
     sPhi[tid] = ph;
   }
   __syncthreads();
-  for (int t = tid; t < TILE * K; t += 256) {
+  for (int t = tid; t < TILE * K; t += 64 * NW) {
     const int row = t / K, k = t % K;
     const double u = sD[row];
     const double x = u - a.mu[k];
@@ -132,12 +133,12 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
   }
   __syncthreads();
 
-  // embedding map f0 = W0 e + b0  (3F outputs; wave covers 3F/4 columns)
+  // embedding map f0 = W0 e + b0  (3F outputs; wave covers 3F/NW columns)
   {
-    constexpr int NB = 3 * F / 64;
+    constexpr int NB = 3 * F / (16 * NW);
     floatx4 acc[RB][NB];
     zero_acc_rb<RB, NB>(acc);
-    const int col0 = wave * (3 * F / 4);
+    const int col0 = wave * (3 * F / NW);
     float br[NB];
     load_cols<NB>(a.b0, col0, br);
     wave_mm_rb<RB, NB>(sE, LE, K, a.W0, col0, acc);
@@ -147,10 +148,10 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
   }
   for (int l = 0; l < a.L; ++l) {
     {  // z1 = Wa e + ba
-      constexpr int NB = F / 64;
+      constexpr int NB = F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (F / 4);
+      const int col0 = wave * (F / NW);
       float br[NB];
       load_cols<NB>(a.ba[l], col0, br);
       wave_mm_rb<RB, NB>(sE, LE, K, a.Wa[l], col0, acc);
@@ -164,10 +165,10 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
     }
     __syncthreads();
     {  // z2 = Wb silu(z1) + bb
-      constexpr int NB = F / 32;
+      constexpr int NB = 2 * F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (F / 2);
+      const int col0 = wave * (2 * F / NW);
       float br[NB];
       load_cols<NB>(a.bb[l], col0, br);
       wave_mm_rb<RB, NB>(sA, L1, F, a.Wb[l], col0, acc);
@@ -181,10 +182,10 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
     }
     __syncthreads();
     {  // z3 = Wc silu(z2) + bc, h = phi silu(z3)
-      constexpr int NB = 3 * F / 64;
+      constexpr int NB = 3 * F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (3 * F / 4);
+      const int col0 = wave * (3 * F / NW);
       float br[NB];
       load_cols<NB>(a.bc[l], col0, br);
       wave_mm_rb<RB, NB>(sA, L2, 2 * F, a.Wc[l], col0, acc);
@@ -203,7 +204,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd(PairFwdArgs a) {
 // ============================================================================ reverse-sweep prologues
 // Both directions of a pair meet in the pair tile, so the pair-level adjoints are formed
 // here from the two atoms' rows (coordinates layout [N, 9, F]) and written straight into
-// LDS as the A operand of the MFMA backprop.  Each wave owns R/4 rows; lane l holds the
+// LDS as the A operand of the MFMA backprop.  Each of the NW waves owns R/NW rows; lane l holds the
 // V = F/64 channels V*l .. V*l+V-1 (one vector access per coordinate), and per-row scalars
 // are reduced across the wave.  Rows past the tile's valid count read the tile's first pair
 // and store zeros, so the row loop has no branches and its loads can overlap.
@@ -236,11 +237,11 @@ __device__ __forceinline__ void ld_row(const TZ *p, float (&o)[V]) {
 
 // dE/df0 = (da, db, dc) for both directions of the pair -> lds[row][0..3F); returns the pair's
 // dE/dphi and dE/dvhat (embedding part) through the per-row LDS arrays.
-template <int F, int R, class TL>
+template <int F, int R, class TL, int NW = 4>
 __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const int32_t *pairs, int64_t max_pairs,
                                                    int64_t p0, int nvalid, const float (*sU)[3], const float *sPhi,
                                                    TL *lds, int ld, float *sDphi, float (*sDv)[3]) {
-  constexpr int V = F / 64, rows = R / 4;
+  constexpr int V = F / 64, rows = R / NW;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int f = lane * V;
 #pragma unroll
@@ -318,11 +319,11 @@ __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const in
 
 // Layer l: dh = <part(Y_j), dM_i> + <part(Y_i), dM_j> per channel; then
 // lds[row][c] = dh phi silu'(z3) and dE/dphi += sum_c dh silu(z3).
-template <int F, int R, class TL, class TZ>
+template <int F, int R, class TL, class TZ, int NW = 4>
 __device__ __forceinline__ void filter_adjoint_rows(const float *Y, const float *dM, const TZ *z3,
                                                     const int32_t *pairs, int64_t max_pairs, int64_t p0, int nvalid,
                                                     const float *sPhi, TL *lds, int ld, float *sDphi) {
-  constexpr int V = F / 64, rows = R / 4;
+  constexpr int V = F / 64, rows = R / NW;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int f = lane * V;
 #pragma unroll
@@ -392,15 +393,16 @@ __device__ __forceinline__ void geometry_adjoint_rows(const PairGeo &g, const fl
 // One LDS buffer holds the tile's current adjoint: dE/df0, then per layer dz3, dz2, dz1, and
 // finally dE/de.  Each product keeps its result in registers until every wave has finished
 // reading the buffer, so the tile needs ~50 KB of LDS and two blocks share a CU.
-template <int F, int K, int RB, int MINB>
-__global__ void __launch_bounds__(256, MINB) k_pair_bwd(PairBwdArgs a) {
+template <int F, int K, int RB, int NW, int MINB>
+__global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
   constexpr int TILE = 16 * RB;
   constexpr int L3 = 3 * F + kPad, L2 = 2 * F + kPad, L1 = F + kPad, LE = K + kPad;
   __shared__ __attribute__((aligned(16))) float sG[TILE * L3];
   __shared__ float sPhi[TILE], sDphi[TILE], sU[TILE][3], sDv[TILE][3];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = xcd_block() * TILE;
-  if (p0 >= P) return;
+  const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
+  if (tile < 0) return;
+  const int64_t p0 = tile * TILE;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
   constexpr int NWDE = K / 16;   // waves that own the dE/de accumulator (16 columns each)
@@ -420,7 +422,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd(PairBwdArgs a) {
   }
   __syncthreads();
   // embedding adjoint: dE/df0 -> sG, dE/dphi and dE/dvhat per pair
-  embed_adjoint_rows<F, TILE>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
+  embed_adjoint_rows<F, TILE, float, NW>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
   __syncthreads();
   floatx4 de[RB][1];
   zero_acc_rb<RB, 1>(de);
@@ -429,14 +431,14 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd(PairBwdArgs a) {
 
   for (int l = 0; l < a.L; ++l) {
     const float *z1 = a.z1[l], *z2 = a.z2[l];
-    filter_adjoint_rows<F, TILE>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
+    filter_adjoint_rows<F, TILE, float, float, NW>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
                                   sDphi);
     __syncthreads();
     {  // dz2 = (dz3 Wc) silu'(z2)
-      constexpr int NB = F / 32;
+      constexpr int NB = 2 * F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (F / 2);
+      const int col0 = wave * (2 * F / NW);
       float zp[RB][NB][4];
       load_acc_rows<RB, NB>(z2, 2 * F, p0, nvalid, col0, zp);
       wave_mm_rb<RB, NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
@@ -447,10 +449,10 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd(PairBwdArgs a) {
     }
     __syncthreads();
     {  // dz1 = (dz2 Wb) silu'(z1)
-      constexpr int NB = F / 64;
+      constexpr int NB = F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (F / 4);
+      const int col0 = wave * (F / NW);
       float zp[RB][NB][4];
       load_acc_rows<RB, NB>(z1, F, p0, nvalid, col0, zp);
       wave_mm_rb<RB, NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
@@ -524,8 +526,9 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd_bf16(PairFwdArgsB a) {
   __shared__ __attribute__((aligned(16))) __bf16 sA2[TILE * L2];
   __shared__ double sD[TILE], sPhi[TILE];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = xcd_block() * TILE;
-  if (p0 >= P) return;
+  const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
+  if (tile < 0) return;
+  const int64_t p0 = tile * TILE;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
   if (tid < TILE) {
@@ -626,8 +629,9 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
   __shared__ __attribute__((aligned(16))) __bf16 sG[TILE * L3];   // df0, dz3, dz2, dz1; finally dE/de (f32)
   __shared__ float sPhi[TILE], sDphi[TILE], sU[TILE][3], sDv[TILE][3];
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
-  const int64_t p0 = xcd_block() * TILE;
-  if (p0 >= P) return;
+  const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
+  if (tile < 0) return;
+  const int64_t p0 = tile * TILE;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
   constexpr int NWDE = K / 16;
@@ -697,11 +701,12 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
 }
 
 // ============================================================================ launchers
-// Tile shapes (pairs per tile = 16 * RB, minimum blocks per CU for the register budget).
-// Every shape computes each pair with the same arithmetic in the same order, so results do
-// not depend on the shape; tn_autotune picks the fastest per workload.
-//   FP32: 0 = 32 pairs / 3 blocks, 1 = 32 / 2, 2 = 16 / 4, 3 = 64 / 1
-//   BF16: 0 = 64 pairs / 1 block, 1 = 32 / 2
+// Tile shapes: pairs per tile = 16 RB, NW waves per workgroup, at least MINB workgroups per
+// compute unit (register budget).  Every shape computes each pair with the same arithmetic
+// in the same order, so results do not depend on the shape; tn_autotune picks the fastest.
+//   FP32: 0 = 32 pairs, 4 waves, 3 blocks/CU; 1 = 32, 4, 2; 2 = 16, 4, 4; 3 = 64, 4, 1
+//   BF16: 0 = 64 pairs, 4 waves, 1 block/CU; 1 = 32, 4, 2
+// (Eight-wave FP32 tiles, NW = 8, measured slower on the 6000-atom box and are not built.)
 int pair_variant_count(bool bf16) { return bf16 ? 2 : 4; }
 
 template <int TILE>
@@ -709,22 +714,22 @@ static unsigned tile_grid(int64_t max_pairs) {
   return (unsigned)((max_pairs + TILE - 1) / TILE);
 }
 
-template <int F, int K, int RB, int MINB>
+template <int F, int K, int RB, int NW, int MINB>
 static int launch_fwd_v(hipStream_t s, const PairFwdArgs &a) {
   const unsigned grid = tile_grid<16 * RB>(a.max_pairs);
   if (grid == 0) return TN_OK;
   TimedScope ts("edge_fwd", s);
-  hipLaunchKernelGGL((k_pair_fwd<F, K, RB, MINB>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_pair_fwd<F, K, RB, NW, MINB>), dim3(grid), dim3(64 * NW), 0, s, a);
   TN_LAUNCH_CHECK();
   return TN_OK;
 }
 
-template <int F, int K, int RB, int MINB>
+template <int F, int K, int RB, int NW, int MINB>
 static int launch_bwd_v(hipStream_t s, const PairBwdArgs &a) {
   const unsigned grid = tile_grid<16 * RB>(a.max_pairs);
   if (grid == 0) return TN_OK;
   TimedScope ts("edge_bwd", s);
-  hipLaunchKernelGGL((k_pair_bwd<F, K, RB, MINB>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_pair_bwd<F, K, RB, NW, MINB>), dim3(grid), dim3(64 * NW), 0, s, a);
   TN_LAUNCH_CHECK();
   return TN_OK;
 }
@@ -752,20 +757,20 @@ static int launch_bwd_bf16_v(hipStream_t s, const PairBwdArgsB &a) {
 template <int F, int K>
 static int launch_fwd(hipStream_t s, const PairFwdArgs &a, int v) {
   switch (v) {
-    case 1: return launch_fwd_v<F, K, 2, 2>(s, a);
-    case 2: return launch_fwd_v<F, K, 1, 4>(s, a);
-    case 3: return launch_fwd_v<F, K, 4, 1>(s, a);
-    default: return launch_fwd_v<F, K, 2, 3>(s, a);
+    case 1: return launch_fwd_v<F, K, 2, 4, 2>(s, a);
+    case 2: return launch_fwd_v<F, K, 1, 4, 4>(s, a);
+    case 3: return launch_fwd_v<F, K, 4, 4, 1>(s, a);
+    default: return launch_fwd_v<F, K, 2, 4, 3>(s, a);
   }
 }
 
 template <int F, int K>
 static int launch_bwd(hipStream_t s, const PairBwdArgs &a, int v) {
   switch (v) {
-    case 1: return launch_bwd_v<F, K, 2, 2>(s, a);
-    case 2: return launch_bwd_v<F, K, 1, 4>(s, a);
-    case 3: return launch_bwd_v<F, K, 4, 1>(s, a);
-    default: return launch_bwd_v<F, K, 2, 3>(s, a);
+    case 1: return launch_bwd_v<F, K, 2, 4, 2>(s, a);
+    case 2: return launch_bwd_v<F, K, 1, 4, 4>(s, a);
+    case 3: return launch_bwd_v<F, K, 4, 4, 1>(s, a);
+    default: return launch_bwd_v<F, K, 2, 4, 3>(s, a);
   }
 }
 
