@@ -79,7 +79,7 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
   // room for the derived tables: species tables, basis constants, aligned and transposed
   // copies of the per-pair weights (each start aligned to 64 elements)
   const size_t extra = 2 * Z * F + 2 * K + 2 * (3 * F * K) + (size_t)m->L * 2 * (F * K + 2 * F * F + 6 * F * F) +
-                       (size_t)m->L * 6 * F * F + 64 * (8 + 12 * (size_t)m->L);
+                       (size_t)(m->L + 1) * 6 * F * F + 64 * (11 + 12 * (size_t)m->L);
   packed.assign(total + extra, 0.0);
   size_t off = 0;
   const unsigned char *src = b + kHeaderBytes;
@@ -114,6 +114,7 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
   };
   o.W0f = copy(o.W0, 3 * F, K, false);
   o.W0T = copy(o.W0, 3 * F, K, true);
+  for (int q = 0; q < 3; ++q) o.WmixT[q] = copy(o.Wmix[q], F, F, true);
   for (int l = 0; l < m->L; ++l) {
     LayerOff &lo = o.layer[l];
     lo.Waf = copy(lo.Wa, F, K, false);

@@ -1,9 +1,10 @@
 // Fused TensorNet path: the per-pair work (geometry, radial basis, the embedding's K->3F map
 // and every layer's edge filter, forward and reverse) runs in two MFMA pair-tile kernels;
-// the node-level steps use the shared node kernels.  Precision plan as in the plain path:
-// FP32 arithmetic, with the geometry/basis, the embedding's node stage and the output
-// network in FP64, the per-system energy sum and the per-atom force sum in FP64.  The BF16
-// variant feeds the pair kernels' GEMMs BF16 operands (FP32 accumulation).
+// the node-level steps use the shared node kernels.  Precision plan: FP32 arithmetic, with
+// the geometry/basis, the embedding's node stage (norms, LayerNorm, MLP, gating; its channel
+// mixing is linear and runs in FP32) and the output network in FP64, reading and writing the
+// FP32 feature arrays directly; the per-system energy sum and the per-atom force sum in
+// FP64.  The BF16 variant feeds the pair kernels' GEMMs BF16 operands (FP32 accumulation).
 #include "tn_nodeops.h"
 
 namespace tn {
@@ -33,12 +34,12 @@ using TA = double;
 
 struct FusedWs {
   NbrWs nb;
-  float *geo, *phi, *f0, *Xr;
-  TA *XrA, *T0, *nrm0, *xhat0, *rstd0, *n0, *ez1, *ea1, *ez2, *g, *X0A;
+  float *geo, *phi, *f0, *Xr, *T0;
+  TA *nrm0, *xhat0, *rstd0, *n0, *ez1, *ea1, *ez2, *g;
   std::vector<float *> X, nX, Xb, Y, z1, z2, z3, h, M, P, nP, Pb, D, dM;
-  TA *XLA, *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps, *eps_orig;
-  float *dX = nullptr, *dD, *dPb, *dY, *dXr;
-  TA *dXA, *dT0, *dXrA, *dg, *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
+  TA *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps, *eps_orig;
+  float *dX = nullptr, *dD, *dPb, *dY, *dXr, *dT0;
+  TA *dg, *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
   float *gpair;
 };
 
@@ -49,8 +50,7 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   w->phi = p.take<float>(MP);
   w->f0 = p.take<float>(MP * 3 * F);
   w->Xr = p.take<float>(N * 9 * F);
-  w->XrA = p.take<TA>(N * 9 * F);
-  w->T0 = p.take<TA>(N * 9 * F);
+  w->T0 = p.take<float>(N * 9 * F);
   w->nrm0 = p.take<TA>(N * F);
   w->xhat0 = p.take<TA>(N * F);
   w->rstd0 = p.take<TA>(N);
@@ -59,7 +59,6 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   w->ea1 = p.take<TA>(N * 2 * F);
   w->ez2 = p.take<TA>(N * 3 * F);
   w->g = p.take<TA>(N * 3 * F);
-  w->X0A = p.take<TA>(N * 9 * F);
   w->X.resize(L + 1);
   for (int64_t l = 0; l <= L; ++l) w->X[l] = p.take<float>(N * 9 * F);
   auto per_layer = [&](std::vector<float *> &v, int64_t count) {
@@ -78,7 +77,6 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   per_layer(w->nP, N * F);
   per_layer(w->Pb, N * 9 * F);
   per_layer(w->D, N * 9 * F);
-  w->XLA = p.take<TA>(N * 9 * F);
   w->on = p.take<TA>(N * 3 * F);
   w->oxhat = p.take<TA>(N * 3 * F);
   w->orstd = p.take<TA>(N);
@@ -96,9 +94,7 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   w->dPb = p.take<float>(N * 9 * F);
   w->dY = p.take<float>(N * 9 * F);
   w->dXr = p.take<float>(N * 9 * F);
-  w->dXA = p.take<TA>(N * 9 * F);
-  w->dT0 = p.take<TA>(N * 9 * F);
-  w->dXrA = p.take<TA>(N * 9 * F);
+  w->dT0 = p.take<float>(N * 9 * F);
   w->dg = p.take<TA>(N * 3 * F);
   w->dez2 = p.take<TA>(N * 3 * F);
   w->dez1 = p.take<TA>(N * 2 * F);
@@ -205,9 +201,8 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   if ((rc = embed_gather_w(s, F, N, rowptr, nbr, pid, np, MP, zz, m->max_z, W(o.U), W(o.V), w.geo, w.phi, w.f0,
                            w.Xr)))
     return rc;
-  if ((rc = convert<float, TA>(s, w.Xr, w.XrA, N * 9 * F))) return rc;
   if (N > 0) {
-    hipLaunchKernelGGL(k_node_norm<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XrA, w.nrm0);
+    hipLaunchKernelGGL((k_node_norm<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xr, w.nrm0);
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_layernorm<TA>, dim3((unsigned)N), dim3(128), 0, s, N, (int)F, w.nrm0, WA(o.ln_g),
                        WA(o.ln_b), w.n0, w.xhat0, w.rstd0);
@@ -215,13 +210,16 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   }
   if ((rc = linear_fwd<TA>(s, w.n0, N, F, WA(o.W1), WA(o.b1), 2 * F, w.ea1, w.ez1, 1))) return rc;
   if ((rc = linear_fwd<TA>(s, w.ea1, N, 2 * F, WA(o.W2), WA(o.b2), 3 * F, w.g, w.ez2, 1))) return rc;
-  const TA *Wemb[3] = {WA(o.Wmix[0]), WA(o.Wmix[1]), WA(o.Wmix[2])};
-  if ((rc = mix<TA>(s, w.XrA, w.T0, N, F, Wemb, nullptr, 0, 0))) return rc;
+  // the embedding's channel mixing is linear in the FP32 features and runs in FP32; the
+  // gating product is formed in FP64 and rounded once
+  const float *Wemb[3] = {W(o.Wmix[0]), W(o.Wmix[1]), W(o.Wmix[2])};
+  const float *WembT[3] = {W(o.WmixT[0]), W(o.WmixT[1]), W(o.WmixT[2])};
+  if ((rc = mix<float>(s, w.Xr, w.T0, N, F, Wemb, WembT, 0, 0))) return rc;
   if (N > 0) {
-    hipLaunchKernelGGL(k_gate<TA>, dim3(grid_for(N * 9 * F, bs)), dim3(bs), 0, s, N, (int)F, w.g, w.T0, w.X0A);
+    hipLaunchKernelGGL((k_gate<TA, float>), dim3(grid_for(N * 9 * F, bs)), dim3(bs), 0, s, N, (int)F, w.g, w.T0,
+                       w.X[0]);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = convert<TA, float>(s, w.X0A, w.X[0], N * 9 * F))) return rc;
   // ---- interaction layers: normalise (first layer), mix, message+product, mix, residual(+normalise)
   if (N > 0 && L > 0) {
     hipLaunchKernelGGL(k_normalize<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[0], w.nX[0], w.Xb[0]);
@@ -250,9 +248,8 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   }
   // ---- output network (FP64) and energies
   const int64_t H = F / 2;
-  if ((rc = convert<float, TA>(s, w.X[L], w.XLA, N * 9 * F))) return rc;
   if (N > 0) {
-    hipLaunchKernelGGL(k_out_norms<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XLA, w.on);
+    hipLaunchKernelGGL((k_out_norms<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[L], w.on);
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_layernorm<TA>, dim3((unsigned)N), dim3(128), 0, s, N, (int)(3 * F), w.on, WA(o.oln_g),
                        WA(o.oln_b), w.q, w.oxhat, w.orstd);
@@ -290,10 +287,9 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     hipLaunchKernelGGL(k_layernorm_bwd<TA>, dim3((unsigned)N), dim3(128), 0, s, N, (int)(3 * F), w.dq, w.oxhat,
                        w.orstd, WA(o.oln_g), w.don);
     TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_out_norms_bwd<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XLA, w.don, w.dXA);
+    hipLaunchKernelGGL((k_out_norms_bwd<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[L], w.don, w.dX);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = convert<TA, float>(s, w.dXA, w.dX, N * 9 * F))) return rc;
   for (int64_t l = L - 1; l >= 0; --l) {
     const LayerOff &lo = o.layer[l];
     const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
@@ -318,12 +314,11 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     }
   }
   // ---- embedding adjoint, node part in FP64
-  if ((rc = convert<float, TA>(s, w.dX, w.dXA, N * 9 * F))) return rc;
   if (N > 0) {
-    hipLaunchKernelGGL(k_gate_bwd<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dXA, w.T0, w.g, w.dg, w.dT0);
+    hipLaunchKernelGGL((k_gate_bwd<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dX, w.T0, w.g, w.dg, w.dT0);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = mix<TA>(s, w.dT0, w.dXrA, N, F, Wemb, nullptr, 1, 0))) return rc;
+  if ((rc = mix<float>(s, w.dT0, w.dXr, N, F, Wemb, WembT, 1, 0))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_mul_silu_grad<TA>, dim3(grid_for(N * 3 * F, bs)), dim3(bs), 0, s, N * 3 * F, w.dg, w.ez2,
                        w.dez2);
@@ -335,10 +330,9 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     hipLaunchKernelGGL(k_layernorm_bwd<TA>, dim3((unsigned)N), dim3(128), 0, s, N, (int)F, w.dn0, w.xhat0, w.rstd0,
                        WA(o.ln_g), w.dnrm0);
     TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_norm_bwd_add<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XrA, w.dnrm0, w.dXrA);
+    hipLaunchKernelGGL((k_norm_bwd_add<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xr, w.dnrm0, w.dXr);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = convert<TA, float>(s, w.dXrA, w.dXr, N * 9 * F))) return rc;
   // ---- all per-pair work of the reverse sweep in one MFMA kernel
   if (BF16) {
     PairBwdArgsB pbw;

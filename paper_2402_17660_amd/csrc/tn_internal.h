@@ -43,6 +43,7 @@ struct WeightOff {
   std::vector<LayerOff> layer;
   size_t oln_g, oln_b, Wo, bo, Wh, bh, wout, bout;
   size_t W0T, W0f;  // transposed [K][3F] and aligned copy of W0
+  size_t WmixT[3];  // transposed embedding mixing matrices (adjoint mixing)
   size_t U, V;      // species tables [max_z, F]: Z_ij = U[z_i] + V[z_j]
   size_t mu, beta;  // radial basis constants [K]
   size_t total;     // element count of one packed copy

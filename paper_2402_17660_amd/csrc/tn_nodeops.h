@@ -389,14 +389,16 @@ __device__ inline void store9(T *X, int64_t i, int F, int f, const T c[9]) {
   for (int q = 0; q < 9; ++q) X[i * 9 * F + q * F + f] = c[q];
 }
 
-template <class T>
-__global__ void k_node_norm(int64_t n, int F, const T *X, T *nrm) {
+// Norms in T of features stored as TX (the FP64 island reads FP32 features directly).
+template <class T, class TX = T>
+__global__ void k_node_norm(int64_t n, int F, const TX *X, T *nrm) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9];
-  load9(X, i, F, f, c);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) c[q] = (T)X[i * 9 * F + q * F + f];
   nrm[i * F + f] = norm9(c);
 }
 
@@ -459,14 +461,15 @@ __global__ void __launch_bounds__(128) k_layernorm_bwd(int64_t rows, int C, cons
     dx[r * C + k] = rs * (gmul[k] * dy[r * C + k] - m1 - xhat[r * C + k] * m2);
 }
 
-template <class T>
-__global__ void k_gate(int64_t n, int F, const T *g, const T *T0, T *X) {
+// X = g_part(c) * T0 (gating), product in T, features stored as TX.
+template <class T, class TX = T>
+__global__ void k_gate(int64_t n, int F, const T *g, const TX *T0, TX *X) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * 9 * F) return;
   const int64_t i = t / (9 * F);
   const int rem = (int)(t % (9 * F));
   const int q = rem / F, f = rem % F;
-  X[t] = g[i * 3 * F + coord_part(q) * F + f] * T0[t];
+  X[t] = (TX)(g[i * 3 * F + coord_part(q) * F + f] * (T)T0[t]);
 }
 
 template <class T>
@@ -622,14 +625,15 @@ __global__ void k_residual(int64_t n, int F, const T *Xb, const T *D, T *Xo) {
   store9(Xo, i, F, f, xb);
 }
 
-template <class T>
-__global__ void k_out_norms(int64_t n, int F, const T *X, T *on) {
+template <class T, class TX = T>
+__global__ void k_out_norms(int64_t n, int F, const TX *X, T *on) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9];
-  load9(X, i, F, f, c);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) c[q] = (T)X[i * 9 * F + q * F + f];
   on[i * 3 * F + f] = norm_I(c);
   on[i * 3 * F + F + f] = norm_A(c);
   on[i * 3 * F + 2 * F + f] = norm_S(c);
@@ -682,16 +686,18 @@ __global__ void k_out_final_bwd(int64_t n, int H, const T *hz, const T *w, T *dh
 }
 
 // adjoint of the part norms: dX = sum_part d(norm_part) * grad(norm_part)
-template <class T>
-__global__ void k_out_norms_bwd(int64_t n, int F, const T *X, const T *don, T *dX) {
+template <class T, class TX = T>
+__global__ void k_out_norms_bwd(int64_t n, int F, const TX *X, const T *don, TX *dX) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9], d[9];
-  load9(X, i, F, f, c);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) c[q] = (T)X[i * 9 * F + q * F + f];
   norm_grad_parts(c, don[i * 3 * F + f], don[i * 3 * F + F + f], don[i * 3 * F + 2 * F + f], d);
-  store9(dX, i, F, f, d);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) dX[i * 9 * F + q * F + f] = (TX)d[q];
 }
 
 // X_out = Xb + D + DD:  dD = dX + rec^T(dQ D^T + D^T dQ) with dQ = dec^T(dX)
@@ -815,8 +821,8 @@ __global__ void __launch_bounds__(128) k_edge_bwd_top(int64_t max_pairs, const i
 }
 
 // X0 = g * T0 (per part):  dg[part] = sum_{c in part} dX0_c T0_c;  dT0 = g dX0
-template <class T>
-__global__ void k_gate_bwd(int64_t n, int F, const T *dX, const T *T0, const T *g, T *dg, T *dT0) {
+template <class T, class TX = T>
+__global__ void k_gate_bwd(int64_t n, int F, const TX *dX, const TX *T0, const T *g, T *dg, TX *dT0) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
   const int64_t i = t / F;
@@ -826,8 +832,8 @@ __global__ void k_gate_bwd(int64_t n, int F, const T *dX, const T *T0, const T *
   for (int q = 0; q < 9; ++q) {
     const int64_t o = i * 9 * F + q * F + f;
     const int pt = coord_part(q);
-    s[pt] += dX[o] * T0[o];
-    dT0[o] = g[i * 3 * F + pt * F + f] * dX[o];
+    s[pt] += (T)dX[o] * (T)T0[o];
+    dT0[o] = (TX)(g[i * 3 * F + pt * F + f] * (T)dX[o]);
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) dg[i * 3 * F + q * F + f] = s[q];
@@ -841,18 +847,22 @@ __global__ void k_mul_silu_grad(int64_t n, const T *d, const T *zz, T *out) {
 }
 
 // dX += dn * grad||X||
-template <class T>
-__global__ void k_norm_bwd_add(int64_t n, int F, const T *X, const T *dn, T *dX) {
+template <class T, class TX = T>
+__global__ void k_norm_bwd_add(int64_t n, int F, const TX *X, const T *dn, TX *dX) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9], gn[9];
-  load9(X, i, F, f, c);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) c[q] = (T)X[i * 9 * F + q * F + f];
   const T s = dn[i * F + f];
   norm_grad_parts(c, s, s, s, gn);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) dX[i * 9 * F + q * F + f] += gn[q];
+  for (int q = 0; q < 9; ++q) {
+    TX &d = dX[i * 9 * F + q * F + f];
+    d = (TX)((T)d + gn[q]);
+  }
 }
 
 // Embedding adjoint per pair (one block per pair, threads over channels):
