@@ -39,7 +39,7 @@ struct FusedWs {
   std::vector<float *> X, nX, Xb, Y, z1, z2, z3, h, M, P, nP, Pb, D, dM;
   TA *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps, *eps_orig;
   float *dX = nullptr, *dD, *dPb, *dY, *dXr, *dT0;
-  TA *dg, *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
+  TA *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
   float *gpair;
 };
 
@@ -95,7 +95,6 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   w->dY = p.take<float>(N * 9 * F);
   w->dXr = p.take<float>(N * 9 * F);
   w->dT0 = p.take<float>(N * 9 * F);
-  w->dg = p.take<TA>(N * 3 * F);
   w->dez2 = p.take<TA>(N * 3 * F);
   w->dez1 = p.take<TA>(N * 2 * F);
   w->dn0 = p.take<TA>(N * F);
@@ -121,14 +120,9 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   auto WA = [&](size_t off) { return wptr<TA>(m, off); };
   const WeightOff &o = m->off;
 
-  if (N > 0) {
-    hipLaunchKernelGGL(k_check_inputs<float>, dim3(grid_for(N, bs)), dim3(bs), 0, s, pb.z, pb.batch, N, pb.S,
-                       m->max_z, pb.status);
-    TN_LAUNCH_CHECK();
-  }
   NbrGraph<float> gr;
   if ((rc = build_neighbors<float>(s, N, static_cast<const float *>(pb.pos), pb.z, pb.batch, pb.box, m->r_c, MP, nullptr,
-                                 pb.n_pairs, pb.status, w.nb, &gr)))
+                                 pb.n_pairs, pb.status, w.nb, &gr, pb.S, m->max_z)))
     return rc;
   const int64_t *np = pb.n_pairs;
   const int32_t *rowptr = gr.rowptr, *nbr = gr.nbr, *pid = gr.pid;
@@ -215,16 +209,17 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   const float *Wemb[3] = {W(o.Wmix[0]), W(o.Wmix[1]), W(o.Wmix[2])};
   const float *WembT[3] = {W(o.WmixT[0]), W(o.WmixT[1]), W(o.WmixT[2])};
   if ((rc = mix<float>(s, w.Xr, w.T0, N, F, Wemb, WembT, 0, 0))) return rc;
-  if (N > 0) {
+  // (with layers, the gating also normalises the first layer's input)
+  if (N > 0 && L > 0) {
+    hipLaunchKernelGGL((k_gate_normalize<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.g, w.T0, w.X[0],
+                       w.nX[0], w.Xb[0]);
+    TN_LAUNCH_CHECK();
+  } else if (N > 0) {
     hipLaunchKernelGGL((k_gate<TA, float>), dim3(grid_for(N * 9 * F, bs)), dim3(bs), 0, s, N, (int)F, w.g, w.T0,
                        w.X[0]);
     TN_LAUNCH_CHECK();
   }
-  // ---- interaction layers: normalise (first layer), mix, message+product, mix, residual(+normalise)
-  if (N > 0 && L > 0) {
-    hipLaunchKernelGGL(k_normalize<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[0], w.nX[0], w.Xb[0]);
-    TN_LAUNCH_CHECK();
-  }
+  // ---- interaction layers: mix, message+product, mix, residual(+normalise)
   for (int64_t l = 0; l < L; ++l) {
     const LayerOff &lo = o.layer[l];
     const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
@@ -315,15 +310,11 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   }
   // ---- embedding adjoint, node part in FP64
   if (N > 0) {
-    hipLaunchKernelGGL((k_gate_bwd<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dX, w.T0, w.g, w.dg, w.dT0);
+    hipLaunchKernelGGL((k_gate_bwd<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dX, w.T0, w.g, w.dez2,
+                       w.dT0, w.ez2);
     TN_LAUNCH_CHECK();
   }
   if ((rc = mix<float>(s, w.dT0, w.dXr, N, F, Wemb, WembT, 1, 0))) return rc;
-  if (N > 0) {
-    hipLaunchKernelGGL(k_mul_silu_grad<TA>, dim3(grid_for(N * 3 * F, bs)), dim3(bs), 0, s, N * 3 * F, w.dg, w.ez2,
-                       w.dez2);
-    TN_LAUNCH_CHECK();
-  }
   if ((rc = linear_bwd<TA>(s, w.dez2, N, 3 * F, WA(o.W2), 2 * F, w.dez1, w.ez1, 0))) return rc;
   if ((rc = linear_bwd<TA>(s, w.dez1, N, 2 * F, WA(o.W1), F, w.dn0, nullptr, 0))) return rc;
   if (N > 0) {

@@ -108,7 +108,6 @@ struct NbrWs {
   int32_t *nbr = nullptr, *pid = nullptr;       // [2*max_pairs] CSR rows (sorted by neighbour)
   int32_t *scan_tmp = nullptr;                  // block sums
   int64_t *count64 = nullptr;                   // [2]: total pairs, total directed edges
-  int32_t *flags = nullptr;                     // [0]: batch vector not sorted
   void *spos = nullptr;                         // [N,3] cell-ordered positions (periodic)
   int32_t *sz = nullptr, *sbatch = nullptr, *scell = nullptr;   // cell-ordered z, batch, cell
   int32_t *ipairs = nullptr;                    // [2, max_pairs] internal pair list
@@ -130,7 +129,8 @@ void plan_neighbors(WsPlan &p, int64_t n, int64_t max_pairs, const BoxInfo &bi, 
 template <class T>
 int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, const int32_t *batch,
                     const BoxInfo &bi, double cutoff, int64_t max_pairs, int32_t *public_pairs, int64_t *n_pairs,
-                    int32_t *status, const NbrWs &w, NbrGraph<T> *graph);
+                    int32_t *status, const NbrWs &w, NbrGraph<T> *graph,
+                    int64_t n_systems = 0, int max_z = 0);
 
 // ------------------------------------------------------------------ scans and fills
 int exclusive_scan_i32(hipStream_t s, int32_t *data, int64_t n, int32_t *block_tmp, int64_t *total_out);

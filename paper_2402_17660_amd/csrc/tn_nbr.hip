@@ -137,8 +137,66 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_add(int32_t *data, int64_
     if (base + k < n) data[base + k] += add;
 }
 
+// Single-workgroup scans for short arrays (n <= kSmallScan): one launch instead of three.
+constexpr int kSmallThreads = 1024, kSmallItems = 8, kSmallScan = kSmallThreads * kSmallItems;
+
+__device__ int32_t small_scan_inplace(int32_t *data, int64_t n, int32_t *lds) {
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)t * kSmallItems;
+  int32_t v[kSmallItems];
+  int32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kSmallItems; ++k) {
+    v[k] = (base + k < n) ? data[base + k] : 0;
+    sum += v[k];
+  }
+  lds[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < kSmallThreads; off <<= 1) {
+    const int32_t add = (t >= off) ? lds[t - off] : 0;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  int32_t run = lds[t] - sum;
+  const int32_t total = lds[kSmallThreads - 1];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSmallItems; ++k) {
+    if (base + k < n) data[base + k] = run;
+    run += v[k];
+  }
+  if (t == 0) data[n] = total;
+  return total;
+}
+
+__global__ void __launch_bounds__(kSmallThreads) k_scan_small(int32_t *data, int64_t n) {
+  __shared__ int32_t lds[kSmallThreads];
+  small_scan_inplace(data, n, lds);
+}
+
+// Both neighbour scans (full degree and upper pairs) and the pair total in one launch.
+__global__ void __launch_bounds__(kSmallThreads) k_scan_nbr_small(int32_t *deg, int32_t *nup, int64_t n,
+                                                                  int64_t *count64, int64_t max_pairs,
+                                                                  int64_t *n_pairs, int32_t *status) {
+  __shared__ int32_t lds[kSmallThreads];
+  const int32_t full = small_scan_inplace(deg, n, lds);
+  const int32_t up = small_scan_inplace(nup, n, lds);
+  if (threadIdx.x == 0) {
+    count64[0] = up;
+    count64[1] = full;
+    *n_pairs = up;
+    if (up > max_pairs) set_status(status, TN_STATUS_OVERFLOW);
+  }
+}
+
 // In-place exclusive scan of data[0..n); data[n] receives the total (data must hold n+1).
 int exclusive_scan_i32(hipStream_t s, int32_t *data, int64_t n, int32_t *block_tmp, int64_t *total_out) {
+  if (n <= kSmallScan && !total_out) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallThreads), 0, s, data, n);
+    TN_LAUNCH_CHECK();
+    return TN_OK;
+  }
   const int64_t nblk = (n + kScanTile - 1) / kScanTile;
   if (nblk > 0) {
     hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nblk), dim3(kScanThreads), 0, s, data, n, block_tmp);
@@ -223,7 +281,6 @@ void plan_neighbors(WsPlan &p, int64_t n, int64_t max_pairs, const BoxInfo &bi, 
   w->pid = p.take<int32_t>(2 * max_pairs);
   w->scan_tmp = p.take<int32_t>(scan_tmp_count(n > ncell ? n : ncell));
   w->count64 = p.take<int64_t>(4);
-  w->flags = p.take<int32_t>(4);
 }
 
 struct BoxDev {
@@ -335,22 +392,23 @@ __device__ inline void system_range(const int32_t *batch, int64_t n, int32_t bv,
   hi = a;
 }
 
-__global__ void k_batch_sorted(const int32_t *batch, int64_t n, int32_t *unsorted, int32_t *status) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n || i == 0) return;
-  if (batch[i] < batch[i - 1]) {
-    atomicOr(reinterpret_cast<int *>(unsorted), 1);
-    set_status(status, TN_STATUS_BATCH);
-  }
-}
-
+// Input checks in one pass: batch sorted (systems contiguous) and in [0, n_systems) when
+// n_systems > 0, z in [0, max_z) when z is given, finite positions when check_pos.  An
+// unsorted batch sets TN_STATUS_BATCH, which the candidate sweep reads as "search all atoms".
 template <class T>
-__global__ void k_check_finite(const T *pos, int64_t n, int32_t *status) {
+__global__ void k_validate(const T *pos, const int32_t *z, const int32_t *batch, int64_t n, int64_t n_systems,
+                           int max_z, int check_pos, int32_t *status) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double x, y, z;
-  load_pos(pos, i, x, y, z);
-  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) set_status(status, TN_STATUS_NONFINITE);
+  const int32_t b = batch[i];
+  if (i > 0 && b < batch[i - 1]) set_status(status, TN_STATUS_BATCH);
+  if (n_systems > 0 && (b < 0 || b >= n_systems)) set_status(status, TN_STATUS_BATCH);
+  if (z && max_z > 0 && (z[i] < 0 || z[i] >= max_z)) set_status(status, TN_STATUS_Z);
+  if (check_pos) {
+    double x, y, zz;
+    load_pos(pos, i, x, y, zz);
+    if (!isfinite(x) || !isfinite(y) || !isfinite(zz)) set_status(status, TN_STATUS_NONFINITE);
+  }
 }
 
 // Deterministic order inside each cell: the cell's atoms sorted by original index.  One
@@ -416,7 +474,7 @@ constexpr int kNbrBlock = 256;
 template <class T, class Fn>
 __device__ inline void wave_candidates(int64_t s, const T *pos, const int32_t *batch, int64_t n, const BoxDev &b,
                                        double rc2, const int32_t *scell, const int32_t *cell_start,
-                                       const int32_t *unsorted, Fn &&f) {
+                                       const int32_t *status, Fn &&f) {
   const int lane = threadIdx.x & 63;
   double xi, yi, zi;
   load_pos(pos, s, xi, yi, zi);
@@ -482,7 +540,7 @@ __device__ inline void wave_candidates(int64_t s, const T *pos, const int32_t *b
     }
   } else {
     int64_t lo = 0, hi = n;
-    if (!*unsorted) system_range(batch, n, bs, lo, hi);
+    if (!(*status & TN_STATUS_BATCH)) system_range(batch, n, bs, lo, hi);
     for (int64_t q0 = lo; q0 < hi; q0 += 64) {
       const int64_t j = q0 + lane;
       bool pred = false;
@@ -499,11 +557,11 @@ __device__ inline void wave_candidates(int64_t s, const T *pos, const int32_t *b
 template <class T>
 __global__ void __launch_bounds__(kNbrBlock) k_nbr_count(const T *pos, const int32_t *batch, int64_t n, BoxDev b,
                                                          double rc2, const int32_t *scell, const int32_t *cell_start,
-                                                         const int32_t *unsorted, int32_t *deg, int32_t *nup) {
+                                                         const int32_t *status, int32_t *deg, int32_t *nup) {
   const int64_t s = (blockIdx.x * (int64_t)kNbrBlock + threadIdx.x) >> 6;
   if (s >= n) return;
   int32_t full = 0, upper = 0;
-  wave_candidates(s, pos, batch, n, b, rc2, scell, cell_start, unsorted, [&](bool pred, int32_t j) {
+  wave_candidates(s, pos, batch, n, b, rc2, scell, cell_start, status, [&](bool pred, int32_t j) {
     const uint64_t m = __ballot(pred);
     const uint64_t mu = __ballot(pred && j > s);
     full += __popcll(m);
@@ -518,14 +576,14 @@ __global__ void __launch_bounds__(kNbrBlock) k_nbr_count(const T *pos, const int
 template <class T>
 __global__ void __launch_bounds__(kNbrBlock) k_nbr_write(const T *pos, const int32_t *batch, int64_t n, BoxDev b,
                                                          double rc2, const int32_t *scell, const int32_t *cell_start,
-                                                         const int32_t *unsorted, const int32_t *rowptr,
+                                                         const int32_t *status, const int32_t *rowptr,
                                                          const int64_t *count64, int64_t max_pairs, int32_t *nbr) {
   const int64_t s = (blockIdx.x * (int64_t)kNbrBlock + threadIdx.x) >> 6;
   if (s >= n || count64[0] > max_pairs) return;
   const int lane = threadIdx.x & 63;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int32_t e = rowptr[s];
-  wave_candidates(s, pos, batch, n, b, rc2, scell, cell_start, unsorted, [&](bool pred, int32_t j) {
+  wave_candidates(s, pos, batch, n, b, rc2, scell, cell_start, status, [&](bool pred, int32_t j) {
     const uint64_t m = __ballot(pred);
     if (pred) nbr[e + __popcll(m & below)] = j;
     e += __popcll(m);
@@ -604,7 +662,7 @@ __global__ void k_pairs_public(const int64_t *count64, int64_t max_pairs, const 
 template <class T>
 int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, const int32_t *batch,
                     const BoxInfo &bi, double cutoff, int64_t max_pairs, int32_t *public_pairs, int64_t *n_pairs,
-                    int32_t *status, const NbrWs &w, NbrGraph<T> *graph) {
+                    int32_t *status, const NbrWs &w, NbrGraph<T> *graph, int64_t n_systems, int max_z) {
   const BoxDev b = to_dev(bi);
   const double rc2 = cutoff * cutoff;
   const int blk = 128;
@@ -616,9 +674,9 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, co
   out.z = z;
   out.batch = batch;
   out.perm = nullptr;
-  if ((rc = fill_i32(s, w.flags, 4, 0))) return rc;
-  if (n > 0) {
-    hipLaunchKernelGGL(k_batch_sorted, dim3(g), dim3(blk), 0, s, batch, n, w.flags, status);
+  if (n > 0) {   // the cell binning checks the positions itself
+    hipLaunchKernelGGL(k_validate<T>, dim3(g), dim3(blk), 0, s, pos, z, batch, n, n_systems, max_z,
+                       bi.cells ? 0 : 1, status);
     TN_LAUNCH_CHECK();
   }
   if (bi.cells) {
@@ -646,22 +704,25 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, co
       out.batch = w.sbatch;
       out.perm = w.cell_atoms;
     }
-  } else if (n > 0) {
-    hipLaunchKernelGGL(k_check_finite<T>, dim3(g), dim3(blk), 0, s, pos, n, status);
-    TN_LAUNCH_CHECK();
   }
   if (n > 0) {
     hipLaunchKernelGGL(k_nbr_count<T>, dim3(gw), dim3(kNbrBlock), 0, s, out.pos, out.batch, n, b, rc2, w.scell,
-                       w.cell_start, w.flags, w.deg, w.nup);
+                       w.cell_start, status, w.deg, w.nup);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = exclusive_scan_i32(s, w.deg, n, w.scan_tmp, w.count64 + 1))) return rc;
-  if ((rc = exclusive_scan_i32(s, w.nup, n, w.scan_tmp, w.count64 + 0))) return rc;
-  hipLaunchKernelGGL(k_nbr_total, dim3(1), dim3(64), 0, s, w.count64, max_pairs, n_pairs, status);
-  TN_LAUNCH_CHECK();
+  if (n <= kSmallScan) {
+    hipLaunchKernelGGL(k_scan_nbr_small, dim3(1), dim3(kSmallThreads), 0, s, w.deg, w.nup, n, w.count64, max_pairs,
+                       n_pairs, status);
+    TN_LAUNCH_CHECK();
+  } else {
+    if ((rc = exclusive_scan_i32(s, w.deg, n, w.scan_tmp, w.count64 + 1))) return rc;
+    if ((rc = exclusive_scan_i32(s, w.nup, n, w.scan_tmp, w.count64 + 0))) return rc;
+    hipLaunchKernelGGL(k_nbr_total, dim3(1), dim3(64), 0, s, w.count64, max_pairs, n_pairs, status);
+    TN_LAUNCH_CHECK();
+  }
   if (n > 0) {
     hipLaunchKernelGGL(k_nbr_write<T>, dim3(gw), dim3(kNbrBlock), 0, s, out.pos, out.batch, n, b, rc2, w.scell,
-                       w.cell_start, w.flags, w.deg, w.count64, max_pairs, w.nbr);
+                       w.cell_start, status, w.deg, w.count64, max_pairs, w.nbr);
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_pair_ids, dim3(gw), dim3(kNbrBlock), 0, s, n, w.deg, w.nup, w.nbr, w.count64, max_pairs,
                        w.pid, w.ipairs);
@@ -682,9 +743,9 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, co
 
 template int build_neighbors<float>(hipStream_t, int64_t, const float *, const int32_t *, const int32_t *,
                                     const BoxInfo &, double, int64_t, int32_t *, int64_t *, int32_t *, const NbrWs &,
-                                    NbrGraph<float> *);
+                                    NbrGraph<float> *, int64_t, int);
 template int build_neighbors<double>(hipStream_t, int64_t, const double *, const int32_t *, const int32_t *,
                                      const BoxInfo &, double, int64_t, int32_t *, int64_t *, int32_t *,
-                                     const NbrWs &, NbrGraph<double> *);
+                                     const NbrWs &, NbrGraph<double> *, int64_t, int);
 
 }  // namespace tn

@@ -303,15 +303,6 @@ __device__ inline int64_t pair_bound(const int64_t *n_pairs, int64_t max_pairs) 
   return P < max_pairs ? P : max_pairs;
 }
 
-template <class T>
-__global__ void k_check_inputs(const int32_t *z, const int32_t *batch, int64_t n, int64_t S, int max_z,
-                               int32_t *status) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (z[i] < 0 || z[i] >= max_z) set_status(status, TN_STATUS_Z);
-  if (batch[i] < 0 || batch[i] >= S) set_status(status, TN_STATUS_BATCH);
-}
-
 __device__ inline int clamp_z(int32_t z, int max_z) { return z < 0 ? 0 : (z >= max_z ? max_z - 1 : z); }
 
 // Per pair: unit vector, distance, cutoff phi(d), exp-normal basis e_k(d).  Evaluated in
@@ -470,6 +461,28 @@ __global__ void k_gate(int64_t n, int F, const T *g, const TX *T0, TX *X) {
   const int rem = (int)(t % (9 * F));
   const int q = rem / F, f = rem % F;
   X[t] = (TX)(g[i * 3 * F + coord_part(q) * F + f] * (T)T0[t]);
+}
+
+// X = g_part(c) * T0 (gating) followed by the first layer's normalisation:
+// nX = ||X||, Xb = X / (||X|| + 1).  One thread per (atom, channel); products in T.
+template <class T, class TX>
+__global__ void k_gate_normalize(int64_t n, int F, const T *g, const TX *T0, TX *X, TX *nX, TX *Xb) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  const int64_t i = t / F;
+  const int f = (int)(t % F);
+  TX c[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int64_t o = i * 9 * F + q * F + f;
+    c[q] = (TX)(g[i * 3 * F + coord_part(q) * F + f] * (T)T0[o]);
+    X[o] = c[q];
+  }
+  const TX nn = norm9(c);
+  nX[i * F + f] = nn;
+  const TX sc = TX(1) / (nn + TX(1));
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Xb[i * 9 * F + q * F + f] = c[q] * sc;
 }
 
 template <class T>
@@ -821,8 +834,10 @@ __global__ void __launch_bounds__(128) k_edge_bwd_top(int64_t max_pairs, const i
 }
 
 // X0 = g * T0 (per part):  dg[part] = sum_{c in part} dX0_c T0_c;  dT0 = g dX0
+// With ez given, dg leaves multiplied by silu'(ez) (the adjoint of the MLP's last SiLU).
 template <class T, class TX = T>
-__global__ void k_gate_bwd(int64_t n, int F, const TX *dX, const TX *T0, const T *g, T *dg, TX *dT0) {
+__global__ void k_gate_bwd(int64_t n, int F, const TX *dX, const TX *T0, const T *g, T *dg, TX *dT0,
+                           const T *ez = nullptr) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
   const int64_t i = t / F;
@@ -836,7 +851,10 @@ __global__ void k_gate_bwd(int64_t n, int F, const TX *dX, const TX *T0, const T
     dT0[o] = (TX)(g[i * 3 * F + pt * F + f] * (T)dX[o]);
   }
 #pragma unroll
-  for (int q = 0; q < 3; ++q) dg[i * 3 * F + q * F + f] = s[q];
+  for (int q = 0; q < 3; ++q) {
+    const int64_t o = i * 3 * F + q * F + f;
+    dg[o] = ez ? s[q] * silu_grad(ez[o]) : s[q];
+  }
 }
 
 template <class T>

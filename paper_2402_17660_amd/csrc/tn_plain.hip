@@ -146,14 +146,9 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
   auto WA = [&](size_t off) { return wptr<TA>(m, off); };
   const WeightOff &o = m->off;
 
-  if (N > 0) {
-    hipLaunchKernelGGL(k_check_inputs<T>, dim3(grid_for(N, bs)), dim3(bs), 0, s, pb.z, pb.batch, N, pb.S, m->max_z,
-                       pb.status);
-    TN_LAUNCH_CHECK();
-  }
   NbrGraph<T> gr;
   if ((rc = build_neighbors<T>(s, N, static_cast<const T *>(pb.pos), pb.z, pb.batch, pb.box, m->r_c, MP, nullptr,
-                                 pb.n_pairs, pb.status, w.nb, &gr)))
+                                 pb.n_pairs, pb.status, w.nb, &gr, pb.S, m->max_z)))
     return rc;
   const int64_t *np = pb.n_pairs;
   const int32_t *rowptr = gr.rowptr, *nbr = gr.nbr, *pid = gr.pid;
