@@ -9,10 +9,13 @@ same seeded inputs from `synth`, nothing else.
 Contents
   blob       independent parser of the weight blob
   neighbors  O1: unordered pair set {i<j, same system, d^2 < r_c^2} with the
-             minimum image in a rectangular box (brute force + a CPU cell list)
+             minimum image in a rectangular or triclinic cell (brute force +
+             a CPU cell list)
   model      O2-O6: geometry, exp-normal basis, cosine cutoff, embedding,
              interaction layers, output network, energies, and forces by
              torch.autograd, all in float64 on full 3x3 matrices
+  train      the energy + force loss and its parameter gradient by torch
+             double autograd (the training step's reference)
 
 Every function cites the part of the paper it follows (TorchMD-Net 2.0,
 arXiv 2402.17660): the TensorNet paragraph of Sec. 2.1.1, the hyper-parameter
@@ -38,3 +41,4 @@ from .model import (  # noqa: F401
     layer_norm,
     silu,
 )
+from .train import training_loss, training_loss_and_grad  # noqa: F401,E402
