@@ -153,6 +153,38 @@ int tn_energy_forces(const tn_model *m, void *stream, int64_t n_atoms, int64_t n
                      int precision, int path, double *energy, void *forces, int64_t *n_pairs, int32_t *status,
                      void *ws, size_t ws_bytes);
 
+/* -------------------------------------------------------- training step ---
+ * Force training (Sec. 2.5: training on forces differentiates through the
+ * force computation a second time; Sec. 3 trains on energies and forces
+ * together) with the loss
+ *   loss = w_energy * mean_s (E_s - energy_ref_s)^2
+ *        + w_force  * mean_{i,a} (F_ia - forces_ref_ia)^2,   F = -dE/dpos,
+ * and its gradient with respect to every tensor of the weight blob.  Two
+ * passes: energies and forces (the plain path), then the reverse sweep to the
+ * parameters on dual numbers whose positions carry the tangent d loss/dF, so
+ * the force term's mixed second derivative comes out exactly (forward over
+ * reverse), not by finite differences.
+ *   tn_param_count: number of float64 values in the blob's tensors (the
+ *     length of grad), or -1 for a null model.
+ *   tn_train_workspace_bytes: ws size for tn_train_grad, 0 if invalid.
+ *   precision: TN_FP64 or TN_FP32 (every step of both passes in that type;
+ *     pos and forces typed as for tn_energy_forces).  Others: TN_E_UNSUPPORTED.
+ *   energy_ref [n_systems], forces_ref [n_atoms, 3]: float64 targets (device).
+ *   loss: one float64 (device); energy [n_systems] float64 and forces
+ *     [n_atoms, 3] receive the model's predictions at pos.
+ *   grad: [tn_param_count] float64 (device), overwritten, blob tensor order
+ *     and shapes (the model's own weights are not changed).
+ * Pair budget and status as for tn_energy_forces; TN_E_UNSUPPORTED when
+ * max_pairs or n_atoms exceeds 1048560. */
+int64_t tn_param_count(const tn_model *m);
+size_t tn_train_workspace_bytes(const tn_model *m, int64_t n_atoms, int64_t n_systems, int64_t max_pairs,
+                                const double *box, int precision);
+int tn_train_grad(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, const void *pos,
+                  const int32_t *z, const int32_t *batch, const double *box, int64_t max_pairs, int precision,
+                  const double *energy_ref, const double *forces_ref, double w_energy, double w_force,
+                  double *loss, double *energy, void *forces, double *grad, int64_t *n_pairs, int32_t *status,
+                  void *ws, size_t ws_bytes);
+
 /* ------------------------------------------------------ pair-tile tuning ---
  * The fused path evaluates every layer's edge filter once per unordered pair
  * in MFMA tiles (Sec. 2.5: per-pair work dominates; the paper picks kernel

@@ -40,6 +40,10 @@ PROTOTYPES = {
     "tn_model_set_pair_variant": (_i32, [_vp, _i32, _i32, _i32]),
     "tn_autotune": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
                            _vp]),
+    "tn_param_count": (_i64, [_vp]),
+    "tn_train_workspace_bytes": (_sz, [_vp, _i64, _i64, _i64, _vp, _i32]),
+    "tn_train_grad": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _dbl, _dbl, _vp, _vp,
+                             _vp, _vp, _vp, _vp, _vp, _sz]),
     "tn_timing_enable": (_i32, [_i32]),
     "tn_timing_reset": (_i32, []),
     "tn_timing_read": (_i32, [_c.c_char_p, _c.POINTER(_dbl), _c.POINTER(_i64)]),

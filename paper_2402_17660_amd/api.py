@@ -192,6 +192,70 @@ class TensorNet:
         return self._run(pos, z, batch, n_systems, box, max_pairs, precision, path, True, check,
                          energy_out=energy_out, forces_out=forces_out)
 
+    def param_shapes(self):
+        """(name, shape) of every tensor of the weight blob, in blob order: the layout of the flat gradient
+        tn_train_grad writes."""
+        F, K, Z = self.F, self.K, self.max_z
+        out = [("emb.E", (Z, F)), ("emb.Wz", (F, 2 * F)), ("emb.bz", (F,)), ("emb.W0", (3 * F, K)),
+               ("emb.b0", (3 * F,)), ("emb.ln_g", (F,)), ("emb.ln_b", (F,)), ("emb.W1", (2 * F, F)),
+               ("emb.b1", (2 * F,)), ("emb.W2", (3 * F, 2 * F)), ("emb.b2", (3 * F,)), ("emb.WI", (F, F)),
+               ("emb.WA", (F, F)), ("emb.WS", (F, F))]
+        for layer in range(self.L):
+            p = f"layer{layer}."
+            out += [(p + "Wa", (F, K)), (p + "ba", (F,)), (p + "Wb", (2 * F, F)), (p + "bb", (2 * F,)),
+                    (p + "Wc", (3 * F, 2 * F)), (p + "bc", (3 * F,)), (p + "W1I", (F, F)), (p + "W1A", (F, F)),
+                    (p + "W1S", (F, F)), (p + "W2I", (F, F)), (p + "W2A", (F, F)), (p + "W2S", (F, F))]
+        out += [("out.ln_g", (3 * F,)), ("out.ln_b", (3 * F,)), ("out.Wo", (F, 3 * F)), ("out.bo", (F,)),
+                ("out.Wh", (F // 2, F)), ("out.bh", (F // 2,)), ("out.W2", (1, F // 2)), ("out.b2", (1,))]
+        return out
+
+    def split_params(self, flat: torch.Tensor) -> dict:
+        """Views of a flat blob-ordered tensor (a gradient from train_grad) by tensor name."""
+        out, off = {}, 0
+        for name, shape in self.param_shapes():
+            n = int(np.prod(shape))
+            out[name] = flat[off:off + n].view(shape)
+            off += n
+        if off != flat.numel():
+            raise TensorNetError(f"expected {off} values, got {flat.numel()}")
+        return out
+
+    def param_count(self) -> int:
+        return int(L.lib().tn_param_count(self._h))
+
+    def train_grad(self, pos, z, batch, n_systems, energy_ref, forces_ref, box=None, max_pairs=None,
+                   precision="fp64", w_energy=1.0, w_force=1.0, check=True, grad_out=None):
+        """One training step's loss and weight gradient (tn_train_grad).  Returns (loss [1] float64, energies,
+        forces, grad [param_count] float64), all on the device."""
+        dev = self.device
+        pdt = torch.float64 if precision == "fp64" else torch.float32
+        _require_device(pos, "pos", pdt, dev)
+        _require_device(z, "z", torch.int32, dev)
+        _require_device(batch, "batch", torch.int32, dev)
+        _require_device(energy_ref, "energy_ref", torch.float64, dev)
+        _require_device(forces_ref, "forces_ref", torch.float64, dev)
+        n = pos.shape[0]
+        if max_pairs is None:
+            max_pairs = max(64 * n, 1)
+        boxarr, boxp = _box_arg(box)
+        nbytes = L.lib().tn_train_workspace_bytes(self._h, n, n_systems, max_pairs, boxp, _PREC[precision])
+        if nbytes == 0:
+            raise TensorNetError(f"invalid training request (precision={precision}, box, sizes)")
+        buf = self.ws.get(nbytes)
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+        E = torch.empty(n_systems, dtype=torch.float64, device=dev)
+        Fo = torch.empty((n, 3), dtype=pdt, device=dev)
+        grad = grad_out if grad_out is not None else torch.empty(self.param_count(), dtype=torch.float64,
+                                                                 device=dev)
+        rc = L.lib().tn_train_grad(self._h, _stream(dev), n, n_systems, _ptr(pos), _ptr(z), _ptr(batch), boxp,
+                                   max_pairs, _PREC[precision], _ptr(energy_ref), _ptr(forces_ref), float(w_energy),
+                                   float(w_force), _ptr(loss), _ptr(E), _ptr(Fo), _ptr(grad), _ptr(self.n_pairs),
+                                   _ptr(self.status), _ptr(buf), buf.numel())
+        _check(rc, "tn_train_grad")
+        if check:
+            self.check()
+        return loss, E, Fo, grad
+
     @staticmethod
     def pair_variant_count(precision="fp32") -> int:
         return int(L.lib().tn_pair_variant_count(_PREC[precision]))

@@ -1,0 +1,749 @@
+// Training step: the energy + force loss and its gradient with respect to every weight.
+//
+// Force training (Sec. 2.5; the loss of Sec. 3 weighs energy and force errors) needs the
+// parameter gradient of a function of the forces, which are themselves the negative
+// position gradient of the energy: a second derivative through the whole network.  With
+//   loss = w_E mean_s (E_s - E*_s)^2 + w_F mean_{i,a} (F_ia - F*_ia)^2,   F = -dE/dr,
+//   a_s = d loss / d E_s,   W_ia = d loss / d F_ia,
+// the gradient is  sum_s a_s dE_s/dtheta - D_W (d E_tot / d theta),  where D_W is the
+// directional derivative along positions r + eps W.  The step computes it in two passes:
+//   1. energies and forces at r (the plain path), the loss, a_s and W;
+//   2. the hand-written reverse sweep energy -> parameters, run on dual numbers whose
+//      positions carry the tangent W and whose per-system seeds are (-1, a_s): the eps parts
+//      of the parameter adjoints are then exactly the loss gradient (forward-over-reverse).
+// Pass 2 is the plain path's forward and reverse sweep with T = Dual<S> everywhere (no
+// precision islands: S is the precision asked for) plus the parameter adjoints, which the
+// energy/forces sweep does not need: outer products of layer adjoints with layer inputs for
+// every linear map and mixing matrix, column sums for biases and LayerNorm gains, and the
+// species tables U, V (Z_ij = U[z_i] + V[z_j]) pulled back to the embedding E, W_z, b_z.
+// The reverse sweep stops at the parameters: no position adjoints are formed in pass 2.
+#include "tn_nodeops.h"
+#include "tn_dual.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace tn {
+
+constexpr int kSlices = 32;   // row slices of a parameter-adjoint reduction
+
+// Rows of a feature array: row r starts at (r / rg) * gs + (c0 + r % rg) * cs.  One row per
+// pair or atom (rg = 1, gs = row length) or, for a mixing matrix, the coordinates of one part
+// (rg = 1, 3 or 5 coordinates starting at c0, gs = 9F, cs = F).
+struct RowMap {
+  int rg = 1;
+  int64_t gs = 0;
+  int c0 = 0;
+  int64_t cs = 0;
+};
+__device__ inline int64_t row_at(const RowMap &m, int64_t r) {
+  return (r / m.rg) * m.gs + (m.c0 + r % m.rg) * m.cs;
+}
+inline RowMap rows_of(int64_t len) { return RowMap{1, len, 0, 0}; }
+inline RowMap part_rows(int part, int64_t F) {
+  const int c0 = part == 0 ? 0 : (part == 1 ? 1 : 4), nc = part == 0 ? 1 : (part == 1 ? 3 : 5);
+  return RowMap{nc, 9 * F, c0, F};
+}
+inline int64_t part_count(int part) { return part == 0 ? 1 : (part == 1 ? 3 : 5); }
+
+// P[z][o][k] = sum over rows r of slice z (r < min(R, *Rdev)) of A(r, o) * B(r, k), B = 1 when
+// null.  16x16 outputs per block, 16 rows staged per step; every block writes its outputs.
+template <class T>
+__global__ void __launch_bounds__(256) k_wgrad_part(const T *A, RowMap ma, const T *B, RowMap mb, int64_t R,
+                                                    const int64_t *Rdev, int O, int Kc, int64_t slice, T *P) {
+  __shared__ T As[16][17];
+  __shared__ T Bs[16][17];
+  int64_t Rn = R;
+  if (Rdev) {
+    const int64_t md = *Rdev;
+    if (md < Rn) Rn = md;
+  }
+  const int o0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
+  const int64_t rb = (int64_t)blockIdx.z * slice;
+  const int64_t re = rb + slice < Rn ? rb + slice : Rn;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  T acc = T(0);
+  for (int64_t r0 = rb; r0 < re; r0 += 16) {
+    const int64_t r = r0 + ty;
+    As[ty][tx] = (r < re && o0 + tx < O) ? A[row_at(ma, r) + o0 + tx] : T(0);
+    T bv = T(0);
+    if (r < re && k0 + tx < Kc) bv = B ? B[row_at(mb, r) + k0 + tx] : T(1);
+    Bs[ty][tx] = bv;
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) acc += As[rr][ty] * Bs[rr][tx];
+    __syncthreads();
+  }
+  const int o = o0 + ty, k = k0 + tx;
+  if (o < O && k < Kc) P[((int64_t)blockIdx.z * O + o) * Kc + k] = acc;
+}
+
+// C[o * ldc + k] += sum_z P[z][o][k], the slices summed in a fixed order.
+template <class T>
+__global__ void k_sum_slices(int O, int Kc, int G, const T *P, T *C, int64_t ldc) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)O * Kc) return;
+  const int o = (int)(t / Kc), k = (int)(t % Kc);
+  T s = T(0);
+  for (int z = 0; z < G; ++z) s += P[(int64_t)z * O * Kc + t];
+  C[o * ldc + k] += s;
+}
+
+// P[z][c] = sum over rows r of slice z of rs[r] * A[r*C + c] * B[r*C + c] (rs, B = 1 when null).
+template <class T>
+__global__ void k_coldot_part(const T *A, const T *B, const T *rs, int64_t R, int C, int64_t slice, T *P) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int64_t rb = (int64_t)blockIdx.y * slice;
+  const int64_t re = rb + slice < R ? rb + slice : R;
+  T s = T(0);
+  for (int64_t r = rb; r < re; ++r) {
+    T v = A[r * C + c];
+    if (B) v *= B[r * C + c];
+    if (rs) v *= rs[r];
+    s += v;
+  }
+  P[(int64_t)blockIdx.y * C + c] = s;
+}
+
+template <class T>
+struct Reducer {
+  T *part = nullptr;
+  int64_t cap = 0;   // elements of part
+
+  static int slices(int64_t R) {
+    const int64_t g = (R + 2047) / 2048;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kSlices, g));
+  }
+  // C[o][k] (row stride ldc) += sum_r A(r, o) B(r, k)
+  int wgrad(hipStream_t s, const T *A, RowMap ma, const T *B, RowMap mb, int64_t R, const int64_t *Rdev, int O,
+            int Kc, T *C, int64_t ldc) const {
+    if (R <= 0 || O <= 0 || Kc <= 0) return TN_OK;
+    const int G = slices(R);
+    if ((int64_t)G * O * Kc > cap) return TN_E_WORKSPACE;
+    const int64_t slice = ((R + G - 1) / G + 15) / 16 * 16;
+    hipLaunchKernelGGL(k_wgrad_part<T>, dim3((unsigned)((Kc + 15) / 16), (unsigned)((O + 15) / 16), (unsigned)G),
+                       dim3(256), 0, s, A, ma, B, mb, R, Rdev, O, Kc, slice, part);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for((int64_t)O * Kc, 256)), dim3(256), 0, s, O, Kc, G,
+                       (const T *)part, C, ldc);
+    TN_LAUNCH_CHECK();
+    return TN_OK;
+  }
+  // weight and bias of y = x W^T + b from the pre-activation adjoint dz
+  int linear(hipStream_t s, const T *dz, const T *x, int64_t R, const int64_t *Rdev, int O, int Kin, T *dW,
+             T *db) const {
+    int rc = wgrad(s, dz, rows_of(O), x, rows_of(Kin), R, Rdev, O, Kin, dW, Kin);
+    if (rc) return rc;
+    return wgrad(s, dz, rows_of(O), nullptr, rows_of(1), R, Rdev, O, 1, db, 1);
+  }
+  // out[c] += sum_r rs[r] A[r][c] B[r][c]
+  int coldot(hipStream_t s, const T *A, const T *B, const T *rs, int64_t R, int C, T *out) const {
+    if (R <= 0 || C <= 0) return TN_OK;
+    const int G = slices(R);
+    if ((int64_t)G * C > cap) return TN_E_WORKSPACE;
+    const int64_t slice = (R + G - 1) / G;
+    hipLaunchKernelGGL(k_coldot_part<T>, dim3((unsigned)((C + 127) / 128), (unsigned)G), dim3(128), 0, s, A, B, rs,
+                       R, C, slice, part);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for(C, 256)), dim3(256), 0, s, 1, C, G, (const T *)part, out,
+                       (int64_t)C);
+    TN_LAUNCH_CHECK();
+    return TN_OK;
+  }
+};
+
+// ---------------------------------------------------------------- pass 1: loss and seeds
+// loss = w_E/S sum_s e_s^2 + w_F/(3N) sum f^2 with e = E - E*, f = F - F*;
+// seed_s = (-1, d loss/d E_s), wt = d loss / dF (caller's atom order).  One block.
+template <class S>
+__global__ void __launch_bounds__(256) k_loss(int64_t n, int64_t ns, const double *E, const double *Eref,
+                                              const S *Fv, const double *Fref, double wE, double wF, double *loss,
+                                              Dual<S> *seed, double *wt) {
+  __shared__ double lds[256];
+  double ae = 0.0, af = 0.0;
+  const double inv_s = ns > 0 ? 1.0 / (double)ns : 0.0;
+  const double inv_f = n > 0 ? 1.0 / (3.0 * (double)n) : 0.0;
+  for (int64_t k = threadIdx.x; k < ns; k += 256) {
+    const double e = E[k] - Eref[k];
+    ae += e * e;
+    seed[k] = Dual<S>(S(-1), (S)(2.0 * wE * e * inv_s));
+  }
+  for (int64_t k = threadIdx.x; k < 3 * n; k += 256) {
+    const double f = (double)Fv[k] - Fref[k];
+    af += f * f;
+    wt[k] = 2.0 * wF * f * inv_f;
+  }
+  const double te = block_sum(ae, lds);
+  const double tf = block_sum(af, lds);
+  if (threadIdx.x == 0) *loss = wE * te * inv_s + wF * tf * inv_f;
+}
+
+// ---------------------------------------------------------------- pass 2 helpers
+template <class S>
+__global__ void k_to_dual(int64_t n, const double *w, Dual<S> *out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) out[t] = Dual<S>((S)w[t], S(0));
+}
+
+// Positions r + eps W in the internal atom order (perm maps internal -> caller index).
+template <class S>
+__global__ void k_pos_dual(int64_t n, const S *pos, const int32_t *perm, const double *wt, Dual<S> *posD) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = perm ? perm[i] : i;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) posD[3 * i + a] = Dual<S>(pos[3 * i + a], (S)wt[3 * o + a]);
+}
+
+template <class S>
+__device__ inline Dual<S> narrow(Dual<double> x) { return Dual<S>((S)x.v, (S)x.d); }
+
+// Pair geometry and radial basis on dual positions, evaluated in Dual<double> and rounded
+// once: the lattice shift of the minimum image is a constant, so it moves the value only.
+template <class S>
+__global__ void k_geom_dual(const int32_t *pairs, int64_t max_pairs, const int64_t *n_pairs, const Dual<S> *posD,
+                            Lattice box, double r_c, double r_lo, double alpha, const double *mu, const double *beta,
+                            int K, Dual<S> *geo, Dual<S> *phi, Dual<S> *rbf) {
+  using DD = Dual<double>;
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= pair_bound(n_pairs, max_pairs)) return;
+  const int64_t i = pairs[p], j = pairs[max_pairs + p];
+  DD v[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    v[a] = DD((double)posD[3 * j + a].v - (double)posD[3 * i + a].v,
+              (double)posD[3 * j + a].d - (double)posD[3 * i + a].d);
+  double x = v[0].v, y = v[1].v, z = v[2].v;
+  min_image(box, x, y, z);
+  v[0].v = x;
+  v[1].v = y;
+  v[2].v = z;
+  const DD d = dsqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const DD inv = DD(1.0) / d;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) geo[4 * p + a] = narrow<S>(v[a] * inv);
+  geo[4 * p + 3] = narrow<S>(d);
+  const DD ph = DD(0.5) * (dcos(DD(M_PI) * d / DD(r_c)) + DD(1.0));
+  phi[p] = narrow<S>(ph);
+  const DD u = dexp(-DD(alpha) * (d - DD(r_lo)));
+  for (int k = 0; k < K; ++k) {
+    const DD t = u - DD(mu[k]);
+    rbf[p * K + k] = narrow<S>(ph * dexp(-DD(beta[k]) * t * t));
+  }
+}
+
+// Per-atom seed: that of the atom's system (zero for a system index outside [0, ns), which
+// the neighbour search has already flagged in the status word).
+template <class T>
+__global__ void k_seed_atoms(int64_t n, int64_t ns, const int32_t *batch, const T *seed, T *sd) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t b = batch[i];
+  sd[i] = (b >= 0 && b < ns) ? seed[b] : T(0);
+}
+
+// eps_i = w . silu(hz_i) + b with seed sd_i on eps_i:  dhz = sd_i w silu'(hz)
+template <class T>
+__global__ void k_out_final_bwd_seed(int64_t n, int H, const T *hz, const T *w, const T *sd, T *dhz) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * H) return;
+  const int64_t i = t / H;
+  const int k = (int)(t % H);
+  dhz[t] = sd[i] * w[k] * silu_grad(hz[t]);
+}
+
+// Adjoint of the species factor of each pair's embedding message, both directions:
+// dZ[p][0][f] = d E / d Z_ij[f] (receiver i), dZ[p][1][f] = d E / d Z_ji[f] (receiver j).
+template <class T>
+__global__ void k_embed_dz(const int32_t *pairs, int64_t max_pairs, const int64_t *n_pairs, int F, const T *geo,
+                           const T *phi, const T *f0, const T *dXr, T *dZ) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t p = t / F;
+  if (p >= pair_bound(n_pairs, max_pairs)) return;
+  const int f = (int)(t % F);
+  const int64_t i = pairs[p], j = pairs[max_pairs + p];
+  const T ux = geo[4 * p], uy = geo[4 * p + 1], uz = geo[4 * p + 2];
+  T s5[5];
+  s0_coords(ux, uy, uz, s5);
+  const T a = f0[p * 3 * F + f], b = f0[p * 3 * F + F + f], c = f0[p * 3 * F + 2 * F + f];
+  T di[9], dj[9];
+  load9(dXr, i, F, f, di);
+  load9(dXr, j, F, f, dj);
+  const T giA = di[1] * ux + di[2] * uy + di[3] * uz;
+  const T gjA = -(dj[1] * ux + dj[2] * uy + dj[3] * uz);
+  T giS = T(0), gjS = T(0);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    giS += di[4 + q] * s5[q];
+    gjS += dj[4 + q] * s5[q];
+  }
+  const T ph = phi[p];
+  dZ[p * 2 * F + f] = ph * (a * di[0] + b * giA + c * giS);
+  dZ[p * 2 * F + F + f] = ph * (a * dj[0] + b * gjA + c * gjS);
+}
+
+// dU[s] = sum of dZ over the pair directions whose receiver has species s, dV[s] over those
+// whose sender has it.  One block per (species, 64 channels); four row groups per block.
+template <class T>
+__global__ void __launch_bounds__(256) k_species_dz(const int32_t *pairs, int64_t max_pairs, const int64_t *n_pairs,
+                                                    int F, const int32_t *z, int max_z, const T *dZ, T *dU, T *dV) {
+  __shared__ T lu[4][64];
+  __shared__ T lv[4][64];
+  const int sp = blockIdx.x;
+  const int f = blockIdx.y * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
+  const int64_t P = pair_bound(n_pairs, max_pairs);
+  T u = T(0), v = T(0);
+  if (f < F) {
+    for (int64_t p = grp; p < P; p += 4) {
+      const int zi = clamp_z(z[pairs[p]], max_z), zj = clamp_z(z[pairs[max_pairs + p]], max_z);
+      if (zi != sp && zj != sp) continue;
+      const T dij = dZ[p * 2 * F + f], dji = dZ[p * 2 * F + F + f];
+      if (zi == sp) { u += dij; v += dji; }
+      if (zj == sp) { u += dji; v += dij; }
+    }
+  }
+  lu[grp][threadIdx.x & 63] = u;
+  lv[grp][threadIdx.x & 63] = v;
+  __syncthreads();
+  if (grp == 0 && f < F) {
+    const int l = threadIdx.x;
+    dU[(int64_t)sp * F + f] = lu[0][l] + lu[1][l] + lu[2][l] + lu[3][l];
+    dV[(int64_t)sp * F + f] = lv[0][l] + lv[1][l] + lv[2][l] + lv[3][l];
+  }
+}
+
+template <class S>
+__global__ void k_grad_out(int64_t n, const Dual<S> *g, double *out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) out[t] = (double)g[t].d;
+}
+
+// ---------------------------------------------------------------- workspace
+template <class S>
+struct TrainWs {
+  using D = Dual<S>;
+  void *plain = nullptr;
+  size_t plain_bytes = 0;
+  double *wt = nullptr;
+  D *seed, *sd;
+  NbrWs nb;
+  D *wD, *gD, *dU, *dV, *part, *posD;
+  D *geo, *phi, *rbf, *f0, *Xr, *T0, *nrm0, *xhat0, *rstd0, *n0, *ez1, *ea1, *ez2, *g;
+  std::vector<D *> X, nX, Xb, Y, z1, a1, z2, a2, z3, h, M, P, nP, Pb, Dl;
+  D *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps;
+  D *dX, *dD, *dPb, *dY, *dM, *dXr, *dT0, *dg, *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
+  D *dh, *dz3, *dz2, *dz1, *dphi, *dvhat, *df0, *dZ;
+  int64_t part_cap = 0;
+};
+
+// The weight blob's tensors come first in the packed copy, in blob order, ending with the
+// output bias (one element).
+inline int64_t param_count(const tn_model *m) { return (int64_t)m->off.bout + 1; }
+
+template <class S>
+static void plan_train(WsPlan &p, const tn_model *m, int64_t N, int64_t NS, int64_t MP, const BoxInfo &bi,
+                       size_t plain_bytes, TrainWs<S> *w) {
+  using D = Dual<S>;
+  const int64_t F = m->F, K = m->K, L = m->L, Z = m->max_z;
+  w->plain = p.take<char>(plain_bytes);
+  w->plain_bytes = plain_bytes;
+  w->wt = p.take<double>(3 * N);
+  w->seed = p.take<D>(NS);
+  w->sd = p.take<D>(N);
+  plan_neighbors(p, N, MP, bi, &w->nb);
+  w->wD = p.take<D>(m->off.total);
+  w->gD = p.take<D>(param_count(m));
+  w->dU = p.take<D>(Z * F);
+  w->dV = p.take<D>(Z * F);
+  w->part_cap = (int64_t)kSlices * std::max<int64_t>(6 * F * F, 3 * F * K);
+  w->part = p.take<D>(w->part_cap);
+  w->posD = p.take<D>(3 * N);
+  w->geo = p.take<D>(4 * MP);
+  w->phi = p.take<D>(MP);
+  w->rbf = p.take<D>(MP * K);
+  w->f0 = p.take<D>(MP * 3 * F);
+  w->Xr = p.take<D>(N * 9 * F);
+  w->T0 = p.take<D>(N * 9 * F);
+  w->nrm0 = p.take<D>(N * F);
+  w->xhat0 = p.take<D>(N * F);
+  w->rstd0 = p.take<D>(N);
+  w->n0 = p.take<D>(N * F);
+  w->ez1 = p.take<D>(N * 2 * F);
+  w->ea1 = p.take<D>(N * 2 * F);
+  w->ez2 = p.take<D>(N * 3 * F);
+  w->g = p.take<D>(N * 3 * F);
+  w->X.resize(L + 1);
+  for (int64_t l = 0; l <= L; ++l) w->X[l] = p.take<D>(N * 9 * F);
+  auto per_layer = [&](std::vector<D *> &v, int64_t count) {
+    v.resize(L);
+    for (int64_t l = 0; l < L; ++l) v[l] = p.take<D>(count);
+  };
+  per_layer(w->nX, N * F);
+  per_layer(w->Xb, N * 9 * F);
+  per_layer(w->Y, N * 9 * F);
+  per_layer(w->z1, MP * F);
+  per_layer(w->a1, MP * F);
+  per_layer(w->z2, MP * 2 * F);
+  per_layer(w->a2, MP * 2 * F);
+  per_layer(w->z3, MP * 3 * F);
+  per_layer(w->h, MP * 3 * F);
+  per_layer(w->M, N * 9 * F);
+  per_layer(w->P, N * 9 * F);
+  per_layer(w->nP, N * F);
+  per_layer(w->Pb, N * 9 * F);
+  per_layer(w->Dl, N * 9 * F);
+  w->on = p.take<D>(N * 3 * F);
+  w->oxhat = p.take<D>(N * 3 * F);
+  w->orstd = p.take<D>(N);
+  w->q = p.take<D>(N * 3 * F);
+  w->oz = p.take<D>(N * F);
+  w->ox = p.take<D>(N * F);
+  w->hz = p.take<D>(N * (F / 2));
+  w->hx = p.take<D>(N * (F / 2));
+  w->eps = p.take<D>(N);
+  w->dX = p.take<D>(N * 9 * F);
+  w->dD = p.take<D>(N * 9 * F);
+  w->dPb = p.take<D>(N * 9 * F);
+  w->dY = p.take<D>(N * 9 * F);
+  w->dM = p.take<D>(N * 9 * F);
+  w->dXr = p.take<D>(N * 9 * F);
+  w->dT0 = p.take<D>(N * 9 * F);
+  w->dg = p.take<D>(N * 3 * F);
+  w->dez2 = p.take<D>(N * 3 * F);
+  w->dez1 = p.take<D>(N * 2 * F);
+  w->dn0 = p.take<D>(N * F);
+  w->dnrm0 = p.take<D>(N * F);
+  w->dhz = p.take<D>(N * (F / 2));
+  w->dox = p.take<D>(N * F);
+  w->dq = p.take<D>(N * 3 * F);
+  w->don = p.take<D>(N * 3 * F);
+  w->dh = p.take<D>(MP * 3 * F);
+  w->dz3 = p.take<D>(MP * 3 * F);
+  w->dz2 = p.take<D>(MP * 2 * F);
+  w->dz1 = p.take<D>(MP * F);
+  w->dphi = p.take<D>(MP);
+  w->dvhat = p.take<D>(3 * MP);
+  w->df0 = p.take<D>(MP * 3 * F);
+  w->dZ = p.take<D>(MP * 2 * F);
+}
+
+static size_t train_bytes(const tn_model *m, int64_t n, int64_t ns, int64_t mp, const BoxInfo &bi, int prec) {
+  const size_t pb = plain_workspace_bytes(m, n, ns, mp, bi, prec, 1);
+  WsPlan p(nullptr);
+  if (prec == TN_FP64) {
+    TrainWs<double> w;
+    plan_train(p, m, n, ns, mp, bi, pb, &w);
+  } else {
+    TrainWs<float> w;
+    plan_train(p, m, n, ns, mp, bi, pb, &w);
+  }
+  return p.off;
+}
+
+// ---------------------------------------------------------------- the step
+template <class S>
+static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const double *Eref, const double *Fref,
+                     double wE, double wF, double *loss, double *grad, void *ws, size_t ws_bytes) {
+  using D = Dual<S>;
+  const int64_t N = pb.n, NS = pb.S, MP = pb.max_pairs, F = m->F, K = m->K, L = m->L, Z = m->max_z;
+  const int64_t H = F / 2;
+  const int prec = std::is_same<S, double>::value ? TN_FP64 : TN_FP32;
+  const size_t plain_bytes = plain_workspace_bytes(m, N, NS, MP, pb.box, prec, 1);
+  WsPlan plan(ws);
+  TrainWs<S> w;
+  plan_train(plan, m, N, NS, MP, pb.box, plain_bytes, &w);
+  if (plan.off > ws_bytes) return TN_E_WORKSPACE;
+  int rc;
+  const unsigned bs = 256;
+  const WeightOff &o = m->off;
+  const int64_t NP = param_count(m);
+
+  // ---- pass 1: energies and forces at r, the loss, its seeds and the position tangent
+  if ((rc = plain_run(m, s, pb, prec, w.plain, w.plain_bytes))) return rc;
+  hipLaunchKernelGGL(k_loss<S>, dim3(1), dim3(256), 0, s, N, NS, pb.energy, Eref, static_cast<const S *>(pb.forces),
+                     Fref, wE, wF, loss, w.seed, w.wt);
+  TN_LAUNCH_CHECK();
+
+  // ---- pass 2: dual forward
+  hipLaunchKernelGGL(k_to_dual<S>, dim3(grid_for((int64_t)o.total, bs)), dim3(bs), 0, s, (int64_t)o.total, m->w64,
+                     w.wD);
+  TN_LAUNCH_CHECK();
+  if ((rc = fill_bytes_zero(s, w.gD, NP * sizeof(D)))) return rc;
+  auto W = [&](size_t off) { return static_cast<const D *>(w.wD + off); };
+  auto G = [&](size_t off) { return w.gD + off; };
+  Reducer<D> red{w.part, w.part_cap};
+
+  NbrGraph<S> gr;
+  if ((rc = build_neighbors<S>(s, N, static_cast<const S *>(pb.pos), pb.z, pb.batch, pb.box, m->r_c, MP, nullptr,
+                               pb.n_pairs, pb.status, w.nb, &gr, NS, m->max_z)))
+    return rc;
+  const int64_t *np = pb.n_pairs;
+  const int32_t *rowptr = gr.rowptr, *nbr = gr.nbr, *pid = gr.pid, *zz = gr.z;
+  const unsigned gN = grid_for(N, bs), gNF = grid_for(N * F, bs);
+  if (N > 0) {
+    hipLaunchKernelGGL(k_pos_dual<S>, dim3(gN), dim3(bs), 0, s, N, gr.pos, gr.perm, (const double *)w.wt, w.posD);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_seed_atoms<D>, dim3(gN), dim3(bs), 0, s, N, NS, gr.batch, (const D *)w.seed, w.sd);
+    TN_LAUNCH_CHECK();
+  }
+  if (MP > 0) {
+    hipLaunchKernelGGL(k_geom_dual<S>, dim3(grid_for(MP, bs)), dim3(bs), 0, s, gr.pairs, MP, np,
+                       (const D *)w.posD, pb.box.lat, m->r_c, m->r_lo, m->alpha, m->w64 + o.mu, m->w64 + o.beta,
+                       (int)K, w.geo, w.phi, w.rbf);
+    TN_LAUNCH_CHECK();
+  }
+  // embedding
+  if ((rc = linear_fwd<D>(s, w.rbf, MP, K, W(o.W0), W(o.b0), 3 * F, w.f0, nullptr, 0, nullptr, np))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_embed_gather<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, zz,
+                       m->max_z, W(o.U), W(o.V), (const D *)w.geo, (const D *)w.phi, (const D *)w.f0, w.Xr);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_node_norm<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Xr, w.nrm0);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_layernorm<D>, dim3((unsigned)N), dim3(128), 0, s, N, (int)F, (const D *)w.nrm0,
+                       W(o.ln_g), W(o.ln_b), w.n0, w.xhat0, w.rstd0);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = linear_fwd<D>(s, w.n0, N, F, W(o.W1), W(o.b1), 2 * F, w.ea1, w.ez1, 1))) return rc;
+  if ((rc = linear_fwd<D>(s, w.ea1, N, 2 * F, W(o.W2), W(o.b2), 3 * F, w.g, w.ez2, 1))) return rc;
+  const D *Wemb[3] = {W(o.Wmix[0]), W(o.Wmix[1]), W(o.Wmix[2])};
+  if ((rc = mix<D>(s, w.Xr, w.T0, N, F, Wemb, nullptr, 0, 0))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_gate<D>, dim3(grid_for(N * 9 * F, bs)), dim3(bs), 0, s, N, (int)F, (const D *)w.g,
+                       (const D *)w.T0, w.X[0]);
+    TN_LAUNCH_CHECK();
+  }
+  // interaction layers
+  for (int64_t l = 0; l < L; ++l) {
+    const LayerOff &lo = o.layer[l];
+    if (N > 0) {
+      hipLaunchKernelGGL(k_normalize<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.X[l], w.nX[l], w.Xb[l]);
+      TN_LAUNCH_CHECK();
+    }
+    const D *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
+    if ((rc = mix<D>(s, w.Xb[l], w.Y[l], N, F, W1, nullptr, 0, 0))) return rc;
+    if ((rc = linear_fwd<D>(s, w.rbf, MP, K, W(lo.Wa), W(lo.ba), F, w.a1[l], w.z1[l], 1, nullptr, np))) return rc;
+    if ((rc = linear_fwd<D>(s, w.a1[l], MP, F, W(lo.Wb), W(lo.bb), 2 * F, w.a2[l], w.z2[l], 1, nullptr, np)))
+      return rc;
+    if ((rc = linear_fwd<D>(s, w.a2[l], MP, 2 * F, W(lo.Wc), W(lo.bc), 3 * F, w.h[l], w.z3[l], 1, w.phi, np)))
+      return rc;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_message<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP,
+                         (const D *)w.h[l], (const D *)w.Y[l], w.M[l], 0);
+      TN_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_product<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Y[l], (const D *)w.M[l],
+                         w.P[l], w.nP[l], w.Pb[l]);
+      TN_LAUNCH_CHECK();
+    }
+    const D *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
+    if ((rc = mix<D>(s, w.Pb[l], w.Dl[l], N, F, W2, nullptr, 0, 0))) return rc;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_residual<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Xb[l], (const D *)w.Dl[l],
+                         w.X[l + 1]);
+      TN_LAUNCH_CHECK();
+    }
+  }
+  // output network
+  if (N > 0) {
+    hipLaunchKernelGGL(k_out_norms<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.X[L], w.on);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_layernorm<D>, dim3((unsigned)N), dim3(128), 0, s, N, (int)(3 * F), (const D *)w.on,
+                       W(o.oln_g), W(o.oln_b), w.q, w.oxhat, w.orstd);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = linear_fwd<D>(s, w.q, N, 3 * F, W(o.Wo), W(o.bo), F, w.ox, w.oz, 1))) return rc;
+  if ((rc = linear_fwd<D>(s, w.ox, N, F, W(o.Wh), W(o.bh), H, w.hx, w.hz, 1))) return rc;
+
+  // ---- pass 2: reverse sweep to the parameters, seeds sd_i = seed_{system of i}
+  if (N > 0) {
+    hipLaunchKernelGGL(k_out_final_bwd_seed<D>, dim3(grid_for(N * H, bs)), dim3(bs), 0, s, N, (int)H,
+                       (const D *)w.hz, W(o.wout), (const D *)w.sd, w.dhz);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = red.coldot(s, w.hx, nullptr, w.sd, N, (int)H, G(o.wout)))) return rc;
+  if ((rc = red.coldot(s, w.sd, nullptr, nullptr, N, 1, G(o.bout)))) return rc;
+  if ((rc = red.linear(s, w.dhz, w.ox, N, nullptr, (int)H, (int)F, G(o.Wh), G(o.bh)))) return rc;
+  if ((rc = linear_bwd<D>(s, w.dhz, N, H, W(o.Wh), F, w.dox, w.oz, 0))) return rc;
+  if ((rc = red.linear(s, w.dox, w.q, N, nullptr, (int)F, (int)(3 * F), G(o.Wo), G(o.bo)))) return rc;
+  if ((rc = linear_bwd<D>(s, w.dox, N, F, W(o.Wo), 3 * F, w.dq, nullptr, 0))) return rc;
+  if ((rc = red.coldot(s, w.dq, w.oxhat, nullptr, N, (int)(3 * F), G(o.oln_g)))) return rc;
+  if ((rc = red.coldot(s, w.dq, nullptr, nullptr, N, (int)(3 * F), G(o.oln_b)))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_layernorm_bwd<D>, dim3((unsigned)N), dim3(128), 0, s, N, (int)(3 * F), (const D *)w.dq,
+                       (const D *)w.oxhat, (const D *)w.orstd, W(o.oln_g), w.don);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_out_norms_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.X[L],
+                       (const D *)w.don, w.dX);
+    TN_LAUNCH_CHECK();
+  }
+  if (MP > 0 && (rc = fill_bytes_zero(s, w.dphi, MP * sizeof(D)))) return rc;
+  for (int64_t l = L - 1; l >= 0; --l) {
+    const LayerOff &lo = o.layer[l];
+    const D *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
+    const D *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
+    if (N > 0) {
+      hipLaunchKernelGGL(k_residual_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Dl[l],
+                         (const D *)w.dX, w.dD);
+      TN_LAUNCH_CHECK();
+    }
+    for (int q = 0; q < 3; ++q)
+      if ((rc = red.wgrad(s, w.dD, part_rows(q, F), w.Pb[l], part_rows(q, F), N * part_count(q), nullptr, (int)F,
+                          (int)F, G(lo.W2[q]), F)))
+        return rc;
+    if ((rc = mix<D>(s, w.dD, w.dPb, N, F, W2, nullptr, 1, 0))) return rc;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_product_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.dPb, (const D *)w.P[l],
+                         (const D *)w.nP[l], (const D *)w.Y[l], (const D *)w.M[l], w.dY, w.dM);
+      TN_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_message<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP,
+                         (const D *)w.h[l], (const D *)w.dM, w.dY, 1);
+      TN_LAUNCH_CHECK();
+    }
+    if (MP > 0) {
+      hipLaunchKernelGGL(k_message_bwd_pair<D>, dim3(grid_for(MP * F, bs)), dim3(bs), 0, s, gr.pairs, MP, np, (int)F,
+                         (const D *)w.Y[l], (const D *)w.dM, w.dh);
+      TN_LAUNCH_CHECK();
+    }
+    for (int q = 0; q < 3; ++q)
+      if ((rc = red.wgrad(s, w.dY, part_rows(q, F), w.Xb[l], part_rows(q, F), N * part_count(q), nullptr, (int)F,
+                          (int)F, G(lo.W1[q]), F)))
+        return rc;
+    if ((rc = mix<D>(s, w.dY, w.dX, N, F, W1, nullptr, 1, 1))) return rc;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_normalize_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.X[l],
+                         (const D *)w.nX[l], w.dX);
+      TN_LAUNCH_CHECK();
+    }
+    if (MP > 0) {
+      hipLaunchKernelGGL(k_edge_bwd_top<D>, dim3((unsigned)MP), dim3(128), 0, s, MP, np, (int)(3 * F),
+                         (const D *)w.dh, (const D *)w.z3[l], (const D *)w.phi, w.dz3, w.dphi);
+      TN_LAUNCH_CHECK();
+    }
+    if ((rc = red.linear(s, w.dz3, w.a2[l], MP, np, (int)(3 * F), (int)(2 * F), G(lo.Wc), G(lo.bc)))) return rc;
+    if ((rc = linear_bwd<D>(s, w.dz3, MP, 3 * F, W(lo.Wc), 2 * F, w.dz2, w.z2[l], 0, np))) return rc;
+    if ((rc = red.linear(s, w.dz2, w.a1[l], MP, np, (int)(2 * F), (int)F, G(lo.Wb), G(lo.bb)))) return rc;
+    if ((rc = linear_bwd<D>(s, w.dz2, MP, 2 * F, W(lo.Wb), F, w.dz1, w.z1[l], 0, np))) return rc;
+    if ((rc = red.linear(s, w.dz1, w.rbf, MP, np, (int)F, (int)K, G(lo.Wa), G(lo.ba)))) return rc;
+  }
+  // embedding: dX holds dE/dX0
+  if (N > 0) {
+    hipLaunchKernelGGL(k_gate_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.dX, (const D *)w.T0,
+                       (const D *)w.g, w.dg, w.dT0, nullptr);
+    TN_LAUNCH_CHECK();
+  }
+  for (int q = 0; q < 3; ++q)
+    if ((rc = red.wgrad(s, w.dT0, part_rows(q, F), w.Xr, part_rows(q, F), N * part_count(q), nullptr, (int)F, (int)F,
+                        G(o.Wmix[q]), F)))
+      return rc;
+  if ((rc = mix<D>(s, w.dT0, w.dXr, N, F, Wemb, nullptr, 1, 0))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_mul_silu_grad<D>, dim3(grid_for(N * 3 * F, bs)), dim3(bs), 0, s, N * 3 * F, (const D *)w.dg,
+                       (const D *)w.ez2, w.dez2);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = red.linear(s, w.dez2, w.ea1, N, nullptr, (int)(3 * F), (int)(2 * F), G(o.W2), G(o.b2)))) return rc;
+  if ((rc = linear_bwd<D>(s, w.dez2, N, 3 * F, W(o.W2), 2 * F, w.dez1, w.ez1, 0))) return rc;
+  if ((rc = red.linear(s, w.dez1, w.n0, N, nullptr, (int)(2 * F), (int)F, G(o.W1), G(o.b1)))) return rc;
+  if ((rc = linear_bwd<D>(s, w.dez1, N, 2 * F, W(o.W1), F, w.dn0, nullptr, 0))) return rc;
+  if ((rc = red.coldot(s, w.dn0, w.xhat0, nullptr, N, (int)F, G(o.ln_g)))) return rc;
+  if ((rc = red.coldot(s, w.dn0, nullptr, nullptr, N, (int)F, G(o.ln_b)))) return rc;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_layernorm_bwd<D>, dim3((unsigned)N), dim3(128), 0, s, N, (int)F, (const D *)w.dn0,
+                       (const D *)w.xhat0, (const D *)w.rstd0, W(o.ln_g), w.dnrm0);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_norm_bwd_add<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Xr, (const D *)w.dnrm0,
+                       w.dXr);
+    TN_LAUNCH_CHECK();
+  }
+  if (MP > 0) {
+    hipLaunchKernelGGL(k_embed_bwd_pair<D>, dim3((unsigned)MP), dim3(128), 0, s, gr.pairs, MP, np, (int)F, zz,
+                       m->max_z, W(o.U), W(o.V), (const D *)w.geo, (const D *)w.phi, (const D *)w.f0,
+                       (const D *)w.dXr, w.df0, w.dphi, w.dvhat);
+    TN_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_embed_dz<D>, dim3(grid_for(MP * F, bs)), dim3(bs), 0, s, gr.pairs, MP, np, (int)F,
+                       (const D *)w.geo, (const D *)w.phi, (const D *)w.f0, (const D *)w.dXr, w.dZ);
+    TN_LAUNCH_CHECK();
+  }
+  if ((rc = red.linear(s, w.df0, w.rbf, MP, np, (int)(3 * F), (int)K, G(o.W0), G(o.b0)))) return rc;
+  // species tables U = W_z[:, :F] E + b_z, V = W_z[:, F:] E  ->  E, W_z, b_z
+  if (MP > 0) {
+    hipLaunchKernelGGL(k_species_dz<D>, dim3((unsigned)Z, (unsigned)((F + 63) / 64)), dim3(256), 0, s, gr.pairs, MP,
+                       np, (int)F, zz, m->max_z, (const D *)w.dZ, w.dU, w.dV);
+    TN_LAUNCH_CHECK();
+    if ((rc = red.wgrad(s, w.dU, rows_of(F), W(o.E), rows_of(F), Z, nullptr, (int)F, (int)F, G(o.Wz), 2 * F)))
+      return rc;
+    if ((rc = red.wgrad(s, w.dV, rows_of(F), W(o.E), rows_of(F), Z, nullptr, (int)F, (int)F, G(o.Wz) + F, 2 * F)))
+      return rc;
+    if ((rc = red.wgrad(s, w.dU, rows_of(F), nullptr, rows_of(1), Z, nullptr, (int)F, 1, G(o.bz), 1))) return rc;
+    for (int half = 0; half < 2; ++half) {
+      GemmArgs<D> ga;
+      ga.A = half ? w.dV : w.dU; ga.lda = F;
+      ga.B = W(o.Wz) + half * F; ga.ldb = 2 * F; ga.transB = 0;
+      ga.C = G(o.E); ga.ldc = F; ga.accumulate = 1;
+      ga.M = Z; ga.N = F; ga.K = F;
+      if ((rc = gemm(s, ga))) return rc;
+    }
+  }
+  if (NP > 0) {
+    hipLaunchKernelGGL(k_grad_out<S>, dim3(grid_for(NP, bs)), dim3(bs), 0, s, NP, (const D *)w.gD, grad);
+    TN_LAUNCH_CHECK();
+  }
+  return TN_OK;
+}
+
+}  // namespace tn
+
+using namespace tn;
+
+extern "C" {
+
+int64_t tn_param_count(const tn_model *m) { return m ? param_count(m) : -1; }
+
+size_t tn_train_workspace_bytes(const tn_model *m, int64_t n_atoms, int64_t n_systems, int64_t max_pairs,
+                                const double *box, int precision) {
+  if (!m || n_atoms < 0 || n_systems < 0 || max_pairs < 0) return 0;
+  if (precision != TN_FP32 && precision != TN_FP64) return 0;
+  BoxInfo bi;
+  if (box_info(box, m->r_c, &bi)) return 0;
+  return train_bytes(m, n_atoms, n_systems, max_pairs, bi, precision);
+}
+
+int tn_train_grad(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, const void *pos,
+                  const int32_t *z, const int32_t *batch, const double *box, int64_t max_pairs, int precision,
+                  const double *energy_ref, const double *forces_ref, double w_energy, double w_force, double *loss,
+                  double *energy, void *forces, double *grad, int64_t *n_pairs, int32_t *status, void *ws,
+                  size_t ws_bytes) {
+  if (!m || n_atoms < 0 || n_systems < 0 || max_pairs < 0 || max_pairs > (int64_t(1) << 30) ||
+      n_atoms >= (int64_t(1) << 31))
+    return TN_E_ARG;
+  if (precision != TN_FP32 && precision != TN_FP64) return TN_E_UNSUPPORTED;
+  if (n_atoms > 0 && (!pos || !z || !batch || n_systems < 1 || !forces || !forces_ref)) return TN_E_ARG;
+  if (n_systems > 0 && (!energy || !energy_ref)) return TN_E_ARG;
+  if (!loss || !grad || !n_pairs || !status || !ws) return TN_E_ARG;
+  if (!std::isfinite(w_energy) || !std::isfinite(w_force)) return TN_E_ARG;
+  // the scalar products launch one block row per 16 rows of a pair array
+  if ((max_pairs + 15) / 16 > 65535 || (n_atoms + 15) / 16 > 65535) return TN_E_UNSUPPORTED;
+  Problem pb;
+  int rc = box_info(box, m->r_c, &pb.box);
+  if (rc) return rc;
+  if (hipSetDevice(m->device) != hipSuccess) return TN_E_HIP;
+  pb.n = n_atoms;
+  pb.S = n_systems;
+  pb.max_pairs = max_pairs;
+  pb.pos = pos;
+  pb.z = z;
+  pb.batch = batch;
+  pb.energy = energy;
+  pb.forces = forces;
+  pb.n_pairs = n_pairs;
+  pb.status = status;
+  pb.want_forces = true;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((rc = fill_i32(s, status, 1, 0))) return rc;
+  if (precision == TN_FP64)
+    return run_train<double>(m, s, pb, energy_ref, forces_ref, w_energy, w_force, loss, grad, ws, ws_bytes);
+  return run_train<float>(m, s, pb, energy_ref, forces_ref, w_energy, w_force, loss, grad, ws, ws_bytes);
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+"""GPU training step (loss and weight gradient, tn_train_grad) against the FP64 oracle's
+double-autograd gradient (oracle.train).
+
+Bars: in FP64 the dual-number pass differs from the oracle only by rounding order, so the
+loss is held to 1e-11 relative and every gradient tensor to 1e-10 of its largest entry
+(measured: below 1e-14).  In FP32 every step runs in single precision (unit roundoff 6e-8)
+through sums of up to a few thousand terms and about twenty layers of products, so errors of
+order 1e-6 to 1e-5 are expected; the bars are 1e-4 of each tensor's largest entry and 1e-5
+on the loss (measured: 3e-6 and 2e-7).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import TensorNetOracle
+from oracle.train import training_loss_and_grad
+from paper_2402_17660_amd import TensorNet
+from tests.util import random_box, random_molecule, small_blob
+
+pytestmark = pytest.mark.gpu
+
+BARS = {"fp64": (1e-11, 1e-10), "fp32": (1e-5, 1e-4)}
+
+
+def _molecules(sizes, seed):
+    parts = [random_molecule(n, seed + n) for n in sizes]
+    pos = np.concatenate([p for p, _ in parts])
+    z = np.concatenate([q for _, q in parts])
+    batch = np.concatenate([np.full(len(p), s, np.int32) for s, (p, _) in enumerate(parts)])
+    return pos, z, batch
+
+
+def _gpu(dev, blob, pos, z, batch, box, S, E_ref, F_ref, precision, w_energy=1.0, w_force=1.0):
+    m = TensorNet(blob, dev)
+    pdt = torch.float64 if precision == "fp64" else torch.float32
+    t = lambda a, dt: torch.tensor(np.asarray(a), dtype=dt, device=dev)
+    loss, E, F, g = m.train_grad(t(pos, pdt), t(z, torch.int32), t(batch, torch.int32), S, t(E_ref, torch.float64),
+                                 t(F_ref, torch.float64), box=box, precision=precision, w_energy=w_energy,
+                                 w_force=w_force)
+    grads = {k: v.cpu().numpy() for k, v in m.split_params(g).items()}
+    return float(loss.item()), E.cpu().numpy(), F.cpu().numpy().astype(np.float64), grads, g
+
+
+def _check(label, precision, loss, grads, loss_ref, grads_ref):
+    tl, tg = BARS[precision]
+    assert set(grads) == set(grads_ref)
+    worst, where = 0.0, None
+    for k, ref in grads_ref.items():
+        scale = np.abs(ref).max()
+        err = np.abs(grads[k] - ref).max() / scale if scale > 0 else np.abs(grads[k]).max()
+        if err > worst:
+            worst, where = err, k
+    lerr = abs(loss - loss_ref) / abs(loss_ref)
+    print(f"{label}: loss {loss:.6e} rel err {lerr:.2e}; worst gradient tensor {where} rel err {worst:.2e}",
+          flush=True)
+    assert lerr <= tl, (label, lerr)
+    assert worst <= tg, (label, where, worst)
+
+
+def _case(sizes, F, K, L, seed):
+    pos, z, batch = _molecules(sizes, seed)
+    S = len(sizes)
+    E_ref, F_ref = TensorNetOracle(small_blob(F=F, K=K, L=L, seed=seed + 1000)).energy_forces(pos, z, batch, None, S)
+    blob = small_blob(F=F, K=K, L=L, seed=seed + 2000)
+    return pos, z, batch, S, E_ref, F_ref, blob
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("sizes,F,K,L", [((9, 14), 16, 8, 2), ((12, 17, 23, 31, 40, 8, 19), 32, 16, 2)])
+def test_gradient_matches_oracle_molecules(dev, precision, sizes, F, K, L):
+    pos, z, batch, S, E_ref, F_ref, blob = _case(sizes, F, K, L, 3)
+    loss_ref, g_ref = training_loss_and_grad(TensorNetOracle(blob), pos, z, batch, None, S, E_ref, F_ref)
+    loss, E, Fo, grads, _ = _gpu(dev, blob, pos, z, batch, None, S, E_ref, F_ref, precision)
+    _check(f"molecules {sizes} F={F} {precision}", precision, loss, grads, loss_ref, g_ref)
+
+
+@pytest.mark.parametrize("w_energy,w_force", [(0.3, 0.0), (0.0, 2.0)])
+def test_loss_weights(dev, w_energy, w_force):
+    pos, z, batch, S, E_ref, F_ref, blob = _case((11, 20, 7), 16, 8, 2, 5)
+    loss_ref, g_ref = training_loss_and_grad(TensorNetOracle(blob), pos, z, batch, None, S, E_ref, F_ref,
+                                             w_energy=w_energy, w_force=w_force)
+    loss, _, _, grads, _ = _gpu(dev, blob, pos, z, batch, None, S, E_ref, F_ref, "fp64", w_energy, w_force)
+    _check(f"weights {w_energy}:{w_force}", "fp64", loss, grads, loss_ref, g_ref)
+
+
+def test_gradient_matches_oracle_periodic_box(dev):
+    """600 atoms in a periodic box: the cell list reorders atoms, so seeds and position
+    tangents go through the permutation."""
+    pos, z, box = random_box(600, 77, (600 / 0.1) ** (1 / 3))
+    batch = np.zeros(len(pos), np.int32)
+    E_ref, F_ref = TensorNetOracle(small_blob(F=16, K=8, L=1, seed=78)).energy_forces(pos, z, batch, box, 1)
+    blob = small_blob(F=16, K=8, L=1, seed=79)
+    loss_ref, g_ref = training_loss_and_grad(TensorNetOracle(blob), pos, z, batch, box, 1, E_ref, F_ref)
+    loss, _, _, grads, _ = _gpu(dev, blob, pos, z, batch, box, 1, E_ref, F_ref, "fp64")
+    _check("periodic box 600", "fp64", loss, grads, loss_ref, g_ref)
+
+
+def test_zero_loss_and_gradient_at_own_predictions(dev):
+    """Targets equal to the step's own predictions: loss and every gradient entry exactly zero."""
+    pos, z, batch, S, E_ref, F_ref, blob = _case((13, 9, 21), 16, 8, 2, 9)
+    for precision in ("fp64", "fp32"):
+        _, E, Fo, _, _ = _gpu(dev, blob, pos, z, batch, None, S, E_ref, F_ref, precision)
+        loss, _, _, _, g = _gpu(dev, blob, pos, z, batch, None, S, E, Fo, precision)
+        assert loss == 0.0, precision
+        assert bool((g == 0).all()), precision
+
+
+def test_deterministic(dev):
+    pos, z, batch, S, E_ref, F_ref, blob = _case((15, 22), 16, 8, 2, 11)
+    a = _gpu(dev, blob, pos, z, batch, None, S, E_ref, F_ref, "fp32")[4]
+    b = _gpu(dev, blob, pos, z, batch, None, S, E_ref, F_ref, "fp32")[4]
+    assert torch.equal(a, b)
+
+
+def test_empty_input(dev):
+    m = TensorNet(small_blob(F=16, K=8, L=2, seed=4), dev)
+    e = torch.empty(0, dtype=torch.float64, device=dev)
+    loss, E, Fo, g = m.train_grad(torch.empty((0, 3), dtype=torch.float64, device=dev),
+                                  torch.empty(0, dtype=torch.int32, device=dev),
+                                  torch.empty(0, dtype=torch.int32, device=dev), 0, e,
+                                  torch.empty((0, 3), dtype=torch.float64, device=dev), precision="fp64")
+    assert float(loss.item()) == 0.0
+    assert g.numel() == m.param_count() and bool((g == 0).all())

@@ -109,3 +109,21 @@ def test_pair_variant_queries_on_host():
     assert lib.tn_pair_variant_count(L.TN_BF16) >= 2
     assert lib.tn_pair_variant_count(L.TN_FP64) == 0
     assert lib.tn_model_set_pair_variant(None, L.TN_FP32, 0, 0) == L.TN_E_ARG
+
+
+def test_training_entry_points_reject_bad_requests_on_host():
+    lib = L.lib()
+    assert lib.tn_param_count(None) == -1
+    assert lib.tn_train_workspace_bytes(None, 10, 1, 100, None, L.TN_FP64) == 0
+    one = ctypes.c_void_p(1)   # never dereferenced: every call below fails its argument checks first
+    head = (None, None, 10, 1, one, one, one, None, 100)
+    tail = (one, one, 1.0, 1.0, one, one, one, one, one, one, one, 1 << 20)
+    assert lib.tn_train_grad(*head, L.TN_FP64, *tail) == L.TN_E_ARG   # null model
+    assert lib.tn_train_grad(one, None, -1, 1, one, one, one, None, 100, L.TN_FP64, *tail) == L.TN_E_ARG
+    assert lib.tn_train_grad(one, None, 10, 1, one, one, one, None, 100, L.TN_BF16, *tail) == L.TN_E_UNSUPPORTED
+    no_ref = (one, None, 1.0, 1.0, one, one, one, one, one, one, one, 1 << 20)
+    assert lib.tn_train_grad(one, None, 10, 1, one, one, one, None, 100, L.TN_FP64, *no_ref) == L.TN_E_ARG
+    bad_w = (one, one, float("nan"), 1.0, one, one, one, one, one, one, one, 1 << 20)
+    assert lib.tn_train_grad(one, None, 10, 1, one, one, one, None, 100, L.TN_FP64, *bad_w) == L.TN_E_ARG
+    huge = (1 << 20) * 16
+    assert lib.tn_train_grad(one, None, 10, 1, one, one, one, None, huge, L.TN_FP64, *tail) == L.TN_E_UNSUPPORTED
