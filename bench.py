@@ -97,10 +97,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-atoms", type=int, default=3000)
     ap.add_argument("--budget", type=float, default=1.05, help="max_pairs = budget * true pair count")
-    ap.add_argument("--extra", default="batch,md,table2,nbr",
+    ap.add_argument("--extra", default="batch,md,table2,nbr,train",
                     help="extra workloads: batch (512 molecules, captured), md (100 captured velocity-Verlet steps, "
                          "100k atoms), table2 (the paper's Table 2 sizes and 0/1/2 layers, captured), nbr "
-                         "(neighbour-search study on random clouds); 'none' = none")
+                         "(neighbour-search study on random clouds), train (one training step on 64 molecules, "
+                         "loss on energies and forces, exact weight gradient); 'none' = none")
     ap.add_argument("--md-steps", type=int, default=100)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed variants, copy this many MiB device-to-device once (a reference "
@@ -450,7 +451,68 @@ def extra_nbr(args, dev):
                          "65536 points per system)", sweep=sweep, batch_split=split)
 
 
-EXTRA = {"batch": extra_batch, "md": extra_md, "table2": extra_table2, "nbr": extra_nbr}
+def extra_train(args, dev):
+    """One training step: 64 molecules of 16-128 atoms (0.05 A noise), hidden 128, 3 layers, cutoff 5 A; loss =
+    mean squared energy error + mean squared force error against a teacher network of the same shape (seed 3000),
+    and the exact gradient of that loss with respect to every weight of the student (tn_train_grad: energies and
+    forces, then the dual-number reverse sweep to the weights).  FP32 (the workload's precision) and FP64."""
+    import torch
+    from paper_2402_17660_amd import TensorNet, build_neighbors
+    from synth import make_config, make_weights, write_blob
+    c = make_config(4)
+    N, S = len(c["pos"]), c["n_systems"]
+    pos32 = torch.tensor(c["pos"], device=dev)
+    z = torch.tensor(c["z"], device=dev)
+    batch = torch.tensor(c["batch"], device=dev)
+    _, n_pairs, _ = build_neighbors(pos32, batch, c["r_c"], 64 * N)
+    true_pairs = int(n_pairs.item())
+    mp = int(math.ceil(1.05 * true_pairs / 1024.0) * 1024)
+    teacher = TensorNet(write_blob(make_weights(c["F"], c["K"], c["L"], c["max_z"], seed=3000), c["F"], c["K"],
+                                   c["L"], c["max_z"], c["r_c"]), dev)
+    E_t, F_t = teacher.energy_forces(pos32, z, batch, S, max_pairs=mp, precision="fp32", path="fused")
+    E_ref, F_ref = E_t.clone(), F_t.double()
+    teacher.close()
+    student = TensorNet(_blob_for(c), dev)
+    out = dict(workload="64 molecules, sizes uniform 16-128 atoms, 0.05 A noise; hidden 128, 3 layers, 32 RBF, "
+                        "cutoff 5 A; one training step = loss on energies and forces + exact weight gradient",
+               n_atoms=N, n_systems=S, n_pairs=true_pairs, max_pairs=mp, n_params=student.param_count())
+    grads = {}
+    for prec in ("fp32", "fp64"):
+        pos = pos32 if prec == "fp32" else pos32.double()
+        for _ in range(2):
+            loss, E, Fo, g = student.train_grad(pos, z, batch, S, E_ref, F_ref, max_pairs=mp, precision=prec)
+        torch.cuda.synchronize()
+        reps = 10
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            student.train_grad(pos, z, batch, S, E_ref, F_ref, max_pairs=mp, precision=prec, check=False,
+                               grad_out=g)
+        stop.record()
+        torch.cuda.synchronize()
+        student.check()
+        ms = start.elapsed_time(stop) / reps
+        grads[prec] = g.clone()
+        out[prec] = dict(ms_per_step=ms, atom_steps_per_s=N / (ms * 1e-3), loss=float(loss.item()),
+                         grad_norm=float(g.norm().item()))
+        log(f"train/{prec}: {ms:.2f} ms per training step ({N / (ms * 1e-3):.3e} atoms/s), loss "
+            f"{out[prec]['loss']:.6e}, |grad| {out[prec]['grad_norm']:.6e}")
+    d = (grads["fp32"] - grads["fp64"]).abs().max() / grads["fp64"].abs().max()
+    out["fp32_vs_fp64_grad_max_rel"] = float(d.item())
+    # the inference step on the same inputs, for the training overhead
+    for _ in range(2):
+        student.energy_forces(pos32, z, batch, S, max_pairs=mp, precision="fp32", path="fused")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        student.energy_forces(pos32, z, batch, S, max_pairs=mp, precision="fp32", path="fused", check=False)
+    torch.cuda.synchronize()
+    out["energy_forces_fused_fp32_ms"] = (time.perf_counter() - t0) / 10 * 1e3
+    student.close()
+    return out
+
+
+EXTRA = {"batch": extra_batch, "md": extra_md, "table2": extra_table2, "nbr": extra_nbr, "train": extra_train}
 
 
 if __name__ == "__main__":

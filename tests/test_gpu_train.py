@@ -122,3 +122,51 @@ def test_empty_input(dev):
                                   torch.empty((0, 3), dtype=torch.float64, device=dev), precision="fp64")
     assert float(loss.item()) == 0.0
     assert g.numel() == m.param_count() and bool((g == 0).all())
+
+
+def _cfg4_blob(seed):
+    from synth import make_config, make_weights, write_blob
+    c = make_config(4)
+    return write_blob(make_weights(c["F"], c["K"], c["L"], c["max_z"], seed=seed), c["F"], c["K"], c["L"],
+                      c["max_z"], c["r_c"])
+
+
+def test_full_model_size_sample_matches_oracle(dev):
+    """The training workload's model (hidden 128, 3 layers, 32 RBF, student weights) on three of its
+    molecules, targets from the teacher network in the oracle."""
+    from synth import make_config
+    c = make_config(4)
+    sel = np.isin(c["batch"], [0, 1, 2])
+    pos, z, batch = c["pos"][sel].astype(np.float64), c["z"][sel], c["batch"][sel]
+    E_ref, F_ref = TensorNetOracle(_cfg4_blob(3000)).energy_forces(pos, z, batch, None, 3)
+    blob = _cfg4_blob(c["weight_seed"])
+    loss_ref, g_ref = training_loss_and_grad(TensorNetOracle(blob), pos, z, batch, None, 3, E_ref, F_ref)
+    for precision in ("fp64", "fp32"):
+        loss, _, _, grads, _ = _gpu(dev, blob, pos, z, batch, None, 3, E_ref, F_ref, precision)
+        _check(f"hidden 128 x 3 layers, 3 molecules {precision}", precision, loss, grads, loss_ref, g_ref)
+
+
+def test_full_batch_fp32_against_fp64(dev):
+    """All 64 molecules (4759 atoms) with seeded random targets: the FP32 step against the FP64 step,
+    to the FP32 bars (a property of the arithmetic that holds at any size)."""
+    from synth import make_config
+    c = make_config(4)
+    rng = np.random.default_rng(4004)
+    S = c["n_systems"]
+    E_ref = rng.normal(0.0, 10.0, size=S)
+    F_ref = rng.normal(0.0, 1.0, size=(len(c["pos"]), 3))
+    blob = _cfg4_blob(c["weight_seed"])
+    mp = 20 * len(c["pos"])   # about 13 unordered pairs per atom in these molecules
+    ref = _gpu_mp(dev, blob, c, E_ref, F_ref, "fp64", mp)
+    got = _gpu_mp(dev, blob, c, E_ref, F_ref, "fp32", mp)
+    _check("full batch fp32 vs fp64", "fp32", got[0], got[3], ref[0], ref[3])
+
+
+def _gpu_mp(dev, blob, c, E_ref, F_ref, precision, max_pairs):
+    m = TensorNet(blob, dev)
+    pdt = torch.float64 if precision == "fp64" else torch.float32
+    t = lambda a, dt: torch.tensor(np.asarray(a), dtype=dt, device=dev)
+    loss, E, F, g = m.train_grad(t(c["pos"], pdt), t(c["z"], torch.int32), t(c["batch"], torch.int32),
+                                 c["n_systems"], t(E_ref, torch.float64), t(F_ref, torch.float64),
+                                 max_pairs=max_pairs, precision=precision)
+    return float(loss.item()), E, F, {k: v.cpu().numpy() for k, v in m.split_params(g).items()}
