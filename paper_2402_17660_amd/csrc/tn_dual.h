@@ -19,6 +19,7 @@ namespace tn {
 
 template <class S>
 struct Dual {
+  using scalar = S;
   S v, d;
   Dual() = default;   // trivial, so arrays of Dual may live in LDS
   template <class U, class = typename std::enable_if<std::is_arithmetic<U>::value>::type>

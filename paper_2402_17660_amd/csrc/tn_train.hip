@@ -25,7 +25,8 @@
 
 namespace tn {
 
-constexpr int kSlices = 32;   // row slices of a parameter-adjoint reduction
+constexpr int kSlices = 32;      // row slices of a parameter-adjoint outer-product reduction
+constexpr int kColSlices = 256;  // row slices of a column reduction (64 rows or more each)
 
 // Rows of a feature array: row r starts at (r / rg) * gs + (c0 + r % rg) * cs.  One row per
 // pair or atom (rg = 1, gs = row length) or, for a mixing matrix, the coordinates of one part
@@ -46,38 +47,6 @@ inline RowMap part_rows(int part, int64_t F) {
 }
 inline int64_t part_count(int part) { return part == 0 ? 1 : (part == 1 ? 3 : 5); }
 
-// P[z][o][k] = sum over rows r of slice z (r < min(R, *Rdev)) of A(r, o) * B(r, k), B = 1 when
-// null.  16x16 outputs per block, 16 rows staged per step; every block writes its outputs.
-template <class T>
-__global__ void __launch_bounds__(256) k_wgrad_part(const T *A, RowMap ma, const T *B, RowMap mb, int64_t R,
-                                                    const int64_t *Rdev, int O, int Kc, int64_t slice, T *P) {
-  __shared__ T As[16][17];
-  __shared__ T Bs[16][17];
-  int64_t Rn = R;
-  if (Rdev) {
-    const int64_t md = *Rdev;
-    if (md < Rn) Rn = md;
-  }
-  const int o0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
-  const int64_t rb = (int64_t)blockIdx.z * slice;
-  const int64_t re = rb + slice < Rn ? rb + slice : Rn;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  T acc = T(0);
-  for (int64_t r0 = rb; r0 < re; r0 += 16) {
-    const int64_t r = r0 + ty;
-    As[ty][tx] = (r < re && o0 + tx < O) ? A[row_at(ma, r) + o0 + tx] : T(0);
-    T bv = T(0);
-    if (r < re && k0 + tx < Kc) bv = B ? B[row_at(mb, r) + k0 + tx] : T(1);
-    Bs[ty][tx] = bv;
-    __syncthreads();
-#pragma unroll
-    for (int rr = 0; rr < 16; ++rr) acc += As[rr][ty] * Bs[rr][tx];
-    __syncthreads();
-  }
-  const int o = o0 + ty, k = k0 + tx;
-  if (o < O && k < Kc) P[((int64_t)blockIdx.z * O + o) * Kc + k] = acc;
-}
-
 // C[o * ldc + k] += sum_z P[z][o][k], the slices summed in a fixed order.
 template <class T>
 __global__ void k_sum_slices(int O, int Kc, int G, const T *P, T *C, int64_t ldc) {
@@ -89,13 +58,20 @@ __global__ void k_sum_slices(int O, int Kc, int G, const T *P, T *C, int64_t ldc
   C[o * ldc + k] += s;
 }
 
-// P[z][c] = sum over rows r of slice z of rs[r] * A[r*C + c] * B[r*C + c] (rs, B = 1 when null).
+// P[z][c] = sum over rows r < min(R, *Rdev) of slice z of rs[r] * A[r*C + c] * B[r*C + c] (rs, B = 1
+// when null).
 template <class T>
-__global__ void k_coldot_part(const T *A, const T *B, const T *rs, int64_t R, int C, int64_t slice, T *P) {
+__global__ void k_coldot_part(const T *A, const T *B, const T *rs, int64_t R, const int64_t *Rdev, int C,
+                              int64_t slice, T *P) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
+  int64_t Rn = R;
+  if (Rdev) {
+    const int64_t md = *Rdev;
+    if (md < Rn) Rn = md;
+  }
   const int64_t rb = (int64_t)blockIdx.y * slice;
-  const int64_t re = rb + slice < R ? rb + slice : R;
+  const int64_t re = rb + slice < Rn ? rb + slice : Rn;
   T s = T(0);
   for (int64_t r = rb; r < re; ++r) {
     T v = A[r * C + c];
@@ -104,6 +80,273 @@ __global__ void k_coldot_part(const T *A, const T *B, const T *rs, int64_t R, in
     s += v;
   }
   P[(int64_t)blockIdx.y * C + c] = s;
+}
+
+// ---------------------------------------------------------------- dual products on the matrix cores
+// C = epilogue(A B) with A dual and B real (a weight matrix: the weights carry no tangent),
+// the same product and epilogue as GemmArgs / k_gemm_mfma: bias (real), pre-activation store,
+// SiLU, row scale, silu'(gate) factor and accumulation, each applied in dual arithmetic.  The
+// value and the eps part of A are staged as two LDS tiles and share every B fragment: two
+// MFMA 16x16x4 per fragment pair instead of one.
+template <class S>
+struct DualGemmArgs {
+  const Dual<S> *A = nullptr; int64_t lda = 0;
+  const S *B = nullptr; int64_t ldb = 0; int transB = 0;
+  Dual<S> *C = nullptr; int64_t ldc = 0;
+  const S *bias = nullptr;
+  Dual<S> *Z = nullptr; int64_t ldz = 0;
+  int act = 0;
+  const Dual<S> *rowscale = nullptr;
+  const Dual<S> *gate = nullptr; int64_t ldg = 0;
+  int accumulate = 0;
+  int64_t M = 0, N = 0, K = 0;
+  const int64_t *Mdev = nullptr;
+  int64_t zoff = 0;
+  int zpart = 0;
+  const S *Bz[3] = {nullptr, nullptr, nullptr};
+};
+
+template <class S, int BM>
+__global__ void __launch_bounds__(256) k_gemm_dual(DualGemmArgs<S> g) {
+  using D = Dual<S>;
+  using V = typename MfmaVec<S>::type;
+  constexpr int RBW = BM / 32;
+  constexpr int PERA = BM * GBK / 256, PERB = GBN * GBK / 256;
+  __shared__ S Av[BM][GBK + 1];
+  __shared__ S Ad[BM][GBK + 1];
+  __shared__ S Bs[GBN][GBK + 1];
+  int64_t Mrows = g.M;
+  if (g.Mdev) {
+    const int64_t md = *g.Mdev;
+    if (md < Mrows) Mrows = md;
+  }
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * GBN;
+  if (m0 >= Mrows) return;
+  const int z = blockIdx.z;
+  const D *__restrict__ A = g.A + z * g.zoff;
+  const S *__restrict__ B = g.zpart ? g.Bz[coord_part(z)] : g.B;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 32;
+  const int r16 = lane & 15, q = lane >> 4;
+  D ra[PERA];
+  S rb[PERB];
+  auto load_chunk = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < PERA; ++e) {
+      const int t = tid + 256 * e, mm_ = t / GBK, kk = t % GBK;
+      const int64_t m = m0 + mm_, k = k0 + kk;
+      ra[e] = (m < Mrows && k < g.K) ? A[m * g.lda + k] : D(S(0), S(0));
+    }
+#pragma unroll
+    for (int e = 0; e < PERB; ++e) {
+      const int t = tid + 256 * e;
+      int nn, kk;
+      if (g.transB) { nn = t / GBK; kk = t % GBK; } else { kk = t / GBN; nn = t % GBN; }
+      const int64_t n = n0 + nn, k = k0 + kk;
+      S v = S(0);
+      if (n < g.N && k < g.K) v = g.transB ? B[n * g.ldb + k] : B[k * g.ldb + n];
+      rb[e] = v;
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int e = 0; e < PERA; ++e) {
+      const int t = tid + 256 * e;
+      Av[t / GBK][t % GBK] = ra[e].v;
+      Ad[t / GBK][t % GBK] = ra[e].d;
+    }
+#pragma unroll
+    for (int e = 0; e < PERB; ++e) {
+      const int t = tid + 256 * e;
+      int nn, kk;
+      if (g.transB) { nn = t / GBK; kk = t % GBK; } else { kk = t / GBN; nn = t % GBN; }
+      Bs[nn][kk] = rb[e];
+    }
+  };
+  V accv[RBW][2], accd[RBW][2];
+#pragma unroll
+  for (int a = 0; a < RBW; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      accv[a][b] = V{S(0), S(0), S(0), S(0)};
+      accd[a][b] = V{S(0), S(0), S(0), S(0)};
+    }
+  load_chunk(0);
+  for (int64_t k0 = 0; k0 < g.K; k0 += GBK) {
+    store_chunk();
+    __syncthreads();
+    if (k0 + GBK < g.K) load_chunk(k0 + GBK);
+#pragma unroll
+    for (int s4 = 0; s4 < GBK; s4 += 4) {
+      const S b0 = Bs[wc + r16][s4 + q], b1 = Bs[wc + 16 + r16][s4 + q];
+#pragma unroll
+      for (int a = 0; a < RBW; ++a) {
+        const S av = Av[wr + 16 * a + r16][s4 + q], ad = Ad[wr + 16 * a + r16][s4 + q];
+        accv[a][0] = mfma_16x16x4(av, b0, accv[a][0]);
+        accv[a][1] = mfma_16x16x4(av, b1, accv[a][1]);
+        accd[a][0] = mfma_16x16x4(ad, b0, accd[a][0]);
+        accd[a][1] = mfma_16x16x4(ad, b1, accd[a][1]);
+      }
+    }
+    __syncthreads();
+  }
+  D *C = g.C + z * g.zoff;
+  S bias[2] = {S(0), S(0)};
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int64_t n = n0 + wc + cb * 16 + r16;
+    if (g.bias && n < g.N) bias[cb] = g.bias[n];
+  }
+#pragma unroll
+  for (int rb_ = 0; rb_ < RBW; ++rb_)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t m = m0 + wr + rb_ * 16 + (sizeof(S) == 4 ? 4 * q + t : 4 * t + q);
+        const int64_t n = n0 + wc + cb * 16 + r16;
+        if (m >= Mrows || n >= g.N) continue;
+        D v(accv[rb_][cb][t] + bias[cb], accd[rb_][cb][t]);
+        if (g.Z) g.Z[z * g.zoff + m * g.ldz + n] = v;
+        if (g.act == 1) v = silu(v);
+        if (g.rowscale) v *= g.rowscale[m];
+        if (g.gate) v *= silu_grad(g.gate[z * g.zoff + m * g.ldg + n]);
+        D *dst = C + m * g.ldc + n;
+        if (g.accumulate) *dst += v; else *dst = v;
+      }
+}
+
+template <class S>
+inline int dgemm(hipStream_t s, const DualGemmArgs<S> &g, int zdim = 1) {
+  if (g.M <= 0 || g.N <= 0) return TN_OK;
+  const int64_t nb = (g.N + GBN - 1) / GBN;
+  const int64_t tiles64 = nb * ((g.M + 63) / 64) * zdim;
+  if (tiles64 < 512) {
+    dim3 grid((unsigned)nb, (unsigned)((g.M + 31) / 32), (unsigned)zdim);
+    hipLaunchKernelGGL((k_gemm_dual<S, 32>), grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid((unsigned)nb, (unsigned)((g.M + 63) / 64), (unsigned)zdim);
+    hipLaunchKernelGGL((k_gemm_dual<S, 64>), grid, dim3(256), 0, s, g);
+  }
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
+// y = act(x W^T + b), W [Nout, Kin] real
+template <class S>
+inline int dlinear_fwd(hipStream_t s, const Dual<S> *x, int64_t M, int64_t Kin, const S *W, const S *b, int64_t Nout,
+                       Dual<S> *y, Dual<S> *z_pre, int act, const Dual<S> *rowscale = nullptr,
+                       const int64_t *Mdev = nullptr) {
+  DualGemmArgs<S> g;
+  g.A = x; g.lda = Kin; g.B = W; g.ldb = Kin; g.transB = 1;
+  g.C = y; g.ldc = Nout; g.bias = b; g.Z = z_pre; g.ldz = Nout; g.act = act; g.rowscale = rowscale;
+  g.M = M; g.N = Nout; g.K = Kin; g.Mdev = Mdev;
+  return dgemm(s, g);
+}
+
+// dx (+)= (dy W) * silu'(gate)
+template <class S>
+inline int dlinear_bwd(hipStream_t s, const Dual<S> *dy, int64_t M, int64_t Nout, const S *W, int64_t Kin,
+                       Dual<S> *dx, const Dual<S> *gate, int accumulate, const int64_t *Mdev = nullptr) {
+  DualGemmArgs<S> g;
+  g.A = dy; g.lda = Nout; g.B = W; g.ldb = Kin; g.transB = 0;
+  g.C = dx; g.ldc = Kin; g.gate = gate; g.ldg = Kin; g.accumulate = accumulate;
+  g.M = M; g.N = Kin; g.K = Nout; g.Mdev = Mdev;
+  return dgemm(s, g);
+}
+
+// per-part channel mixing of [N, 9, F] dual features with real matrices (forward or adjoint)
+template <class S>
+inline int dmix(hipStream_t s, const Dual<S> *in, Dual<S> *out, int64_t N, int64_t F, const S *const W[3],
+                int adjoint, int accumulate) {
+  if (N <= 0) return TN_OK;
+  DualGemmArgs<S> g;
+  g.A = in; g.lda = 9 * F; g.C = out; g.ldc = 9 * F; g.transB = adjoint ? 0 : 1; g.ldb = F;
+  g.M = N; g.N = F; g.K = F; g.zoff = F; g.zpart = 1; g.accumulate = accumulate;
+  for (int q = 0; q < 3; ++q) g.Bz[q] = W[q];
+  return dgemm(s, g, 9);
+}
+
+// Parameter adjoints on the matrix cores: P[z][o][k] = sum over the rows r of slice z of
+// A(r, o) B(r, k), both dual: value A_v B_v, eps part A_d B_v + A_v B_d (three MFMA per
+// fragment).  64x64 outputs per block, 32 rows staged per step in LDS as [row][column] tiles
+// (coalesced along the feature axis); lane l of MFMA 16x16x4 supplies A(r0 + l/16, o0 + l%16)
+// and B(r0 + l/16, k0 + l%16).  Every block writes its outputs.
+constexpr int WRC = 32;
+template <class S>
+__global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma, const Dual<S> *B, RowMap mb,
+                                                    int64_t R, const int64_t *Rdev, int O, int Kc, int64_t slice,
+                                                    Dual<S> *P) {
+  using D = Dual<S>;
+  using V = typename MfmaVec<S>::type;
+  __shared__ S Av[WRC][64 + 1], Ad[WRC][64 + 1], Bv[WRC][64 + 1], Bd[WRC][64 + 1];
+  int64_t Rn = R;
+  if (Rdev) {
+    const int64_t md = *Rdev;
+    if (md < Rn) Rn = md;
+  }
+  const int o0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
+  const int64_t rb = (int64_t)blockIdx.z * slice;
+  const int64_t re = rb + slice < Rn ? rb + slice : Rn;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wo = (wave >> 1) * 32, wk = (wave & 1) * 32;
+  const int r16 = lane & 15, q = lane >> 4;
+  V cv[2][2], cd[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cv[a][b] = V{S(0), S(0), S(0), S(0)};
+      cd[a][b] = V{S(0), S(0), S(0), S(0)};
+    }
+  for (int64_t r0 = rb; r0 < re; r0 += WRC) {
+#pragma unroll
+    for (int e = 0; e < WRC * 64 / 256; ++e) {
+      const int t = tid + 256 * e, rr = t / 64, cc = t % 64;
+      const int64_t r = r0 + rr;
+      D x(S(0), S(0)), y(S(0), S(0));
+      if (r < re) {
+        if (o0 + cc < O) x = A[row_at(ma, r) + o0 + cc];
+        if (k0 + cc < Kc) y = B[row_at(mb, r) + k0 + cc];
+      }
+      Av[rr][cc] = x.v;
+      Ad[rr][cc] = x.d;
+      Bv[rr][cc] = y.v;
+      Bd[rr][cc] = y.d;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < WRC; s4 += 4) {
+      S bv[2], bd[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        bv[b] = Bv[s4 + q][wk + 16 * b + r16];
+        bd[b] = Bd[s4 + q][wk + 16 * b + r16];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const S av = Av[s4 + q][wo + 16 * a + r16], ad = Ad[s4 + q][wo + 16 * a + r16];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cv[a][b] = mfma_16x16x4(av, bv[b], cv[a][b]);
+          cd[a][b] = mfma_16x16x4(ad, bv[b], cd[a][b]);
+          cd[a][b] = mfma_16x16x4(av, bd[b], cd[a][b]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int o = o0 + wo + 16 * a + (sizeof(S) == 4 ? 4 * q + t : 4 * t + q);
+        const int k = k0 + wk + 16 * b + r16;
+        if (o < O && k < Kc) P[((int64_t)blockIdx.z * O + o) * Kc + k] = D(cv[a][b][t], cd[a][b][t]);
+      }
 }
 
 template <class T>
@@ -115,15 +358,15 @@ struct Reducer {
     const int64_t g = (R + 2047) / 2048;
     return (int)std::max<int64_t>(1, std::min<int64_t>(kSlices, g));
   }
-  // C[o][k] (row stride ldc) += sum_r A(r, o) B(r, k)
+  // C[o][k] (row stride ldc) += sum_r A(r, o) B(r, k), rows r < min(R, *Rdev)
   int wgrad(hipStream_t s, const T *A, RowMap ma, const T *B, RowMap mb, int64_t R, const int64_t *Rdev, int O,
             int Kc, T *C, int64_t ldc) const {
     if (R <= 0 || O <= 0 || Kc <= 0) return TN_OK;
     const int G = slices(R);
     if ((int64_t)G * O * Kc > cap) return TN_E_WORKSPACE;
-    const int64_t slice = ((R + G - 1) / G + 15) / 16 * 16;
-    hipLaunchKernelGGL(k_wgrad_part<T>, dim3((unsigned)((Kc + 15) / 16), (unsigned)((O + 15) / 16), (unsigned)G),
-                       dim3(256), 0, s, A, ma, B, mb, R, Rdev, O, Kc, slice, part);
+    const int64_t slice = ((R + G - 1) / G + WRC - 1) / WRC * WRC;
+    hipLaunchKernelGGL(k_wgrad_mfma<typename T::scalar>, dim3((unsigned)((Kc + 63) / 64), (unsigned)((O + 63) / 64),
+                       (unsigned)G), dim3(256), 0, s, A, ma, B, mb, R, Rdev, O, Kc, slice, part);
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for((int64_t)O * Kc, 256)), dim3(256), 0, s, O, Kc, G,
                        (const T *)part, C, ldc);
@@ -135,16 +378,17 @@ struct Reducer {
              T *db) const {
     int rc = wgrad(s, dz, rows_of(O), x, rows_of(Kin), R, Rdev, O, Kin, dW, Kin);
     if (rc) return rc;
-    return wgrad(s, dz, rows_of(O), nullptr, rows_of(1), R, Rdev, O, 1, db, 1);
+    return coldot(s, dz, nullptr, nullptr, R, Rdev, O, db);
   }
-  // out[c] += sum_r rs[r] A[r][c] B[r][c]
-  int coldot(hipStream_t s, const T *A, const T *B, const T *rs, int64_t R, int C, T *out) const {
+  // out[c] += sum_r rs[r] A[r][c] B[r][c], rows r < min(R, *Rdev)
+  int coldot(hipStream_t s, const T *A, const T *B, const T *rs, int64_t R, const int64_t *Rdev, int C,
+             T *out) const {
     if (R <= 0 || C <= 0) return TN_OK;
-    const int G = slices(R);
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(kColSlices, (R + 63) / 64));
     if ((int64_t)G * C > cap) return TN_E_WORKSPACE;
     const int64_t slice = (R + G - 1) / G;
     hipLaunchKernelGGL(k_coldot_part<T>, dim3((unsigned)((C + 127) / 128), (unsigned)G), dim3(128), 0, s, A, B, rs,
-                       R, C, slice, part);
+                       R, Rdev, C, slice, part);
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for(C, 256)), dim3(256), 0, s, 1, C, G, (const T *)part, out,
                        (int64_t)C);
@@ -283,24 +527,43 @@ __global__ void k_embed_dz(const int32_t *pairs, int64_t max_pairs, const int64_
   dZ[p * 2 * F + F + f] = ph * (a * dj[0] + b * gjA + c * gjS);
 }
 
-// dU[s] = sum of dZ over the pair directions whose receiver has species s, dV[s] over those
-// whose sender has it.  One block per (species, 64 channels); four row groups per block.
+// Per atom a, the adjoints of its species rows: dUa[a] = sum of dZ over the pair directions that
+// a receives, dVa[a] over those it sends.  A stored pair (i, j) has i < j, so along the CSR row of
+// a a neighbour b > a means a is the pair's i.  One thread per (atom, channel).
 template <class T>
-__global__ void __launch_bounds__(256) k_species_dz(const int32_t *pairs, int64_t max_pairs, const int64_t *n_pairs,
-                                                    int F, const int32_t *z, int max_z, const T *dZ, T *dU, T *dV) {
+__global__ void k_atom_dz(int64_t n, int F, const int32_t *rowptr, const int32_t *nbr, const int32_t *pid,
+                          const int64_t *n_pairs, int64_t max_pairs, const T *dZ, T *dUa, T *dVa) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  const int64_t a = t / F;
+  const int f = (int)(t % F);
+  T u = T(0), v = T(0);
+  if (pairs_ok(n_pairs, max_pairs)) {
+    for (int32_t e = rowptr[a]; e < rowptr[a + 1]; ++e) {
+      const int64_t p = pid[e];
+      const T d0 = dZ[p * 2 * F + f], d1 = dZ[p * 2 * F + F + f];
+      if (nbr[e] > a) { u += d0; v += d1; } else { u += d1; v += d0; }
+    }
+  }
+  dUa[t] = u;
+  dVa[t] = v;
+}
+
+// dU[s] = sum of dUa over the atoms of species s, likewise dV.  One block per (species, 64
+// channels), four atom groups per block summed in a fixed order.
+template <class T>
+__global__ void __launch_bounds__(256) k_species_sum(int64_t n, int F, const int32_t *z, int max_z, const T *dUa,
+                                                     const T *dVa, T *dU, T *dV) {
   __shared__ T lu[4][64];
   __shared__ T lv[4][64];
   const int sp = blockIdx.x;
   const int f = blockIdx.y * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
-  const int64_t P = pair_bound(n_pairs, max_pairs);
   T u = T(0), v = T(0);
   if (f < F) {
-    for (int64_t p = grp; p < P; p += 4) {
-      const int zi = clamp_z(z[pairs[p]], max_z), zj = clamp_z(z[pairs[max_pairs + p]], max_z);
-      if (zi != sp && zj != sp) continue;
-      const T dij = dZ[p * 2 * F + f], dji = dZ[p * 2 * F + F + f];
-      if (zi == sp) { u += dij; v += dji; }
-      if (zj == sp) { u += dji; v += dij; }
+    for (int64_t a = grp; a < n; a += 4) {
+      if (clamp_z(z[a], max_z) != sp) continue;
+      u += dUa[a * F + f];
+      v += dVa[a * F + f];
     }
   }
   lu[grp][threadIdx.x & 63] = u;
@@ -328,7 +591,7 @@ struct TrainWs {
   double *wt = nullptr;
   D *seed, *sd;
   NbrWs nb;
-  D *wD, *gD, *dU, *dV, *part, *posD;
+  D *wD, *gD, *dU, *dV, *dUa, *dVa, *part, *posD;
   D *geo, *phi, *rbf, *f0, *Xr, *T0, *nrm0, *xhat0, *rstd0, *n0, *ez1, *ea1, *ez2, *g;
   std::vector<D *> X, nX, Xb, Y, z1, a1, z2, a2, z3, h, M, P, nP, Pb, Dl;
   D *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps;
@@ -356,7 +619,9 @@ static void plan_train(WsPlan &p, const tn_model *m, int64_t N, int64_t NS, int6
   w->gD = p.take<D>(param_count(m));
   w->dU = p.take<D>(Z * F);
   w->dV = p.take<D>(Z * F);
-  w->part_cap = (int64_t)kSlices * std::max<int64_t>(6 * F * F, 3 * F * K);
+  w->dUa = p.take<D>(N * F);
+  w->dVa = p.take<D>(N * F);
+  w->part_cap = std::max<int64_t>((int64_t)kSlices * std::max<int64_t>(6 * F * F, 3 * F * K), kColSlices * 3 * F);
   w->part = p.take<D>(w->part_cap);
   w->posD = p.take<D>(3 * N);
   w->geo = p.take<D>(4 * MP);
@@ -471,6 +736,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
   TN_LAUNCH_CHECK();
   if ((rc = fill_bytes_zero(s, w.gD, NP * sizeof(D)))) return rc;
   auto W = [&](size_t off) { return static_cast<const D *>(w.wD + off); };
+  auto Wr = [&](size_t off) { return wptr<S>(m, off); };   // real weights for the matrix products
   auto G = [&](size_t off) { return w.gD + off; };
   Reducer<D> red{w.part, w.part_cap};
 
@@ -494,7 +760,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
     TN_LAUNCH_CHECK();
   }
   // embedding
-  if ((rc = linear_fwd<D>(s, w.rbf, MP, K, W(o.W0), W(o.b0), 3 * F, w.f0, nullptr, 0, nullptr, np))) return rc;
+  if ((rc = dlinear_fwd<S>(s, w.rbf, MP, K, Wr(o.W0), Wr(o.b0), 3 * F, w.f0, nullptr, 0, nullptr, np))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_embed_gather<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, zz,
                        m->max_z, W(o.U), W(o.V), (const D *)w.geo, (const D *)w.phi, (const D *)w.f0, w.Xr);
@@ -505,10 +771,10 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
                        W(o.ln_g), W(o.ln_b), w.n0, w.xhat0, w.rstd0);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = linear_fwd<D>(s, w.n0, N, F, W(o.W1), W(o.b1), 2 * F, w.ea1, w.ez1, 1))) return rc;
-  if ((rc = linear_fwd<D>(s, w.ea1, N, 2 * F, W(o.W2), W(o.b2), 3 * F, w.g, w.ez2, 1))) return rc;
-  const D *Wemb[3] = {W(o.Wmix[0]), W(o.Wmix[1]), W(o.Wmix[2])};
-  if ((rc = mix<D>(s, w.Xr, w.T0, N, F, Wemb, nullptr, 0, 0))) return rc;
+  if ((rc = dlinear_fwd<S>(s, w.n0, N, F, Wr(o.W1), Wr(o.b1), 2 * F, w.ea1, w.ez1, 1))) return rc;
+  if ((rc = dlinear_fwd<S>(s, w.ea1, N, 2 * F, Wr(o.W2), Wr(o.b2), 3 * F, w.g, w.ez2, 1))) return rc;
+  const S *Wemb[3] = {Wr(o.Wmix[0]), Wr(o.Wmix[1]), Wr(o.Wmix[2])};
+  if ((rc = dmix<S>(s, w.Xr, w.T0, N, F, Wemb, 0, 0))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_gate<D>, dim3(grid_for(N * 9 * F, bs)), dim3(bs), 0, s, N, (int)F, (const D *)w.g,
                        (const D *)w.T0, w.X[0]);
@@ -521,12 +787,12 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
       hipLaunchKernelGGL(k_normalize<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.X[l], w.nX[l], w.Xb[l]);
       TN_LAUNCH_CHECK();
     }
-    const D *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
-    if ((rc = mix<D>(s, w.Xb[l], w.Y[l], N, F, W1, nullptr, 0, 0))) return rc;
-    if ((rc = linear_fwd<D>(s, w.rbf, MP, K, W(lo.Wa), W(lo.ba), F, w.a1[l], w.z1[l], 1, nullptr, np))) return rc;
-    if ((rc = linear_fwd<D>(s, w.a1[l], MP, F, W(lo.Wb), W(lo.bb), 2 * F, w.a2[l], w.z2[l], 1, nullptr, np)))
+    const S *W1[3] = {Wr(lo.W1[0]), Wr(lo.W1[1]), Wr(lo.W1[2])};
+    if ((rc = dmix<S>(s, w.Xb[l], w.Y[l], N, F, W1, 0, 0))) return rc;
+    if ((rc = dlinear_fwd<S>(s, w.rbf, MP, K, Wr(lo.Wa), Wr(lo.ba), F, w.a1[l], w.z1[l], 1, nullptr, np))) return rc;
+    if ((rc = dlinear_fwd<S>(s, w.a1[l], MP, F, Wr(lo.Wb), Wr(lo.bb), 2 * F, w.a2[l], w.z2[l], 1, nullptr, np)))
       return rc;
-    if ((rc = linear_fwd<D>(s, w.a2[l], MP, 2 * F, W(lo.Wc), W(lo.bc), 3 * F, w.h[l], w.z3[l], 1, w.phi, np)))
+    if ((rc = dlinear_fwd<S>(s, w.a2[l], MP, 2 * F, Wr(lo.Wc), Wr(lo.bc), 3 * F, w.h[l], w.z3[l], 1, w.phi, np)))
       return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_message<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP,
@@ -536,8 +802,8 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
                          w.P[l], w.nP[l], w.Pb[l]);
       TN_LAUNCH_CHECK();
     }
-    const D *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
-    if ((rc = mix<D>(s, w.Pb[l], w.Dl[l], N, F, W2, nullptr, 0, 0))) return rc;
+    const S *W2[3] = {Wr(lo.W2[0]), Wr(lo.W2[1]), Wr(lo.W2[2])};
+    if ((rc = dmix<S>(s, w.Pb[l], w.Dl[l], N, F, W2, 0, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_residual<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Xb[l], (const D *)w.Dl[l],
                          w.X[l + 1]);
@@ -552,8 +818,8 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
                        W(o.oln_g), W(o.oln_b), w.q, w.oxhat, w.orstd);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = linear_fwd<D>(s, w.q, N, 3 * F, W(o.Wo), W(o.bo), F, w.ox, w.oz, 1))) return rc;
-  if ((rc = linear_fwd<D>(s, w.ox, N, F, W(o.Wh), W(o.bh), H, w.hx, w.hz, 1))) return rc;
+  if ((rc = dlinear_fwd<S>(s, w.q, N, 3 * F, Wr(o.Wo), Wr(o.bo), F, w.ox, w.oz, 1))) return rc;
+  if ((rc = dlinear_fwd<S>(s, w.ox, N, F, Wr(o.Wh), Wr(o.bh), H, w.hx, w.hz, 1))) return rc;
 
   // ---- pass 2: reverse sweep to the parameters, seeds sd_i = seed_{system of i}
   if (N > 0) {
@@ -561,14 +827,14 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
                        (const D *)w.hz, W(o.wout), (const D *)w.sd, w.dhz);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = red.coldot(s, w.hx, nullptr, w.sd, N, (int)H, G(o.wout)))) return rc;
-  if ((rc = red.coldot(s, w.sd, nullptr, nullptr, N, 1, G(o.bout)))) return rc;
+  if ((rc = red.coldot(s, w.hx, nullptr, w.sd, N, nullptr, (int)H, G(o.wout)))) return rc;
+  if ((rc = red.coldot(s, w.sd, nullptr, nullptr, N, nullptr, 1, G(o.bout)))) return rc;
   if ((rc = red.linear(s, w.dhz, w.ox, N, nullptr, (int)H, (int)F, G(o.Wh), G(o.bh)))) return rc;
-  if ((rc = linear_bwd<D>(s, w.dhz, N, H, W(o.Wh), F, w.dox, w.oz, 0))) return rc;
+  if ((rc = dlinear_bwd<S>(s, w.dhz, N, H, Wr(o.Wh), F, w.dox, w.oz, 0))) return rc;
   if ((rc = red.linear(s, w.dox, w.q, N, nullptr, (int)F, (int)(3 * F), G(o.Wo), G(o.bo)))) return rc;
-  if ((rc = linear_bwd<D>(s, w.dox, N, F, W(o.Wo), 3 * F, w.dq, nullptr, 0))) return rc;
-  if ((rc = red.coldot(s, w.dq, w.oxhat, nullptr, N, (int)(3 * F), G(o.oln_g)))) return rc;
-  if ((rc = red.coldot(s, w.dq, nullptr, nullptr, N, (int)(3 * F), G(o.oln_b)))) return rc;
+  if ((rc = dlinear_bwd<S>(s, w.dox, N, F, Wr(o.Wo), 3 * F, w.dq, nullptr, 0))) return rc;
+  if ((rc = red.coldot(s, w.dq, w.oxhat, nullptr, N, nullptr, (int)(3 * F), G(o.oln_g)))) return rc;
+  if ((rc = red.coldot(s, w.dq, nullptr, nullptr, N, nullptr, (int)(3 * F), G(o.oln_b)))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_layernorm_bwd<D>, dim3((unsigned)N), dim3(128), 0, s, N, (int)(3 * F), (const D *)w.dq,
                        (const D *)w.oxhat, (const D *)w.orstd, W(o.oln_g), w.don);
@@ -580,8 +846,8 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
   if (MP > 0 && (rc = fill_bytes_zero(s, w.dphi, MP * sizeof(D)))) return rc;
   for (int64_t l = L - 1; l >= 0; --l) {
     const LayerOff &lo = o.layer[l];
-    const D *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
-    const D *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
+    const S *W1[3] = {Wr(lo.W1[0]), Wr(lo.W1[1]), Wr(lo.W1[2])};
+    const S *W2[3] = {Wr(lo.W2[0]), Wr(lo.W2[1]), Wr(lo.W2[2])};
     if (N > 0) {
       hipLaunchKernelGGL(k_residual_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Dl[l],
                          (const D *)w.dX, w.dD);
@@ -591,7 +857,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
       if ((rc = red.wgrad(s, w.dD, part_rows(q, F), w.Pb[l], part_rows(q, F), N * part_count(q), nullptr, (int)F,
                           (int)F, G(lo.W2[q]), F)))
         return rc;
-    if ((rc = mix<D>(s, w.dD, w.dPb, N, F, W2, nullptr, 1, 0))) return rc;
+    if ((rc = dmix<S>(s, w.dD, w.dPb, N, F, W2, 1, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_product_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.dPb, (const D *)w.P[l],
                          (const D *)w.nP[l], (const D *)w.Y[l], (const D *)w.M[l], w.dY, w.dM);
@@ -609,7 +875,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
       if ((rc = red.wgrad(s, w.dY, part_rows(q, F), w.Xb[l], part_rows(q, F), N * part_count(q), nullptr, (int)F,
                           (int)F, G(lo.W1[q]), F)))
         return rc;
-    if ((rc = mix<D>(s, w.dY, w.dX, N, F, W1, nullptr, 1, 1))) return rc;
+    if ((rc = dmix<S>(s, w.dY, w.dX, N, F, W1, 1, 1))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_normalize_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.X[l],
                          (const D *)w.nX[l], w.dX);
@@ -621,9 +887,9 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
       TN_LAUNCH_CHECK();
     }
     if ((rc = red.linear(s, w.dz3, w.a2[l], MP, np, (int)(3 * F), (int)(2 * F), G(lo.Wc), G(lo.bc)))) return rc;
-    if ((rc = linear_bwd<D>(s, w.dz3, MP, 3 * F, W(lo.Wc), 2 * F, w.dz2, w.z2[l], 0, np))) return rc;
+    if ((rc = dlinear_bwd<S>(s, w.dz3, MP, 3 * F, Wr(lo.Wc), 2 * F, w.dz2, w.z2[l], 0, np))) return rc;
     if ((rc = red.linear(s, w.dz2, w.a1[l], MP, np, (int)(2 * F), (int)F, G(lo.Wb), G(lo.bb)))) return rc;
-    if ((rc = linear_bwd<D>(s, w.dz2, MP, 2 * F, W(lo.Wb), F, w.dz1, w.z1[l], 0, np))) return rc;
+    if ((rc = dlinear_bwd<S>(s, w.dz2, MP, 2 * F, Wr(lo.Wb), F, w.dz1, w.z1[l], 0, np))) return rc;
     if ((rc = red.linear(s, w.dz1, w.rbf, MP, np, (int)F, (int)K, G(lo.Wa), G(lo.ba)))) return rc;
   }
   // embedding: dX holds dE/dX0
@@ -636,18 +902,18 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
     if ((rc = red.wgrad(s, w.dT0, part_rows(q, F), w.Xr, part_rows(q, F), N * part_count(q), nullptr, (int)F, (int)F,
                         G(o.Wmix[q]), F)))
       return rc;
-  if ((rc = mix<D>(s, w.dT0, w.dXr, N, F, Wemb, nullptr, 1, 0))) return rc;
+  if ((rc = dmix<S>(s, w.dT0, w.dXr, N, F, Wemb, 1, 0))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_mul_silu_grad<D>, dim3(grid_for(N * 3 * F, bs)), dim3(bs), 0, s, N * 3 * F, (const D *)w.dg,
                        (const D *)w.ez2, w.dez2);
     TN_LAUNCH_CHECK();
   }
   if ((rc = red.linear(s, w.dez2, w.ea1, N, nullptr, (int)(3 * F), (int)(2 * F), G(o.W2), G(o.b2)))) return rc;
-  if ((rc = linear_bwd<D>(s, w.dez2, N, 3 * F, W(o.W2), 2 * F, w.dez1, w.ez1, 0))) return rc;
+  if ((rc = dlinear_bwd<S>(s, w.dez2, N, 3 * F, Wr(o.W2), 2 * F, w.dez1, w.ez1, 0))) return rc;
   if ((rc = red.linear(s, w.dez1, w.n0, N, nullptr, (int)(2 * F), (int)F, G(o.W1), G(o.b1)))) return rc;
-  if ((rc = linear_bwd<D>(s, w.dez1, N, 2 * F, W(o.W1), F, w.dn0, nullptr, 0))) return rc;
-  if ((rc = red.coldot(s, w.dn0, w.xhat0, nullptr, N, (int)F, G(o.ln_g)))) return rc;
-  if ((rc = red.coldot(s, w.dn0, nullptr, nullptr, N, (int)F, G(o.ln_b)))) return rc;
+  if ((rc = dlinear_bwd<S>(s, w.dez1, N, 2 * F, Wr(o.W1), F, w.dn0, nullptr, 0))) return rc;
+  if ((rc = red.coldot(s, w.dn0, w.xhat0, nullptr, N, nullptr, (int)F, G(o.ln_g)))) return rc;
+  if ((rc = red.coldot(s, w.dn0, nullptr, nullptr, N, nullptr, (int)F, G(o.ln_b)))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_layernorm_bwd<D>, dim3((unsigned)N), dim3(128), 0, s, N, (int)F, (const D *)w.dn0,
                        (const D *)w.xhat0, (const D *)w.rstd0, W(o.ln_g), w.dnrm0);
@@ -667,22 +933,27 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
   }
   if ((rc = red.linear(s, w.df0, w.rbf, MP, np, (int)(3 * F), (int)K, G(o.W0), G(o.b0)))) return rc;
   // species tables U = W_z[:, :F] E + b_z, V = W_z[:, F:] E  ->  E, W_z, b_z
-  if (MP > 0) {
-    hipLaunchKernelGGL(k_species_dz<D>, dim3((unsigned)Z, (unsigned)((F + 63) / 64)), dim3(256), 0, s, gr.pairs, MP,
-                       np, (int)F, zz, m->max_z, (const D *)w.dZ, w.dU, w.dV);
+  if (N > 0) {
+    hipLaunchKernelGGL(k_atom_dz<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP,
+                       (const D *)w.dZ, w.dUa, w.dVa);
+    TN_LAUNCH_CHECK();
+  }
+  {
+    hipLaunchKernelGGL(k_species_sum<D>, dim3((unsigned)Z, (unsigned)((F + 63) / 64)), dim3(256), 0, s, N, (int)F,
+                       zz, m->max_z, (const D *)w.dUa, (const D *)w.dVa, w.dU, w.dV);
     TN_LAUNCH_CHECK();
     if ((rc = red.wgrad(s, w.dU, rows_of(F), W(o.E), rows_of(F), Z, nullptr, (int)F, (int)F, G(o.Wz), 2 * F)))
       return rc;
     if ((rc = red.wgrad(s, w.dV, rows_of(F), W(o.E), rows_of(F), Z, nullptr, (int)F, (int)F, G(o.Wz) + F, 2 * F)))
       return rc;
-    if ((rc = red.wgrad(s, w.dU, rows_of(F), nullptr, rows_of(1), Z, nullptr, (int)F, 1, G(o.bz), 1))) return rc;
+    if ((rc = red.coldot(s, w.dU, nullptr, nullptr, Z, nullptr, (int)F, G(o.bz)))) return rc;
     for (int half = 0; half < 2; ++half) {
-      GemmArgs<D> ga;
+      DualGemmArgs<S> ga;
       ga.A = half ? w.dV : w.dU; ga.lda = F;
-      ga.B = W(o.Wz) + half * F; ga.ldb = 2 * F; ga.transB = 0;
+      ga.B = Wr(o.Wz) + half * F; ga.ldb = 2 * F; ga.transB = 0;
       ga.C = G(o.E); ga.ldc = F; ga.accumulate = 1;
       ga.M = Z; ga.N = F; ga.K = F;
-      if ((rc = gemm(s, ga))) return rc;
+      if ((rc = dgemm(s, ga))) return rc;
     }
   }
   if (NP > 0) {
