@@ -25,7 +25,7 @@
 
 namespace tn {
 
-constexpr int kSlices = 32;      // row slices of a parameter-adjoint outer-product reduction
+constexpr int kSlices = 256;     // most row slices of a parameter-adjoint outer-product reduction
 constexpr int kColSlices = 256;  // row slices of a column reduction (64 rows or more each)
 
 // Rows of a feature array: row r starts at (r / rg) * gs + (c0 + r % rg) * cs.  One row per
@@ -38,7 +38,9 @@ struct RowMap {
   int64_t cs = 0;
 };
 __device__ inline int64_t row_at(const RowMap &m, int64_t r) {
-  return (r / m.rg) * m.gs + (m.c0 + r % m.rg) * m.cs;
+  if (m.rg == 1) return r * m.gs + m.c0 * m.cs;
+  const uint32_t r32 = (uint32_t)r, g = r32 / (uint32_t)m.rg;   // part rows: r < 5 N < 2^31
+  return (int64_t)g * m.gs + (m.c0 + (int)(r32 - g * (uint32_t)m.rg)) * m.cs;
 }
 inline RowMap rows_of(int64_t len) { return RowMap{1, len, 0, 0}; }
 inline RowMap part_rows(int part, int64_t F) {
@@ -300,22 +302,34 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma,
       cv[a][b] = V{S(0), S(0), S(0), S(0)};
       cd[a][b] = V{S(0), S(0), S(0), S(0)};
     }
-  for (int64_t r0 = rb; r0 < re; r0 += WRC) {
+  constexpr int PER = WRC * 64 / 256;
+  D xa[PER], xb[PER];
+  auto load_rows = [&](int64_t r0) {
 #pragma unroll
-    for (int e = 0; e < WRC * 64 / 256; ++e) {
+    for (int e = 0; e < PER; ++e) {
       const int t = tid + 256 * e, rr = t / 64, cc = t % 64;
       const int64_t r = r0 + rr;
-      D x(S(0), S(0)), y(S(0), S(0));
+      xa[e] = D(S(0), S(0));
+      xb[e] = D(S(0), S(0));
       if (r < re) {
-        if (o0 + cc < O) x = A[row_at(ma, r) + o0 + cc];
-        if (k0 + cc < Kc) y = B[row_at(mb, r) + k0 + cc];
+        if (o0 + cc < O) xa[e] = A[row_at(ma, r) + o0 + cc];
+        if (k0 + cc < Kc) xb[e] = B[row_at(mb, r) + k0 + cc];
       }
-      Av[rr][cc] = x.v;
-      Ad[rr][cc] = x.d;
-      Bv[rr][cc] = y.v;
-      Bd[rr][cc] = y.d;
+    }
+  };
+  // the next rows' global loads are issued before the current rows' products
+  if (rb < re) load_rows(rb);
+  for (int64_t r0 = rb; r0 < re; r0 += WRC) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int t = tid + 256 * e, rr = t / 64, cc = t % 64;
+      Av[rr][cc] = xa[e].v;
+      Ad[rr][cc] = xa[e].d;
+      Bv[rr][cc] = xb[e].v;
+      Bd[rr][cc] = xb[e].d;
     }
     __syncthreads();
+    if (r0 + WRC < re) load_rows(r0 + WRC);
 #pragma unroll
     for (int s4 = 0; s4 < WRC; s4 += 4) {
       S bv[2], bd[2];
@@ -354,15 +368,19 @@ struct Reducer {
   T *part = nullptr;
   int64_t cap = 0;   // elements of part
 
-  static int slices(int64_t R) {
-    const int64_t g = (R + 2047) / 2048;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kSlices, g));
+  // Row slices of an outer-product reduction: enough blocks to fill the chip (about eight per
+  // compute unit), at least 256 rows per slice, and the partial sums within the scratch.
+  int slices(int64_t R, int O, int Kc) const {
+    const int64_t tiles = (int64_t)((O + 63) / 64) * ((Kc + 63) / 64);
+    int64_t g = std::min<int64_t>((2048 + tiles - 1) / tiles, (R + 255) / 256);
+    g = std::min<int64_t>(g, std::min<int64_t>(kSlices, cap / ((int64_t)O * Kc)));
+    return (int)std::max<int64_t>(1, g);
   }
   // C[o][k] (row stride ldc) += sum_r A(r, o) B(r, k), rows r < min(R, *Rdev)
   int wgrad(hipStream_t s, const T *A, RowMap ma, const T *B, RowMap mb, int64_t R, const int64_t *Rdev, int O,
             int Kc, T *C, int64_t ldc) const {
     if (R <= 0 || O <= 0 || Kc <= 0) return TN_OK;
-    const int G = slices(R);
+    const int G = slices(R, O, Kc);
     if ((int64_t)G * O * Kc > cap) return TN_E_WORKSPACE;
     const int64_t slice = ((R + G - 1) / G + WRC - 1) / WRC * WRC;
     hipLaunchKernelGGL(k_wgrad_mfma<typename T::scalar>, dim3((unsigned)((Kc + 63) / 64), (unsigned)((O + 63) / 64),
@@ -621,7 +639,8 @@ static void plan_train(WsPlan &p, const tn_model *m, int64_t N, int64_t NS, int6
   w->dV = p.take<D>(Z * F);
   w->dUa = p.take<D>(N * F);
   w->dVa = p.take<D>(N * F);
-  w->part_cap = std::max<int64_t>((int64_t)kSlices * std::max<int64_t>(6 * F * F, 3 * F * K), kColSlices * 3 * F);
+  // partial sums: up to 96 slices of the largest weight matrix (3F x 2F or 3F x K)
+  w->part_cap = std::max<int64_t>((int64_t)96 * std::max<int64_t>(6 * F * F, 3 * F * K), kColSlices * 3 * F);
   w->part = p.take<D>(w->part_cap);
   w->posD = p.take<D>(3 * N);
   w->geo = p.take<D>(4 * MP);
