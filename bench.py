@@ -451,13 +451,52 @@ def extra_nbr(args, dev):
                          "65536 points per system)", sweep=sweep, batch_split=split)
 
 
+def timing(L_, name):
+    """(total ms, launches) of a named scope in the library's timing registry."""
+    import ctypes
+    tot, cnt = ctypes.c_double(), ctypes.c_int64()
+    L_.tn_timing_read(name.encode(), ctypes.byref(tot), ctypes.byref(cnt))
+    return tot.value, cnt.value
+
+
+def train_wgrad_flops(F, K, L, n_atoms, n_pairs, max_z):
+    """Algorithmic FLOPs of the training step's parameter adjoints (outer products of layer adjoints with layer
+    inputs) on dual numbers: per weight entry and row, one value product and two tangent products (6 FLOP)."""
+    pair = n_pairs * (L * (F * K + 2 * F * F + 6 * F * F) + 3 * F * K)
+    node = n_atoms * ((1 + 2 * L) * 9 * F * F + 2 * F * F + 6 * F * F + 3 * F * F + (F // 2) * F)
+    species = 2 * max_z * F * F
+    return 6.0 * (pair + node + species)
+
+
+def train_cpu_baseline(c, n_mol):
+    """The oracle's training step (double autograd, FP64) on the first n_mol molecules of the workload."""
+    import numpy as np
+    import torch
+    from oracle import TensorNetOracle
+    from oracle.train import training_loss_and_grad
+    from synth import make_weights, write_blob
+    sel = c["batch"] < n_mol
+    pos, z, batch = c["pos"][sel].astype(np.float64), c["z"][sel], c["batch"][sel]
+    blob = lambda seed: write_blob(make_weights(c["F"], c["K"], c["L"], c["max_z"], seed=seed), c["F"], c["K"],
+                                   c["L"], c["max_z"], c["r_c"])
+    E_ref, F_ref = TensorNetOracle(blob(3000)).energy_forces(pos, z, batch, None, n_mol)
+    student = TensorNetOracle(blob(c["weight_seed"]))
+    t = time.perf_counter()
+    training_loss_and_grad(student, pos, z, batch, None, n_mol, E_ref, F_ref)
+    dt = time.perf_counter() - t
+    n = int(sel.sum())
+    return dict(value=n / dt, unit="atoms/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"one FP64 training step (loss, forces, weight gradient by double autograd) on the first {n_mol} "
+                       f"molecules of the workload ({n} atoms), {dt:.1f} s; teacher targets excluded")
+
+
 def extra_train(args, dev):
     """One training step: 64 molecules of 16-128 atoms (0.05 A noise), hidden 128, 3 layers, cutoff 5 A; loss =
     mean squared energy error + mean squared force error against a teacher network of the same shape (seed 3000),
     and the exact gradient of that loss with respect to every weight of the student (tn_train_grad: energies and
     forces, then the dual-number reverse sweep to the weights).  FP32 (the workload's precision) and FP64."""
     import torch
-    from paper_2402_17660_amd import TensorNet, build_neighbors
+    from paper_2402_17660_amd import TensorNet, build_neighbors, lib
     from synth import make_config, make_weights, write_blob
     c = make_config(4)
     N, S = len(c["pos"]), c["n_systems"]
@@ -477,12 +516,16 @@ def extra_train(args, dev):
                         "cutoff 5 A; one training step = loss on energies and forces + exact weight gradient",
                n_atoms=N, n_systems=S, n_pairs=true_pairs, max_pairs=mp, n_params=student.param_count())
     grads = {}
+    L_ = lib()
+    wflop = train_wgrad_flops(c["F"], c["K"], c["L"], N, true_pairs, c["max_z"])
     for prec in ("fp32", "fp64"):
         pos = pos32 if prec == "fp32" else pos32.double()
         for _ in range(2):
             loss, E, Fo, g = student.train_grad(pos, z, batch, S, E_ref, F_ref, max_pairs=mp, precision=prec)
         torch.cuda.synchronize()
         reps = 10
+        L_.tn_timing_reset()
+        L_.tn_timing_enable(1)
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         start.record()
         for _ in range(reps):
@@ -490,13 +533,24 @@ def extra_train(args, dev):
                                grad_out=g)
         stop.record()
         torch.cuda.synchronize()
+        L_.tn_timing_enable(0)
         student.check()
         ms = start.elapsed_time(stop) / reps
+        wg_ms, wg_launches = timing(L_, "train_wgrad")
+        wg_ms /= reps
         grads[prec] = g.clone()
+        achieved = wflop / (wg_ms * 1e-3) / 1e12 if wg_ms > 0 else None
+        peak = PEAK[prec] / 1e12
         out[prec] = dict(ms_per_step=ms, atom_steps_per_s=N / (ms * 1e-3), loss=float(loss.item()),
-                         grad_norm=float(g.norm().item()))
+                         grad_norm=float(g.norm().item()),
+                         roofline=dict(bound="mfma", kernel="k_wgrad_mfma (parameter adjoints, dual)",
+                                       achieved=achieved, peak=peak, unit="TFLOP/s",
+                                       frac=achieved / peak if achieved else None, traffic=None,
+                                       ms_per_step=wg_ms, launches_per_step=wg_launches / reps,
+                                       flop_per_step=wflop))
         log(f"train/{prec}: {ms:.2f} ms per training step ({N / (ms * 1e-3):.3e} atoms/s), loss "
-            f"{out[prec]['loss']:.6e}, |grad| {out[prec]['grad_norm']:.6e}")
+            f"{out[prec]['loss']:.6e}, |grad| {out[prec]['grad_norm']:.6e}; parameter adjoints {wg_ms:.2f} ms "
+            f"({achieved:.1f} TFLOP/s of {peak:.1f})")
     d = (grads["fp32"] - grads["fp64"]).abs().max() / grads["fp64"].abs().max()
     out["fp32_vs_fp64_grad_max_rel"] = float(d.item())
     # the inference step on the same inputs, for the training overhead
@@ -509,6 +563,9 @@ def extra_train(args, dev):
     torch.cuda.synchronize()
     out["energy_forces_fused_fp32_ms"] = (time.perf_counter() - t0) / 10 * 1e3
     student.close()
+    if not args.no_cpu_baseline:
+        log("timing the oracle's training step on the host ...")
+        out["cpu_baseline"] = train_cpu_baseline(c, 20)
     return out
 
 

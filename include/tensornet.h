@@ -160,15 +160,18 @@ int tn_energy_forces(const tn_model *m, void *stream, int64_t n_atoms, int64_t n
  *   loss = w_energy * mean_s (E_s - energy_ref_s)^2
  *        + w_force  * mean_{i,a} (F_ia - forces_ref_ia)^2,   F = -dE/dpos,
  * and its gradient with respect to every tensor of the weight blob.  Two
- * passes: energies and forces (the plain path), then the reverse sweep to the
+ * passes: energies and forces (as tn_energy_forces: the fused path in FP32
+ * where its pair kernels cover the model's sizes, else the plain path), then
+ * the reverse sweep to the
  * parameters on dual numbers whose positions carry the tangent d loss/dF, so
  * the force term's mixed second derivative comes out exactly (forward over
  * reverse), not by finite differences.
  *   tn_param_count: number of float64 values in the blob's tensors (the
  *     length of grad), or -1 for a null model.
  *   tn_train_workspace_bytes: ws size for tn_train_grad, 0 if invalid.
- *   precision: TN_FP64 or TN_FP32 (every step of both passes in that type;
- *     pos and forces typed as for tn_energy_forces).  Others: TN_E_UNSUPPORTED.
+ *   precision: TN_FP64 or TN_FP32 (the second pass computes every step in that
+ *     type; pos and forces typed as for tn_energy_forces).  Others:
+ *     TN_E_UNSUPPORTED.
  *   energy_ref [n_systems], forces_ref [n_atoms, 3]: float64 targets (device).
  *   loss: one float64 (device); energy [n_systems] float64 and forces
  *     [n_atoms, 3] receive the model's predictions at pos.

@@ -7,7 +7,8 @@
 //   a_s = d loss / d E_s,   W_ia = d loss / d F_ia,
 // the gradient is  sum_s a_s dE_s/dtheta - D_W (d E_tot / d theta),  where D_W is the
 // directional derivative along positions r + eps W.  The step computes it in two passes:
-//   1. energies and forces at r (the plain path), the loss, a_s and W;
+//   1. energies and forces at r (the fused path in FP32, else the plain path), the loss, a_s
+//      and W;
 //   2. the hand-written reverse sweep energy -> parameters, run on dual numbers whose
 //      positions carry the tangent W and whose per-system seeds are (-1, a_s): the eps parts
 //      of the parameter adjoints are then exactly the loss gradient (forward-over-reverse).
@@ -383,6 +384,7 @@ struct Reducer {
     const int G = slices(R, O, Kc);
     if ((int64_t)G * O * Kc > cap) return TN_E_WORKSPACE;
     const int64_t slice = ((R + G - 1) / G + WRC - 1) / WRC * WRC;
+    TimedScope ts("train_wgrad", s);
     hipLaunchKernelGGL(k_wgrad_mfma<typename T::scalar>, dim3((unsigned)((Kc + 63) / 64), (unsigned)((O + 63) / 64),
                        (unsigned)G), dim3(256), 0, s, A, ma, B, mb, R, Rdev, O, Kc, slice, part);
     TN_LAUNCH_CHECK();
@@ -712,8 +714,18 @@ static void plan_train(WsPlan &p, const tn_model *m, int64_t N, int64_t NS, int6
   w->dZ = p.take<D>(MP * 2 * F);
 }
 
+// Pass 1 (energies and forces) runs on the fused path in FP32 where its pair kernels cover the
+// model's sizes, else on the plain path.
+static bool pass1_fused(const tn_model *m, int prec) {
+  return prec == TN_FP32 && pair_kernels_support(m->F, m->K, m->L, false);
+}
+static size_t pass1_bytes(const tn_model *m, int64_t n, int64_t ns, int64_t mp, const BoxInfo &bi, int prec) {
+  return pass1_fused(m, prec) ? fused_workspace_bytes(m, n, ns, mp, bi, prec, 1)
+                              : plain_workspace_bytes(m, n, ns, mp, bi, prec, 1);
+}
+
 static size_t train_bytes(const tn_model *m, int64_t n, int64_t ns, int64_t mp, const BoxInfo &bi, int prec) {
-  const size_t pb = plain_workspace_bytes(m, n, ns, mp, bi, prec, 1);
+  const size_t pb = pass1_bytes(m, n, ns, mp, bi, prec);
   WsPlan p(nullptr);
   if (prec == TN_FP64) {
     TrainWs<double> w;
@@ -733,7 +745,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
   const int64_t N = pb.n, NS = pb.S, MP = pb.max_pairs, F = m->F, K = m->K, L = m->L, Z = m->max_z;
   const int64_t H = F / 2;
   const int prec = std::is_same<S, double>::value ? TN_FP64 : TN_FP32;
-  const size_t plain_bytes = plain_workspace_bytes(m, N, NS, MP, pb.box, prec, 1);
+  const size_t plain_bytes = pass1_bytes(m, N, NS, MP, pb.box, prec);
   WsPlan plan(ws);
   TrainWs<S> w;
   plan_train(plan, m, N, NS, MP, pb.box, plain_bytes, &w);
@@ -744,7 +756,9 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
   const int64_t NP = param_count(m);
 
   // ---- pass 1: energies and forces at r, the loss, its seeds and the position tangent
-  if ((rc = plain_run(m, s, pb, prec, w.plain, w.plain_bytes))) return rc;
+  rc = pass1_fused(m, prec) ? fused_run(m, s, pb, prec, w.plain, w.plain_bytes)
+                            : plain_run(m, s, pb, prec, w.plain, w.plain_bytes);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_loss<S>, dim3(1), dim3(256), 0, s, N, NS, pb.energy, Eref, static_cast<const S *>(pb.forces),
                      Fref, wE, wF, loss, w.seed, w.wt);
   TN_LAUNCH_CHECK();
