@@ -50,15 +50,22 @@ inline RowMap part_rows(int part, int64_t F) {
 }
 inline int64_t part_count(int part) { return part == 0 ? 1 : (part == 1 ? 3 : 5); }
 
-// C[o * ldc + k] += sum_z P[z][o][k], the slices summed in a fixed order.
+// C[o * ldc + k] += sum_z P[z][o][k], the slices summed in a fixed order: 64 outputs per
+// block, four groups of slices (z = g mod 4) per output, the groups combined in order.
 template <class T>
-__global__ void k_sum_slices(int O, int Kc, int G, const T *P, T *C, int64_t ldc) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)O * Kc) return;
-  const int o = (int)(t / Kc), k = (int)(t % Kc);
+__global__ void __launch_bounds__(256) k_sum_slices(int O, int Kc, int G, const T *P, T *C, int64_t ldc) {
+  __shared__ T part[4][64];
+  const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t t = blockIdx.x * (int64_t)64 + l, n = (int64_t)O * Kc;
   T s = T(0);
-  for (int z = 0; z < G; ++z) s += P[(int64_t)z * O * Kc + t];
-  C[o * ldc + k] += s;
+  if (t < n)
+    for (int z = g; z < G; z += 4) s += P[(int64_t)z * n + t];
+  part[g][l] = s;
+  __syncthreads();
+  if (g == 0 && t < n) {
+    const int o = (int)(t / Kc), k = (int)(t % Kc);
+    C[o * ldc + k] += ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
+  }
 }
 
 // P[z][c] = sum over rows r < min(R, *Rdev) of slice z of rs[r] * A[r*C + c] * B[r*C + c] (rs, B = 1
@@ -384,11 +391,14 @@ struct Reducer {
     const int G = slices(R, O, Kc);
     if ((int64_t)G * O * Kc > cap) return TN_E_WORKSPACE;
     const int64_t slice = ((R + G - 1) / G + WRC - 1) / WRC * WRC;
-    TimedScope ts("train_wgrad", s);
-    hipLaunchKernelGGL(k_wgrad_mfma<typename T::scalar>, dim3((unsigned)((Kc + 63) / 64), (unsigned)((O + 63) / 64),
-                       (unsigned)G), dim3(256), 0, s, A, ma, B, mb, R, Rdev, O, Kc, slice, part);
-    TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for((int64_t)O * Kc, 256)), dim3(256), 0, s, O, Kc, G,
+    {
+      TimedScope ts("train_wgrad", s);
+      hipLaunchKernelGGL(k_wgrad_mfma<typename T::scalar>, dim3((unsigned)((Kc + 63) / 64),
+                         (unsigned)((O + 63) / 64), (unsigned)G), dim3(256), 0, s, A, ma, B, mb, R, Rdev, O, Kc,
+                         slice, part);
+      TN_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for((int64_t)O * Kc, 64)), dim3(256), 0, s, O, Kc, G,
                        (const T *)part, C, ldc);
     TN_LAUNCH_CHECK();
     return TN_OK;
@@ -410,7 +420,7 @@ struct Reducer {
     hipLaunchKernelGGL(k_coldot_part<T>, dim3((unsigned)((C + 127) / 128), (unsigned)G), dim3(128), 0, s, A, B, rs,
                        R, Rdev, C, slice, part);
     TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for(C, 256)), dim3(256), 0, s, 1, C, G, (const T *)part, out,
+    hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for(C, 64)), dim3(256), 0, s, 1, C, G, (const T *)part, out,
                        (int64_t)C);
     TN_LAUNCH_CHECK();
     return TN_OK;
