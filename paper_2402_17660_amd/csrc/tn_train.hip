@@ -580,29 +580,35 @@ __global__ void k_atom_dz(int64_t n, int F, const int32_t *rowptr, const int32_t
 }
 
 // dU[s] = sum of dUa over the atoms of species s, likewise dV.  One block per (species, 64
-// channels), four atom groups per block summed in a fixed order.
+// channels); sixteen atom groups per block, combined in a fixed order.
 template <class T>
-__global__ void __launch_bounds__(256) k_species_sum(int64_t n, int F, const int32_t *z, int max_z, const T *dUa,
-                                                     const T *dVa, T *dU, T *dV) {
-  __shared__ T lu[4][64];
-  __shared__ T lv[4][64];
+__global__ void __launch_bounds__(1024) k_species_sum(int64_t n, int F, const int32_t *z, int max_z, const T *dUa,
+                                                      const T *dVa, T *dU, T *dV) {
+  __shared__ T lu[16][64];
+  __shared__ T lv[16][64];
   const int sp = blockIdx.x;
-  const int f = blockIdx.y * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int f = blockIdx.y * 64 + l;
   T u = T(0), v = T(0);
   if (f < F) {
-    for (int64_t a = grp; a < n; a += 4) {
+    for (int64_t a = grp; a < n; a += 16) {
       if (clamp_z(z[a], max_z) != sp) continue;
       u += dUa[a * F + f];
       v += dVa[a * F + f];
     }
   }
-  lu[grp][threadIdx.x & 63] = u;
-  lv[grp][threadIdx.x & 63] = v;
+  lu[grp][l] = u;
+  lv[grp][l] = v;
   __syncthreads();
   if (grp == 0 && f < F) {
-    const int l = threadIdx.x;
-    dU[(int64_t)sp * F + f] = lu[0][l] + lu[1][l] + lu[2][l] + lu[3][l];
-    dV[(int64_t)sp * F + f] = lv[0][l] + lv[1][l] + lv[2][l] + lv[3][l];
+    T su = T(0), sv = T(0);
+#pragma unroll
+    for (int g = 0; g < 16; ++g) {
+      su += lu[g][l];
+      sv += lv[g][l];
+    }
+    dU[(int64_t)sp * F + f] = su;
+    dV[(int64_t)sp * F + f] = sv;
   }
 }
 
@@ -982,7 +988,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
     TN_LAUNCH_CHECK();
   }
   {
-    hipLaunchKernelGGL(k_species_sum<D>, dim3((unsigned)Z, (unsigned)((F + 63) / 64)), dim3(256), 0, s, N, (int)F,
+    hipLaunchKernelGGL(k_species_sum<D>, dim3((unsigned)Z, (unsigned)((F + 63) / 64)), dim3(1024), 0, s, N, (int)F,
                        zz, m->max_z, (const D *)w.dUa, (const D *)w.dVa, w.dU, w.dV);
     TN_LAUNCH_CHECK();
     if ((rc = red.wgrad(s, w.dU, rows_of(F), W(o.E), rows_of(F), Z, nullptr, (int)F, (int)F, G(o.Wz), 2 * F)))

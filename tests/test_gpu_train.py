@@ -170,3 +170,17 @@ def _gpu_mp(dev, blob, c, E_ref, F_ref, precision, max_pairs):
                                  c["n_systems"], t(E_ref, torch.float64), t(F_ref, torch.float64),
                                  max_pairs=max_pairs, precision=precision)
     return float(loss.item()), E, F, {k: v.cpu().numpy() for k, v in m.split_params(g).items()}
+
+
+def test_gradient_matches_oracle_triclinic_cell(dev):
+    """A reduced triclinic cell: the minimum image shifts the dual displacement's value by a
+    lattice vector and leaves its tangent alone."""
+    from tests.util import random_in_cell, random_triclinic_cell
+    H = random_triclinic_cell(131, 4.5)
+    pos, z = random_in_cell(300, 132, H)
+    batch = np.zeros(len(pos), np.int32)
+    E_ref, F_ref = TensorNetOracle(small_blob(F=16, K=8, L=1, seed=133)).energy_forces(pos, z, batch, H, 1)
+    blob = small_blob(F=16, K=8, L=1, seed=134)
+    loss_ref, g_ref = training_loss_and_grad(TensorNetOracle(blob), pos, z, batch, H, 1, E_ref, F_ref)
+    loss, _, _, grads, _ = _gpu(dev, blob, pos, z, batch, H, 1, E_ref, F_ref, "fp64")
+    _check("triclinic cell 300", "fp64", loss, grads, loss_ref, g_ref)
