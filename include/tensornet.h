@@ -53,7 +53,7 @@ typedef enum {
   TN_E_HIP = -3,        /* a HIP runtime call or kernel launch failed */
   TN_E_BOX = -4,        /* a cell height is less than twice the cutoff */
   TN_E_WORKSPACE = -5,  /* ws_bytes smaller than the workspace query returned */
-  TN_E_UNSUPPORTED = -6 /* valid request this build does not implement (e.g. precision/path pair) */
+  TN_E_UNSUPPORTED = -6 /* valid request this library does not implement (e.g. precision/path pair) */
 } tn_status;
 
 /* Bits of the device status word. */
