@@ -399,6 +399,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
   constexpr int L3 = 3 * F + kPad, L2 = 2 * F + kPad, L1 = F + kPad, LE = K + kPad;
   __shared__ __attribute__((aligned(16))) float sG[TILE * L3];
   __shared__ float sPhi[TILE], sDphi[TILE], sU[TILE][3], sDv[TILE][3];
+  __shared__ PairGeo sGeo[TILE];   // FP64 geometry for the final dE/dv, kept out of registers
   const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
   const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
   if (tile < 0) return;
@@ -407,8 +408,8 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
   const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
   constexpr int NWDE = K / 16;   // waves that own the dE/de accumulator (16 columns each)
 
-  PairGeo g{};
   if (tid < TILE) {
+    PairGeo g{};
     float ph = 0.f;
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
@@ -419,6 +420,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
     sU[tid][0] = (float)g.u[0];
     sU[tid][1] = (float)g.u[1];
     sU[tid][2] = (float)g.u[2];
+    sGeo[tid] = g;
   }
   __syncthreads();
   // embedding adjoint: dE/df0 -> sG, dE/dphi and dE/dvhat per pair
@@ -471,7 +473,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
     for_acc_rc(de, wave * 16, [&](int, int, int, int row, int col, float v) { sDE[row * LE + col] = v; });
   __syncthreads();
   if (tid < nvalid)
-    geometry_adjoint_rows<K>(g, sDE + tid * LE, 0, sDphi[tid], sDv[tid], a.alpha, a.r_lo, a.mu, a.beta,
+    geometry_adjoint_rows<K>(sGeo[tid], sDE + tid * LE, 0, sDphi[tid], sDv[tid], a.alpha, a.r_lo, a.mu, a.beta,
                              a.gpair + 3 * (p0 + tid));
 }
 
