@@ -282,15 +282,20 @@ inline int dmix(hipStream_t s, const Dual<S> *in, Dual<S> *out, int64_t N, int64
 // A(r, o) B(r, k), both dual: value A_v B_v, eps part A_d B_v + A_v B_d (three MFMA per
 // fragment).  64x64 outputs per block, 32 rows staged per step in LDS as [row][column] tiles
 // (coalesced along the feature axis); lane l of MFMA 16x16x4 supplies A(r0 + l/16, o0 + l%16)
-// and B(r0 + l/16, k0 + l%16).  Every block writes its outputs.
+// and B(r0 + l/16, k0 + l%16).  Every block writes its outputs.  With Q given, the blocks of
+// the first column block also form the column sums of A over the slice (the bias adjoint of
+// a linear map, from the tiles already in LDS): Q[z][o] = sum_r A(r, o), four row groups
+// per column combined in a fixed order.
 constexpr int WRC = 32;
 template <class S>
 __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma, const Dual<S> *B, RowMap mb,
                                                     int64_t R, const int64_t *Rdev, int O, int Kc, int64_t slice,
-                                                    Dual<S> *P) {
+                                                    Dual<S> *P, Dual<S> *Q) {
   using D = Dual<S>;
   using V = typename MfmaVec<S>::type;
   __shared__ S Av[WRC][64 + 1], Ad[WRC][64 + 1], Bv[WRC][64 + 1], Bd[WRC][64 + 1];
+  const bool colsum = Q != nullptr && blockIdx.x == 0;
+  S qv = S(0), qd = S(0);   // column (tid % 64), rows tid / 64 + 4 m of each staged step
   int64_t Rn = R;
   if (Rdev) {
     const int64_t md = *Rdev;
@@ -338,6 +343,13 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma,
     }
     __syncthreads();
     if (r0 + WRC < re) load_rows(r0 + WRC);
+    if (colsum) {
+#pragma unroll
+      for (int rr = tid >> 6; rr < WRC; rr += 4) {
+        qv += Av[rr][tid & 63];
+        qd += Ad[rr][tid & 63];
+      }
+    }
 #pragma unroll
     for (int s4 = 0; s4 < WRC; s4 += 4) {
       S bv[2], bd[2];
@@ -369,6 +381,15 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma,
         const int k = k0 + wk + 16 * b + r16;
         if (o < O && k < Kc) P[((int64_t)blockIdx.z * O + o) * Kc + k] = D(cv[a][b][t], cd[a][b][t]);
       }
+  if (colsum) {   // reuse the A tiles (every wave is past its last read of them)
+    Av[tid >> 6][tid & 63] = qv;
+    Ad[tid >> 6][tid & 63] = qd;
+    __syncthreads();
+    const int o = o0 + tid;
+    if (tid < 64 && o < O)
+      Q[(int64_t)blockIdx.z * O + o] = D(((Av[0][tid] + Av[1][tid]) + Av[2][tid]) + Av[3][tid],
+                                         ((Ad[0][tid] + Ad[1][tid]) + Ad[2][tid]) + Ad[3][tid]);
+  }
 }
 
 template <class T>
@@ -381,34 +402,39 @@ struct Reducer {
   int slices(int64_t R, int O, int Kc) const {
     const int64_t tiles = (int64_t)((O + 63) / 64) * ((Kc + 63) / 64);
     int64_t g = std::min<int64_t>((2048 + tiles - 1) / tiles, (R + 255) / 256);
-    g = std::min<int64_t>(g, std::min<int64_t>(kSlices, cap / ((int64_t)O * Kc)));
+    g = std::min<int64_t>(g, std::min<int64_t>(kSlices, cap / ((int64_t)O * (Kc + 1))));
     return (int)std::max<int64_t>(1, g);
   }
-  // C[o][k] (row stride ldc) += sum_r A(r, o) B(r, k), rows r < min(R, *Rdev)
+  // C[o][k] (row stride ldc) += sum_r A(r, o) B(r, k), rows r < min(R, *Rdev); with cb given
+  // also cb[o] += sum_r A(r, o)
   int wgrad(hipStream_t s, const T *A, RowMap ma, const T *B, RowMap mb, int64_t R, const int64_t *Rdev, int O,
-            int Kc, T *C, int64_t ldc) const {
+            int Kc, T *C, int64_t ldc, T *cb = nullptr) const {
     if (R <= 0 || O <= 0 || Kc <= 0) return TN_OK;
     const int G = slices(R, O, Kc);
-    if ((int64_t)G * O * Kc > cap) return TN_E_WORKSPACE;
+    if ((int64_t)G * O * (Kc + 1) > cap) return TN_E_WORKSPACE;
+    T *Q = cb ? part + (int64_t)G * O * Kc : nullptr;
     const int64_t slice = ((R + G - 1) / G + WRC - 1) / WRC * WRC;
     {
       TimedScope ts("train_wgrad", s);
       hipLaunchKernelGGL(k_wgrad_mfma<typename T::scalar>, dim3((unsigned)((Kc + 63) / 64),
                          (unsigned)((O + 63) / 64), (unsigned)G), dim3(256), 0, s, A, ma, B, mb, R, Rdev, O, Kc,
-                         slice, part);
+                         slice, part, Q);
       TN_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for((int64_t)O * Kc, 64)), dim3(256), 0, s, O, Kc, G,
                        (const T *)part, C, ldc);
     TN_LAUNCH_CHECK();
+    if (cb) {
+      hipLaunchKernelGGL(k_sum_slices<T>, dim3(grid_for(O, 64)), dim3(256), 0, s, 1, O, G, (const T *)Q, cb,
+                         (int64_t)O);
+      TN_LAUNCH_CHECK();
+    }
     return TN_OK;
   }
   // weight and bias of y = x W^T + b from the pre-activation adjoint dz
   int linear(hipStream_t s, const T *dz, const T *x, int64_t R, const int64_t *Rdev, int O, int Kin, T *dW,
              T *db) const {
-    int rc = wgrad(s, dz, rows_of(O), x, rows_of(Kin), R, Rdev, O, Kin, dW, Kin);
-    if (rc) return rc;
-    return coldot(s, dz, nullptr, nullptr, R, Rdev, O, db);
+    return wgrad(s, dz, rows_of(O), x, rows_of(Kin), R, Rdev, O, Kin, dW, Kin, db);
   }
   // out[c] += sum_r rs[r] A[r][c] B[r][c], rows r < min(R, *Rdev)
   int coldot(hipStream_t s, const T *A, const T *B, const T *rs, int64_t R, const int64_t *Rdev, int C,
@@ -426,6 +452,65 @@ struct Reducer {
     return TN_OK;
   }
 };
+
+// ---------------------------------------------------------------- dual messages
+// M_i (+)= sum over the CSR row of i of h_ij (per part) * Y_j on dual numbers, one wave per
+// atom: lane l holds channels V l .. V l + V - 1 (F = 64 V) and the row's indices are
+// wave-uniform, as in the FP32 gather kernels.
+template <class T, int V>
+__global__ void __launch_bounds__(256) k_message_dual_w(int64_t n, const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
+                                                        const int64_t *n_pairs, int64_t max_pairs,
+                                                        const T *__restrict__ h, const T *__restrict__ Y,
+                                                        T *__restrict__ M, int accumulate) {
+  constexpr int F = 64 * V;
+  const int32_t i = wave_atom();
+  if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
+  const int f = (threadIdx.x & 63) * V;
+  T c[9][V];
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int v = 0; v < V; ++v) c[q][v] = T(0);
+  const int32_t e1 = rowptr[i + 1];
+  for (int32_t e = rowptr[i]; e < e1; ++e) {
+    const int64_t j = nbr[e], p = pid[e];
+    T hh[3][V];
+#pragma unroll
+    for (int pt = 0; pt < 3; ++pt)
+#pragma unroll
+      for (int v = 0; v < V; ++v) hh[pt][v] = h[p * 3 * F + pt * F + f + v];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+#pragma unroll
+      for (int v = 0; v < V; ++v) c[q][v] += hh[coord_part(q)][v] * Y[j * 9 * F + q * F + f + v];
+  }
+  T *m = M + (int64_t)i * 9 * F + f;
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int v = 0; v < V; ++v) m[q * F + v] = accumulate ? m[q * F + v] + c[q][v] : c[q][v];
+}
+
+template <class T>
+inline int dmessage(hipStream_t s, int64_t N, int64_t F, const int32_t *rowptr, const int32_t *nbr, const int32_t *pid,
+                    const int64_t *np, int64_t MP, const T *h, const T *Y, T *M, int accumulate) {
+  if (N <= 0) return TN_OK;
+  if (F == 64 || F == 128 || F == 256) {
+    const dim3 grid(wave_atom_grid(N)), block(256);
+    if (F == 64)
+      hipLaunchKernelGGL((k_message_dual_w<T, 1>), grid, block, 0, s, N, rowptr, nbr, pid, np, MP, h, Y, M, accumulate);
+    else if (F == 128)
+      hipLaunchKernelGGL((k_message_dual_w<T, 2>), grid, block, 0, s, N, rowptr, nbr, pid, np, MP, h, Y, M, accumulate);
+    else
+      hipLaunchKernelGGL((k_message_dual_w<T, 4>), grid, block, 0, s, N, rowptr, nbr, pid, np, MP, h, Y, M, accumulate);
+  } else {
+    hipLaunchKernelGGL(k_message<T>, dim3(grid_for(N * F, 256)), dim3(256), 0, s, N, (int)F, rowptr, nbr, pid, np,
+                       MP, h, Y, M, accumulate);
+  }
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
 
 // ---------------------------------------------------------------- pass 1: loss and seeds
 // loss = w_E/S sum_s e_s^2 + w_F/(3N) sum f^2 with e = E - E*, f = F - F*;
@@ -657,8 +742,8 @@ static void plan_train(WsPlan &p, const tn_model *m, int64_t N, int64_t NS, int6
   w->dV = p.take<D>(Z * F);
   w->dUa = p.take<D>(N * F);
   w->dVa = p.take<D>(N * F);
-  // partial sums: up to 96 slices of the largest weight matrix (3F x 2F or 3F x K)
-  w->part_cap = std::max<int64_t>((int64_t)96 * std::max<int64_t>(6 * F * F, 3 * F * K), kColSlices * 3 * F);
+  // partial sums: up to 96 slices of the largest weight matrix (3F x 2F or 3F x K) and its bias
+  w->part_cap = std::max<int64_t>((int64_t)96 * (std::max<int64_t>(6 * F * F, 3 * F * K) + 3 * F), kColSlices * 3 * F);
   w->part = p.take<D>(w->part_cap);
   w->posD = p.take<D>(3 * N);
   w->geo = p.take<D>(4 * MP);
@@ -844,9 +929,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
     if ((rc = dlinear_fwd<S>(s, w.a2[l], MP, 2 * F, Wr(lo.Wc), Wr(lo.bc), 3 * F, w.h[l], w.z3[l], 1, w.phi, np)))
       return rc;
     if (N > 0) {
-      hipLaunchKernelGGL(k_message<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP,
-                         (const D *)w.h[l], (const D *)w.Y[l], w.M[l], 0);
-      TN_LAUNCH_CHECK();
+      if ((rc = dmessage<D>(s, N, F, rowptr, nbr, pid, np, MP, w.h[l], w.Y[l], w.M[l], 0))) return rc;
       hipLaunchKernelGGL(k_product<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Y[l], (const D *)w.M[l],
                          w.P[l], w.nP[l], w.Pb[l]);
       TN_LAUNCH_CHECK();
@@ -911,9 +994,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
       hipLaunchKernelGGL(k_product_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.dPb, (const D *)w.P[l],
                          (const D *)w.nP[l], (const D *)w.Y[l], (const D *)w.M[l], w.dY, w.dM);
       TN_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_message<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP,
-                         (const D *)w.h[l], (const D *)w.dM, w.dY, 1);
-      TN_LAUNCH_CHECK();
+      if ((rc = dmessage<D>(s, N, F, rowptr, nbr, pid, np, MP, w.h[l], w.dM, w.dY, 1))) return rc;
     }
     if (MP > 0) {
       hipLaunchKernelGGL(k_message_bwd_pair<D>, dim3(grid_for(MP * F, bs)), dim3(bs), 0, s, gr.pairs, MP, np, (int)F,
