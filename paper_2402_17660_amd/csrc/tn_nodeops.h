@@ -352,9 +352,11 @@ inline int mix(hipStream_t s, const T *in, T *out, int64_t N, int64_t F, const T
 // ============================================================================ element kernels
 __device__ inline bool pairs_ok(const int64_t *n_pairs, int64_t max_pairs) { return *n_pairs <= max_pairs; }
 
+// Pairs a pair-indexed kernel works on: all of them, or none after a pair overflow (the
+// neighbour search then leaves the internal pair list unwritten, so no entry may be read).
 __device__ inline int64_t pair_bound(const int64_t *n_pairs, int64_t max_pairs) {
   const int64_t P = *n_pairs;
-  return P < max_pairs ? P : max_pairs;
+  return P <= max_pairs ? P : 0;
 }
 
 __device__ inline int clamp_z(int32_t z, int max_z) { return z < 0 ? 0 : (z >= max_z ? max_z - 1 : z); }

@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_fwd(PairFwdArgs a) {
   __shared__ __attribute__((aligned(16))) float sE[TILE * LE];
   __shared__ __attribute__((aligned(16))) float sA[TILE * L2];
   __shared__ double sD[TILE], sPhi[TILE];
-  const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
+  const int64_t P = *a.n_pairs <= a.max_pairs ? *a.n_pairs : 0;   // no pair list after an overflow
   const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
   if (tile < 0) return;
   const int64_t p0 = tile * TILE;
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
   __shared__ __attribute__((aligned(16))) float sG[TILE * L3];
   __shared__ float sPhi[TILE], sDphi[TILE], sU[TILE][3], sDv[TILE][3];
   __shared__ PairGeo sGeo[TILE];   // FP64 geometry for the final dE/dv, kept out of registers
-  const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
+  const int64_t P = *a.n_pairs <= a.max_pairs ? *a.n_pairs : 0;   // no pair list after an overflow
   const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
   if (tile < 0) return;
   const int64_t p0 = tile * TILE;
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_fwd_bf16(PairFwdArgsB a) {
   __shared__ __attribute__((aligned(16))) __bf16 sA1[TILE * L1];
   __shared__ __attribute__((aligned(16))) __bf16 sA2[TILE * L2];
   __shared__ double sD[TILE], sPhi[TILE];
-  const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
+  const int64_t P = *a.n_pairs <= a.max_pairs ? *a.n_pairs : 0;   // no pair list after an overflow
   const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
   if (tile < 0) return;
   const int64_t p0 = tile * TILE;
@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
   static_assert(TILE * LE * 4 <= TILE * L3 * 2, "dE/de must fit in the adjoint buffer");
   __shared__ __attribute__((aligned(16))) __bf16 sG[TILE * L3];   // df0, dz3, dz2, dz1; finally dE/de (f32)
   __shared__ float sPhi[TILE], sDphi[TILE], sU[TILE][3], sDv[TILE][3];
-  const int64_t P = *a.n_pairs < a.max_pairs ? *a.n_pairs : a.max_pairs;
+  const int64_t P = *a.n_pairs <= a.max_pairs ? *a.n_pairs : 0;   // no pair list after an overflow
   const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
   if (tile < 0) return;
   const int64_t p0 = tile * TILE;

@@ -178,6 +178,25 @@ def test_overflow_and_bad_inputs_flagged(dev, cfg0):
     assert int(m.status.item()) & L.TN_STATUS_BATCH
 
 
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp32", "plain"), ("fp32", "fused"),
+                                            ("bf16", "fused")])
+def test_overflow_with_stale_workspace(dev, precision, path):
+    """After a pair overflow the internal pair list is never written; with a workspace full of
+    stale bytes every path must still finish and flag the overflow."""
+    m = TensorNet(small_blob(F=64, K=32, L=2, seed=21), dev)
+    pos, z = random_molecule(40, 22)
+    pdt = torch.float64 if precision == "fp64" else torch.float32
+    p = torch.tensor(pos, dtype=pdt, device=dev)
+    zt = torch.tensor(z, device=dev)
+    bt = torch.zeros(len(pos), dtype=torch.int32, device=dev)
+    m.energy_forces(p, zt, bt, 1, precision=precision, path=path)
+    m.ws.buf.fill_(0x7F)
+    m.energy_forces(p, zt, bt, 1, max_pairs=8, precision=precision, path=path, check=False)
+    torch.cuda.synchronize()
+    assert int(m.status.item()) & L.TN_STATUS_OVERFLOW
+    assert int(m.n_pairs.item()) > 8
+
+
 def test_autograd_function(dev, cfg0):
     c, blob, E_ref, F_ref = cfg0
     m = TensorNet(blob, dev)

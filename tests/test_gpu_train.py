@@ -184,3 +184,18 @@ def test_gradient_matches_oracle_triclinic_cell(dev):
     loss_ref, g_ref = training_loss_and_grad(TensorNetOracle(blob), pos, z, batch, H, 1, E_ref, F_ref)
     loss, _, _, grads, _ = _gpu(dev, blob, pos, z, batch, H, 1, E_ref, F_ref, "fp64")
     _check("triclinic cell 300", "fp64", loss, grads, loss_ref, g_ref)
+
+
+def test_pair_budget_overflow_is_flagged(dev):
+    """Too small a pair budget: the step returns, the status word carries the overflow bit."""
+    from paper_2402_17660_amd import TensorNetError
+    pos, z, batch, S, E_ref, F_ref, blob = _case((9, 14), 16, 8, 2, 3)
+    m = TensorNet(blob, dev)
+    t = lambda a, dt: torch.tensor(np.asarray(a), dtype=dt, device=dev)
+    m.train_grad(t(pos, torch.float64), t(z, torch.int32), t(batch, torch.int32), S, t(E_ref, torch.float64),
+                 t(F_ref, torch.float64), precision="fp64")
+    m.ws.buf.fill_(0x7F)   # stale workspace: no pair index may be read from it after an overflow
+    with pytest.raises(TensorNetError, match="pair overflow"):
+        m.train_grad(t(pos, torch.float64), t(z, torch.int32), t(batch, torch.int32), S, t(E_ref, torch.float64),
+                     t(F_ref, torch.float64), max_pairs=16, precision="fp64")
+    assert int(m.n_pairs.item()) > 16
