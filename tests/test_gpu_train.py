@@ -199,3 +199,20 @@ def test_pair_budget_overflow_is_flagged(dev):
         m.train_grad(t(pos, torch.float64), t(z, torch.int32), t(batch, torch.int32), S, t(E_ref, torch.float64),
                      t(F_ref, torch.float64), max_pairs=16, precision="fp64")
     assert int(m.n_pairs.item()) > 16
+
+
+def test_systems_without_pairs(dev):
+    """A one-atom system and a two-atom system farther apart than the cutoff sit between two
+    molecules: their energies depend on the species only, their forces are zero."""
+    parts = [random_molecule(12, 41), (np.zeros((1, 3)), np.array([6], np.int32)),
+             (np.array([[0.0, 0.0, 0.0], [6.0, 0.0, 0.0]]), np.array([1, 8], np.int32)), random_molecule(9, 42)]
+    pos = np.concatenate([p for p, _ in parts])
+    z = np.concatenate([q for _, q in parts]).astype(np.int32)
+    batch = np.concatenate([np.full(len(p), s, np.int32) for s, (p, _) in enumerate(parts)])
+    S = len(parts)
+    E_ref, F_ref = TensorNetOracle(small_blob(F=16, K=8, L=2, seed=43)).energy_forces(pos, z, batch, None, S)
+    blob = small_blob(F=16, K=8, L=2, seed=44)
+    loss_ref, g_ref = training_loss_and_grad(TensorNetOracle(blob), pos, z, batch, None, S, E_ref, F_ref)
+    for precision in ("fp64", "fp32"):
+        loss, _, _, grads, _ = _gpu(dev, blob, pos, z, batch, None, S, E_ref, F_ref, precision)
+        _check(f"systems without pairs {precision}", precision, loss, grads, loss_ref, g_ref)
