@@ -241,32 +241,39 @@ template <int F, int R, class TL, int NW = 4>
 __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const int32_t *pairs, int64_t max_pairs,
                                                    int64_t p0, int nvalid, const float (*sU)[3], const float *sPhi,
                                                    TL *lds, int ld, float *sDphi, float (*sDv)[3]) {
+#pragma clang fp contract(on)   // fused multiply-adds per expression only, so every tile shape rounds alike
   constexpr int V = F / 64, rows = R / NW;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int f = lane * V;
+  // the first atom's rows are reloaded only when it changes (pairs sorted by (i, j))
+  int64_t prev_i = -1;
+  float ci[9][V], Ui[V], Vi[V];
 #pragma unroll
   for (int rr = 0; rr < rows; ++rr) {
     const int row = wave * rows + rr;
     const bool valid = row < nvalid;
     const int64_t p = p0 + (valid ? row : 0);
     const int64_t i = pairs[p], j = pairs[max_pairs + p];
-    int zi = bg.z[i], zj = bg.z[j];
-    zi = zi < 0 ? 0 : (zi >= bg.max_z ? bg.max_z - 1 : zi);
+    if (i != prev_i) {
+      int zi = bg.z[i];
+      zi = zi < 0 ? 0 : (zi >= bg.max_z ? bg.max_z - 1 : zi);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) ldv<V>(bg.dXr + i * 9 * F + q * F + f, ci[q]);
+      ldv<V>(bg.U + zi * F + f, Ui);
+      ldv<V>(bg.V + zi * F + f, Vi);
+      prev_i = i;
+    }
+    int zj = bg.z[j];
     zj = zj < 0 ? 0 : (zj >= bg.max_z ? bg.max_z - 1 : zj);
     const float ux = sU[row][0], uy = sU[row][1], uz = sU[row][2];
     const float ph = sPhi[row];
     float s5[5];
     s0_coords(ux, uy, uz, s5);
-    const float *di = bg.dXr + i * 9 * F + f, *dj = bg.dXr + j * 9 * F + f;
-    float ci[9][V], cj[9][V], Ui[V], Uj[V], Vi[V], Vj[V], a[V], b[V], c[V];
+    const float *dj = bg.dXr + j * 9 * F + f;
+    float cj[9][V], Uj[V], Vj[V], a[V], b[V], c[V];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      ldv<V>(di + q * F, ci[q]);
-      ldv<V>(dj + q * F, cj[q]);
-    }
-    ldv<V>(bg.U + zi * F + f, Ui);
+    for (int q = 0; q < 9; ++q) ldv<V>(dj + q * F, cj[q]);
     ldv<V>(bg.U + zj * F + f, Uj);
-    ldv<V>(bg.V + zi * F + f, Vi);
     ldv<V>(bg.V + zj * F + f, Vj);
     ldv<V>(bg.f0 + p * 3 * F + f, a);
     ldv<V>(bg.f0 + p * 3 * F + F + f, b);
@@ -323,17 +330,29 @@ template <int F, int R, class TL, class TZ, int NW = 4>
 __device__ __forceinline__ void filter_adjoint_rows(const float *Y, const float *dM, const TZ *z3,
                                                     const int32_t *pairs, int64_t max_pairs, int64_t p0, int nvalid,
                                                     const float *sPhi, TL *lds, int ld, float *sDphi) {
+#pragma clang fp contract(on)   // fused multiply-adds per expression only, so every tile shape rounds alike
   constexpr int V = F / 64, rows = R / NW;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int f = lane * V;
+  // consecutive pairs mostly share their first atom (the list is sorted by (i, j)): its rows
+  // are reloaded only when i changes
+  int64_t prev_i = -1;
+  float yi[9][V], gi[9][V];
 #pragma unroll
   for (int rr = 0; rr < rows; ++rr) {
     const int row = wave * rows + rr;
     const bool valid = row < nvalid;
     const int64_t p = p0 + (valid ? row : 0);
     const int64_t i = pairs[p], j = pairs[max_pairs + p];
-    const float *yi = Y + i * 9 * F + f, *yj = Y + j * 9 * F + f, *gi = dM + i * 9 * F + f,
-                *gj = dM + j * 9 * F + f;
+    if (i != prev_i) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        ldv<V>(Y + i * 9 * F + q * F + f, yi[q]);
+        ldv<V>(dM + i * 9 * F + q * F + f, gi[q]);
+      }
+      prev_i = i;
+    }
+    const float *yj = Y + j * 9 * F + f, *gj = dM + j * 9 * F + f;
     const float ph = sPhi[row];
     float dh[3][V], zz[3][V];
 #pragma unroll
@@ -344,13 +363,11 @@ __device__ __forceinline__ void filter_adjoint_rows(const float *Y, const float 
     }
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      float a[V], b[V], c[V], d[V];
+      float a[V], d[V];
       ldv<V>(yj + q * F, a);
-      ldv<V>(gi + q * F, b);
-      ldv<V>(yi + q * F, c);
       ldv<V>(gj + q * F, d);
 #pragma unroll
-      for (int v = 0; v < V; ++v) dh[coord_part(q)][v] += a[v] * b[v] + c[v] * d[v];
+      for (int v = 0; v < V; ++v) dh[coord_part(q)][v] += a[v] * gi[q][v] + yi[q][v] * d[v];
     }
     float part = 0.f;
 #pragma unroll
