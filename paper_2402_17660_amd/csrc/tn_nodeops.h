@@ -155,63 +155,10 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
       }
 }
 
-// The same product with the same epilogue for arithmetic types that have no matrix-core
-// instruction (the dual numbers of the training step): one 16x16 output tile per block,
-// K staged through LDS in chunks of 16, one output per thread.
-template <class T>
-__global__ void __launch_bounds__(256) k_gemm_scalar(GemmArgs<T> g) {
-  __shared__ T As[16][17];
-  __shared__ T Bs[16][17];
-  int64_t Mrows = g.M;
-  if (g.Mdev) {
-    const int64_t md = *g.Mdev;
-    if (md < Mrows) Mrows = md;
-  }
-  const int64_t m0 = (int64_t)blockIdx.y * 16, n0 = (int64_t)blockIdx.x * 16;
-  if (m0 >= Mrows) return;
-  const int z = blockIdx.z;
-  const T *A = g.A + z * g.zoff;
-  const T *B = g.zpart ? g.Bz[coord_part(z)] : g.B;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  T acc = T(0);
-  for (int64_t k0 = 0; k0 < g.K; k0 += 16) {
-    {
-      const int64_t m = m0 + ty, k = k0 + tx;
-      As[ty][tx] = (m < Mrows && k < g.K) ? A[m * g.lda + k] : T(0);
-    }
-    {
-      const int64_t n = n0 + ty, k = k0 + tx;
-      T v = T(0);
-      if (n < g.N && k < g.K) v = g.transB ? B[n * g.ldb + k] : B[k * g.ldb + n];
-      Bs[ty][tx] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) acc += As[ty][kk] * Bs[tx][kk];
-    __syncthreads();
-  }
-  const int64_t m = m0 + ty, n = n0 + tx;
-  if (m >= Mrows || n >= g.N) return;
-  T v = acc;
-  if (g.bias) v += g.bias[n];
-  if (g.Z) g.Z[z * g.zoff + m * g.ldz + n] = v;
-  if (g.act == 1) v = silu(v);
-  if (g.rowscale) v *= g.rowscale[m];
-  if (g.gate) v *= silu_grad(g.gate[z * g.zoff + m * g.ldg + n]);
-  T *dst = g.C + z * g.zoff + m * g.ldc + n;
-  if (g.accumulate) *dst += v; else *dst = v;
-}
-
 // Products with few 64-row tiles (fewer than two per compute unit) use 32-row tiles.
 template <class T>
 inline int gemm(hipStream_t s, const GemmArgs<T> &g, int zdim = 1) {
   if (g.M <= 0 || g.N <= 0) return TN_OK;
-  if constexpr (!std::is_same<T, float>::value && !std::is_same<T, double>::value) {
-    dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 15) / 16), (unsigned)zdim);
-    hipLaunchKernelGGL(k_gemm_scalar<T>, grid, dim3(256), 0, s, g);
-    TN_LAUNCH_CHECK();
-    return TN_OK;
-  } else {
   const int64_t nb = (g.N + GBN - 1) / GBN;
   const int64_t tiles64 = nb * ((g.M + 63) / 64) * zdim;
   if (tiles64 < 512) {
@@ -223,7 +170,6 @@ inline int gemm(hipStream_t s, const GemmArgs<T> &g, int zdim = 1) {
   }
   TN_LAUNCH_CHECK();
   return TN_OK;
-  }
 }
 
 // y = act(x W^T + b) over rows of x; W is [Nout, Kin] (torch Linear layout).
