@@ -216,3 +216,28 @@ def test_systems_without_pairs(dev):
     for precision in ("fp64", "fp32"):
         loss, _, _, grads, _ = _gpu(dev, blob, pos, z, batch, None, S, E_ref, F_ref, precision)
         _check(f"systems without pairs {precision}", precision, loss, grads, loss_ref, g_ref)
+
+
+def test_training_step_in_a_hip_graph(dev):
+    """The step allocates nothing and never synchronises, so it can be captured: replays (with
+    eager work and synchronisation between them) reproduce the eager gradient bit for bit."""
+    pos, z, batch, S, E_ref, F_ref, blob = _case((12, 17, 23), 64, 16, 2, 13)
+    m = TensorNet(blob, dev)
+    t = lambda a, dt: torch.tensor(np.asarray(a), dtype=dt, device=dev)
+    args = (t(pos, torch.float32), t(z, torch.int32), t(batch, torch.int32), S, t(E_ref, torch.float64),
+            t(F_ref, torch.float64))
+    grad = torch.empty(m.param_count(), dtype=torch.float64, device=dev)
+    _, _, _, eager = m.train_grad(*args, precision="fp32")
+    eager = eager.clone()
+    m.train_grad(*args, precision="fp32", check=False, grad_out=grad)   # workspace sized before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        m.train_grad(*args, precision="fp32", check=False, grad_out=grad)
+    for _ in range(3):
+        grad.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        m.check()
+        assert torch.equal(grad, eager)
+        m.train_grad(args[0].double(), *args[1:], precision="fp64")   # eager work between replays
