@@ -5,7 +5,9 @@
  * search of Sec. 2.5.1 (cell list with rectangular or triclinic periodic
  * boundaries, or a brute-force search inside each system), the TensorNet network of
  * Sec. 2.1.1 with the hyper-parameters of Sec. 2.4, and forces as the negative
- * position gradient of the per-system energy (Sec. 2, model composition).
+ * position gradient of the per-system energy (Sec. 2, model composition); and
+ * the training step on energies and forces (Sec. 2.5, Sec. 3): the loss and its
+ * exact gradient with respect to every weight.
  *
  * Conventions shared by every entry point
  *   - Every array argument is a DEVICE pointer owned by the caller, except
