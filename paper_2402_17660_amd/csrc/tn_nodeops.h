@@ -1009,8 +1009,20 @@ __device__ __forceinline__ int32_t wave_atom() {
 
 inline unsigned wave_atom_grid(int64_t n) { return (unsigned)((n + 3) / 4); }
 
+// The gathers below split an atom's channels over G waves (F = 64 V G): wave g of the atom's
+// group owns channels (64 g + l) V .. +V-1.  More waves per atom keep more loads in flight
+// when there are few atoms per compute unit.
+template <int G>
+__device__ __forceinline__ int32_t group_atom() {
+  return __builtin_amdgcn_readfirstlane((int32_t)(xcd_block() * (4 / G) + (threadIdx.x >> 6) / G));
+}
+template <int V, int G>
+__device__ __forceinline__ int group_channel() {
+  return ((((int)threadIdx.x >> 6) % G) * 64 + ((int)threadIdx.x & 63)) * V;
+}
+
 // X_i = sum_j phi Z_ij (a 1 + b A0(u_ij) + c S0(u_ij))
-template <int V>
+template <int V, int G = 1>
 __global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t *__restrict__ rowptr,
                                                         const int32_t *__restrict__ nbr,
                                                         const int32_t *__restrict__ pid, const int64_t *n_pairs,
@@ -1018,10 +1030,10 @@ __global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t
                                                         const float *__restrict__ U, const float *__restrict__ Vt,
                                                         const float *__restrict__ geo, const float *__restrict__ phi,
                                                         const float *__restrict__ f0, float *__restrict__ X) {
-  constexpr int F = 64 * V;
-  const int32_t i = wave_atom();
+  constexpr int F = 64 * V * G;
+  const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  const int f = (threadIdx.x & 63) * V;
+  const int f = group_channel<V, G>();
   float ui[V];
   ldv<V>(U + (int64_t)clamp_z(z[i], max_z) * F + f, ui);
   float c[9][V];
@@ -1061,12 +1073,12 @@ __global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t
 }
 
 // c[q] = sum over the CSR row of i of h_part(q)(pair) * Y_j[q]
-template <int V>
+template <int V, int G>
 __device__ __forceinline__ void gather_message(int32_t i, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
                                                const float *__restrict__ h, const float *__restrict__ Y, int f,
                                                float (&c)[9][V]) {
-  constexpr int F = 64 * V;
+  constexpr int F = 64 * V * G;
 #pragma unroll
   for (int q = 0; q < 9; ++q)
 #pragma unroll
@@ -1088,18 +1100,18 @@ __device__ __forceinline__ void gather_message(int32_t i, const int32_t *__restr
 }
 
 // M_i (+)= sum_j h_part(c)(d_ij) * Y_j[c]
-template <int V>
+template <int V, int G = 1>
 __global__ void __launch_bounds__(256) k_message_w(int64_t n, const int32_t *__restrict__ rowptr,
                                                    const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
                                                    const int64_t *n_pairs, int64_t max_pairs,
                                                    const float *__restrict__ h, const float *__restrict__ Y,
                                                    float *__restrict__ M, int accumulate) {
-  constexpr int F = 64 * V;
-  const int32_t i = wave_atom();
+  constexpr int F = 64 * V * G;
+  const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  const int f = (threadIdx.x & 63) * V;
+  const int f = group_channel<V, G>();
   float c[9][V];
-  gather_message<V>(i, rowptr, nbr, pid, h, Y, f, c);
+  gather_message<V, G>(i, rowptr, nbr, pid, h, Y, f, c);
   float *m = M + (int64_t)i * 9 * F + f;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -1114,7 +1126,7 @@ __global__ void __launch_bounds__(256) k_message_w(int64_t n, const int32_t *__r
 }
 
 // M_i = sum_j h_part(c) * Y_j[c]; P = Y M + M Y; Pb = P / (||P|| + 1).  Writes M, P, ||P||, Pb.
-template <int V>
+template <int V, int G = 1>
 __global__ void __launch_bounds__(256) k_message_product_w(int64_t n, const int32_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ nbr,
                                                            const int32_t *__restrict__ pid, const int64_t *n_pairs,
@@ -1122,12 +1134,12 @@ __global__ void __launch_bounds__(256) k_message_product_w(int64_t n, const int3
                                                            const float *__restrict__ Y, float *__restrict__ M,
                                                            float *__restrict__ P, float *__restrict__ nP,
                                                            float *__restrict__ Pb) {
-  constexpr int F = 64 * V;
-  const int32_t i = wave_atom();
+  constexpr int F = 64 * V * G;
+  const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  const int f = (threadIdx.x & 63) * V;
+  const int f = group_channel<V, G>();
   float mc[9][V], yc[9][V];
-  gather_message<V>(i, rowptr, nbr, pid, h, Y, f, mc);
+  gather_message<V, G>(i, rowptr, nbr, pid, h, Y, f, mc);
   const int64_t base = (int64_t)i * 9 * F + f;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -1206,18 +1218,19 @@ __global__ void __launch_bounds__(256) k_force_gather_w(int64_t n, const int32_t
   }
 }
 
-// Launch one of the wave-per-atom kernels above for F = 64 V (V = 1, 2, 4).
+// Launch one of the wave-per-atom gathers above: F = 64 one wave per atom; F = 128 and 256
+// two waves per atom with V = F/128 channels per lane.
 #define TN_WAVE_GATHER_LAUNCHER(NAME, KERNEL)                                                   \
   template <class... A>                                                                         \
   inline int NAME(hipStream_t s, int64_t F, int64_t n, A... a) {                                \
     if (n <= 0) return TN_OK;                                                                   \
-    const dim3 g(wave_atom_grid(n)), b(256);                                                    \
+    const dim3 b(256);                                                                          \
     if (F == 64)                                                                                \
-      hipLaunchKernelGGL(KERNEL<1>, g, b, 0, s, n, a...);                                       \
+      hipLaunchKernelGGL((KERNEL<1, 1>), dim3(wave_atom_grid(n)), b, 0, s, n, a...);           \
     else if (F == 128)                                                                          \
-      hipLaunchKernelGGL(KERNEL<2>, g, b, 0, s, n, a...);                                       \
+      hipLaunchKernelGGL((KERNEL<1, 2>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, a...);       \
     else if (F == 256)                                                                          \
-      hipLaunchKernelGGL(KERNEL<4>, g, b, 0, s, n, a...);                                       \
+      hipLaunchKernelGGL((KERNEL<2, 2>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, a...);       \
     else                                                                                        \
       return TN_E_UNSUPPORTED;                                                                  \
     TN_LAUNCH_CHECK();                                                                          \
