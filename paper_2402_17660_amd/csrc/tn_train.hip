@@ -454,19 +454,19 @@ struct Reducer {
 };
 
 // ---------------------------------------------------------------- dual messages
-// M_i (+)= sum over the CSR row of i of h_ij (per part) * Y_j on dual numbers, one wave per
-// atom: lane l holds channels V l .. V l + V - 1 (F = 64 V) and the row's indices are
-// wave-uniform, as in the FP32 gather kernels.
-template <class T, int V>
+// M_i (+)= sum over the CSR row of i of h_ij (per part) * Y_j on dual numbers, G waves per
+// atom: lane l of wave g holds channels (64 g + l) V .. +V-1 (F = 64 V G) and the row's
+// indices are wave-uniform, as in the FP32 gather kernels.
+template <class T, int V, int G>
 __global__ void __launch_bounds__(256) k_message_dual_w(int64_t n, const int32_t *__restrict__ rowptr,
                                                         const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
                                                         const int64_t *n_pairs, int64_t max_pairs,
                                                         const T *__restrict__ h, const T *__restrict__ Y,
                                                         T *__restrict__ M, int accumulate) {
-  constexpr int F = 64 * V;
-  const int32_t i = wave_atom();
+  constexpr int F = 64 * V * G;
+  const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  const int f = (threadIdx.x & 63) * V;
+  const int f = group_channel<V, G>();
   T c[9][V];
 #pragma unroll
   for (int q = 0; q < 9; ++q)
@@ -497,13 +497,16 @@ inline int dmessage(hipStream_t s, int64_t N, int64_t F, const int32_t *rowptr, 
                     const int64_t *np, int64_t MP, const T *h, const T *Y, T *M, int accumulate) {
   if (N <= 0) return TN_OK;
   if (F == 64 || F == 128 || F == 256) {
-    const dim3 grid(wave_atom_grid(N)), block(256);
+    const dim3 block(256);
     if (F == 64)
-      hipLaunchKernelGGL((k_message_dual_w<T, 1>), grid, block, 0, s, N, rowptr, nbr, pid, np, MP, h, Y, M, accumulate);
+      hipLaunchKernelGGL((k_message_dual_w<T, 1, 1>), dim3(wave_atom_grid(N)), block, 0, s, N, rowptr, nbr, pid, np,
+                         MP, h, Y, M, accumulate);
     else if (F == 128)
-      hipLaunchKernelGGL((k_message_dual_w<T, 2>), grid, block, 0, s, N, rowptr, nbr, pid, np, MP, h, Y, M, accumulate);
+      hipLaunchKernelGGL((k_message_dual_w<T, 1, 2>), dim3(wave_atom_grid(2 * N)), block, 0, s, N, rowptr, nbr, pid,
+                         np, MP, h, Y, M, accumulate);
     else
-      hipLaunchKernelGGL((k_message_dual_w<T, 4>), grid, block, 0, s, N, rowptr, nbr, pid, np, MP, h, Y, M, accumulate);
+      hipLaunchKernelGGL((k_message_dual_w<T, 2, 2>), dim3(wave_atom_grid(2 * N)), block, 0, s, N, rowptr, nbr, pid,
+                         np, MP, h, Y, M, accumulate);
   } else {
     hipLaunchKernelGGL(k_message<T>, dim3(grid_for(N * F, 256)), dim3(256), 0, s, N, (int)F, rowptr, nbr, pid, np,
                        MP, h, Y, M, accumulate);
