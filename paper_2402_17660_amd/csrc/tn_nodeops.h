@@ -194,13 +194,14 @@ inline int linear_bwd(hipStream_t s, const T *dy, int64_t M, int64_t Nout, const
   return gemm(s, g);
 }
 
-// FP32 channel mixing on the matrix cores.  A block stages 16 atoms x 9 coordinates x F
-// channels (contiguous in memory) in LDS with padded rows and computes 64*NB output channels;
-// each of the four waves takes 16*NB of them for the 1 + 3 + 5 coordinate rows of the I, A and S
-// parts, so one weight fragment feeds every coordinate of its part.  Bt[p] is the [F][F] matrix
-// whose row n holds the input weights of output channel n (W_p itself for the forward mixing,
-// its transpose for the adjoint).  Tiles are numbered so that consecutive tiles, which share
-// the same 16 atoms, are dispatched to the same XCD.
+// FP32 channel mixing on the matrix cores.  A block takes one part (I, A or S: 1, 3 or 5
+// coordinates) of 16 atoms, stages those coordinates (contiguous per atom, F channels each)
+// in LDS with padded rows, and computes 64*NB output channels; each of the four waves takes
+// 16*NB of them for the part's coordinate rows, so one weight fragment feeds every
+// coordinate of the part.  Bt[p] is the [F][F] matrix whose row n holds the input weights of
+// output channel n (W_p itself for the forward mixing, its transpose for the adjoint).
+// Blocks are numbered so that the column blocks and parts of the same 16 atoms are
+// dispatched to the same XCD.
 template <int F, int NB>
 __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float *__restrict__ out, int64_t N,
                                              const float *__restrict__ B0, const float *__restrict__ B1,
@@ -208,62 +209,63 @@ __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float
                                              int64_t ntiles) {
   constexpr int LD = F + 4;
   constexpr int KC = F / 16;
-  // the three parts' weight fragments stay in registers when they fit (F <= 128)
-  constexpr bool kBreg = 3 * KC * NB * 4 <= 96;
-  __shared__ __attribute__((aligned(16))) float sA[16 * 9 * LD];
+  // this wave's weight fragments of its part stay in registers when they fit
+  constexpr bool kBreg = KC * NB * 4 <= 64;
+  __shared__ __attribute__((aligned(16))) float sA[16 * 5 * LD];
   const int64_t per_xcd = (int64_t)gridDim.x / 8;
   const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= ntiles) return;
-  const int64_t a0 = (t / ncb) * 16;
-  const int cblk = (int)(t % ncb);
+  const int64_t a0 = (t / (3 * ncb)) * 16;
+  const int part = (int)(t % 3);
+  const int cblk = (int)((t / 3) % ncb);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col0 = cblk * 64 * NB + wave * 16 * NB;
-  float4 bI[kBreg ? KC : 1][NB], bA[kBreg ? KC : 1][NB], bS[kBreg ? KC : 1][NB];
-  if constexpr (kBreg) {   // issued before the tile staging so the two overlap
-    load_bfrag<NB, KC>(B0, F, col0, bI);
-    load_bfrag<NB, KC>(B1, F, col0, bA);
-    load_bfrag<NB, KC>(B2, F, col0, bS);
-  }
   const int64_t navail = N - a0 < 16 ? N - a0 : 16;
-  const float4 *src = reinterpret_cast<const float4 *>(in + a0 * 9 * F);
-  for (int e = threadIdx.x; e < 16 * 9 * (F / 4); e += 256) {
-    const int row = e / (F / 4), c4 = e % (F / 4);
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (row / 9 < navail) v = src[e];
-    *reinterpret_cast<float4 *>(sA + row * LD + 4 * c4) = v;
-  }
-  __syncthreads();
   const int r16 = lane & 15, q = lane >> 4;
-  auto part = [&](auto c0_tag, auto nc_tag, const float *Bt, const auto &breg) {
+  auto run = [&](auto c0_tag, auto nc_tag, const float *Bt) {
     constexpr int C0 = decltype(c0_tag)::value, NC = decltype(nc_tag)::value;
+    float4 breg[kBreg ? KC : 1][NB];
+    if constexpr (kBreg) load_bfrag<NB, KC>(Bt, F, col0, breg);   // overlaps the staging below
+    const float4 *src = reinterpret_cast<const float4 *>(in + a0 * 9 * F);
+    for (int e = threadIdx.x; e < 16 * NC * (F / 4); e += 256) {
+      const int row = e / (F / 4), c4 = e % (F / 4);   // row = atom * NC + coordinate
+      const int at = row / NC, cc = row % NC;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (at < navail) v = src[(at * 9 + C0 + cc) * (F / 4) + c4];
+      *reinterpret_cast<float4 *>(sA + row * LD + 4 * c4) = v;
+    }
+    __syncthreads();
     floatx4 acc[NC][NB];
     zero_acc_rb<NC, NB>(acc);
     if constexpr (kBreg)
-      wave_mm_rows_breg<NC, NB, KC>(sA + C0 * LD, 9 * LD, LD, breg, acc);
+      wave_mm_rows_breg<NC, NB, KC>(sA, NC * LD, LD, breg, acc);
     else
-      wave_mm_rows<NC, NB>(sA + C0 * LD, 9 * LD, LD, F, Bt, col0, acc);
+      wave_mm_rows<NC, NB>(sA, NC * LD, LD, F, Bt, col0, acc);
 #pragma unroll
     for (int rb = 0; rb < NC; ++rb)
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int a = 4 * q + e;
-          if (a >= navail) continue;
-          float *dst = out + ((a0 + a) * 9 + C0 + rb) * F + col0 + cb * 16 + r16;
+          const int at = 4 * q + e;
+          if (at >= navail) continue;
+          float *dst = out + ((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16;
           if (accumulate) *dst += acc[rb][cb][e]; else *dst = acc[rb][cb][e];
         }
   };
-  part(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}, B0, bI);
-  part(std::integral_constant<int, 1>{}, std::integral_constant<int, 3>{}, B1, bA);
-  part(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2, bS);
+  if (part == 0)
+    run(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}, B0);
+  else if (part == 1)
+    run(std::integral_constant<int, 1>{}, std::integral_constant<int, 3>{}, B1);
+  else
+    run(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2);
 }
 
 template <int F, int NB>
 inline int launch_mix(hipStream_t s, const float *in, float *out, int64_t N, const float *const Bt[3],
                       int accumulate) {
   constexpr int ncb = F / (64 * NB);
-  const int64_t ntiles = (N + 15) / 16 * ncb;
+  const int64_t ntiles = (N + 15) / 16 * ncb * 3;
   const int64_t grid = (ntiles + 7) / 8 * 8;
   hipLaunchKernelGGL((k_mix<F, NB>), dim3((unsigned)grid), dim3(256), 0, s, in, out, N, Bt[0], Bt[1], Bt[2],
                      accumulate, ncb, ntiles);
