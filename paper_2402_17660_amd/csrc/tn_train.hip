@@ -718,7 +718,7 @@ struct TrainWs {
   D *wD, *gD, *dU, *dV, *dUa, *dVa, *part, *posD;
   D *geo, *phi, *rbf, *f0, *Xr, *T0, *nrm0, *xhat0, *rstd0, *n0, *ez1, *ea1, *ez2, *g;
   std::vector<D *> X, nX, Xb, Y, z1, a1, z2, a2, z3, h, M, P, nP, Pb, Dl;
-  D *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps;
+  D *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx;
   D *dX, *dD, *dPb, *dY, *dM, *dXr, *dT0, *dg, *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
   D *dh, *dz3, *dz2, *dz1, *dphi, *dvhat, *df0, *dZ;
   int64_t part_cap = 0;
@@ -791,7 +791,6 @@ static void plan_train(WsPlan &p, const tn_model *m, int64_t N, int64_t NS, int6
   w->ox = p.take<D>(N * F);
   w->hz = p.take<D>(N * (F / 2));
   w->hx = p.take<D>(N * (F / 2));
-  w->eps = p.take<D>(N);
   w->dX = p.take<D>(N * 9 * F);
   w->dD = p.take<D>(N * 9 * F);
   w->dPb = p.take<D>(N * 9 * F);
