@@ -155,13 +155,15 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
       }
 }
 
-// Products with few 64-row tiles (fewer than two per compute unit) use 32-row tiles.
+// Products with few 64-row tiles use 32-row tiles: fewer than two per compute unit in FP32,
+// fewer than eight in FP64 (whose matrix instructions take twice as long, so a 64-row tile
+// keeps a compute unit busy twice as long).
 template <class T>
 inline int gemm(hipStream_t s, const GemmArgs<T> &g, int zdim = 1) {
   if (g.M <= 0 || g.N <= 0) return TN_OK;
   const int64_t nb = (g.N + GBN - 1) / GBN;
   const int64_t tiles64 = nb * ((g.M + 63) / 64) * zdim;
-  if (tiles64 < 512) {
+  if (tiles64 < (sizeof(T) == 8 ? 2048 : 512)) {
     dim3 grid((unsigned)nb, (unsigned)((g.M + 31) / 32), (unsigned)zdim);
     hipLaunchKernelGGL((k_gemm_mfma<T, 32>), grid, dim3(256), 0, s, g);
   } else {
