@@ -148,7 +148,7 @@ def main():
             run()
             model.check()
             # pick the pair-tile shapes for this workload (setup, outside the timed region)
-            shapes = (model.autotune(pos, z, batch, 1, box=box, max_pairs=max_pairs, precision=prec, reps=5)
+            shapes = (model.autotune(pos, z, batch, 1, box=box, max_pairs=max_pairs, precision=prec, reps=10)
                       if path == "fused" else None)
         except TensorNetError as e:
             log(f"{path}/{prec}: unavailable ({e})")
