@@ -668,24 +668,33 @@ __global__ void k_out_final(int64_t n, int H, const T *hx, const T *w, const T *
   eps[i] = s;
 }
 
+// First index i in [0, n) with batch[i] >= key (n if none) for a sorted batch vector, found by
+// the whole block: each round probes blockDim.x evenly spaced entries at once and keeps the gap
+// where the comparison changes, so a few thousand atoms take two rounds of parallel loads
+// instead of a dozen dependent ones.  Every thread of the block must call it.
+__device__ inline int64_t block_lower_bound(const int32_t *batch, int64_t n, int32_t key) {
+  int64_t a = 0, e = n;   // the answer lies in [a, e]
+  while (a < e) {
+    const int64_t step = (e - a + blockDim.x - 1) / blockDim.x;
+    const int64_t p = a + (int64_t)threadIdx.x * step;
+    const int c = __syncthreads_count(p < e && batch[p] < key);   // the true probes form a prefix
+    if (c == 0) break;                                              // batch[a] >= key
+    const int64_t last = a + (int64_t)(c - 1) * step;               // batch[last] < key
+    const int64_t next = a + (int64_t)c * step;                     // batch[next] >= key, or past e
+    a = last + 1;
+    if (next < e) e = next;
+  }
+  return a;
+}
+
 // E_s = sum over the (contiguous) atoms of system s, in FP64; one block per system.
 template <class T>
 __global__ void __launch_bounds__(128) k_energy_reduce(int64_t n, const T *eps, const int32_t *batch, double *E,
                                                        int32_t *status) {
   __shared__ double lds[128];
   const int32_t s = blockIdx.x;
-  int64_t a = 0, e = n;
-  while (a < e) {
-    const int64_t m = (a + e) >> 1;
-    if (batch[m] < s) a = m + 1; else e = m;
-  }
-  const int64_t lo = a;
-  e = n;
-  while (a < e) {
-    const int64_t m = (a + e) >> 1;
-    if (batch[m] <= s) a = m + 1; else e = m;
-  }
-  const int64_t hi = a;
+  const int64_t lo = block_lower_bound(batch, n, s);
+  const int64_t hi = block_lower_bound(batch, n, s + 1);
   double acc = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += 128) acc += (double)eps[i];
   const double tot = block_sum(acc, lds);
