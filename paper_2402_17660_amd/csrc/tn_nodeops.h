@@ -413,7 +413,8 @@ __device__ inline T block_sum(T v, T *lds) {
   return r;
 }
 
-// LayerNorm over rows of length C (population variance, eps 1e-5, affine g/b).
+// LayerNorm over rows of length C (population variance, eps 1e-5, affine g/b); one block per
+// row, launched with one wave (blockDim.x a power of two up to 128).
 template <class T>
 __global__ void __launch_bounds__(128) k_layernorm(int64_t rows, int C, const T *x, const T *gmul, const T *badd,
                                                    T *y, T *xhat, T *rstd) {
@@ -421,16 +422,16 @@ __global__ void __launch_bounds__(128) k_layernorm(int64_t rows, int C, const T 
   const int64_t r = blockIdx.x;
   if (r >= rows) return;
   T s = T(0);
-  for (int k = threadIdx.x; k < C; k += 128) s += x[r * C + k];
+  for (int k = threadIdx.x; k < C; k += blockDim.x) s += x[r * C + k];
   const T mean = block_sum(s, lds) / T(C);
   T v = T(0);
-  for (int k = threadIdx.x; k < C; k += 128) {
+  for (int k = threadIdx.x; k < C; k += blockDim.x) {
     const T d = x[r * C + k] - mean;
     v += d * d;
   }
   const T var = block_sum(v, lds) / T(C);
   const T rs = T(1) / dsqrt(var + T(1e-5));
-  for (int k = threadIdx.x; k < C; k += 128) {
+  for (int k = threadIdx.x; k < C; k += blockDim.x) {
     const T h = (x[r * C + k] - mean) * rs;
     xhat[r * C + k] = h;
     y[r * C + k] = h * gmul[k] + badd[k];
@@ -446,7 +447,7 @@ __global__ void __launch_bounds__(128) k_layernorm_bwd(int64_t rows, int C, cons
   const int64_t r = blockIdx.x;
   if (r >= rows) return;
   T s1 = T(0), s2 = T(0);
-  for (int k = threadIdx.x; k < C; k += 128) {
+  for (int k = threadIdx.x; k < C; k += blockDim.x) {
     const T gd = gmul[k] * dy[r * C + k];
     s1 += gd;
     s2 += gd * xhat[r * C + k];
@@ -454,7 +455,7 @@ __global__ void __launch_bounds__(128) k_layernorm_bwd(int64_t rows, int C, cons
   const T m1 = block_sum(s1, lds) / T(C);
   const T m2 = block_sum(s2, lds) / T(C);
   const T rs = rstd[r];
-  for (int k = threadIdx.x; k < C; k += 128)
+  for (int k = threadIdx.x; k < C; k += blockDim.x)
     dx[r * C + k] = rs * (gmul[k] * dy[r * C + k] - m1 - xhat[r * C + k] * m2);
 }
 
@@ -659,14 +660,6 @@ __global__ void k_out_norms(int64_t n, int F, const TX *X, T *on) {
 }
 
 // eps_i = w . hx_i + b (final scalar of the output network)
-template <class T>
-__global__ void k_out_final(int64_t n, int H, const T *hx, const T *w, const T *b, T *eps) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  T s = b[0];
-  for (int k = 0; k < H; ++k) s += w[k] * hx[i * H + k];
-  eps[i] = s;
-}
 
 // First index i in [0, n) with batch[i] >= key (n if none) for a sorted batch vector, found by
 // the whole block: each round probes blockDim.x evenly spaced entries at once and keeps the gap
@@ -1196,6 +1189,21 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// eps_i = w . hx_i + b, one wave per atom: lanes stride over the H hidden units, then a fixed
+// butterfly sums the lanes (the output layer's per-atom dot products, FP64).
+template <class T>
+__global__ void __launch_bounds__(256) k_out_final_w(int64_t n, int H, const T *__restrict__ hx,
+                                                     const T *__restrict__ w, const T *__restrict__ b,
+                                                     T *__restrict__ eps) {
+  const int32_t i = wave_atom();
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0;
+  for (int k = lane; k < H; k += 64) acc += w[k] * hx[(int64_t)i * H + k];
+  acc = wave_sum_d(acc);
+  if (lane == 0) eps[i] = acc + b[0];
 }
 
 // F_i = sum over the CSR row of i of +-g_pair in FP64: lanes stride over the row, then a fixed
