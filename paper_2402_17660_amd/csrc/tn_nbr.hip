@@ -397,8 +397,13 @@ __device__ inline void system_range(const int32_t *batch, int64_t n, int32_t bv,
 // unsorted batch sets TN_STATUS_BATCH, which the candidate sweep reads as "search all atoms".
 template <class T>
 __global__ void k_validate(const T *pos, const int32_t *z, const int32_t *batch, int64_t n, int64_t n_systems,
-                           int max_z, int check_pos, int32_t *status) {
+                           int max_z, int check_pos, int32_t *status, int32_t *zero_a, int64_t na, int32_t *zero_b,
+                           int64_t nb) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // also clears the cell list's counters for the kernels that follow (saves two launches)
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < na; k += stride) zero_a[k] = 0;
+  for (int64_t k = i; k < nb; k += stride) zero_b[k] = 0;
   if (i >= n) return;
   const int32_t b = batch[i];
   if (i > 0 && b < batch[i - 1]) set_status(status, TN_STATUS_BATCH);
@@ -674,15 +679,16 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, co
   out.z = z;
   out.batch = batch;
   out.perm = nullptr;
+  const int64_t ncell = bi.cells ? (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2] : 0;
   if (n > 0) {   // the cell binning checks the positions itself
     hipLaunchKernelGGL(k_validate<T>, dim3(g), dim3(blk), 0, s, pos, z, batch, n, n_systems, max_z,
-                       bi.cells ? 0 : 1, status);
+                       bi.cells ? 0 : 1, status, w.cell_count, bi.cells ? ncell + 1 : 0, w.cell_fill, ncell);
     TN_LAUNCH_CHECK();
-  }
-  if (bi.cells) {
-    const int64_t ncell = (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2];
+  } else if (bi.cells) {
     if ((rc = fill_i32(s, w.cell_count, ncell + 1, 0))) return rc;
     if ((rc = fill_i32(s, w.cell_fill, ncell, 0))) return rc;
+  }
+  if (bi.cells) {
     if (n > 0) {
       hipLaunchKernelGGL(k_cell_assign<T>, dim3(g), dim3(blk), 0, s, pos, n, b, w.cell_of, w.cell_count, status);
       TN_LAUNCH_CHECK();
