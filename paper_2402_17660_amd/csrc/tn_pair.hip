@@ -209,10 +209,27 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_fwd(PairFwdArgs a) {
 // are reduced across the wave.  Rows past the tile's valid count read the tile's first pair
 // and store zeros, so the row loop has no branches and its loads can overlap.
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 64 lanes of a wave, returned wave-uniform.  Inside each row of 16 lanes the
+// partners are swapped by DPP (xor 1 and xor 2 inside a quad, then the mirror inside each half
+// row and inside the row), so every lane of a row ends with the same row sum; the four row sums
+// are then added in a fixed order.  The order does not depend on the caller, so every tile
+// shape rounds alike.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  const int b = __builtin_bit_cast(int, v);
+  const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 0));
+  const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 16));
+  const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 32));
+  const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 48));
+  return (r0 + r1) + (r2 + r3);
 }
 
 template <class TL, int V>
@@ -235,9 +252,50 @@ __device__ __forceinline__ void ld_row(const TZ *p, float (&o)[V]) {
   }
 }
 
+// The pair indices of this wave's rows, read once at the start of a prologue (rows past the
+// tile's valid count take the tile's first pair).
+template <int rows>
+__device__ __forceinline__ int64_t wave_row_pair(int64_t p0, int nvalid, int wave, int rr) {
+  const int row = wave * rows + rr;
+  return p0 + (row < nvalid ? row : 0);
+}
+
+template <int rows>
+__device__ __forceinline__ void wave_pair_rows(const int32_t *pairs, int64_t max_pairs, int64_t p0, int nvalid,
+                                               int wave, int32_t (&pi)[rows], int32_t (&pj)[rows]) {
+#pragma unroll
+  for (int rr = 0; rr < rows; ++rr) {
+    const int64_t p = wave_row_pair<rows>(p0, nvalid, wave, rr);
+    pi[rr] = pairs[p];
+    pj[rr] = pairs[max_pairs + p];
+  }
+}
+
+// The second atom's rows and the pair's f0 for the embedding adjoint.  The atom rows ("near":
+// mostly cache hits) and the pair's row ("far": written by the forward pass, read from HBM) can
+// be loaded one row ahead separately.
+template <int F>
+struct EmbedRowJ {
+  static constexpr int V = F / 64;
+  float c[9][V], U[V], W[V], a[V], b[V], cc[V];
+  __device__ __forceinline__ void load_near(const BwdGather &bg, int64_t j, int f) {
+    int zj = bg.z[j];
+    zj = zj < 0 ? 0 : (zj >= bg.max_z ? bg.max_z - 1 : zj);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ldv<V>(bg.dXr + j * 9 * F + q * F + f, c[q]);
+    ldv<V>(bg.U + zj * F + f, U);
+    ldv<V>(bg.V + zj * F + f, W);
+  }
+  __device__ __forceinline__ void load_far(const BwdGather &bg, int64_t p, int f) {
+    ldv<V>(bg.f0 + p * 3 * F + f, a);
+    ldv<V>(bg.f0 + p * 3 * F + F + f, b);
+    ldv<V>(bg.f0 + p * 3 * F + 2 * F + f, cc);
+  }
+};
+
 // dE/df0 = (da, db, dc) for both directions of the pair -> lds[row][0..3F); returns the pair's
 // dE/dphi and dE/dvhat (embedding part) through the per-row LDS arrays.
-template <int F, int R, class TL, int NW = 4>
+template <int F, int R, class TL, int NW = 4, int PF = 2>
 __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const int32_t *pairs, int64_t max_pairs,
                                                    int64_t p0, int nvalid, const float (*sU)[3], const float *sPhi,
                                                    TL *lds, int ld, float *sDphi, float (*sDv)[3]) {
@@ -245,15 +303,21 @@ __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const in
   constexpr int V = F / 64, rows = R / NW;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int f = lane * V;
-  // the first atom's rows are reloaded only when it changes (pairs sorted by (i, j))
+  int32_t pi[rows], pj[rows];
+  wave_pair_rows<rows>(pairs, max_pairs, p0, nvalid, wave, pi, pj);
+  // the first atom's rows are reloaded only when it changes (pairs sorted by (i, j)); the next
+  // row's pair row (PF >= 1, 6 registers per lane) and atom rows (PF = 2, about 25 more) are
+  // loaded one row ahead so that their latency overlaps a row's work
   int64_t prev_i = -1;
   float ci[9][V], Ui[V], Vi[V];
+  EmbedRowJ<F> nxt;
+  if constexpr (PF >= 1) nxt.load_far(bg, wave_row_pair<rows>(p0, nvalid, wave, 0), f);
+  if constexpr (PF >= 2) nxt.load_near(bg, pj[0], f);
 #pragma unroll
   for (int rr = 0; rr < rows; ++rr) {
     const int row = wave * rows + rr;
     const bool valid = row < nvalid;
-    const int64_t p = p0 + (valid ? row : 0);
-    const int64_t i = pairs[p], j = pairs[max_pairs + p];
+    const int64_t i = pi[rr];
     if (i != prev_i) {
       int zi = bg.z[i];
       zi = zi < 0 ? 0 : (zi >= bg.max_z ? bg.max_z - 1 : zi);
@@ -263,31 +327,28 @@ __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const in
       ldv<V>(bg.V + zi * F + f, Vi);
       prev_i = i;
     }
-    int zj = bg.z[j];
-    zj = zj < 0 ? 0 : (zj >= bg.max_z ? bg.max_z - 1 : zj);
+    EmbedRowJ<F> cur = nxt;
+    if constexpr (PF < 2) cur.load_near(bg, pj[rr], f);
+    if constexpr (PF < 1) cur.load_far(bg, wave_row_pair<rows>(p0, nvalid, wave, rr), f);
+    if (rr + 1 < rows) {
+      if constexpr (PF >= 1) nxt.load_far(bg, wave_row_pair<rows>(p0, nvalid, wave, rr + 1), f);
+      if constexpr (PF >= 2) nxt.load_near(bg, pj[rr + 1], f);
+    }
     const float ux = sU[row][0], uy = sU[row][1], uz = sU[row][2];
     const float ph = sPhi[row];
     float s5[5];
     s0_coords(ux, uy, uz, s5);
-    const float *dj = bg.dXr + j * 9 * F + f;
-    float cj[9][V], Uj[V], Vj[V], a[V], b[V], c[V];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) ldv<V>(dj + q * F, cj[q]);
-    ldv<V>(bg.U + zj * F + f, Uj);
-    ldv<V>(bg.V + zj * F + f, Vj);
-    ldv<V>(bg.f0 + p * 3 * F + f, a);
-    ldv<V>(bg.f0 + p * 3 * F + F + f, b);
-    ldv<V>(bg.f0 + p * 3 * F + 2 * F + f, c);
     float oI[V], oA[V], oS[V];
     float aphi = 0.f, av0 = 0.f, av1 = 0.f, av2 = 0.f;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      const float Zij = Ui[v] + Vj[v], Zji = Uj[v] + Vi[v];
+      const float Zij = Ui[v] + cur.W[v], Zji = cur.U[v] + Vi[v];
+      const float a = cur.a[v], b = cur.b[v], c = cur.cc[v];
       float xi[9], xj[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         xi[q] = ci[q][v];
-        xj[q] = cj[q][v];
+        xj[q] = cur.c[q][v];
       }
       const float giA = xi[1] * ux + xi[2] * uy + xi[3] * uz;
       const float gjA = -(xj[1] * ux + xj[2] * uy + xj[3] * uz);
@@ -300,13 +361,13 @@ __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const in
       oI[v] = valid ? ph * (Zij * xi[0] + Zji * xj[0]) : 0.f;
       oA[v] = valid ? ph * (Zij * giA + Zji * gjA) : 0.f;
       oS[v] = valid ? ph * (Zij * giS + Zji * gjS) : 0.f;
-      aphi += Zij * (a[v] * xi[0] + b[v] * giA + c[v] * giS) + Zji * (a[v] * xj[0] + b[v] * gjA + c[v] * gjS);
+      aphi += Zij * (a * xi[0] + b * giA + c * giS) + Zji * (a * xj[0] + b * gjA + c * gjS);
       float gsi[3], gsj[3];
       s0_dot_grad(xi + 4, ux, uy, uz, gsi);
       s0_dot_grad(xj + 4, ux, uy, uz, gsj);
-      av0 += ph * (b[v] * (Zij * xi[1] - Zji * xj[1]) + c[v] * (Zij * gsi[0] + Zji * gsj[0]));
-      av1 += ph * (b[v] * (Zij * xi[2] - Zji * xj[2]) + c[v] * (Zij * gsi[1] + Zji * gsj[1]));
-      av2 += ph * (b[v] * (Zij * xi[3] - Zji * xj[3]) + c[v] * (Zij * gsi[2] + Zji * gsj[2]));
+      av0 += ph * (b * (Zij * xi[1] - Zji * xj[1]) + c * (Zij * gsi[0] + Zji * gsj[0]));
+      av1 += ph * (b * (Zij * xi[2] - Zji * xj[2]) + c * (Zij * gsi[1] + Zji * gsj[1]));
+      av2 += ph * (b * (Zij * xi[3] - Zji * xj[3]) + c * (Zij * gsi[2] + Zji * gsj[2]));
     }
     st_row<TL, V>(lds + row * ld + f, oI);
     st_row<TL, V>(lds + row * ld + F + f, oA);
@@ -324,9 +385,28 @@ __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const in
   }
 }
 
+// The second atom's rows of Y and dE/dM ("near") and the pair's stored z3 ("far") for one
+// layer's filter adjoint.
+template <int F, class TZ>
+struct FilterRowJ {
+  static constexpr int V = F / 64;
+  float y[9][V], g[9][V], z[3][V];
+  __device__ __forceinline__ void load_near(const float *Y, const float *dM, int64_t j, int f) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      ldv<V>(Y + j * 9 * F + q * F + f, y[q]);
+      ldv<V>(dM + j * 9 * F + q * F + f, g[q]);
+    }
+  }
+  __device__ __forceinline__ void load_far(const TZ *z3, int64_t p, int f) {
+#pragma unroll
+    for (int pt = 0; pt < 3; ++pt) ld_row<TZ, V>(z3 + p * 3 * F + pt * F + f, z[pt]);
+  }
+};
+
 // Layer l: dh = <part(Y_j), dM_i> + <part(Y_i), dM_j> per channel; then
 // lds[row][c] = dh phi silu'(z3) and dE/dphi += sum_c dh silu(z3).
-template <int F, int R, class TL, class TZ, int NW = 4>
+template <int F, int R, class TL, class TZ, int NW = 4, int PF = 2>
 __device__ __forceinline__ void filter_adjoint_rows(const float *Y, const float *dM, const TZ *z3,
                                                     const int32_t *pairs, int64_t max_pairs, int64_t p0, int nvalid,
                                                     const float *sPhi, TL *lds, int ld, float *sDphi) {
@@ -334,16 +414,21 @@ __device__ __forceinline__ void filter_adjoint_rows(const float *Y, const float 
   constexpr int V = F / 64, rows = R / NW;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int f = lane * V;
+  int32_t pi[rows], pj[rows];
+  wave_pair_rows<rows>(pairs, max_pairs, p0, nvalid, wave, pi, pj);
   // consecutive pairs mostly share their first atom (the list is sorted by (i, j)): its rows
-  // are reloaded only when i changes
+  // are reloaded only when i changes; the next row's z3 (PF >= 1, 6 registers per lane) and atom
+  // rows (PF = 2, 36 more) are loaded one row ahead
   int64_t prev_i = -1;
   float yi[9][V], gi[9][V];
+  FilterRowJ<F, TZ> nxt;
+  if constexpr (PF >= 1) nxt.load_far(z3, wave_row_pair<rows>(p0, nvalid, wave, 0), f);
+  if constexpr (PF >= 2) nxt.load_near(Y, dM, pj[0], f);
 #pragma unroll
   for (int rr = 0; rr < rows; ++rr) {
     const int row = wave * rows + rr;
     const bool valid = row < nvalid;
-    const int64_t p = p0 + (valid ? row : 0);
-    const int64_t i = pairs[p], j = pairs[max_pairs + p];
+    const int64_t i = pi[rr];
     if (i != prev_i) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
@@ -352,31 +437,31 @@ __device__ __forceinline__ void filter_adjoint_rows(const float *Y, const float 
       }
       prev_i = i;
     }
-    const float *yj = Y + j * 9 * F + f, *gj = dM + j * 9 * F + f;
+    FilterRowJ<F, TZ> cur = nxt;
+    if constexpr (PF < 2) cur.load_near(Y, dM, pj[rr], f);
+    if constexpr (PF < 1) cur.load_far(z3, wave_row_pair<rows>(p0, nvalid, wave, rr), f);
+    if (rr + 1 < rows) {
+      if constexpr (PF >= 1) nxt.load_far(z3, wave_row_pair<rows>(p0, nvalid, wave, rr + 1), f);
+      if constexpr (PF >= 2) nxt.load_near(Y, dM, pj[rr + 1], f);
+    }
     const float ph = sPhi[row];
-    float dh[3][V], zz[3][V];
+    float dh[3][V];
 #pragma unroll
-    for (int pt = 0; pt < 3; ++pt) {
-      ld_row<TZ, V>(z3 + p * 3 * F + pt * F + f, zz[pt]);
+    for (int pt = 0; pt < 3; ++pt)
 #pragma unroll
       for (int v = 0; v < V; ++v) dh[pt][v] = 0.f;
-    }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      float a[V], d[V];
-      ldv<V>(yj + q * F, a);
-      ldv<V>(gj + q * F, d);
+    for (int q = 0; q < 9; ++q)
 #pragma unroll
-      for (int v = 0; v < V; ++v) dh[coord_part(q)][v] += a[v] * gi[q][v] + yi[q][v] * d[v];
-    }
+      for (int v = 0; v < V; ++v) dh[coord_part(q)][v] += cur.y[q][v] * gi[q][v] + yi[q][v] * cur.g[q][v];
     float part = 0.f;
 #pragma unroll
     for (int pt = 0; pt < 3; ++pt) {
       float o[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        o[v] = valid ? dh[pt][v] * ph * fast_silu_grad(zz[pt][v]) : 0.f;
-        part += dh[pt][v] * fast_silu(zz[pt][v]);
+        o[v] = valid ? dh[pt][v] * ph * fast_silu_grad(cur.z[pt][v]) : 0.f;
+        part += dh[pt][v] * fast_silu(cur.z[pt][v]);
       }
       st_row<TL, V>(lds + row * ld + pt * F + f, o);
     }
@@ -406,6 +491,62 @@ __device__ __forceinline__ void geometry_adjoint_rows(const PairGeo &g, const fl
   gout[2] = (float)(dd * g.u[2] + (gz - proj * g.u[2]) * inv);
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_d(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each aligned group of eight lanes (xor 1, xor 2 inside a quad, then the mirror
+// inside the half row); every lane of the group ends with the same value.
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_mov_d<0xB1>(v);
+  v += dpp_mov_d<0x4E>(v);
+  v += dpp_mov_d<0x141>(v);
+  return v;
+}
+
+// dE/dv for a tile's pairs from dE/de (LDS [TILE][ldE]), dE/dphi and dE/dvhat (per-row LDS) and
+// the FP64 geometry (LDS).  Eight threads per pair split the K basis derivatives (thread s takes
+// k = s, s + 8, ...) and add them in a fixed order, the same for every tile shape.
+template <int K, int TILE, int NT>
+__device__ __forceinline__ void geometry_adjoint_tile(const PairGeo *sGeo, const float *sDE, int ldE,
+                                                      const float *sDphi, const float (*sDv)[3], int nvalid,
+                                                      double alpha, double r_lo, const double *mu,
+                                                      const double *beta, float *gout) {
+  static_assert(K % 8 == 0 && NT % 64 == 0, "eight threads per pair");
+  const int tid = threadIdx.x, s = tid & 7;
+#pragma unroll
+  for (int row0 = 0; row0 < TILE; row0 += NT / 8) {
+    const int row = row0 + (tid >> 3);
+    if (row < TILE) {   // whole groups of eight lanes
+      const PairGeo &g = sGeo[row];
+      const double u = exp(-alpha * (g.d - r_lo));
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < K / 8; ++m) {
+        const int k = s + 8 * m;
+        const double x = u - mu[k];
+        const double gk = exp(-beta[k] * x * x);
+        const double dek = g.dphi * gk + g.phi * gk * 2.0 * alpha * beta[k] * u * x;
+        acc += (double)sDE[row * ldE + k] * dek;
+      }
+      acc = group8_sum(acc);
+      if (s == 0 && row < nvalid) {
+        const double dd = (double)sDphi[row] * g.dphi + acc;
+        const double gx = sDv[row][0], gy = sDv[row][1], gz = sDv[row][2];
+        const double proj = gx * g.u[0] + gy * g.u[1] + gz * g.u[2];
+        const double inv = 1.0 / g.d;
+        gout[3 * row + 0] = (float)(dd * g.u[0] + (gx - proj * g.u[0]) * inv);
+        gout[3 * row + 1] = (float)(dd * g.u[1] + (gy - proj * g.u[1]) * inv);
+        gout[3 * row + 2] = (float)(dd * g.u[2] + (gz - proj * g.u[2]) * inv);
+      }
+    }
+  }
+}
+
 // ============================================================================ reverse
 // One LDS buffer holds the tile's current adjoint: dE/df0, then per layer dz3, dz2, dz1, and
 // finally dE/de.  Each product keeps its result in registers until every wave has finished
@@ -423,7 +564,8 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
   const int64_t p0 = tile * TILE;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nvalid = (int)((P - p0) < TILE ? (P - p0) : TILE);
-  constexpr int NWDE = K / 16;   // waves that own the dE/de accumulator (16 columns each)
+  // dE/de is split into (16-row block, 16-column block) pieces dealt round-robin to the waves
+  constexpr int KB = K / 16, NDE = (RB * KB + NW - 1) / NW;
 
   if (tid < TILE) {
     PairGeo g{};
@@ -441,16 +583,25 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
   }
   __syncthreads();
   // embedding adjoint: dE/df0 -> sG, dE/dphi and dE/dvhat per pair
-  embed_adjoint_rows<F, TILE, float, NW>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
+  constexpr int PF = MINB <= 2 ? 2 : (MINB == 3 ? 1 : 0);   // how much of the next row the prologues prefetch (registers)
+  embed_adjoint_rows<F, TILE, float, NW, PF>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
   __syncthreads();
-  floatx4 de[RB][1];
-  zero_acc_rb<RB, 1>(de);
-  if (wave < NWDE) wave_mm_rb<RB, 1>(sG, L3, 3 * F, a.W0T, wave * 16, de);
+  floatx4 de[NDE][1][1];
+  auto de_product = [&](const float *act, int ld, int Kin, const float *Bt) {
+#pragma unroll
+    for (int n = 0; n < NDE; ++n) {
+      const int c = wave + NW * n;
+      if (c < RB * KB) wave_mm_rows<1, 1>(act + (c / KB) * 16 * ld, ld, 16 * ld, Kin, Bt, (c % KB) * 16, de[n]);
+    }
+  };
+#pragma unroll
+  for (int n = 0; n < NDE; ++n) zero_acc_rb<1, 1>(de[n]);
+  de_product(sG, L3, 3 * F, a.W0T);
   __syncthreads();
 
   for (int l = 0; l < a.L; ++l) {
     const float *z1 = a.z1[l], *z2 = a.z2[l];
-    filter_adjoint_rows<F, TILE, float, float, NW>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
+    filter_adjoint_rows<F, TILE, float, float, NW, PF>(a.g.Y[l], a.g.dM[l], a.z3[l], a.pairs, a.max_pairs, p0, nvalid, sPhi, sG, L3,
                                   sDphi);
     __syncthreads();
     {  // dz2 = (dz3 Wc) silu'(z2)
@@ -481,17 +632,22 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
       });
     }
     __syncthreads();
-    if (wave < NWDE) wave_mm_rb<RB, 1>(sG, L1, F, a.WaT[l], wave * 16, de);   // de += dz1 Wa
+    de_product(sG, L1, F, a.WaT[l]);   // de += dz1 Wa
     __syncthreads();
   }
 
   float *sDE = sG;   // [TILE][K+4]
-  if (wave < NWDE)
-    for_acc_rc(de, wave * 16, [&](int, int, int, int row, int col, float v) { sDE[row * LE + col] = v; });
+#pragma unroll
+  for (int n = 0; n < NDE; ++n) {
+    const int c = wave + NW * n;
+    if (c < RB * KB)
+      for_acc_rc(de[n], (c % KB) * 16, [&](int, int, int, int row, int col, float v) {
+        sDE[((c / KB) * 16 + row) * LE + col] = v;
+      });
+  }
   __syncthreads();
-  if (tid < nvalid)
-    geometry_adjoint_rows<K>(sGeo[tid], sDE + tid * LE, 0, sDphi[tid], sDv[tid], a.alpha, a.r_lo, a.mu, a.beta,
-                             a.gpair + 3 * (p0 + tid));
+  geometry_adjoint_tile<K, TILE, 64 * NW>(sGeo, sDE, LE, sDphi, sDv, nvalid, a.alpha, a.r_lo, a.mu, a.beta,
+                                          a.gpair + 3 * p0);
 }
 
 // ============================================================================ BF16 variant
@@ -723,10 +879,10 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
 // Tile shapes: pairs per tile = 16 RB, NW waves per workgroup, at least MINB workgroups per
 // compute unit (register budget).  Every shape computes each pair with the same arithmetic
 // in the same order, so results do not depend on the shape; tn_autotune picks the fastest.
-//   FP32: 0 = 32 pairs, 4 waves, 3 blocks/CU; 1 = 32, 4, 2; 2 = 16, 4, 4; 3 = 64, 4, 1
-//   BF16: 0 = 64 pairs, 4 waves, 1 block/CU; 1 = 32, 4, 2
+//   FP32: 0 = 32 pairs, 4 waves, 3 blocks/CU; 1 = 32, 4, 2; 2 = 16, 4, 4; 3 = 64, 4, 1; 4 = 48, 4, 2
+//   BF16: 0 = 64 pairs, 4 waves, 1 block/CU; 1 = 32, 4, 2; 2 = 48, 4, 2
 // (Eight-wave FP32 tiles, NW = 8, measured slower on the 6000-atom box and are not built.)
-int pair_variant_count(bool bf16) { return bf16 ? 2 : 4; }
+int pair_variant_count(bool bf16) { return bf16 ? 3 : 5; }
 
 template <int TILE>
 static unsigned tile_grid(int64_t max_pairs) {
@@ -779,6 +935,7 @@ static int launch_fwd(hipStream_t s, const PairFwdArgs &a, int v) {
     case 1: return launch_fwd_v<F, K, 2, 4, 2>(s, a);
     case 2: return launch_fwd_v<F, K, 1, 4, 4>(s, a);
     case 3: return launch_fwd_v<F, K, 4, 4, 1>(s, a);
+    case 4: return launch_fwd_v<F, K, 3, 4, 2>(s, a);
     default: return launch_fwd_v<F, K, 2, 4, 3>(s, a);
   }
 }
@@ -789,6 +946,7 @@ static int launch_bwd(hipStream_t s, const PairBwdArgs &a, int v) {
     case 1: return launch_bwd_v<F, K, 2, 4, 2>(s, a);
     case 2: return launch_bwd_v<F, K, 1, 4, 4>(s, a);
     case 3: return launch_bwd_v<F, K, 4, 4, 1>(s, a);
+    case 4: return launch_bwd_v<F, K, 3, 4, 2>(s, a);
     default: return launch_bwd_v<F, K, 2, 4, 3>(s, a);
   }
 }
@@ -796,12 +954,14 @@ static int launch_bwd(hipStream_t s, const PairBwdArgs &a, int v) {
 template <int F, int K>
 static int launch_fwd_bf16(hipStream_t s, const PairFwdArgsB &a, int v) {
   if (v == 1) return launch_fwd_bf16_v<F, K, 2, 2>(s, a);
+  if (v == 2) return launch_fwd_bf16_v<F, K, 3, 2>(s, a);
   return launch_fwd_bf16_v<F, K, 4, 1>(s, a);
 }
 
 template <int F, int K>
 static int launch_bwd_bf16(hipStream_t s, const PairBwdArgsB &a, int v) {
   if (v == 1) return launch_bwd_bf16_v<F, K, 2, 2>(s, a);
+  if (v == 2) return launch_bwd_bf16_v<F, K, 3, 2>(s, a);
   return launch_bwd_bf16_v<F, K, 4, 1>(s, a);
 }
 
