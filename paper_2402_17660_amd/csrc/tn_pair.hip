@@ -69,6 +69,51 @@ __device__ __forceinline__ void load_acc_rows(const TZ *z, int ldz, int64_t p0, 
     }
 }
 
+// The FP32 kernels store the pre-activations z1 and z2 in 16-pair blocks, column-major inside a
+// block: entry (p, c) of a C-column array sits at ((p / 16) * C + c) * 16 + p % 16.  The four
+// rows an accumulator lane holds are then one 16-byte access, and the sixteen lanes of a row
+// group cover 1 KB without gaps.  Only rows below nvalid are written; the buffers hold whole
+// blocks, so the reverse kernel may read a block's unwritten rows (their values are not used).
+template <int RB, int NB>
+__device__ __forceinline__ void store_acc_blocked(float *z, int C, int64_t p0, int nvalid, int col0,
+                                                  const floatx4 (&acc)[RB][NB]) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int row = rb * 16 + 4 * q;
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      float *dst = z + ((p0 / 16 + rb) * C + col0 + cb * 16 + r) * 16 + 4 * q;
+      if (row + 3 < nvalid) {
+        *reinterpret_cast<floatx4 *>(dst) = acc[rb][cb];
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (row + t < nvalid) dst[t] = acc[rb][cb][t];
+      }
+    }
+  }
+}
+
+// Reads what store_acc_blocked wrote, at this lane's accumulator positions; row blocks that
+// start past nvalid are not read (zeros).
+template <int RB, int NB>
+__device__ __forceinline__ void load_acc_blocked(const float *z, int C, int64_t p0, int nvalid, int col0,
+                                                 float (&o)[RB][NB][4]) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+      if (rb * 16 < nvalid) v = *reinterpret_cast<const floatx4 *>(z + ((p0 / 16 + rb) * C + col0 + cb * 16 + r) * 16 + 4 * q);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) o[rb][cb][t] = v[t];
+    }
+}
+
 // Pair geometry in FP64 from the FP32 positions: unit vector, distance, cutoff and its derivative.
 struct PairGeo {
   double u[3], d, phi, dphi;
@@ -156,12 +201,12 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_fwd(PairFwdArgs a) {
       load_cols<NB>(a.ba[l], col0, br);
       wave_mm_rb<RB, NB>(sE, LE, K, a.Wa[l], col0, acc);
       __syncthreads();   // the previous layer's last product has finished reading sA
-      float *z1 = a.z1[l];
-      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+      for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
         const float z = v + br[cb];
-        if (row < nvalid) z1[(p0 + row) * F + col] = z;
+        acc[rb][cb][t] = z;
         sA[row * L1 + col] = fast_silu(z);
       });
+      store_acc_blocked<RB, NB>(a.z1[l], F, p0, nvalid, col0, acc);
     }
     __syncthreads();
     {  // z2 = Wb silu(z1) + bb
@@ -173,12 +218,12 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_fwd(PairFwdArgs a) {
       load_cols<NB>(a.bb[l], col0, br);
       wave_mm_rb<RB, NB>(sA, L1, F, a.Wb[l], col0, acc);
       __syncthreads();
-      float *z2 = a.z2[l];
-      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
+      for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
         const float z = v + br[cb];
-        if (row < nvalid) z2[(p0 + row) * 2 * F + col] = z;
+        acc[rb][cb][t] = z;
         sA[row * L2 + col] = fast_silu(z);
       });
+      store_acc_blocked<RB, NB>(a.z2[l], 2 * F, p0, nvalid, col0, acc);
     }
     __syncthreads();
     {  // z3 = Wc silu(z2) + bc, h = phi silu(z3)
@@ -583,7 +628,8 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
   }
   __syncthreads();
   // embedding adjoint: dE/df0 -> sG, dE/dphi and dE/dvhat per pair
-  constexpr int PF = MINB <= 2 ? 2 : (MINB == 3 ? 1 : 0);   // how much of the next row the prologues prefetch (registers)
+  // how much of the next row the prologues prefetch, by the register budget (MINB waves per SIMD)
+  constexpr int PF = MINB <= 2 ? 2 : (MINB == 3 ? 1 : 0);
   embed_adjoint_rows<F, TILE, float, NW, PF>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
   __syncthreads();
   floatx4 de[NDE][1][1];
@@ -610,7 +656,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
       zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (2 * F / NW);
       float zp[RB][NB][4];
-      load_acc_rows<RB, NB>(z2, 2 * F, p0, nvalid, col0, zp);
+      load_acc_blocked<RB, NB>(z2, 2 * F, p0, nvalid, col0, zp);
       wave_mm_rb<RB, NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
@@ -624,7 +670,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
       zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / NW);
       float zp[RB][NB][4];
-      load_acc_rows<RB, NB>(z1, F, p0, nvalid, col0, zp);
+      load_acc_blocked<RB, NB>(z1, F, p0, nvalid, col0, zp);
       wave_mm_rb<RB, NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
@@ -876,12 +922,16 @@ __global__ void __launch_bounds__(256, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
 }
 
 // ============================================================================ launchers
-// Tile shapes: pairs per tile = 16 RB, NW waves per workgroup, at least MINB workgroups per
-// compute unit (register budget).  Every shape computes each pair with the same arithmetic
-// in the same order, so results do not depend on the shape; tn_autotune picks the fastest.
-//   FP32: 0 = 32 pairs, 4 waves, 3 blocks/CU; 1 = 32, 4, 2; 2 = 16, 4, 4; 3 = 64, 4, 1; 4 = 48, 4, 2
-//   BF16: 0 = 64 pairs, 4 waves, 1 block/CU; 1 = 32, 4, 2; 2 = 48, 4, 2
-// (Eight-wave FP32 tiles, NW = 8, measured slower on the 6000-atom box and are not built.)
+// Tile shapes: pairs per tile = 16 RB, NW waves per workgroup; MINB, the launch bound's
+// minimum waves per SIMD, caps the registers at 512 / MINB per lane and so allows MINB * 4 / NW
+// workgroups per compute unit (LDS permitting).  Every shape computes each pair with the same
+// arithmetic in the same order, so results do not depend on the shape; tn_autotune picks the
+// fastest.  Workgroups per CU:
+//   FP32: 0 = 32 pairs, 4 waves, 3 per CU; 1 = 32, 4, 2; 2 = 16, 4, 4; 3 = 64, 4, 1;
+//         4 = 48, 4, 2
+//   BF16: 0 = 64 pairs, 4 waves, 1 per CU; 1 = 32, 4, 2; 2 = 48, 4, 2
+// (Eight-wave tiles, NW = 8, measured slower on the 6000-atom box: 32 pairs, and 48 pairs at
+// two workgroups per CU, where the 128-register cap spills; they are not built.)
 int pair_variant_count(bool bf16) { return bf16 ? 3 : 5; }
 
 template <int TILE>
