@@ -228,13 +228,23 @@ __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float
     constexpr int C0 = decltype(c0_tag)::value, NC = decltype(nc_tag)::value;
     float4 breg[kBreg ? KC : 1][NB];
     if constexpr (kBreg) load_bfrag<NB, KC>(Bt, F, col0, breg);   // overlaps the staging below
+    // every load of the staging is issued before the first LDS write, so their latencies overlap
     const float4 *src = reinterpret_cast<const float4 *>(in + a0 * 9 * F);
-    for (int e = threadIdx.x; e < 16 * NC * (F / 4); e += 256) {
+    constexpr int NE = 16 * NC * (F / 4), IT = (NE + 255) / 256;
+    float4 stage[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + 256 * it;
       const int row = e / (F / 4), c4 = e % (F / 4);   // row = atom * NC + coordinate
       const int at = row / NC, cc = row % NC;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (at < navail) v = src[(at * 9 + C0 + cc) * (F / 4) + c4];
-      *reinterpret_cast<float4 *>(sA + row * LD + 4 * c4) = v;
+      stage[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NE && at < navail) stage[it] = src[(at * 9 + C0 + cc) * (F / 4) + c4];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + 256 * it;
+      const int row = e / (F / 4), c4 = e % (F / 4);
+      if (e < NE) *reinterpret_cast<float4 *>(sA + row * LD + 4 * c4) = stage[it];
     }
     __syncthreads();
     floatx4 acc[NC][NB];
@@ -243,6 +253,25 @@ __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float
       wave_mm_rows_breg<NC, NB, KC>(sA, NC * LD, LD, breg, acc);
     else
       wave_mm_rows<NC, NB>(sA, NC * LD, LD, F, Bt, col0, acc);
+    // accumulating: all old values are loaded before the first store
+    if (accumulate) {
+      float old[NC][NB][4];
+#pragma unroll
+      for (int rb = 0; rb < NC; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int at = 4 * q + e;
+            old[rb][cb][e] = at < navail ? out[((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16] : 0.f;
+          }
+#pragma unroll
+      for (int rb = 0; rb < NC; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[rb][cb][e] = old[rb][cb][e] + acc[rb][cb][e];
+    }
 #pragma unroll
     for (int rb = 0; rb < NC; ++rb)
 #pragma unroll
@@ -250,9 +279,7 @@ __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int at = 4 * q + e;
-          if (at >= navail) continue;
-          float *dst = out + ((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16;
-          if (accumulate) *dst += acc[rb][cb][e]; else *dst = acc[rb][cb][e];
+          if (at < navail) out[((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16] = acc[rb][cb][e];
         }
   };
   if (part == 0)
