@@ -136,22 +136,39 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
     const int64_t n = n0 + wc + cb * 16 + r16;
     if (g.bias && n < g.N) bias[cb] = g.bias[n];
   }
+  // The epilogue's per-entry inputs (row scale, gate, old output) are all loaded before the
+  // first store, so their latencies overlap.
+  auto ep_m = [&](int rb_, int t) -> int64_t {
+    return m0 + wr + rb_ * 16 + (sizeof(T) == 4 ? 4 * q + t : 4 * t + q);
+  };
+  T rs[RBW][2][4], gt[RBW][2][4], old[RBW][2][4];
 #pragma unroll
   for (int rb_ = 0; rb_ < RBW; ++rb_)
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int64_t m = m0 + wr + rb_ * 16 + (sizeof(T) == 4 ? 4 * q + t : 4 * t + q);
-        const int64_t n = n0 + wc + cb * 16 + r16;
+        const int64_t m = ep_m(rb_, t), n = n0 + wc + cb * 16 + r16;
+        const bool ok = m < Mrows && n < g.N;
+        rs[rb_][cb][t] = (ok && g.rowscale) ? g.rowscale[m] : T(1);
+        gt[rb_][cb][t] = (ok && g.gate) ? g.gate[z * g.zoff + m * g.ldg + n] : T(0);
+        old[rb_][cb][t] = (ok && g.accumulate) ? C[m * g.ldc + n] : T(0);
+      }
+#pragma unroll
+  for (int rb_ = 0; rb_ < RBW; ++rb_)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t m = ep_m(rb_, t), n = n0 + wc + cb * 16 + r16;
         if (m >= Mrows || n >= g.N) continue;
         T v = acc[rb_][cb][t] + bias[cb];
         if (g.Z) g.Z[z * g.zoff + m * g.ldz + n] = v;
         if (g.act == 1) v = silu(v);
-        if (g.rowscale) v *= g.rowscale[m];
-        if (g.gate) v *= silu_grad(g.gate[z * g.zoff + m * g.ldg + n]);
+        if (g.rowscale) v *= rs[rb_][cb][t];
+        if (g.gate) v *= silu_grad(gt[rb_][cb][t]);
         T *dst = C + m * g.ldc + n;
-        if (g.accumulate) *dst += v; else *dst = v;
+        if (g.accumulate) *dst = old[rb_][cb][t] + v; else *dst = v;
       }
 }
 
