@@ -258,6 +258,32 @@ def test_pair_tile_shapes_are_bitwise_identical(dev, box600, precision):
         m.set_pair_variant(precision, nv, 0)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_mixed_tile_shapes_and_exact_budget(dev, box600, precision):
+    """The forward and reverse pair kernels may run with different tile shapes (the autotuner
+    picks each on its own), so everything they hand over (f0, the stored pre-activations, z1
+    and z2 in 16-pair blocks in FP32) must not depend on the tile.  With the budget equal to
+    the true pair count (not a multiple of 16 here), the last tile and the last 16-pair block
+    reach past max_pairs.  Every combination must reproduce shape (0, 0) bit for bit."""
+    pos, z, box = box600
+    blob = small_blob(F=128, K=32, L=2, seed=93)
+    m = TensorNet(blob, dev)
+    nv = TensorNet.pair_variant_count(precision)
+    batch = np.zeros(600, np.int32)
+    m.set_pair_variant(precision, 0, 0)
+    E0, F0 = gpu_ef(dev, m, pos, z, batch, box, 1, precision, "fused")
+    n_pairs = int(m.n_pairs.item())
+    assert n_pairs % 16 != 0   # 11294 pairs on this box
+    combos = [(f, b) for f in range(nv) for b in range(nv) if f != b] + [(v, v) for v in range(nv)]
+    for f, b in combos:
+        m.set_pair_variant(precision, f, b)
+        for mp in (n_pairs, n_pairs + 5):
+            E, Fv = gpu_ef(dev, m, pos, z, batch, box, 1, precision, "fused", max_pairs=mp)
+            print(f"{precision} shapes fwd {f} bwd {b} max_pairs {mp}: E={E[0]:.10f}", flush=True)
+            assert int(m.n_pairs.item()) == n_pairs
+            assert np.array_equal(E, E0) and np.array_equal(Fv, F0), (f, b, mp)
+
+
 def test_autotune_picks_a_shape_and_keeps_results(dev, box600):
     pos, z, box = box600
     m = TensorNet(small_blob(F=128, K=32, L=2, seed=93), dev)
