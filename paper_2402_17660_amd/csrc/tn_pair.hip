@@ -9,7 +9,7 @@
 //             atoms' adjoint rows (gathered in the tile's prologue), then per layer
 //             dz3 = dh phi silu'(z3), dz2 = (dz3 Wc) silu'(z2), dz1 = (dz2 Wb) silu'(z1),
 //             de += dz1 Wa;  de += df0 W0;  then dE/dv from de, dE/dphi, dE/dvhat (FP64)
-// Tiles hold 16 RB pairs (RB = 1, 2, 4; see the launchers); the four waves of a workgroup
+// Tiles hold 16 RB pairs (RB = 1 to 4; see the launchers); the NW waves of a workgroup
 // split the output columns, each wave covering all rows in RB 16-row MFMA blocks.
 // Activations live in LDS (row padding of
 // 4 floats), weights stream from L2 as 16-byte loads.  The K index inside each 16-wide
