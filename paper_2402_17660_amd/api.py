@@ -320,7 +320,8 @@ def capture(model: "TensorNet", pos, z, batch, n_systems, box=None, max_pairs=No
             path="fused", n_steps=0, vel=None, inv_mass=None, dt_fs=1.0, energy_out=None, forces_out=None):
     """Record one energy+forces evaluation (n_steps=0) or n_steps velocity-Verlet steps into a graph.
 
-    Returns (graph, energy, forces, n_pairs, status); the tensors are the graph's outputs.
+    For MD, forces_out must hold F(pos) when the graph is first replayed; without it the forces of the
+    current positions are computed here, before the capture.  Returns (graph, energy, forces, n_pairs, status); the tensors are the graph's outputs.
     """
     dev = model.device
     pdt = torch.float64 if precision == "fp64" else torch.float32
@@ -336,7 +337,14 @@ def capture(model: "TensorNet", pos, z, batch, n_systems, box=None, max_pairs=No
         raise TensorNetError("invalid capture request")
     ws = torch.empty(int(need) + 4096, dtype=torch.uint8, device=dev)
     E = energy_out if energy_out is not None else torch.empty(n_systems, dtype=torch.float64, device=dev)
-    Fo = forces_out if forces_out is not None else torch.zeros((n, 3), dtype=pdt, device=dev)
+    if forces_out is not None:
+        Fo = forces_out
+    elif n_steps > 0:
+        # the first half kick of a replay needs F(pos) on entry
+        _, Fo = model.energy_forces(pos, z, batch, n_systems, box=box, max_pairs=max_pairs, precision=precision,
+                                    path=path)
+    else:
+        Fo = torch.zeros((n, 3), dtype=pdt, device=dev)
     n_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     if n_steps > 0:

@@ -4,8 +4,9 @@ Calls only the FP64 oracle and the seeded generators; run from the repository
 root:  python tests/golden/make_golden.py [cfg ...]
 Each file holds E [S], F [N,3] (float64) and the pair count of the oracle's
 neighbour set, for the workload of the same number (synth.CONFIGS).  For the
-100k-atom box (workload 3) the file holds exact forces of atoms near two
-centres (see sampled_forces_periodic) instead.
+100k-atom box (workload 3), oracle_cfg3_sampled.npz holds exact forces of atoms
+near two centres (see sampled_forces_periodic) and oracle_cfg3_energy.npz the
+whole box's energy from the forward pass alone (argument 33 writes only that).
 """
 
 import os
@@ -58,10 +59,32 @@ def sampled_forces_periodic(cfg, centres=(0, 50_000), radius=35.0, core=5.0):
     print(f"-> {path}", flush=True)
 
 
+def box_energy(cfg):
+    """The oracle's energy of a whole periodic box (forward only, no autograd), with the sum of
+    the per-atom energy magnitudes: the denominator for a near-cancelling sum."""
+    c = make_config(cfg)
+    w = make_weights(c["F"], c["K"], c["L"], c["max_z"], seed=c["weight_seed"])
+    o = TensorNetOracle(write_blob(w, c["F"], c["K"], c["L"], c["max_z"], c["r_c"]))
+    t = time.time()
+    pairs = o.pairs(c["pos"], c["batch"], c["box"])
+    cap = {}
+    E = o.energy(c["pos"], c["z"], c["batch"], c["box"], c["n_systems"], pairs=pairs, capture=cap)
+    eps = cap["atom_energy"].numpy()
+    path = os.path.join(HERE, f"oracle_cfg{cfg}_energy.npz")
+    np.savez_compressed(path, E=E, abs_atom_energy_sum=np.array([np.abs(eps).sum()]),
+                        n_pairs=np.int64(len(pairs)))
+    print(f"cfg {cfg}: N={len(c['pos'])} pairs={len(pairs)} E={E} sum|eps|={np.abs(eps).sum():.6f} "
+          f"{time.time() - t:.1f}s -> {path}", flush=True)
+
+
 def main(cfgs):
     for cfg in cfgs:
         if cfg == 3:
             sampled_forces_periodic(cfg)
+            box_energy(cfg)
+            continue
+        if cfg == 33:   # the 100k-atom box's energy alone
+            box_energy(3)
             continue
         c = make_config(cfg)
         w = make_weights(c["F"], c["K"], c["L"], c["max_z"], seed=c["weight_seed"])

@@ -198,3 +198,39 @@ def test_triclinic_two_systems_one_cell(dev):
     batch = np.array([0] * 200 + [1] * 150, np.int32)
     ref = check_against_oracle(dev, pos, batch, H, 4.5)
     assert np.all(batch[ref[:, 0]] == batch[ref[:, 1]])
+
+
+@pytest.mark.parametrize("method", ["auto", "brute"])
+def test_exact_cutoff_distance_is_excluded(dev, method):
+    # d^2 == r_c^2 exactly in FP64 (3-4-5 and axis-aligned pairs) is not a pair; one float32 ulp
+    # inside is; coincident atoms are (d = 0 < r_c); the same decisions as the oracle's pins
+    pos = np.array([[0, 0, 0], [3, 4, 0], [0, 0, 5], [0, 4.9999995, 0], [0, 0, 0], [-3, 0, -4]], np.float32)
+    got = check_against_oracle(dev, pos, np.zeros(len(pos), np.int32), None, 5.0, method=method)
+    s = {tuple(p) for p in got}
+    assert (0, 1) not in s and (0, 2) not in s and (0, 5) not in s
+    assert (0, 3) in s and (0, 4) in s
+    # across a periodic face: x = 0.5 and x = 7.5 in a 12 A box are 5 A apart through the face
+    box = np.diag([12.0, 12.0, 12.0])
+    pos = np.array([[0.5, 6, 6], [7.5, 6, 6], [7.5000005, 6, 6], [6, 0.25, 6], [6, 7.25, 6]], np.float32)
+    for m in (("auto", "brute") if method == "auto" else ("brute",)):
+        got = check_against_oracle(dev, pos, np.zeros(len(pos), np.int32), box, 5.0, method=m)
+        s = {tuple(p) for p in got}
+        assert (0, 1) not in s and (3, 4) not in s
+        assert (0, 2) in s
+
+
+def test_half_box_displacements_round_half_to_even(dev):
+    # Delta / L exactly +1/2 and -1/2 (rint rounds both to zero): the minimum-image vector keeps
+    # |v| = L/2, which at r_c = L/2 is exactly the cutoff and is excluded; atoms a whole box
+    # apart coincide; the remaining pairs are ordinary.  Cell list and brute force agree with
+    # the oracle on every pair
+    box_len = 10.0
+    box = np.diag([box_len] * 3)
+    pos = np.array([[0, 0, 0], [5, 0, 0], [0, 0, 4], [-5, 0, 0], [0, 5, 0], [0, -5, 0], [2.5, 2.5, 2.5],
+                    [0, 0, -5], [10, 0, 3], [1, 1, 1]], np.float32)
+    for method in ("auto", "brute"):
+        got = check_against_oracle(dev, pos, np.zeros(len(pos), np.int32), box, 5.0, method=method)
+        s = {tuple(p) for p in got}
+        assert (0, 1) not in s and (0, 3) not in s and (0, 4) not in s and (0, 5) not in s and (0, 7) not in s
+        assert (1, 3) in s and (4, 5) in s     # a whole box apart: distance 0
+        assert (0, 2) in s and (0, 9) in s

@@ -47,6 +47,40 @@ def rel_energy_err(E, E_ref):
     return float(np.max(np.abs(E - E_ref) / np.abs(E_ref)))
 
 
+def energy_errors_r21(E, E_ref, abs_sum):
+    """Per-system energy errors with the denominator of the error metric: |E_ref| normally, and
+    sum_i |eps_i| (the per-atom energy magnitudes of the system) when |E_ref| < 1e-3 sum_i |eps_i|,
+    i.e. when the energy is a near-cancelling sum.  Returns (errors, near-cancelling mask)."""
+    E = np.asarray(E, dtype=np.float64)
+    E_ref = np.asarray(E_ref, dtype=np.float64)
+    abs_sum = np.asarray(abs_sum, dtype=np.float64)
+    near = np.abs(E_ref) < 1e-3 * abs_sum
+    den = np.where(near, abs_sum, np.abs(E_ref))
+    return np.abs(E - E_ref) / den, near
+
+
+def oracle_energy_forces_r21(oracle, pos, z, batch, box, S):
+    """The oracle's (E [S], F, sum_i |eps_i| per system)."""
+    cap = {}
+    E, F = oracle.energy_forces(pos, z, batch, box, S, capture=cap)
+    abs_sum = np.zeros(S)
+    np.add.at(abs_sum, np.asarray(batch), np.abs(cap["atom_energy"].numpy()))
+    return E, F, abs_sum
+
+
+def max_atom_dev(Fv, F_ref):
+    """Largest per-atom force deviation relative to the largest reference force."""
+    d = np.asarray(Fv, np.float64) - np.asarray(F_ref, np.float64)
+    return float(np.sqrt((d * d).sum(1)).max() / np.sqrt((np.asarray(F_ref, np.float64) ** 2).sum(1)).max())
+
+
+def poison_workspace(model, n, S, max_pairs, box=None, precision="fp32", path="fused"):
+    """Fill the model's workspace with 0xFF bytes (NaN in FP32 and FP64) before a parity call, so a
+    kernel reading scratch it did not write shows up as a wrong result."""
+    buf = model.ws.get(model.workspace_bytes(n, S, max_pairs, box=box, precision=precision, path=path))
+    buf.fill_(0xFF)
+
+
 def rel_rms(Fv, F_ref):
     Fv = np.asarray(Fv, dtype=np.float64)
     F_ref = np.asarray(F_ref, dtype=np.float64)
