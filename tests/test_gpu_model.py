@@ -3,8 +3,9 @@
 Tolerances: the plain FP64 path is held to 1e-10 (it differs from the oracle
 only by summation order); FP32 paths to energy relative error <= 1e-6 and force
 relative RMS <= 1e-5; BF16 to force relative RMS <= 2e-2 and every atom's force
-within 0.1 of the largest reference force.  Energy errors of near-cancelling
-sums (|E| < 1e-3 sum_i |eps_i|) are taken relative to sum_i |eps_i|.  Every
+within 0.1 of the largest reference force.  Where the oracle's per-atom
+energies are known, the energy error is taken relative to max(|E|, 0.1 sum_i |eps_i|),
+so a cancelling sum is judged against the size of its terms.  Every
 workspace is filled with NaN bytes before the call.
 """
 
@@ -57,7 +58,7 @@ def assert_close(E, F, E_ref, F_ref, precision, label, abs_sum=None):
         ee, near = float(errs.max()), bool(nearm.any())
     fe = rel_rms(F, F_ref)
     fa = max_atom_dev(F, F_ref)
-    print(f"{label}: energy rel err {ee:.3e}{' (near-cancelling: / sum|eps|)' if near else ''}, force rel RMS "
+    print(f"{label}: energy rel err {ee:.3e}{' (cancelling sum: / 0.1 sum|eps|)' if near else ''}, force rel RMS "
           f"{fe:.3e}, max atom dev {fa:.3e}", flush=True)
     if te is not None:
         assert ee <= te, (label, ee)
@@ -131,7 +132,7 @@ def test_workloads(dev, cfg, path, precision):
 @pytest.mark.parametrize("L_layers", [0, 1, 3])
 @pytest.mark.parametrize("wseed", [70, 71, 72])
 def test_fused_layer_counts(dev, L_layers, wseed):
-    # several weight seeds, near-cancelling energies included: those are judged against sum |eps_i|
+    # several weight seeds, cancelling energies included: those are judged against 0.1 sum |eps_i|
     pos, z = random_molecule(40, 60 + L_layers)
     blob = small_blob(F=64, K=32, L=L_layers, seed=wseed)
     E_ref, F_ref, abs_sum = oracle_energy_forces_r21(TensorNetOracle(blob), pos.astype(np.float32), z,
@@ -159,7 +160,7 @@ def test_100k_box_full_size(dev, precision):
     if os.path.exists(ge):
         ref = np.load(ge)
         errs, near = energy_errors_r21(E, ref["E"], ref["abs_atom_energy_sum"])
-        msg += f", energy rel err {errs[0]:.3e}" + (" (near-cancelling: / sum|eps|)" if near[0] else "")
+        msg += f", energy rel err {errs[0]:.3e}" + (" (cancelling sum: / 0.1 sum|eps|)" if near[0] else "")
         if precision == "fp32":
             assert errs[0] <= TOL["fp32"][0], errs
     print(msg, flush=True)

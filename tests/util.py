@@ -47,15 +47,17 @@ def rel_energy_err(E, E_ref):
     return float(np.max(np.abs(E - E_ref) / np.abs(E_ref)))
 
 
-def energy_errors_r21(E, E_ref, abs_sum):
-    """Per-system energy errors with the denominator of the error metric: |E_ref| normally, and
-    sum_i |eps_i| (the per-atom energy magnitudes of the system) when |E_ref| < 1e-3 sum_i |eps_i|,
-    i.e. when the energy is a near-cancelling sum.  Returns (errors, near-cancelling mask)."""
+def energy_errors_r21(E, E_ref, abs_sum, floor=0.1):
+    """Per-system energy errors |E - E_ref| / max(|E_ref|, floor * sum_i |eps_i|), with sum_i |eps_i| the
+    per-atom energy magnitudes of the system.  A sum whose condition number sum_i |eps_i| / |E_ref| exceeds
+    1 / floor is judged against floor * sum_i |eps_i|: the rounding of the per-atom terms scales with that,
+    not with the cancelled result.  The denominator is continuous in E_ref.  Returns (errors, mask of the
+    ill-conditioned systems)."""
     E = np.asarray(E, dtype=np.float64)
     E_ref = np.asarray(E_ref, dtype=np.float64)
     abs_sum = np.asarray(abs_sum, dtype=np.float64)
-    near = np.abs(E_ref) < 1e-3 * abs_sum
-    den = np.where(near, abs_sum, np.abs(E_ref))
+    near = np.abs(E_ref) < floor * abs_sum
+    den = np.maximum(np.abs(E_ref), floor * abs_sum)
     return np.abs(E - E_ref) / den, near
 
 
