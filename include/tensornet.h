@@ -155,6 +155,32 @@ int tn_energy_forces(const tn_model *m, void *stream, int64_t n_atoms, int64_t n
                      int precision, int path, double *energy, void *forces, int64_t *n_pairs, int32_t *status,
                      void *ws, size_t ws_bytes);
 
+/* ------------------------------------------- without a caller workspace ---
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ * tn_energy_forces_static is tn_energy_forces (same arguments, outputs,
+ * status word and errors) with the scratch space taken from the library's
+ * own static device array of TN_STATIC_WS_BYTES bytes instead of a `ws`
+ * argument.  The call allocates and frees nothing: the array is part of the
+ * library's code object, so every GPU the library runs on holds one copy of
+ * it until the process ends; its device address is looked up once per device
+ * (at tn_model_create, with that device current).
+ *   - A request whose workspace (tn_workspace_bytes with want_forces 1)
+ *     exceeds TN_STATIC_WS_BYTES is rejected with TN_E_WORKSPACE before any
+ *     work is enqueued (and a message on stderr); use tn_energy_forces then.
+ *     128 MiB covers, e.g., a molecule of a few hundred atoms with the pair
+ *     budget of 32 pairs per atom at hidden size 128 on the fused path.
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents (nothing in it needs to start at zero).  Calls whose
+ *     work overlaps on one GPU (different streams, or host threads without
+ *     ordering) RACE on it and give undefined results: order them on one
+ *     stream or serialise them. */
+#define TN_STATIC_WS_BYTES ((size_t)128 << 20)
+int tn_energy_forces_static(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, const void *pos,
+                            const int32_t *z, const int32_t *batch, const double *box, int64_t max_pairs,
+                            int precision, int path, double *energy, void *forces, int64_t *n_pairs,
+                            int32_t *status);
+
 /* -------------------------------------------------------- training step ---
  * Force training (Sec. 2.5: training on forces differentiates through the
  * force computation a second time; Sec. 3 trains on energies and forces

@@ -14,6 +14,7 @@ TN_STATUS_OVERFLOW, TN_STATUS_BATCH, TN_STATUS_Z, TN_STATUS_NONFINITE = 1, 2, 4,
 TN_FP32, TN_BF16, TN_FP64 = 0, 1, 2
 TN_FUSED, TN_PLAIN = 0, 1
 TN_NBR_AUTO, TN_NBR_CELL, TN_NBR_BRUTE = 0, 1, 2
+TN_STATIC_WS_BYTES = 128 << 20   # size of the library's static scratch (tn_energy_forces_static)
 
 _c = ctypes
 _vp, _i32, _i64, _sz, _dbl = _c.c_void_p, _c.c_int, _c.c_int64, _c.c_size_t, _c.c_double
@@ -32,6 +33,8 @@ PROTOTYPES = {
     "tn_energy": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz]),
     "tn_energy_forces": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp,
                                 _vp, _sz]),
+    "tn_energy_forces_static": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp,
+                                       _vp, _vp]),
     "tn_md_capture": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, _i64, _i32, _i32, _vp,
                              _vp, _vp, _vp, _vp, _sz, _c.POINTER(_vp)]),
     "tn_graph_replay": (_i32, [_vp, _vp]),

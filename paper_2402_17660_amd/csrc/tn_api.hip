@@ -154,6 +154,36 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
   return TN_OK;
 }
 
+// ------------------------------------------------------------------ static scratch
+// The library's own device scratch for tn_energy_forces_static: one array per GPU (each device
+// holds its own copy of a __device__ variable), never allocated or freed by a call.  In host
+// code `scratch` is only a host-side stand-in for the symbol; its device address on each GPU
+// is looked up once with hipGetSymbolAddress and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[TN_STATIC_WS_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The address of `scratch` on `device` (which must be current); looked up on the first call
+// per device.  Returns TN_OK, TN_E_ARG (device index out of range) or TN_E_HIP.
+int scratch_on_device(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices) return TN_E_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      std::fprintf(stderr, "tensornet: hipGetSymbolAddress(scratch) on device %d failed: %s\n", device,
+                   hipGetErrorString(e));
+      return TN_E_HIP;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return TN_OK;
+}
+
 // ------------------------------------------------------------------ timing registry
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
@@ -326,6 +356,11 @@ int tn_model_create(const void *blob, size_t blob_bytes, int device, tn_model **
     delete m;
     return TN_E_HIP;
   }
+  void *scratch_ptr = nullptr;   // set-up of tn_energy_forces_static's scratch on this device
+  if (device < kMaxDevices && (rc = scratch_on_device(device, &scratch_ptr)) != TN_OK) {
+    delete m;
+    return rc;
+  }
   const size_t n = packed.size();
   std::vector<float> f32(n);
   std::vector<__bf16> f16(n);
@@ -470,6 +505,28 @@ int tn_energy_forces(const tn_model *m, void *stream, int64_t n_atoms, int64_t n
   if (!forces && n_atoms > 0) return TN_E_ARG;
   return run_model(m, stream, n_atoms, n_systems, pos, z, batch, box, max_pairs, precision, path, energy, forces,
                    n_pairs, status, ws, ws_bytes);
+}
+
+int tn_energy_forces_static(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, const void *pos,
+                            const int32_t *z, const int32_t *batch, const double *box, int64_t max_pairs,
+                            int precision, int path, double *energy, void *forces, int64_t *n_pairs,
+                            int32_t *status) {
+  if (!m || (!forces && n_atoms > 0)) return TN_E_ARG;
+  const size_t need = tn_workspace_bytes(m, n_atoms, n_systems, max_pairs, box, precision, path, 1);
+  if (need == 0) return TN_E_ARG;
+  if (need > (size_t)TN_STATIC_WS_BYTES) {
+    std::fprintf(stderr,
+                 "tensornet: tn_energy_forces_static needs %zu bytes of scratch for %lld atoms and max_pairs %lld; "
+                 "the static scratch holds %zu (use tn_energy_forces with a workspace)\n",
+                 need, (long long)n_atoms, (long long)max_pairs, (size_t)TN_STATIC_WS_BYTES);
+    return TN_E_WORKSPACE;
+  }
+  if (hipSetDevice(m->device) != hipSuccess) return TN_E_HIP;
+  void *ws = nullptr;
+  const int rc = scratch_on_device(m->device, &ws);
+  if (rc) return rc;
+  return run_model(m, stream, n_atoms, n_systems, pos, z, batch, box, max_pairs, precision, path, energy, forces,
+                   n_pairs, status, ws, (size_t)TN_STATIC_WS_BYTES);
 }
 
 }  // extern "C"
