@@ -65,7 +65,7 @@ def timed_kernels(path, F, K, L):
 
 
 KERNEL_NAMES = {"edge_fwd": "k_pair_fwd", "edge_bwd": "k_pair_bwd", "plain_edge_gemm_c": "k_gemm_mfma"}
-PAIR_SOURCES = ("tn_pair.hip", "tn_mfma.h", "tn_device.h", "tn_internal.h")
+PAIR_SOURCES = ("tn_pair.hip", "tn_pairtile.h", "tn_mfma.h", "tn_device.h", "tn_internal.h")
 
 
 def kernel_code_hash():
@@ -358,7 +358,8 @@ def summarize(name, r):
                      energy_rel=f(q["energy_rel_err"], 2), force_rel_rms=f(q["force_rel_rms"], 2)) for q in r["rows"]]
     if name == "batch":
         return {p: dict(ms=f(r[p]["ms_per_step"]), value=f(r[p]["value"]), energy_rel=f(r[p]["energy_rel_err"], 2),
-                        force_rel_rms=f(r[p]["force_rel_rms"], 2)) for p in ("fp32", "bf16") if p in r}
+                        force_rel_rms=f(r[p]["force_rel_rms"], 2))
+                for p in ("fp32", "bf16", "molecule_fp32", "molecule_bf16") if p in r}
     if name == "md":
         return {p: dict(ms_per_step=f(r[p]["ms_per_step"]), value=f(r[p]["value"]), status=r[p]["status"],
                         total_energy_max_dev_eV=f(r[p]["total_max_dev"]), min_pair_distance=f(r[p]["min_pair_distance"]),
@@ -382,7 +383,9 @@ def _blob_for(c):
 
 
 def extra_batch(args, dev):
-    """512 isolated molecules of 8-64 atoms: one captured graph per evaluation, FP32 vs BF16."""
+    """512 isolated molecules of 8-64 atoms: one captured graph per evaluation, FP32 vs BF16, with the fused
+    path (one launch per operation over the whole batch) and the molecule path (one launch in which a
+    workgroup owns each molecule; pair budget 32 per atom)."""
     import numpy as np
     import torch
     from paper_2402_17660_amd import TensorNet, capture
@@ -398,9 +401,13 @@ def extra_batch(args, dev):
     out = dict(workload="512 isolated molecules, sizes uniform 8-64 atoms (centred at the origin), hidden 128, "
                         "2 layers, cutoff 5 A; one captured HIP graph per energy+forces call",
                n_atoms=N, n_pairs=int(golden["n_pairs"]), max_pairs=mp)
-    for prec in ("fp32", "bf16"):
-        shapes = model.autotune(pos, z, batch, c["n_systems"], max_pairs=mp, precision=prec, reps=3)
-        g, E, Fo, n_pairs, status = capture(model, pos, z, batch, c["n_systems"], max_pairs=mp, precision=prec)
+    for prec, path in (("fp32", "fused"), ("bf16", "fused"), ("fp32", "molecule"), ("bf16", "molecule")):
+        key = prec if path == "fused" else f"molecule_{prec}"
+        shapes = None
+        if path == "fused":
+            shapes = model.autotune(pos, z, batch, c["n_systems"], max_pairs=mp, precision=prec, reps=3)
+        g, E, Fo, n_pairs, status = capture(model, pos, z, batch, c["n_systems"],
+                                            max_pairs=mp if path == "fused" else 32 * N, precision=prec, path=path)
         for _ in range(3):
             g.replay()
         torch.cuda.synchronize()
@@ -414,11 +421,11 @@ def extra_batch(args, dev):
         ms = start.elapsed_time(stop) / reps
         Ev = E.cpu().numpy()
         Fv = Fo.double().cpu().numpy()
-        out[prec] = dict(ms_per_step=ms, value=N / (ms * 1e-3), status=int(status.item()), pair_tile_shapes=shapes,
-                         energy_rel_err=float(np.max(np.abs(Ev - golden["E"]) / np.abs(golden["E"]))),
-                         force_rel_rms=float(np.linalg.norm(Fv - golden["F"]) / np.linalg.norm(golden["F"])))
-        log(f"batch/{prec}: {ms:.3f} ms/step, {out[prec]['value']:.3e} atom-steps/s, "
-            f"E err {out[prec]['energy_rel_err']:.2e}, F err {out[prec]['force_rel_rms']:.2e}")
+        out[key] = dict(ms_per_step=ms, value=N / (ms * 1e-3), status=int(status.item()), pair_tile_shapes=shapes,
+                        energy_rel_err=float(np.max(np.abs(Ev - golden["E"]) / np.abs(golden["E"]))),
+                        force_rel_rms=float(np.linalg.norm(Fv - golden["F"]) / np.linalg.norm(golden["F"])))
+        log(f"batch/{path}/{prec}: {ms:.3f} ms/step, {out[key]['value']:.3e} atom-steps/s, "
+            f"E err {out[key]['energy_rel_err']:.2e}, F err {out[key]['force_rel_rms']:.2e}")
         g.close()
     return out
 
@@ -521,8 +528,9 @@ def extra_md(args, dev):
 
 def extra_anchor(args, dev):
     """The correctness anchor: one isolated 48-atom molecule (hidden 64, 2 layers, cutoff 4.5 A).  The plain
-    path in FP64 and the fused path in FP32 (and BF16), eager calls and one captured graph per call; microseconds
-    per energy+forces call, errors against the oracle's stored values."""
+    path in FP64, the fused path in FP32 (and BF16) and the molecule path (one launch, a workgroup per
+    molecule) in FP32 and BF16, eager calls and one captured graph per call; microseconds per energy+forces
+    call, errors against the oracle's stored values."""
     import numpy as np
     import torch
     from paper_2402_17660_amd import TensorNet, capture
@@ -536,7 +544,8 @@ def extra_anchor(args, dev):
     mp = 32 * N
     out = dict(workload="one isolated 48-atom molecule, hidden 64, 2 layers, 32 RBF, cutoff 4.5 A; max_pairs 32 N",
                n_atoms=N, n_pairs=int(golden["n_pairs"]), rows=[])
-    for path, prec in (("plain", "fp64"), ("fused", "fp32"), ("fused", "bf16"), ("plain", "fp32")):
+    for path, prec in (("plain", "fp64"), ("fused", "fp32"), ("fused", "bf16"), ("plain", "fp32"), ("molecule", "fp32"),
+                       ("molecule", "bf16")):
         pdt = torch.float64 if prec == "fp64" else torch.float32
         pos = torch.tensor(c["pos"], dtype=pdt, device=dev)
         E_out = torch.empty(1, dtype=torch.float64, device=dev)
@@ -749,11 +758,12 @@ def timing(L_, name):
 
 def train_wgrad_flops(F, K, L, n_atoms, n_pairs, max_z):
     """Algorithmic FLOPs of the training step's parameter adjoints (outer products of layer adjoints with layer
-    inputs) on dual numbers: per weight entry and row, one value product and two tangent products (6 FLOP)."""
+    inputs) on dual numbers: per weight entry and row, the two tangent products the loss gradient needs
+    (4 FLOP); the value part is not formed."""
     pair = n_pairs * (L * (F * K + 2 * F * F + 6 * F * F) + 3 * F * K)
     node = n_atoms * ((1 + 2 * L) * 9 * F * F + 2 * F * F + 6 * F * F + 3 * F * F + (F // 2) * F)
     species = 2 * max_z * F * F
-    return 6.0 * (pair + node + species)
+    return 4.0 * (pair + node + species)
 
 
 def train_cpu_baseline(c, n_mol):

@@ -65,7 +65,7 @@ typedef enum {
 #define TN_STATUS_NONFINITE 8  /* non-finite position or energy */
 
 typedef enum { TN_FP32 = 0, TN_BF16 = 1, TN_FP64 = 2 } tn_precision;
-typedef enum { TN_FUSED = 0, TN_PLAIN = 1 } tn_path;
+typedef enum { TN_FUSED = 0, TN_PLAIN = 1, TN_MOLECULE = 2 } tn_path;
 
 /* Status code to a static English string. */
 const char *tn_status_string(int status);
@@ -138,8 +138,24 @@ int tn_build_neighbors_method(void *stream, int64_t n_atoms, const void *pos, in
  *   batch   [n_atoms] int32 sorted system index
  *   energy  [n_systems] float64 output
  * precision: TN_FP64 (plain path only), TN_FP32, TN_BF16 (GEMM operands in
- * BF16, FP32 accumulation; fused path only).  path: TN_FUSED or TN_PLAIN
- * (one kernel per operation, every intermediate through memory). */
+ * BF16, FP32 accumulation; fused and molecule paths only).  path:
+ *   TN_FUSED     every operation one launch over all atoms or pairs of the
+ *                batch (the per-pair work of all layers in two MFMA kernels)
+ *   TN_PLAIN     one kernel per operation, every intermediate through memory
+ *   TN_MOLECULE  isolated systems only (box == NULL, else TN_E_UNSUPPORTED),
+ *                TN_FP32 or TN_BF16, hidden size 64 or 128 with 32 radial
+ *                functions (else TN_E_UNSUPPORTED): one launch over the batch
+ *                in which a workgroup owns whole systems and runs every
+ *                stage (neighbour search by brute force over the system,
+ *                layers, output, reverse sweep) with workgroup barriers
+ *                only, so a small molecule costs one launch instead of one
+ *                per operation (Sec. 2.5: launch overhead bounds small
+ *                systems).  The arithmetic is the fused path's.  The pair
+ *                budget is split in proportion to the atoms: a system of n
+ *                of the n_atoms atoms gets about n * max_pairs / n_atoms pair
+ *                slots; a system with more pairs sets TN_STATUS_OVERFLOW
+ *                (*n_pairs is still the true total).  Best for systems of up
+ *                to a few hundred atoms. */
 size_t tn_workspace_bytes(const tn_model *m, int64_t n_atoms, int64_t n_systems, int64_t max_pairs,
                           const double *box, int precision, int path, int want_forces);
 int tn_energy(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_systems, const void *pos,
@@ -205,8 +221,7 @@ int tn_energy_forces_static(const tn_model *m, void *stream, int64_t n_atoms, in
  *     [n_atoms, 3] receive the model's predictions at pos.
  *   grad: [tn_param_count] float64 (device), overwritten, blob tensor order
  *     and shapes (the model's own weights are not changed).
- * Pair budget and status as for tn_energy_forces; TN_E_UNSUPPORTED when
- * max_pairs or n_atoms exceeds 1048560. */
+ * Pair budget, size limits and status as for tn_energy_forces. */
 int64_t tn_param_count(const tn_model *m);
 size_t tn_train_workspace_bytes(const tn_model *m, int64_t n_atoms, int64_t n_systems, int64_t max_pairs,
                                 const double *box, int precision);

@@ -6,13 +6,15 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtensornet.so")
+# TN_LIBRARY names another build of the same library (the host-side AddressSanitizer build of
+# the CPU tests); by default the one built next to this file
+LIB_PATH = os.environ.get("TN_LIBRARY") or os.path.join(HERE, "libtensornet.so")
 
 TN_OK = 0
 TN_E_ARG, TN_E_BLOB, TN_E_HIP, TN_E_BOX, TN_E_WORKSPACE, TN_E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 TN_STATUS_OVERFLOW, TN_STATUS_BATCH, TN_STATUS_Z, TN_STATUS_NONFINITE = 1, 2, 4, 8
 TN_FP32, TN_BF16, TN_FP64 = 0, 1, 2
-TN_FUSED, TN_PLAIN = 0, 1
+TN_FUSED, TN_PLAIN, TN_MOLECULE = 0, 1, 2
 TN_NBR_AUTO, TN_NBR_CELL, TN_NBR_BRUTE = 0, 1, 2
 TN_STATIC_WS_BYTES = 128 << 20   # size of the library's static scratch (tn_energy_forces_static)
 

@@ -15,7 +15,7 @@ import torch
 from . import _lib as L
 
 _PREC = {"fp32": L.TN_FP32, "bf16": L.TN_BF16, "fp64": L.TN_FP64}
-_PATH = {"fused": L.TN_FUSED, "plain": L.TN_PLAIN}
+_PATH = {"fused": L.TN_FUSED, "plain": L.TN_PLAIN, "molecule": L.TN_MOLECULE}
 
 
 class TensorNetError(RuntimeError):

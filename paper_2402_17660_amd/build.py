@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtensornet.so")
-SOURCES = ["tn_api.hip", "tn_nbr.hip", "tn_plain.hip", "tn_pair.hip", "tn_fused.hip", "tn_md.hip", "tn_train.hip"]
+SOURCES = ["tn_api.hip", "tn_nbr.hip", "tn_plain.hip", "tn_pair.hip", "tn_fused.hip", "tn_mol.hip", "tn_md.hip",
+           "tn_train.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -376,6 +376,10 @@ int tn_model_create(const void *blob, size_t blob_bytes, int device, tn_model **
     tn_model_destroy(m);
     return TN_E_HIP;
   }
+  if ((rc = molecule_setup(m)) != TN_OK) {
+    tn_model_destroy(m);
+    return rc;
+  }
   *out = m;
   return TN_OK;
 }
@@ -383,6 +387,7 @@ int tn_model_create(const void *blob, size_t blob_bytes, int device, tn_model **
 void tn_model_destroy(tn_model *m) {
   if (!m) return;
   (void)hipSetDevice(m->device);
+  if (m->mol_const) (void)hipFree(m->mol_const);
   if (m->w64) (void)hipFree(m->w64);
   if (m->w32) (void)hipFree(m->w32);
   if (m->w16) (void)hipFree(m->w16);
@@ -453,6 +458,10 @@ size_t tn_workspace_bytes(const tn_model *m, int64_t n_atoms, int64_t n_systems,
     if (precision != TN_FP32 && precision != TN_BF16) return 0;
     return fused_workspace_bytes(m, n_atoms, n_systems, max_pairs, bi, precision, want_forces);
   }
+  if (path == TN_MOLECULE) {
+    if ((precision != TN_FP32 && precision != TN_BF16) || bi.periodic) return 0;
+    return molecule_workspace_bytes(m, n_atoms, n_systems, max_pairs, precision, want_forces);
+  }
   return 0;
 }
 
@@ -467,9 +476,9 @@ static int run_model(const tn_model *m, void *stream, int64_t n_atoms, int64_t n
   if (!energy && n_systems > 0) return TN_E_ARG;
   if (!n_pairs || !status || !ws) return TN_E_ARG;
   if (precision != TN_FP32 && precision != TN_BF16 && precision != TN_FP64) return TN_E_ARG;
-  if (path != TN_FUSED && path != TN_PLAIN) return TN_E_ARG;
+  if (path != TN_FUSED && path != TN_PLAIN && path != TN_MOLECULE) return TN_E_ARG;
   if (path == TN_PLAIN && precision == TN_BF16) return TN_E_UNSUPPORTED;
-  if (path == TN_FUSED && precision == TN_FP64) return TN_E_UNSUPPORTED;
+  if ((path == TN_FUSED || path == TN_MOLECULE) && precision == TN_FP64) return TN_E_UNSUPPORTED;
   Problem pb;
   int rc = box_info(box, m->r_c, &pb.box);
   if (rc) return rc;
@@ -488,6 +497,7 @@ static int run_model(const tn_model *m, void *stream, int64_t n_atoms, int64_t n
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((rc = fill_i32(s, status, 1, 0))) return rc;
   if (path == TN_PLAIN) return plain_run(m, s, pb, precision, ws, ws_bytes);
+  if (path == TN_MOLECULE) return molecule_run(m, s, pb, precision, ws, ws_bytes);
   return fused_run(m, s, pb, precision, ws, ws_bytes);
 }
 

@@ -2,9 +2,11 @@
 // and every layer's edge filter, forward and reverse) runs in two MFMA pair-tile kernels;
 // the node-level steps use the shared node kernels.  Precision plan: FP32 arithmetic, with
 // the geometry/basis, the embedding's node stage (norms, LayerNorm, MLP, gating; its channel
-// mixing is linear and runs in FP32) and the output network in FP64, reading and writing the
-// FP32 feature arrays directly; the per-system energy sum and the per-atom force sum in
-// FP64.  The BF16 variant feeds the pair kernels' GEMMs BF16 operands (FP32 accumulation).
+// mixing is linear and runs in FP32) and the output network in FP64 ("islands"), reading and
+// writing the FP32 feature arrays directly; the per-system energy sum and the per-atom force
+// sum in FP64.  The BF16 variant feeds the pair kernels' GEMMs BF16 operands (FP32
+// accumulation), stores the edge filters h in BF16 for the message gathers, and runs the
+// islands in FP32 (its error budget is set by the BF16 operands).
 #include "tn_nodeops.h"
 
 namespace tn {
@@ -30,20 +32,22 @@ int pair_variant(const tn_model *m, bool bf16, int64_t max_pairs, bool reverse) 
 
 namespace {
 
-using TA = double;
-
+template <class TA>
 struct FusedWs {
   NbrWs nb;
   float *geo, *phi, *f0, *Xr, *T0;
   TA *nrm0, *xhat0, *rstd0, *n0, *ez1, *ea1, *ez2, *g;
   std::vector<float *> X, nX, Xb, Y, z1, z2, z3, h, M, P, nP, Pb, D, dM;
+  std::vector<__bf16 *> Y16, dM16;   // BF16 copies of Y and dM for the gathers (BF16 path)
   TA *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps, *eps_orig;
   float *dX = nullptr, *dD, *dPb, *dY, *dXr, *dT0;
   TA *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
   float *gpair;
 };
 
-void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxInfo &bi, bool fw, FusedWs *w) {
+template <class TA>
+void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxInfo &bi, bool fw, bool bf16,
+                FusedWs<TA> *w) {
   const int64_t F = m->F, L = m->L;
   plan_neighbors(p, N, MP, bi, &w->nb);
   w->geo = p.take<float>(4 * MP);
@@ -70,7 +74,7 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   per_layer(w->Y, N * 9 * F);
   // z1 and z2 of the FP32 pair kernels are stored in whole 16-pair blocks
   const int64_t MP16 = (MP + 15) / 16 * 16;
-  per_layer(w->z1, MP16 * F);
+  per_layer(w->z1, bf16 ? MP * F / 2 : MP16 * F);
   per_layer(w->z2, MP16 * 2 * F);
   per_layer(w->z3, MP * 3 * F);
   per_layer(w->h, MP * 3 * F);
@@ -79,6 +83,10 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   per_layer(w->nP, N * F);
   per_layer(w->Pb, N * 9 * F);
   per_layer(w->D, N * 9 * F);
+  if (bf16) {
+    w->Y16.resize(L);
+    for (int64_t l = 0; l < L; ++l) w->Y16[l] = p.take<__bf16>(N * 9 * F);
+  }
   w->on = p.take<TA>(N * 3 * F);
   w->oxhat = p.take<TA>(N * 3 * F);
   w->orstd = p.take<TA>(N);
@@ -91,6 +99,10 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   w->eps_orig = p.take<TA>(N);
   if (!fw) return;
   per_layer(w->dM, N * 9 * F);
+  if (bf16) {
+    w->dM16.resize(L);
+    for (int64_t l = 0; l < L; ++l) w->dM16[l] = p.take<__bf16>(N * 9 * F);
+  }
   w->dX = p.take<float>(N * 9 * F);
   w->dD = p.take<float>(N * 9 * F);
   w->dPb = p.take<float>(N * 9 * F);
@@ -110,16 +122,20 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
 
 template <bool BF16>
 int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, size_t ws_bytes) {
+  using TA = typename std::conditional<BF16, float, double>::type;   // the islands' type
+  using TH = typename std::conditional<BF16, __bf16, float>::type;   // the edge filters' type
+  using TY = TH;   // the type of the atom rows the gathers read (Y, dM)
   const int64_t N = pb.n, MP = pb.max_pairs, F = m->F, K = m->K, L = m->L;
   WsPlan plan(ws);
-  FusedWs w;
-  plan_fused(plan, m, N, MP, pb.box, pb.want_forces, &w);
+  FusedWs<TA> w;
+  plan_fused(plan, m, N, MP, pb.box, pb.want_forces, BF16, &w);
   if (plan.off > ws_bytes) return TN_E_WORKSPACE;
   const float *pos = nullptr;
   int rc;
   const unsigned bs = 256;
   auto W = [&](size_t off) { return wptr<float>(m, off); };
   auto WA = [&](size_t off) { return wptr<TA>(m, off); };
+  auto WD = [&](size_t off) { return wptr<double>(m, off); };
   const WeightOff &o = m->off;
 
   NbrGraph<float> gr;
@@ -142,8 +158,8 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     pf.r_c = m->r_c;
     pf.r_lo = m->r_lo;
     pf.alpha = m->alpha;
-    pf.mu = WA(o.mu);
-    pf.beta = WA(o.beta);
+    pf.mu = WD(o.mu);
+    pf.beta = WD(o.beta);
     pf.L = (int)L;
   };
   if (BF16) {
@@ -162,7 +178,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
       pf.z1[l] = reinterpret_cast<__bf16 *>(w.z1[l]);
       pf.z2[l] = reinterpret_cast<__bf16 *>(w.z2[l]);
       pf.z3[l] = reinterpret_cast<__bf16 *>(w.z3[l]);
-      pf.h[l] = w.h[l];
+      pf.h[l] = reinterpret_cast<__bf16 *>(w.h[l]);
     }
     pf.geo = w.geo;
     pf.phi = w.phi;
@@ -226,8 +242,12 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     const LayerOff &lo = o.layer[l];
     const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
     const float *W1T[3] = {W(lo.W1T[0]), W(lo.W1T[1]), W(lo.W1T[2])};
-    if ((rc = mix<float>(s, w.Xb[l], w.Y[l], N, F, W1, W1T, 0, 0))) return rc;
-    if ((rc = message_product_w(s, F, N, rowptr, nbr, pid, np, MP, w.h[l], w.Y[l], w.M[l], w.P[l], w.nP[l],
+    __bf16 *y16 = BF16 ? w.Y16[l] : nullptr;
+    if ((rc = mix<float>(s, w.Xb[l], w.Y[l], N, F, W1, W1T, 0, 0, y16))) return rc;
+    // the neighbours' rows from the BF16 copy in the BF16 path
+    const TY *yg = BF16 ? reinterpret_cast<const TY *>(y16) : reinterpret_cast<const TY *>(w.Y[l]);
+    if ((rc = message_product_w(s, F, N, rowptr, nbr, pid, np, MP, reinterpret_cast<const TH *>(w.h[l]), yg, w.Y[l],
+                                w.M[l], w.P[l], w.nP[l],
                                 w.Pb[l])))
       return rc;
     const float *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
@@ -300,10 +320,12 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     if ((rc = mix<float>(s, w.dD, w.dPb, N, F, W2, W2T, 1, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_product_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dPb, w.P[l], w.nP[l], w.Y[l],
-                         w.M[l], w.dY, w.dM[l]);
+                         w.M[l], w.dY, w.dM[l], BF16 ? w.dM16[l] : nullptr);
       TN_LAUNCH_CHECK();
     }
-    if ((rc = message_w(s, F, N, rowptr, nbr, pid, np, MP, w.h[l], w.dM[l], w.dY, 1))) return rc;
+    const TY *dmg = BF16 ? reinterpret_cast<const TY *>(w.dM16[l]) : reinterpret_cast<const TY *>(w.dM[l]);
+    if ((rc = message_w(s, F, N, rowptr, nbr, pid, np, MP, reinterpret_cast<const TH *>(w.h[l]), dmg, w.dY, 1)))
+      return rc;
     if ((rc = mix<float>(s, w.dY, w.dX, N, F, W1, W1T, 1, 1))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_normalize_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[l], w.nX[l], w.dX);
@@ -347,6 +369,8 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
       pbw.z3[l] = reinterpret_cast<const __bf16 *>(w.z3[l]);
       pbw.g.Y[l] = w.Y[l];
       pbw.g.dM[l] = w.dM[l];
+      pbw.Y16[l] = w.Y16[l];
+      pbw.dM16[l] = w.dM16[l];
     }
     pbw.gpair = w.gpair;
     if ((rc = launch_pair_bwd_bf16(s, (int)F, (int)K, pbw, pair_variant(m, true, MP, true)))) return rc;
@@ -389,8 +413,13 @@ size_t fused_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t ma
   (void)S;
   if ((prec != TN_FP32 && prec != TN_BF16) || !pair_kernels_support(m->F, m->K, m->L, prec == TN_BF16)) return 0;
   WsPlan p(nullptr);
-  FusedWs w;
-  plan_fused(p, m, n, max_pairs, bi, want_forces != 0, &w);
+  if (prec == TN_BF16) {
+    FusedWs<float> w;
+    plan_fused(p, m, n, max_pairs, bi, want_forces != 0, true, &w);
+  } else {
+    FusedWs<double> w;
+    plan_fused(p, m, n, max_pairs, bi, want_forces != 0, false, &w);
+  }
   return p.off;
 }
 

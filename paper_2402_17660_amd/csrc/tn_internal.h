@@ -64,6 +64,7 @@ struct tn_model {
   double *w64 = nullptr;           // packed FP64 weights (device)
   float *w32 = nullptr;            // packed FP32 weights (device)
   __bf16 *w16 = nullptr;           // packed BF16 weights (device)
+  void *mol_const = nullptr;       // the molecule path's weight pointers (device; tn_mol.hip)
 };
 
 namespace tn {
@@ -78,8 +79,8 @@ template <> inline const float *wptr<float>(const tn_model *m, size_t off) { ret
 struct WsPlan {
   char *base = nullptr;
   size_t off = 0;
-  explicit WsPlan(void *b) : base(static_cast<char *>(b)) {}
-  template <class T> T *take(size_t count) {
+  __host__ __device__ explicit WsPlan(void *b) : base(static_cast<char *>(b)) {}
+  template <class T> __host__ __device__ T *take(size_t count) {
     off = (off + kWsAlign - 1) / kWsAlign * kWsAlign;
     T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
     off += count * sizeof(T) + kWsAlign;   // keep a guard gap between buffers
@@ -155,6 +156,15 @@ size_t plain_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t ma
                              int want_forces);
 int plain_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, void *ws, size_t ws_bytes);
 
+// The molecule path: one launch in which a workgroup owns each isolated system (no box).
+size_t molecule_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t max_pairs, int prec,
+                                int want_forces);
+int molecule_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, void *ws, size_t ws_bytes);
+bool molecule_kernels_support(int F, int K, bool bf16);
+// Uploads the molecule path's table of weight pointers at model creation (m->mol_const); a
+// model whose sizes the path does not support gets none.  Returns TN_OK or TN_E_HIP.
+int molecule_setup(tn_model *m);
+
 size_t fused_workspace_bytes(const tn_model *m, int64_t n, int64_t S, int64_t max_pairs, const BoxInfo &bi, int prec,
                              int want_forces);
 int fused_run(const tn_model *m, hipStream_t s, const Problem &pb, int prec, void *ws, size_t ws_bytes);
@@ -215,8 +225,8 @@ struct PairBwdArgs {
 int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a, int variant);
 int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a, int variant);
 
-// BF16-operand variants: weights and stored pre-activations in BF16, biases, basis
-// constants, h and every other stored quantity in FP32/FP64 as above.
+// BF16-operand variants: weights, stored pre-activations and the edge filters h in BF16;
+// biases, basis constants, f0 and every other stored quantity in FP32/FP64 as above.
 struct PairFwdArgsB {
   const int32_t *pairs = nullptr;
   int64_t max_pairs = 0;
@@ -232,7 +242,7 @@ struct PairFwdArgsB {
   int L = 0;
   float *geo = nullptr, *phi = nullptr, *f0 = nullptr;
   __bf16 *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers];
-  float *h[kMaxLayers];
+  __bf16 *h[kMaxLayers];   // the edge filters in BF16 (read by the message gathers)
 };
 
 struct PairBwdArgsB {
@@ -247,6 +257,7 @@ struct PairBwdArgsB {
   const __bf16 *WaT[kMaxLayers], *WbT[kMaxLayers], *WcT[kMaxLayers];
   int L = 0;
   const __bf16 *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers];
+  const __bf16 *Y16[kMaxLayers], *dM16[kMaxLayers];   // BF16 copies of g.Y and g.dM for the filter adjoints
   BwdGather g;
   float *gpair = nullptr;
 };

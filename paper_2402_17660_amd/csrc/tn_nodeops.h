@@ -53,22 +53,25 @@ __device__ __forceinline__ mf_f64x4 mfma_16x16x4(double a, double b, mf_f64x4 c)
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// One BM x 64 output tile: blk is the flat (row tile, column tile) index, z the coordinate
+// batch index; As [BM][GBK+1] and Bs [GBN][GBK+1] are the caller's LDS.  256 threads.
 template <class T, int BM>
-__global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int64_t blk, int z, T (*As)[GBK + 1],
+                                          T (*Bs)[GBK + 1]) {
   using V = typename MfmaVec<T>::type;
   constexpr int RBW = BM / 32;                 // 16-row MFMA blocks per wave
   constexpr int PERA = BM * GBK / 256, PERB = GBN * GBK / 256;   // chunk elements per thread
-  __shared__ T As[BM][GBK + 1];
-  __shared__ T Bs[GBN][GBK + 1];
   int64_t Mrows = g.M;
   if (g.Mdev) {
     const int64_t md = *g.Mdev;
     if (md < Mrows) Mrows = md;
   }
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * GBN;
+  // one flat block index over (row tile, column tile), column tiles fastest (so the blocks that
+  // share a row tile run together); a flat x dimension has no 65535-block limit
+  const int64_t nb = (g.N + GBN - 1) / GBN;
+  const int64_t m0 = (blk / nb) * BM;
+  const int64_t n0 = (blk % nb) * GBN;
   if (m0 >= Mrows) return;
-  const int z = blockIdx.z;
   const T *__restrict__ A = g.A + z * g.zoff;
   const T *__restrict__ B = g.zpart ? g.Bz[coord_part(z)] : g.B;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -172,6 +175,13 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
       }
 }
 
+template <class T, int BM>
+__global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
+  __shared__ T As[BM][GBK + 1];
+  __shared__ T Bs[GBN][GBK + 1];
+  gemm_tile<T, BM>(g, blockIdx.x, blockIdx.z, As, Bs);
+}
+
 // Products with few 64-row tiles use 32-row tiles: fewer than two per compute unit in FP32,
 // fewer than eight in FP64 (whose matrix instructions take twice as long, so a 64-row tile
 // keeps a compute unit busy twice as long).
@@ -181,10 +191,10 @@ inline int gemm(hipStream_t s, const GemmArgs<T> &g, int zdim = 1) {
   const int64_t nb = (g.N + GBN - 1) / GBN;
   const int64_t tiles64 = nb * ((g.M + 63) / 64) * zdim;
   if (tiles64 < (sizeof(T) == 8 ? 2048 : 512)) {
-    dim3 grid((unsigned)nb, (unsigned)((g.M + 31) / 32), (unsigned)zdim);
+    dim3 grid((unsigned)(nb * ((g.M + 31) / 32)), 1, (unsigned)zdim);
     hipLaunchKernelGGL((k_gemm_mfma<T, 32>), grid, dim3(256), 0, s, g);
   } else {
-    dim3 grid((unsigned)nb, (unsigned)((g.M + 63) / 64), (unsigned)zdim);
+    dim3 grid((unsigned)(nb * ((g.M + 63) / 64)), 1, (unsigned)zdim);
     hipLaunchKernelGGL((k_gemm_mfma<T, 64>), grid, dim3(256), 0, s, g);
   }
   TN_LAUNCH_CHECK();
@@ -193,24 +203,38 @@ inline int gemm(hipStream_t s, const GemmArgs<T> &g, int zdim = 1) {
 
 // y = act(x W^T + b) over rows of x; W is [Nout, Kin] (torch Linear layout).
 template <class T>
-inline int linear_fwd(hipStream_t s, const T *x, int64_t M, int64_t Kin, const T *W, const T *b, int64_t Nout,
-                      T *y, T *z_pre, int act, const T *rowscale = nullptr, const int64_t *Mdev = nullptr) {
+__host__ __device__ inline GemmArgs<T> linear_fwd_args(const T *x, int64_t M, int64_t Kin, const T *W, const T *b,
+                                                       int64_t Nout, T *y, T *z_pre, int act,
+                                                       const T *rowscale = nullptr, const int64_t *Mdev = nullptr) {
   GemmArgs<T> g;
   g.A = x; g.lda = Kin; g.B = W; g.ldb = Kin; g.transB = 1;
   g.C = y; g.ldc = Nout; g.bias = b; g.Z = z_pre; g.ldz = Nout; g.act = act; g.rowscale = rowscale;
   g.M = M; g.N = Nout; g.K = Kin; g.Mdev = Mdev;
-  return gemm(s, g);
+  return g;
+}
+
+template <class T>
+inline int linear_fwd(hipStream_t s, const T *x, int64_t M, int64_t Kin, const T *W, const T *b, int64_t Nout,
+                      T *y, T *z_pre, int act, const T *rowscale = nullptr, const int64_t *Mdev = nullptr) {
+  return gemm(s, linear_fwd_args(x, M, Kin, W, b, Nout, y, z_pre, act, rowscale, Mdev));
 }
 
 // dx (+)= (dy W) * silu'(gate); W is [Nout, Kin], dy [M, Nout], dx [M, Kin].
 template <class T>
-inline int linear_bwd(hipStream_t s, const T *dy, int64_t M, int64_t Nout, const T *W, int64_t Kin, T *dx,
-                      const T *gate, int accumulate, const int64_t *Mdev = nullptr) {
+__host__ __device__ inline GemmArgs<T> linear_bwd_args(const T *dy, int64_t M, int64_t Nout, const T *W, int64_t Kin,
+                                                       T *dx, const T *gate, int accumulate,
+                                                       const int64_t *Mdev = nullptr) {
   GemmArgs<T> g;
   g.A = dy; g.lda = Nout; g.B = W; g.ldb = Kin; g.transB = 0;
   g.C = dx; g.ldc = Kin; g.gate = gate; g.ldg = Kin; g.accumulate = accumulate;
   g.M = M; g.N = Kin; g.K = Nout; g.Mdev = Mdev;
-  return gemm(s, g);
+  return g;
+}
+
+template <class T>
+inline int linear_bwd(hipStream_t s, const T *dy, int64_t M, int64_t Nout, const T *W, int64_t Kin, T *dx,
+                      const T *gate, int accumulate, const int64_t *Mdev = nullptr) {
+  return gemm(s, linear_bwd_args(dy, M, Nout, W, Kin, dx, gate, accumulate, Mdev));
 }
 
 // FP32 channel mixing on the matrix cores.  A block takes one part (I, A or S: 1, 3 or 5
@@ -221,19 +245,17 @@ inline int linear_bwd(hipStream_t s, const T *dy, int64_t M, int64_t Nout, const
 // output channel n (W_p itself for the forward mixing, its transpose for the adjoint).
 // Blocks are numbered so that the column blocks and parts of the same 16 atoms are
 // dispatched to the same XCD.
+// Tile t of the mixing (16 atoms, one part, one block of 64 NB output channels); sA is the
+// caller's LDS of 16 * 5 * (F + 4) floats.  256 threads.
 template <int F, int NB>
-__global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float *__restrict__ out, int64_t N,
-                                             const float *__restrict__ B0, const float *__restrict__ B1,
-                                             const float *__restrict__ B2, int accumulate, int ncb,
-                                             int64_t ntiles) {
+__device__ __forceinline__ void mix_tile(const float *__restrict__ in, float *__restrict__ out, int64_t N,
+                                         const float *__restrict__ B0, const float *__restrict__ B1,
+                                         const float *__restrict__ B2, int accumulate, int ncb, int64_t t,
+                                         float *__restrict__ sA, __bf16 *__restrict__ out16 = nullptr) {
   constexpr int LD = F + 4;
   constexpr int KC = F / 16;
   // this wave's weight fragments of its part stay in registers when they fit
   constexpr bool kBreg = KC * NB * 4 <= 64;
-  __shared__ __attribute__((aligned(16))) float sA[16 * 5 * LD];
-  const int64_t per_xcd = (int64_t)gridDim.x / 8;
-  const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (t >= ntiles) return;
   const int64_t a0 = (t / (3 * ncb)) * 16;
   const int part = (int)(t % 3);
   const int cblk = (int)((t / 3) % ncb);
@@ -296,7 +318,11 @@ __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int at = 4 * q + e;
-          if (at < navail) out[((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16] = acc[rb][cb][e];
+          if (at < navail) {
+            const int64_t o = ((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16;
+            out[o] = acc[rb][cb][e];
+            if (out16) out16[o] = (__bf16)acc[rb][cb][e];
+          }
         }
   };
   if (part == 0)
@@ -308,13 +334,25 @@ __global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float
 }
 
 template <int F, int NB>
+__global__ void __launch_bounds__(256) k_mix(const float *__restrict__ in, float *__restrict__ out, int64_t N,
+                                             const float *__restrict__ B0, const float *__restrict__ B1,
+                                             const float *__restrict__ B2, int accumulate, int ncb,
+                                             int64_t ntiles, __bf16 *__restrict__ out16) {
+  __shared__ __attribute__((aligned(16))) float sA[16 * 5 * (F + 4)];
+  const int64_t per_xcd = (int64_t)gridDim.x / 8;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= ntiles) return;
+  mix_tile<F, NB>(in, out, N, B0, B1, B2, accumulate, ncb, t, sA, out16);
+}
+
+template <int F, int NB>
 inline int launch_mix(hipStream_t s, const float *in, float *out, int64_t N, const float *const Bt[3],
-                      int accumulate) {
+                      int accumulate, __bf16 *out16) {
   constexpr int ncb = F / (64 * NB);
   const int64_t ntiles = (N + 15) / 16 * ncb * 3;
   const int64_t grid = (ntiles + 7) / 8 * 8;
   hipLaunchKernelGGL((k_mix<F, NB>), dim3((unsigned)grid), dim3(256), 0, s, in, out, N, Bt[0], Bt[1], Bt[2],
-                     accumulate, ncb, ntiles);
+                     accumulate, ncb, ntiles, out16);
   TN_LAUNCH_CHECK();
   return TN_OK;
 }
@@ -323,19 +361,21 @@ inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 // Per-part channel mixing of [N, 9, F] features: out[n,c,:] = W_part(c) in[n,c,:] (forward)
 // or out[n,c,:] (+)= in[n,c,:] W_part(c) (adjoint).  WT holds the transposed matrices (used by
-// the FP32 matrix-core kernel for the adjoint; may be null otherwise).
+// the FP32 matrix-core kernel for the adjoint; may be null otherwise).  out16, when given (FP32
+// matrix-core kernel only), receives a BF16 copy of out.
 template <class T>
 inline int mix(hipStream_t s, const T *in, T *out, int64_t N, int64_t F, const T *W[3], const T *WT[3], int adjoint,
-               int accumulate) {
+               int accumulate, __bf16 *out16 = nullptr) {
   if (N <= 0) return TN_OK;
   if constexpr (sizeof(T) == 4) {
     const T *const *Bt = adjoint ? WT : W;
     bool ok = Bt != nullptr && aligned16(in) && aligned16(out);
     for (int q = 0; ok && q < 3; ++q) ok = Bt[q] != nullptr && aligned16(Bt[q]);
-    if (ok && F == 64) return launch_mix<64, 1>(s, in, out, N, Bt, accumulate);
-    if (ok && F == 128) return launch_mix<128, 1>(s, in, out, N, Bt, accumulate);
-    if (ok && F == 256) return launch_mix<256, 2>(s, in, out, N, Bt, accumulate);
+    if (ok && F == 64) return launch_mix<64, 1>(s, in, out, N, Bt, accumulate, out16);
+    if (ok && F == 128) return launch_mix<128, 1>(s, in, out, N, Bt, accumulate, out16);
+    if (ok && F == 256) return launch_mix<256, 2>(s, in, out, N, Bt, accumulate, out16);
   }
+  if (out16) return TN_E_UNSUPPORTED;
   GemmArgs<T> g;
   g.A = in; g.lda = 9 * F; g.C = out; g.ldc = 9 * F; g.transB = adjoint ? 0 : 1; g.ldb = F;
   g.M = N; g.N = F; g.K = F; g.zoff = F; g.zpart = 1; g.accumulate = accumulate;
@@ -431,16 +471,20 @@ __device__ inline void store9(T *X, int64_t i, int F, int f, const T c[9]) {
 }
 
 // Norms in T of features stored as TX (the FP64 island reads FP32 features directly).
-template <class T, class TX = T>
-__global__ void k_node_norm(int64_t n, int F, const TX *X, T *nrm) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+template <class T, class TX>
+__device__ inline void node_norm_at(int64_t t, int F, const TX *X, T *nrm) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) c[q] = (T)X[i * 9 * F + q * F + f];
   nrm[i * F + f] = norm9(c);
+}
+template <class T, class TX = T>
+__global__ void k_node_norm(int64_t n, int F, const TX *X, T *nrm) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  node_norm_at<T, TX>(t, F, X, nrm);
 }
 
 // Block-wide sum (blockDim.x threads, power of two <= 1024).
@@ -504,22 +548,24 @@ __global__ void __launch_bounds__(128) k_layernorm_bwd(int64_t rows, int C, cons
 }
 
 // X = g_part(c) * T0 (gating), product in T, features stored as TX.
-template <class T, class TX = T>
-__global__ void k_gate(int64_t n, int F, const T *g, const TX *T0, TX *X) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * 9 * F) return;
+template <class T, class TX>
+__device__ inline void gate_at(int64_t t, int F, const T *g, const TX *T0, TX *X) {
   const int64_t i = t / (9 * F);
   const int rem = (int)(t % (9 * F));
   const int q = rem / F, f = rem % F;
   X[t] = (TX)(g[i * 3 * F + coord_part(q) * F + f] * (T)T0[t]);
 }
+template <class T, class TX = T>
+__global__ void k_gate(int64_t n, int F, const T *g, const TX *T0, TX *X) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * 9 * F) return;
+  gate_at<T, TX>(t, F, g, T0, X);
+}
 
 // X = g_part(c) * T0 (gating) followed by the first layer's normalisation:
 // nX = ||X||, Xb = X / (||X|| + 1).  One thread per (atom, channel); products in T.
 template <class T, class TX>
-__global__ void k_gate_normalize(int64_t n, int F, const T *g, const TX *T0, TX *X, TX *nX, TX *Xb) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+__device__ inline void gate_normalize_at(int64_t t, int F, const T *g, const TX *T0, TX *X, TX *nX, TX *Xb) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   TX c[9];
@@ -535,11 +581,15 @@ __global__ void k_gate_normalize(int64_t n, int F, const T *g, const TX *T0, TX 
 #pragma unroll
   for (int q = 0; q < 9; ++q) Xb[i * 9 * F + q * F + f] = c[q] * sc;
 }
-
-template <class T>
-__global__ void k_normalize(int64_t n, int F, const T *X, T *nX, T *Xb) {
+template <class T, class TX>
+__global__ void k_gate_normalize(int64_t n, int F, const T *g, const TX *T0, TX *X, TX *nX, TX *Xb) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
+  gate_normalize_at<T, TX>(t, F, g, T0, X, nX, Xb);
+}
+
+template <class T>
+__device__ inline void normalize_at(int64_t t, int F, const T *X, T *nX, T *Xb) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9];
@@ -550,6 +600,12 @@ __global__ void k_normalize(int64_t n, int F, const T *X, T *nX, T *Xb) {
 #pragma unroll
   for (int q = 0; q < 9; ++q) c[q] *= s;
   store9(Xb, i, F, f, c);
+}
+template <class T>
+__global__ void k_normalize(int64_t n, int F, const T *X, T *nX, T *Xb) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  normalize_at<T>(t, F, X, nX, Xb);
 }
 
 // M_i (+)= sum_j h_part(c)(d_ij) * Y_j[c] over the CSR row of i.
@@ -649,9 +705,7 @@ __global__ void k_message_product(int64_t n, int F, const int32_t *rowptr, const
 
 // X_out = Xb + D + D D, and for the next layer ||X_out|| and X_out / (||X_out|| + 1).
 template <class T>
-__global__ void k_residual_normalize(int64_t n, int F, const T *Xb, const T *D, T *Xo, T *nXo, T *Xbo) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+__device__ inline void residual_normalize_at(int64_t t, int F, const T *Xb, const T *D, T *Xo, T *nXo, T *Xbo) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T dc[9], Dm[9], Q[9], qc[9], xb[9];
@@ -670,12 +724,16 @@ __global__ void k_residual_normalize(int64_t n, int F, const T *Xb, const T *D, 
   for (int q = 0; q < 9; ++q) xb[q] *= sc;
   store9(Xbo, i, F, f, xb);
 }
+template <class T>
+__global__ void k_residual_normalize(int64_t n, int F, const T *Xb, const T *D, T *Xo, T *nXo, T *Xbo) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  residual_normalize_at<T>(t, F, Xb, D, Xo, nXo, Xbo);
+}
 
 // X_out = Xb + D + D D
 template <class T>
-__global__ void k_residual(int64_t n, int F, const T *Xb, const T *D, T *Xo) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+__device__ inline void residual_at(int64_t t, int F, const T *Xb, const T *D, T *Xo) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T dc[9], Dm[9], Q[9], qc[9], xb[9];
@@ -688,11 +746,15 @@ __global__ void k_residual(int64_t n, int F, const T *Xb, const T *D, T *Xo) {
   for (int q = 0; q < 9; ++q) xb[q] += dc[q] + qc[q];
   store9(Xo, i, F, f, xb);
 }
-
-template <class T, class TX = T>
-__global__ void k_out_norms(int64_t n, int F, const TX *X, T *on) {
+template <class T>
+__global__ void k_residual(int64_t n, int F, const T *Xb, const T *D, T *Xo) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
+  residual_at<T>(t, F, Xb, D, Xo);
+}
+
+template <class T, class TX>
+__device__ inline void out_norms_at(int64_t t, int F, const TX *X, T *on) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9];
@@ -701,6 +763,12 @@ __global__ void k_out_norms(int64_t n, int F, const TX *X, T *on) {
   on[i * 3 * F + f] = norm_I(c);
   on[i * 3 * F + F + f] = norm_A(c);
   on[i * 3 * F + 2 * F + f] = norm_S(c);
+}
+template <class T, class TX = T>
+__global__ void k_out_norms(int64_t n, int F, const TX *X, T *on) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  out_norms_at<T, TX>(t, F, X, on);
 }
 
 // eps_i = w . hx_i + b (final scalar of the output network)
@@ -743,18 +811,20 @@ __global__ void __launch_bounds__(128) k_energy_reduce(int64_t n, const T *eps, 
 
 // ----------------------------------------------------------------------------- backward kernels
 template <class T>
-__global__ void k_out_final_bwd(int64_t n, int H, const T *hz, const T *w, T *dhz) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * H) return;
+__device__ inline void out_final_bwd_at(int64_t t, int H, const T *hz, const T *w, T *dhz) {
   const int k = (int)(t % H);
   dhz[t] = w[k] * silu_grad(hz[t]);
 }
+template <class T>
+__global__ void k_out_final_bwd(int64_t n, int H, const T *hz, const T *w, T *dhz) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * H) return;
+  out_final_bwd_at<T>(t, H, hz, w, dhz);
+}
 
 // adjoint of the part norms: dX = sum_part d(norm_part) * grad(norm_part)
-template <class T, class TX = T>
-__global__ void k_out_norms_bwd(int64_t n, int F, const TX *X, const T *don, TX *dX) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+template <class T, class TX>
+__device__ inline void out_norms_bwd_at(int64_t t, int F, const TX *X, const T *don, TX *dX) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9], d[9];
@@ -764,12 +834,16 @@ __global__ void k_out_norms_bwd(int64_t n, int F, const TX *X, const T *don, TX 
 #pragma unroll
   for (int q = 0; q < 9; ++q) dX[i * 9 * F + q * F + f] = (TX)d[q];
 }
+template <class T, class TX = T>
+__global__ void k_out_norms_bwd(int64_t n, int F, const TX *X, const T *don, TX *dX) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  out_norms_bwd_at<T, TX>(t, F, X, don, dX);
+}
 
 // X_out = Xb + D + DD:  dD = dX + rec^T(dQ D^T + D^T dQ) with dQ = dec^T(dX)
 template <class T>
-__global__ void k_residual_bwd(int64_t n, int F, const T *D, const T *dX, T *dD) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+__device__ inline void residual_bwd_at(int64_t t, int F, const T *D, const T *dX, T *dD) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T dc[9], Dm[9], g[9], dQ[9], A1[9], A2[9], r[9];
@@ -786,13 +860,17 @@ __global__ void k_residual_bwd(int64_t n, int F, const T *D, const T *dX, T *dD)
   for (int q = 0; q < 9; ++q) r[q] += g[q];
   store9(dD, i, F, f, r);
 }
+template <class T>
+__global__ void k_residual_bwd(int64_t n, int F, const T *D, const T *dX, T *dD) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  residual_bwd_at<T>(t, F, D, dX, dD);
+}
 
 // Through Pb = P/(||P||+1) and P = Y M + M Y: dY (overwritten) and dM.
 template <class T>
-__global__ void k_product_bwd(int64_t n, int F, const T *dPb, const T *P, const T *nP, const T *Y, const T *M,
-                              T *dY, T *dM) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+__device__ inline void product_bwd_at(int64_t t, int F, const T *dPb, const T *P, const T *nP, const T *Y, const T *M, T *dY, T *dM,
+                               __bf16 *dM16 = nullptr) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T g[9], pc[9], gn[9];
@@ -826,6 +904,20 @@ __global__ void k_product_bwd(int64_t n, int F, const T *dPb, const T *P, const 
   for (int q = 0; q < 9; ++q) A1[q] += A2[q];
   rec_adj(A1, r);
   store9(dM, i, F, f, r);
+  if constexpr (std::is_same<T, float>::value) {
+    if (dM16) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dM16[i * 9 * F + q * F + f] = (__bf16)r[q];
+    }
+  }
+}
+// dM16, when given, receives a BF16 copy of dM.
+template <class T>
+__global__ void k_product_bwd(int64_t n, int F, const T *dPb, const T *P, const T *nP, const T *Y, const T *M,
+                              T *dY, T *dM, __bf16 *dM16) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  product_bwd_at<T>(t, F, dPb, P, nP, Y, M, dY, dM, dM16);
 }
 
 // dh[p] from both directions of pair p = (i, j): <part(Y_j), dM_i> + <part(Y_i), dM_j> per channel.
@@ -849,9 +941,7 @@ __global__ void k_message_bwd_pair(const int32_t *pairs, int64_t max_pairs, cons
 
 // through Xb = X/(||X||+1): dX = dXb/(n+1) - <dXb, X>/(n+1)^2 grad||X||   (in place on g)
 template <class T>
-__global__ void k_normalize_bwd(int64_t n, int F, const T *X, const T *nX, T *g) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+__device__ inline void normalize_bwd_at(int64_t t, int F, const T *X, const T *nX, T *g) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9], d[9], gn[9];
@@ -865,6 +955,12 @@ __global__ void k_normalize_bwd(int64_t n, int F, const T *X, const T *nX, T *g)
 #pragma unroll
   for (int q = 0; q < 9; ++q) d[q] = d[q] * s - dot * s * s * gn[q];
   store9(g, i, F, f, d);
+}
+template <class T>
+__global__ void k_normalize_bwd(int64_t n, int F, const T *X, const T *nX, T *g) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  normalize_bwd_at<T>(t, F, X, nX, g);
 }
 
 // h = phi * silu(z3):  dz3 = dh * phi * silu'(z3);  dphi += sum dh * silu(z3).  One block per pair.
@@ -887,11 +983,8 @@ __global__ void __launch_bounds__(128) k_edge_bwd_top(int64_t max_pairs, const i
 
 // X0 = g * T0 (per part):  dg[part] = sum_{c in part} dX0_c T0_c;  dT0 = g dX0
 // With ez given, dg leaves multiplied by silu'(ez) (the adjoint of the MLP's last SiLU).
-template <class T, class TX = T>
-__global__ void k_gate_bwd(int64_t n, int F, const TX *dX, const TX *T0, const T *g, T *dg, TX *dT0,
-                           const T *ez = nullptr) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+template <class T, class TX>
+__device__ inline void gate_bwd_at(int64_t t, int F, const TX *dX, const TX *T0, const T *g, T *dg, TX *dT0, const T *ez) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T s[3] = {T(0), T(0), T(0)};
@@ -908,6 +1001,13 @@ __global__ void k_gate_bwd(int64_t n, int F, const TX *dX, const TX *T0, const T
     dg[o] = ez ? s[q] * silu_grad(ez[o]) : s[q];
   }
 }
+template <class T, class TX = T>
+__global__ void k_gate_bwd(int64_t n, int F, const TX *dX, const TX *T0, const T *g, T *dg, TX *dT0,
+                           const T *ez = nullptr) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  gate_bwd_at<T, TX>(t, F, dX, T0, g, dg, dT0, ez);
+}
 
 template <class T>
 __global__ void k_mul_silu_grad(int64_t n, const T *d, const T *zz, T *out) {
@@ -917,10 +1017,8 @@ __global__ void k_mul_silu_grad(int64_t n, const T *d, const T *zz, T *out) {
 }
 
 // dX += dn * grad||X||
-template <class T, class TX = T>
-__global__ void k_norm_bwd_add(int64_t n, int F, const TX *X, const T *dn, TX *dX) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n * F) return;
+template <class T, class TX>
+__device__ inline void norm_bwd_add_at(int64_t t, int F, const TX *X, const T *dn, TX *dX) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T c[9], gn[9];
@@ -933,6 +1031,12 @@ __global__ void k_norm_bwd_add(int64_t n, int F, const TX *X, const T *dn, TX *d
     TX &d = dX[i * 9 * F + q * F + f];
     d = (TX)((T)d + gn[q]);
   }
+}
+template <class T, class TX = T>
+__global__ void k_norm_bwd_add(int64_t n, int F, const TX *X, const T *dn, TX *dX) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  norm_bwd_add_at<T, TX>(t, F, X, dn, dX);
 }
 
 // Embedding adjoint per pair (one block per pair, threads over channels):
@@ -1071,19 +1175,16 @@ __device__ __forceinline__ int group_channel() {
   return ((((int)threadIdx.x >> 6) % G) * 64 + ((int)threadIdx.x & 63)) * V;
 }
 
-// X_i = sum_j phi Z_ij (a 1 + b A0(u_ij) + c S0(u_ij))
-template <int V, int G = 1>
-__global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t *__restrict__ rowptr,
-                                                        const int32_t *__restrict__ nbr,
-                                                        const int32_t *__restrict__ pid, const int64_t *n_pairs,
-                                                        int64_t max_pairs, const int32_t *__restrict__ z, int max_z,
-                                                        const float *__restrict__ U, const float *__restrict__ Vt,
-                                                        const float *__restrict__ geo, const float *__restrict__ phi,
-                                                        const float *__restrict__ f0, float *__restrict__ X) {
+// X_i = sum_j phi Z_ij (a 1 + b A0(u_ij) + c S0(u_ij)) for this lane's channels f .. f+V-1 of
+// atom i, whose CSR row is [e0, e1)
+template <int V, int G>
+__device__ __forceinline__ void embed_gather_wave(int32_t i, int f, int32_t e0, int32_t e1,
+                                                  const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
+                                                  const int32_t *__restrict__ z, int max_z,
+                                                  const float *__restrict__ U, const float *__restrict__ Vt,
+                                                  const float *__restrict__ geo, const float *__restrict__ phi,
+                                                  const float *__restrict__ f0, float *__restrict__ X) {
   constexpr int F = 64 * V * G;
-  const int32_t i = group_atom<G>();
-  if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  const int f = group_channel<V, G>();
   float ui[V];
   ldv<V>(U + (int64_t)clamp_z(z[i], max_z) * F + f, ui);
   float c[9][V];
@@ -1091,8 +1192,7 @@ __global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t
   for (int q = 0; q < 9; ++q)
 #pragma unroll
     for (int v = 0; v < V; ++v) c[q][v] = 0.f;
-  const int32_t e1 = rowptr[i + 1];
-  for (int32_t e = rowptr[i]; e < e1; ++e) {
+  for (int32_t e = e0; e < e1; ++e) {
     const int32_t j = nbr[e];
     const int64_t p = pid[e];
     const float sg = (j > i) ? 1.f : -1.f;
@@ -1122,26 +1222,50 @@ __global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t
   for (int q = 0; q < 9; ++q) stv<V>(x + q * F, c[q]);
 }
 
-// c[q] = sum over the CSR row of i of h_part(q)(pair) * Y_j[q]
-template <int V, int G>
-__device__ __forceinline__ void gather_message(int32_t i, const int32_t *__restrict__ rowptr,
-                                               const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
-                                               const float *__restrict__ h, const float *__restrict__ Y, int f,
-                                               float (&c)[9][V]) {
+template <int V, int G = 1>
+__global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ nbr,
+                                                        const int32_t *__restrict__ pid, const int64_t *n_pairs,
+                                                        int64_t max_pairs, const int32_t *__restrict__ z, int max_z,
+                                                        const float *__restrict__ U, const float *__restrict__ Vt,
+                                                        const float *__restrict__ geo, const float *__restrict__ phi,
+                                                        const float *__restrict__ f0, float *__restrict__ X) {
+  const int32_t i = group_atom<G>();
+  if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
+  embed_gather_wave<V, G>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, z, max_z, U, Vt, geo, phi,
+                          f0, X);
+}
+
+// V consecutive values of a per-pair array stored as float or BF16, as floats.
+template <int V>
+__device__ __forceinline__ void ld_pair_row(const float *p, float (&o)[V]) {
+  ldv<V>(p, o);
+}
+template <int V>
+__device__ __forceinline__ void ld_pair_row(const __bf16 *p, float (&o)[V]) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) o[v] = (float)p[v];
+}
+
+// c[q] = sum over the CSR row [e0, e1) of h_part(q)(pair) * Y_j[q]; h (TH) and the gathered
+// rows Y (TY) in FP32 or BF16
+template <int V, int G, class TH, class TY>
+__device__ __forceinline__ void gather_message(int32_t e0, int32_t e1, const int32_t *__restrict__ nbr,
+                                               const int32_t *__restrict__ pid, const TH *__restrict__ h,
+                                               const TY *__restrict__ Y, int f, float (&c)[9][V]) {
   constexpr int F = 64 * V * G;
 #pragma unroll
   for (int q = 0; q < 9; ++q)
 #pragma unroll
     for (int v = 0; v < V; ++v) c[q][v] = 0.f;
-  const int32_t e1 = rowptr[i + 1];
-  for (int32_t e = rowptr[i]; e < e1; ++e) {
+  for (int32_t e = e0; e < e1; ++e) {
     const int64_t j = nbr[e];
     const int64_t p = pid[e];
     float hh[3][V], y[9][V];
 #pragma unroll
-    for (int pt = 0; pt < 3; ++pt) ldv<V>(h + p * 3 * F + pt * F + f, hh[pt]);
+    for (int pt = 0; pt < 3; ++pt) ld_pair_row<V>(h + p * 3 * F + pt * F + f, hh[pt]);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) ldv<V>(Y + j * 9 * F + q * F + f, y[q]);
+    for (int q = 0; q < 9; ++q) ld_pair_row<V>(Y + j * 9 * F + q * F + f, y[q]);
 #pragma unroll
     for (int q = 0; q < 9; ++q)
 #pragma unroll
@@ -1150,18 +1274,14 @@ __device__ __forceinline__ void gather_message(int32_t i, const int32_t *__restr
 }
 
 // M_i (+)= sum_j h_part(c)(d_ij) * Y_j[c]
-template <int V, int G = 1>
-__global__ void __launch_bounds__(256) k_message_w(int64_t n, const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
-                                                   const int64_t *n_pairs, int64_t max_pairs,
-                                                   const float *__restrict__ h, const float *__restrict__ Y,
-                                                   float *__restrict__ M, int accumulate) {
+template <int V, int G, class TH, class TY>
+__device__ __forceinline__ void message_wave(int32_t i, int f, int32_t e0, int32_t e1,
+                                             const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
+                                             const TH *__restrict__ h, const TY *__restrict__ Y,
+                                             float *__restrict__ M, int accumulate) {
   constexpr int F = 64 * V * G;
-  const int32_t i = group_atom<G>();
-  if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  const int f = group_channel<V, G>();
   float c[9][V];
-  gather_message<V, G>(i, rowptr, nbr, pid, h, Y, f, c);
+  gather_message<V, G, TH, TY>(e0, e1, nbr, pid, h, Y, f, c);
   float *m = M + (int64_t)i * 9 * F + f;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -1175,21 +1295,29 @@ __global__ void __launch_bounds__(256) k_message_w(int64_t n, const int32_t *__r
   }
 }
 
-// M_i = sum_j h_part(c) * Y_j[c]; P = Y M + M Y; Pb = P / (||P|| + 1).  Writes M, P, ||P||, Pb.
-template <int V, int G = 1>
-__global__ void __launch_bounds__(256) k_message_product_w(int64_t n, const int32_t *__restrict__ rowptr,
-                                                           const int32_t *__restrict__ nbr,
-                                                           const int32_t *__restrict__ pid, const int64_t *n_pairs,
-                                                           int64_t max_pairs, const float *__restrict__ h,
-                                                           const float *__restrict__ Y, float *__restrict__ M,
-                                                           float *__restrict__ P, float *__restrict__ nP,
-                                                           float *__restrict__ Pb) {
-  constexpr int F = 64 * V * G;
+template <int V, int G, class TH, class TY>
+__global__ void __launch_bounds__(256) k_message_w(int64_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
+                                                   const int64_t *n_pairs, int64_t max_pairs,
+                                                   const TH *__restrict__ h, const TY *__restrict__ Y,
+                                                   float *__restrict__ M, int accumulate) {
   const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  const int f = group_channel<V, G>();
+  message_wave<V, G, TH, TY>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Y, M, accumulate);
+}
+
+// M_i = sum_j h_part(c) * Y_j[c]; P = Y M + M Y; Pb = P / (||P|| + 1).  Writes M, P, ||P||, Pb.
+// The neighbours' rows come from Yg (TY: Y itself, or its BF16 copy), the atom's own from Y.
+template <int V, int G, class TH, class TY>
+__device__ __forceinline__ void message_product_wave(int32_t i, int f, int32_t e0, int32_t e1,
+                                                     const int32_t *__restrict__ nbr,
+                                                     const int32_t *__restrict__ pid, const TH *__restrict__ h,
+                                                     const TY *__restrict__ Yg, const float *__restrict__ Y,
+                                                     float *__restrict__ M, float *__restrict__ P,
+                                                     float *__restrict__ nP, float *__restrict__ Pb) {
+  constexpr int F = 64 * V * G;
   float mc[9][V], yc[9][V];
-  gather_message<V, G>(i, rowptr, nbr, pid, h, Y, f, mc);
+  gather_message<V, G, TH, TY>(e0, e1, nbr, pid, h, Yg, f, mc);
   const int64_t base = (int64_t)i * 9 * F + f;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -1229,6 +1357,20 @@ __global__ void __launch_bounds__(256) k_message_product_w(int64_t n, const int3
   for (int q = 0; q < 9; ++q) stv<V>(Pb + base + q * F, pc[q]);
 }
 
+template <int V, int G, class TH, class TY>
+__global__ void __launch_bounds__(256) k_message_product_w(int64_t n, const int32_t *__restrict__ rowptr,
+                                                           const int32_t *__restrict__ nbr,
+                                                           const int32_t *__restrict__ pid, const int64_t *n_pairs,
+                                                           int64_t max_pairs, const TH *__restrict__ h,
+                                                           const TY *__restrict__ Yg, const float *__restrict__ Y,
+                                                           float *__restrict__ M, float *__restrict__ P,
+                                                           float *__restrict__ nP, float *__restrict__ Pb) {
+  const int32_t i = group_atom<G>();
+  if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
+  message_product_wave<V, G, TH, TY>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Yg, Y, M, P,
+                                     nP, Pb);
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -1238,11 +1380,8 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // eps_i = w . hx_i + b, one wave per atom: lanes stride over the H hidden units, then a fixed
 // butterfly sums the lanes (the output layer's per-atom dot products, FP64).
 template <class T>
-__global__ void __launch_bounds__(256) k_out_final_w(int64_t n, int H, const T *__restrict__ hx,
-                                                     const T *__restrict__ w, const T *__restrict__ b,
-                                                     T *__restrict__ eps) {
-  const int32_t i = wave_atom();
-  if (i >= n) return;
+__device__ __forceinline__ void out_final_wave(int32_t i, int H, const T *__restrict__ hx, const T *__restrict__ w,
+                                               const T *__restrict__ b, T *__restrict__ eps) {
   const int lane = threadIdx.x & 63;
   double acc = 0.0;
   for (int k = lane; k < H; k += 64) acc += w[k] * hx[(int64_t)i * H + k];
@@ -1250,21 +1389,26 @@ __global__ void __launch_bounds__(256) k_out_final_w(int64_t n, int H, const T *
   if (lane == 0) eps[i] = acc + b[0];
 }
 
-// F_i = sum over the CSR row of i of +-g_pair in FP64: lanes stride over the row, then a fixed
-// butterfly sums the lanes (deterministic).
-template <class T, class TO>
-__global__ void __launch_bounds__(256) k_force_gather_w(int64_t n, const int32_t *__restrict__ rowptr,
-                                                        const int32_t *__restrict__ nbr,
-                                                        const int32_t *__restrict__ pid, const int64_t *n_pairs,
-                                                        int64_t max_pairs, const T *__restrict__ gpair,
-                                                        const int32_t *__restrict__ perm, TO *__restrict__ forces) {
+template <class T>
+__global__ void __launch_bounds__(256) k_out_final_w(int64_t n, int H, const T *__restrict__ hx,
+                                                     const T *__restrict__ w, const T *__restrict__ b,
+                                                     T *__restrict__ eps) {
   const int32_t i = wave_atom();
   if (i >= n) return;
+  out_final_wave<T>(i, H, hx, w, b, eps);
+}
+
+// F_i = sum over the CSR row of i of +-g_pair in FP64: lanes stride over the row, then a fixed
+// butterfly sums the lanes (deterministic).
+// forces[o] for atom i from its CSR row [e0, e1) (rows == false: no pair list, zero force)
+template <class T, class TO>
+__device__ __forceinline__ void force_gather_wave(int32_t i, int64_t o, bool rows, int32_t e0, int32_t e1,
+                                                  const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
+                                                  const T *__restrict__ gpair, TO *__restrict__ forces) {
   const int lane = threadIdx.x & 63;
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  if (pairs_ok(n_pairs, max_pairs)) {
-    const int32_t e1 = rowptr[i + 1];
-    for (int32_t e = rowptr[i] + lane; e < e1; e += 64) {
+  if (rows) {
+    for (int32_t e = e0 + lane; e < e1; e += 64) {
       const int64_t p = pid[e];
       const double sg = (nbr[e] > i) ? 1.0 : -1.0;
       fx += sg * (double)gpair[3 * p];
@@ -1276,11 +1420,23 @@ __global__ void __launch_bounds__(256) k_force_gather_w(int64_t n, const int32_t
   fy = wave_sum_d(fy);
   fz = wave_sum_d(fz);
   if (lane == 0) {
-    const int64_t o = perm ? perm[i] : i;
     forces[3 * o] = (TO)fx;
     forces[3 * o + 1] = (TO)fy;
     forces[3 * o + 2] = (TO)fz;
   }
+}
+
+template <class T, class TO>
+__global__ void __launch_bounds__(256) k_force_gather_w(int64_t n, const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ nbr,
+                                                        const int32_t *__restrict__ pid, const int64_t *n_pairs,
+                                                        int64_t max_pairs, const T *__restrict__ gpair,
+                                                        const int32_t *__restrict__ perm, TO *__restrict__ forces) {
+  const int32_t i = wave_atom();
+  if (i >= n) return;
+  const bool rows = pairs_ok(n_pairs, max_pairs);
+  force_gather_wave<T, TO>(i, perm ? perm[i] : i, rows, rows ? rowptr[i] : 0, rows ? rowptr[i + 1] : 0, nbr, pid,
+                           gpair, forces);
 }
 
 // Launch one of the wave-per-atom gathers above: F = 64 one wave per atom; F = 128 and 256
@@ -1302,9 +1458,34 @@ __global__ void __launch_bounds__(256) k_force_gather_w(int64_t n, const int32_t
     return TN_OK;                                                                               \
   }
 TN_WAVE_GATHER_LAUNCHER(embed_gather_w, k_embed_gather_w)
-TN_WAVE_GATHER_LAUNCHER(message_w, k_message_w)
-TN_WAVE_GATHER_LAUNCHER(message_product_w, k_message_product_w)
 #undef TN_WAVE_GATHER_LAUNCHER
+
+// The message gathers, with the edge filters h (TH) and the gathered atom rows (TY) in FP32 or
+// BF16.
+#define TN_MESSAGE_LAUNCHER(NAME, KERNEL)                                                                   \
+  template <class TH, class TY, class... A>                                                               \
+  inline int NAME(hipStream_t s, int64_t F, int64_t n, const int32_t *rowptr, const int32_t *nbr,          \
+                  const int32_t *pid, const int64_t *n_pairs, int64_t max_pairs, const TH *h, const TY *y, \
+                  A... a) {                                                                                \
+    if (n <= 0) return TN_OK;                                                                              \
+    const dim3 b(256);                                                                                     \
+    if (F == 64)                                                                                           \
+      hipLaunchKernelGGL((KERNEL<1, 1, TH, TY>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid,   \
+                         n_pairs, max_pairs, h, y, a...);                                                  \
+    else if (F == 128)                                                                                     \
+      hipLaunchKernelGGL((KERNEL<1, 2, TH, TY>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr,    \
+                         pid, n_pairs, max_pairs, h, y, a...);                                             \
+    else if (F == 256)                                                                                     \
+      hipLaunchKernelGGL((KERNEL<2, 2, TH, TY>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr,    \
+                         pid, n_pairs, max_pairs, h, y, a...);                                             \
+    else                                                                                                   \
+      return TN_E_UNSUPPORTED;                                                                             \
+    TN_LAUNCH_CHECK();                                                                                     \
+    return TN_OK;                                                                                          \
+  }
+TN_MESSAGE_LAUNCHER(message_w, k_message_w)
+TN_MESSAGE_LAUNCHER(message_product_w, k_message_product_w)
+#undef TN_MESSAGE_LAUNCHER
 
 template <class TI, class TO>
 inline int convert(hipStream_t s, const TI *in, TO *out, int64_t n) {

@@ -281,7 +281,7 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
     if ((rc = mix<T>(s, w.dD, w.dPb, N, F, W2, W2T, 1, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_product_bwd<T>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dPb, w.P[l], w.nP[l], w.Y[l],
-                         w.M[l], w.dY, w.dM);
+                         w.M[l], w.dY, w.dM, nullptr);
       TN_LAUNCH_CHECK();
       hipLaunchKernelGGL(k_message<T>, dim3(gNF), dim3(bs), 0, s, N, (int)F, rowptr, nbr, pid, np, MP, w.h[l], w.dM,
                          w.dY, 1);

@@ -130,8 +130,11 @@ __global__ void __launch_bounds__(256) k_gemm_dual(DualGemmArgs<S> g) {
     const int64_t md = *g.Mdev;
     if (md < Mrows) Mrows = md;
   }
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * GBN;
+  // one flat block index over (row tile, column tile), column tiles fastest (so the blocks that
+  // share a row tile run together); a flat x dimension has no 65535-block limit
+  const int64_t nb = (g.N + GBN - 1) / GBN;
+  const int64_t m0 = (int64_t)(blockIdx.x / nb) * BM;
+  const int64_t n0 = (int64_t)(blockIdx.x % nb) * GBN;
   if (m0 >= Mrows) return;
   const int z = blockIdx.z;
   const D *__restrict__ A = g.A + z * g.zoff;
@@ -233,10 +236,10 @@ inline int dgemm(hipStream_t s, const DualGemmArgs<S> &g, int zdim = 1) {
   const int64_t nb = (g.N + GBN - 1) / GBN;
   const int64_t tiles64 = nb * ((g.M + 63) / 64) * zdim;
   if (tiles64 < 512) {
-    dim3 grid((unsigned)nb, (unsigned)((g.M + 31) / 32), (unsigned)zdim);
+    dim3 grid((unsigned)(nb * ((g.M + 31) / 32)), 1, (unsigned)zdim);
     hipLaunchKernelGGL((k_gemm_dual<S, 32>), grid, dim3(256), 0, s, g);
   } else {
-    dim3 grid((unsigned)nb, (unsigned)((g.M + 63) / 64), (unsigned)zdim);
+    dim3 grid((unsigned)(nb * ((g.M + 63) / 64)), 1, (unsigned)zdim);
     hipLaunchKernelGGL((k_gemm_dual<S, 64>), grid, dim3(256), 0, s, g);
   }
   TN_LAUNCH_CHECK();
@@ -279,13 +282,14 @@ inline int dmix(hipStream_t s, const Dual<S> *in, Dual<S> *out, int64_t N, int64
 }
 
 // Parameter adjoints on the matrix cores: P[z][o][k] = sum over the rows r of slice z of
-// A(r, o) B(r, k), both dual: value A_v B_v, eps part A_d B_v + A_v B_d (three MFMA per
-// fragment).  64x64 outputs per block, 32 rows staged per step in LDS as [row][column] tiles
+// A(r, o) B(r, k), both dual.  Only the eps part A_d B_v + A_v B_d is formed (two MFMA per
+// fragment): the loss gradient is the eps part of every weight adjoint, and nothing reads the
+// value part, which is written as zero.  64x64 outputs per block, 32 rows staged per step in LDS as [row][column] tiles
 // (coalesced along the feature axis); lane l of MFMA 16x16x4 supplies A(r0 + l/16, o0 + l%16)
 // and B(r0 + l/16, k0 + l%16).  Every block writes its outputs.  With Q given, the blocks of
 // the first column block also form the column sums of A over the slice (the bias adjoint of
-// a linear map, from the tiles already in LDS): Q[z][o] = sum_r A(r, o), four row groups
-// per column combined in a fixed order.
+// a linear map, from the tiles already in LDS): Q[z][o] = sum_r A_d(r, o) (eps part only),
+// four row groups per column combined in a fixed order.
 constexpr int WRC = 32;
 template <class S>
 __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma, const Dual<S> *B, RowMap mb,
@@ -295,7 +299,7 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma,
   using V = typename MfmaVec<S>::type;
   __shared__ S Av[WRC][64 + 1], Ad[WRC][64 + 1], Bv[WRC][64 + 1], Bd[WRC][64 + 1];
   const bool colsum = Q != nullptr && blockIdx.x == 0;
-  S qv = S(0), qd = S(0);   // column (tid % 64), rows tid / 64 + 4 m of each staged step
+  S qd = S(0);   // column (tid % 64), rows tid / 64 + 4 m of each staged step
   int64_t Rn = R;
   if (Rdev) {
     const int64_t md = *Rdev;
@@ -307,14 +311,11 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma,
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wo = (wave >> 1) * 32, wk = (wave & 1) * 32;
   const int r16 = lane & 15, q = lane >> 4;
-  V cv[2][2], cd[2][2];
+  V cd[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      cv[a][b] = V{S(0), S(0), S(0), S(0)};
-      cd[a][b] = V{S(0), S(0), S(0), S(0)};
-    }
+    for (int b = 0; b < 2; ++b) cd[a][b] = V{S(0), S(0), S(0), S(0)};
   constexpr int PER = WRC * 64 / 256;
   D xa[PER], xb[PER];
   auto load_rows = [&](int64_t r0) {
@@ -345,10 +346,7 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma,
     if (r0 + WRC < re) load_rows(r0 + WRC);
     if (colsum) {
 #pragma unroll
-      for (int rr = tid >> 6; rr < WRC; rr += 4) {
-        qv += Av[rr][tid & 63];
-        qd += Ad[rr][tid & 63];
-      }
+      for (int rr = tid >> 6; rr < WRC; rr += 4) qd += Ad[rr][tid & 63];
     }
 #pragma unroll
     for (int s4 = 0; s4 < WRC; s4 += 4) {
@@ -363,7 +361,6 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma,
         const S av = Av[s4 + q][wo + 16 * a + r16], ad = Ad[s4 + q][wo + 16 * a + r16];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          cv[a][b] = mfma_16x16x4(av, bv[b], cv[a][b]);
           cd[a][b] = mfma_16x16x4(ad, bv[b], cd[a][b]);
           cd[a][b] = mfma_16x16x4(av, bd[b], cd[a][b]);
         }
@@ -379,16 +376,14 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(const Dual<S> *A, RowMap ma,
       for (int t = 0; t < 4; ++t) {
         const int o = o0 + wo + 16 * a + (sizeof(S) == 4 ? 4 * q + t : 4 * t + q);
         const int k = k0 + wk + 16 * b + r16;
-        if (o < O && k < Kc) P[((int64_t)blockIdx.z * O + o) * Kc + k] = D(cv[a][b][t], cd[a][b][t]);
+        if (o < O && k < Kc) P[((int64_t)blockIdx.z * O + o) * Kc + k] = D(S(0), cd[a][b][t]);
       }
   if (colsum) {   // reuse the A tiles (every wave is past its last read of them)
-    Av[tid >> 6][tid & 63] = qv;
     Ad[tid >> 6][tid & 63] = qd;
     __syncthreads();
     const int o = o0 + tid;
     if (tid < 64 && o < O)
-      Q[(int64_t)blockIdx.z * O + o] = D(((Av[0][tid] + Av[1][tid]) + Av[2][tid]) + Av[3][tid],
-                                         ((Ad[0][tid] + Ad[1][tid]) + Ad[2][tid]) + Ad[3][tid]);
+      Q[(int64_t)blockIdx.z * O + o] = D(S(0), ((Ad[0][tid] + Ad[1][tid]) + Ad[2][tid]) + Ad[3][tid]);
   }
 }
 
@@ -994,7 +989,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
     if ((rc = dmix<S>(s, w.dD, w.dPb, N, F, W2, 1, 0))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_product_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.dPb, (const D *)w.P[l],
-                         (const D *)w.nP[l], (const D *)w.Y[l], (const D *)w.M[l], w.dY, w.dM);
+                         (const D *)w.nP[l], (const D *)w.Y[l], (const D *)w.M[l], w.dY, w.dM, nullptr);
       TN_LAUNCH_CHECK();
       if ((rc = dmessage<D>(s, N, F, rowptr, nbr, pid, np, MP, w.h[l], w.dM, w.dY, 1))) return rc;
     }
@@ -1125,8 +1120,6 @@ int tn_train_grad(const tn_model *m, void *stream, int64_t n_atoms, int64_t n_sy
   if (n_systems > 0 && (!energy || !energy_ref)) return TN_E_ARG;
   if (!loss || !grad || !n_pairs || !status || !ws) return TN_E_ARG;
   if (!std::isfinite(w_energy) || !std::isfinite(w_force)) return TN_E_ARG;
-  // the scalar products launch one block row per 16 rows of a pair array
-  if ((max_pairs + 15) / 16 > 65535 || (n_atoms + 15) / 16 > 65535) return TN_E_UNSUPPORTED;
   Problem pb;
   int rc = box_info(box, m->r_c, &pb.box);
   if (rc) return rc;

@@ -241,3 +241,36 @@ def test_training_step_in_a_hip_graph(dev):
         m.check()
         assert torch.equal(grad, eager)
         m.train_grad(args[0].double(), *args[1:], precision="fp64")   # eager work between replays
+
+
+def test_more_than_a_million_pairs(dev):
+    """A batch past 1,048,576 pairs (which the earlier 16-row block limit refused): 600 copies of
+    a set of molecules have the same mean losses as one copy, so the loss and every gradient
+    tensor must agree with the single copy's up to FP32 summation order; energies and forces
+    match tn_energy_forces on the same inputs."""
+    sizes = (40, 55, 64, 31, 48)
+    pos, z, batch, S, E_ref, F_ref, blob = _case(sizes, 128, 32, 2, 11)
+    reps = 600
+    posr = np.tile(pos, (reps, 1))
+    zr = np.tile(z, reps)
+    batchr = np.concatenate([batch + r * S for r in range(reps)]).astype(np.int32)
+    Er, Fr = np.tile(E_ref, reps), np.tile(F_ref, (reps, 1))
+    m = TensorNet(blob, dev)
+    t = lambda a, dt: torch.tensor(np.asarray(a), dtype=dt, device=dev)
+    loss1, _, _, g1 = m.train_grad(t(pos, torch.float32), t(z, torch.int32), t(batch, torch.int32), S,
+                                   t(E_ref, torch.float64), t(F_ref, torch.float64), max_pairs=40 * len(pos),
+                                   precision="fp32")
+    # a budget just above the true count (the dual workspace is about 60 KB per pair slot)
+    mp = int(int(m.n_pairs.item()) * reps * 1.02) + 1024
+    lossr, Eo, Fo, gr = m.train_grad(t(posr, torch.float32), t(zr, torch.int32), t(batchr, torch.int32), S * reps,
+                                     t(Er, torch.float64), t(Fr, torch.float64), max_pairs=mp, precision="fp32")
+    n_pairs = int(m.n_pairs.item())
+    assert n_pairs > (1 << 20), n_pairs
+    E2, F2 = m.energy_forces(t(posr, torch.float32), t(zr, torch.int32), t(batchr, torch.int32), S * reps,
+                             max_pairs=mp, precision="fp32")
+    assert torch.equal(Eo, E2) and torch.equal(Fo, F2)
+    g1n, grn = g1.cpu().numpy(), gr.cpu().numpy()
+    lerr = abs(float(lossr.item()) - float(loss1.item())) / abs(float(loss1.item()))
+    gerr = float(np.abs(grn - g1n).max() / np.abs(g1n).max())
+    print(f"{n_pairs} pairs: loss rel diff {lerr:.2e}, gradient max diff / max {gerr:.2e}", flush=True)
+    assert lerr <= 1e-5 and gerr <= 1e-4

@@ -125,5 +125,5 @@ def test_training_entry_points_reject_bad_requests_on_host():
     assert lib.tn_train_grad(one, None, 10, 1, one, one, one, None, 100, L.TN_FP64, *no_ref) == L.TN_E_ARG
     bad_w = (one, one, float("nan"), 1.0, one, one, one, one, one, one, one, 1 << 20)
     assert lib.tn_train_grad(one, None, 10, 1, one, one, one, None, 100, L.TN_FP64, *bad_w) == L.TN_E_ARG
-    huge = (1 << 20) * 16
-    assert lib.tn_train_grad(one, None, 10, 1, one, one, one, None, huge, L.TN_FP64, *tail) == L.TN_E_UNSUPPORTED
+    too_many = (1 << 30) + 1   # pair budgets above 2^30 are refused, as for tn_energy_forces
+    assert lib.tn_train_grad(one, None, 10, 1, one, one, one, None, too_many, L.TN_FP64, *tail) == L.TN_E_ARG
