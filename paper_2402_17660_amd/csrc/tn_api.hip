@@ -79,7 +79,7 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
   // room for the derived tables: species tables, basis constants, aligned and transposed
   // copies of the per-pair weights (each start aligned to 64 elements)
   const size_t extra = 2 * Z * F + 2 * K + 2 * (3 * F * K) + (size_t)m->L * 2 * (F * K + 2 * F * F + 6 * F * F) +
-                       (size_t)(m->L + 1) * 6 * F * F + 64 * (11 + 12 * (size_t)m->L);
+                       (size_t)(m->L + 1) * 12 * F * F + 64 * (14 + 18 * (size_t)m->L);
   packed.assign(total + extra, 0.0);
   size_t off = 0;
   const unsigned char *src = b + kHeaderBytes;
@@ -103,8 +103,9 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
   o.V = grab(Z * F);
   o.mu = grab(K);
   o.beta = grab(K);
-  // copies for the fused pair kernels: W0 [3F][K] as is and transposed; per layer Wa [F][K],
-  // Wb [2F][F], Wc [3F][2F] as is and transposed
+  // copies for the fused kernels: W0 [3F][K] as is and transposed; per layer Wa [F][K],
+  // Wb [2F][F], Wc [3F][2F] as is and transposed; every mixing matrix [F][F] transposed (adjoint
+  // mixing) and as is (forward mixing; the blob's own copy need not be 16-byte aligned)
   auto copy = [&](size_t src, size_t rows, size_t cols, bool transpose) {
     const size_t at = grab(rows * cols);
     for (size_t r = 0; r < rows; ++r)
@@ -114,7 +115,10 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
   };
   o.W0f = copy(o.W0, 3 * F, K, false);
   o.W0T = copy(o.W0, 3 * F, K, true);
-  for (int q = 0; q < 3; ++q) o.WmixT[q] = copy(o.Wmix[q], F, F, true);
+  for (int q = 0; q < 3; ++q) {
+    o.WmixT[q] = copy(o.Wmix[q], F, F, true);
+    o.Wmixf[q] = copy(o.Wmix[q], F, F, false);
+  }
   for (int l = 0; l < m->L; ++l) {
     LayerOff &lo = o.layer[l];
     lo.Waf = copy(lo.Wa, F, K, false);
@@ -126,6 +130,8 @@ int parse_blob(const void *blob, size_t bytes, tn_model *m, std::vector<double> 
     for (int q = 0; q < 3; ++q) {
       lo.W1T[q] = copy(lo.W1[q], F, F, true);
       lo.W2T[q] = copy(lo.W2[q], F, F, true);
+      lo.W1f[q] = copy(lo.W1[q], F, F, false);
+      lo.W2f[q] = copy(lo.W2[q], F, F, false);
     }
   }
   o.total = off;

@@ -4,9 +4,10 @@
 // the geometry/basis, the embedding's node stage (norms, LayerNorm, MLP, gating; its channel
 // mixing is linear and runs in FP32) and the output network in FP64 ("islands"), reading and
 // writing the FP32 feature arrays directly; the per-system energy sum and the per-atom force
-// sum in FP64.  The BF16 variant feeds the pair kernels' GEMMs BF16 operands (FP32
-// accumulation), stores the edge filters h in BF16 for the message gathers, and runs the
-// islands in FP32 (its error budget is set by the BF16 operands).
+// sum in FP64.  The BF16 variant feeds the pair kernels' GEMMs and the channel mixing BF16
+// operands (FP32 accumulation and FP32 feature arrays), stores the edge filters h and copies
+// of Y and dE/dM in BF16 for the message gathers, and runs the islands in FP32 (its error
+// budget is set by the BF16 operands).
 #include "tn_nodeops.h"
 
 namespace tn {
@@ -52,7 +53,7 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   plan_neighbors(p, N, MP, bi, &w->nb);
   w->geo = p.take<float>(4 * MP);
   w->phi = p.take<float>(MP);
-  w->f0 = p.take<float>(MP * 3 * F);
+  w->f0 = p.take<float>(bf16 ? MP * 3 * F / 2 : MP * 3 * F);   // BF16 in the BF16 path
   w->Xr = p.take<float>(N * 9 * F);
   w->T0 = p.take<float>(N * 9 * F);
   w->nrm0 = p.take<TA>(N * F);
@@ -149,6 +150,19 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
 
   // ---- all per-pair work of the forward pass in one MFMA kernel
   auto WB = [&](size_t off) { return static_cast<const __bf16 *>(m->w16 + off); };
+  // Per-part channel mixing with one set of matrices (Wf: aligned copies, WT: their transposes):
+  // FP32 matrix-core kernel, or BF16 operands with FP32 accumulation in the BF16 path.
+  auto mixing = [&](const float *in, float *out, const size_t Wf[3], const size_t WT[3], int adjoint,
+                    int accumulate, __bf16 *out16) -> int {
+    if (BF16) {
+      const size_t *off = adjoint ? WT : Wf;
+      const __bf16 *Bt[3] = {WB(off[0]), WB(off[1]), WB(off[2])};
+      return mix_bf16(s, in, out, N, F, Bt, accumulate, out16);
+    }
+    const float *Wm[3] = {W(Wf[0]), W(Wf[1]), W(Wf[2])};
+    const float *WmT[3] = {W(WT[0]), W(WT[1]), W(WT[2])};
+    return mix<float>(s, in, out, N, F, Wm, WmT, adjoint, accumulate, out16);
+  };
   auto fill_common = [&](auto &pf) {
     pf.pairs = gr.pairs;
     pf.max_pairs = MP;
@@ -182,7 +196,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     }
     pf.geo = w.geo;
     pf.phi = w.phi;
-    pf.f0 = w.f0;
+    pf.f0 = reinterpret_cast<__bf16 *>(w.f0);
     if ((rc = launch_pair_fwd_bf16(s, (int)F, (int)K, pf, pair_variant(m, true, MP, false)))) return rc;
   } else {
     PairFwdArgs pf;
@@ -210,8 +224,8 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
 
   // ---- embedding node stage (FP64)
   const unsigned gNF = grid_for(N * F, bs);
-  if ((rc = embed_gather_w(s, F, N, rowptr, nbr, pid, np, MP, zz, m->max_z, W(o.U), W(o.V), w.geo, w.phi, w.f0,
-                           w.Xr)))
+  if ((rc = embed_gather_w(s, F, N, rowptr, nbr, pid, np, MP, zz, m->max_z, W(o.U), W(o.V), w.geo, w.phi,
+                           reinterpret_cast<const TH *>(w.f0), w.Xr)))
     return rc;
   if (N > 0) {
     hipLaunchKernelGGL((k_node_norm<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xr, w.nrm0);
@@ -222,11 +236,9 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   }
   if ((rc = linear_fwd<TA>(s, w.n0, N, F, WA(o.W1), WA(o.b1), 2 * F, w.ea1, w.ez1, 1))) return rc;
   if ((rc = linear_fwd<TA>(s, w.ea1, N, 2 * F, WA(o.W2), WA(o.b2), 3 * F, w.g, w.ez2, 1))) return rc;
-  // the embedding's channel mixing is linear in the FP32 features and runs in FP32; the
-  // gating product is formed in FP64 and rounded once
-  const float *Wemb[3] = {W(o.Wmix[0]), W(o.Wmix[1]), W(o.Wmix[2])};
-  const float *WembT[3] = {W(o.WmixT[0]), W(o.WmixT[1]), W(o.WmixT[2])};
-  if ((rc = mix<float>(s, w.Xr, w.T0, N, F, Wemb, WembT, 0, 0))) return rc;
+  // the embedding's channel mixing is linear in the FP32 features and runs in FP32 (BF16 operands
+  // in the BF16 path); the gating product is formed in FP64 and rounded once
+  if ((rc = mixing(w.Xr, w.T0, o.Wmixf, o.WmixT, 0, 0, nullptr))) return rc;
   // (with layers, the gating also normalises the first layer's input)
   if (N > 0 && L > 0) {
     hipLaunchKernelGGL((k_gate_normalize<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.g, w.T0, w.X[0],
@@ -240,19 +252,15 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   // ---- interaction layers: mix, message+product, mix, residual(+normalise)
   for (int64_t l = 0; l < L; ++l) {
     const LayerOff &lo = o.layer[l];
-    const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
-    const float *W1T[3] = {W(lo.W1T[0]), W(lo.W1T[1]), W(lo.W1T[2])};
     __bf16 *y16 = BF16 ? w.Y16[l] : nullptr;
-    if ((rc = mix<float>(s, w.Xb[l], w.Y[l], N, F, W1, W1T, 0, 0, y16))) return rc;
+    if ((rc = mixing(w.Xb[l], w.Y[l], lo.W1f, lo.W1T, 0, 0, y16))) return rc;
     // the neighbours' rows from the BF16 copy in the BF16 path
     const TY *yg = BF16 ? reinterpret_cast<const TY *>(y16) : reinterpret_cast<const TY *>(w.Y[l]);
     if ((rc = message_product_w(s, F, N, rowptr, nbr, pid, np, MP, reinterpret_cast<const TH *>(w.h[l]), yg, w.Y[l],
                                 w.M[l], w.P[l], w.nP[l],
                                 w.Pb[l])))
       return rc;
-    const float *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
-    const float *W2T[3] = {W(lo.W2T[0]), W(lo.W2T[1]), W(lo.W2T[2])};
-    if ((rc = mix<float>(s, w.Pb[l], w.D[l], N, F, W2, W2T, 0, 0))) return rc;
+    if ((rc = mixing(w.Pb[l], w.D[l], lo.W2f, lo.W2T, 0, 0, nullptr))) return rc;
     if (N > 0) {
       if (l + 1 < L) {
         hipLaunchKernelGGL(k_residual_normalize<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xb[l], w.D[l],
@@ -309,15 +317,11 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   }
   for (int64_t l = L - 1; l >= 0; --l) {
     const LayerOff &lo = o.layer[l];
-    const float *W1[3] = {W(lo.W1[0]), W(lo.W1[1]), W(lo.W1[2])};
-    const float *W1T[3] = {W(lo.W1T[0]), W(lo.W1T[1]), W(lo.W1T[2])};
-    const float *W2[3] = {W(lo.W2[0]), W(lo.W2[1]), W(lo.W2[2])};
-    const float *W2T[3] = {W(lo.W2T[0]), W(lo.W2T[1]), W(lo.W2T[2])};
     if (N > 0) {
       hipLaunchKernelGGL(k_residual_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.D[l], w.dX, w.dD);
       TN_LAUNCH_CHECK();
     }
-    if ((rc = mix<float>(s, w.dD, w.dPb, N, F, W2, W2T, 1, 0))) return rc;
+    if ((rc = mixing(w.dD, w.dPb, lo.W2f, lo.W2T, 1, 0, nullptr))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_product_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dPb, w.P[l], w.nP[l], w.Y[l],
                          w.M[l], w.dY, w.dM[l], BF16 ? w.dM16[l] : nullptr);
@@ -326,7 +330,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     const TY *dmg = BF16 ? reinterpret_cast<const TY *>(w.dM16[l]) : reinterpret_cast<const TY *>(w.dM[l]);
     if ((rc = message_w(s, F, N, rowptr, nbr, pid, np, MP, reinterpret_cast<const TH *>(w.h[l]), dmg, w.dY, 1)))
       return rc;
-    if ((rc = mix<float>(s, w.dY, w.dX, N, F, W1, W1T, 1, 1))) return rc;
+    if ((rc = mixing(w.dY, w.dX, lo.W1f, lo.W1T, 1, 1, nullptr))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_normalize_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[l], w.nX[l], w.dX);
       TN_LAUNCH_CHECK();
@@ -338,7 +342,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
                        w.dT0, w.ez2);
     TN_LAUNCH_CHECK();
   }
-  if ((rc = mix<float>(s, w.dT0, w.dXr, N, F, Wemb, WembT, 1, 0))) return rc;
+  if ((rc = mixing(w.dT0, w.dXr, o.Wmixf, o.WmixT, 1, 0, nullptr))) return rc;
   if ((rc = linear_bwd<TA>(s, w.dez2, N, 3 * F, WA(o.W2), 2 * F, w.dez1, w.ez1, 0))) return rc;
   if ((rc = linear_bwd<TA>(s, w.dez1, N, 2 * F, WA(o.W1), F, w.dn0, nullptr, 0))) return rc;
   if (N > 0) {
@@ -357,7 +361,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     pbw.g.U = W(o.U);
     pbw.g.V = W(o.V);
     pbw.g.max_z = m->max_z;
-    pbw.g.f0 = w.f0;
+    pbw.g.f016 = reinterpret_cast<const __bf16 *>(w.f0);
     pbw.g.dXr = w.dXr;
     for (int64_t l = 0; l < L; ++l) {
       const LayerOff &lo = o.layer[l];

@@ -36,6 +36,7 @@ struct LayerOff {
   size_t WaT, WbT, WcT;   // transposed copies [K][F], [F][2F], [2F][3F] (fused reverse sweep)
   size_t Waf, Wbf, Wcf;   // 64-element aligned copies of Wa, Wb, Wc (fused forward)
   size_t W1T[3], W2T[3];  // transposed mixing matrices, 64-element aligned (adjoint mixing)
+  size_t W1f[3], W2f[3];  // 64-element aligned copies of the mixing matrices (forward mixing)
 };
 
 struct WeightOff {
@@ -44,6 +45,7 @@ struct WeightOff {
   size_t oln_g, oln_b, Wo, bo, Wh, bh, wout, bout;
   size_t W0T, W0f;  // transposed [K][3F] and aligned copy of W0
   size_t WmixT[3];  // transposed embedding mixing matrices (adjoint mixing)
+  size_t Wmixf[3];  // 64-element aligned copies of the embedding mixing matrices
   size_t U, V;      // species tables [max_z, F]: Z_ij = U[z_i] + V[z_j]
   size_t mu, beta;  // radial basis constants [K]
   size_t total;     // element count of one packed copy
@@ -202,6 +204,7 @@ struct BwdGather {
   const float *U = nullptr, *V = nullptr;
   int max_z = 0;
   const float *f0 = nullptr;
+  const __bf16 *f016 = nullptr;   // f0 in BF16 (BF16 path; f0 then unused)
   const float *dXr = nullptr;
   const float *Y[kMaxLayers], *dM[kMaxLayers];
 };
@@ -240,7 +243,8 @@ struct PairFwdArgsB {
   const __bf16 *Wa[kMaxLayers], *Wb[kMaxLayers], *Wc[kMaxLayers];
   const float *ba[kMaxLayers], *bb[kMaxLayers], *bc[kMaxLayers];
   int L = 0;
-  float *geo = nullptr, *phi = nullptr, *f0 = nullptr;
+  float *geo = nullptr, *phi = nullptr;
+  __bf16 *f0 = nullptr;   // the embedding map W0 e + b0 in BF16
   __bf16 *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers];
   __bf16 *h[kMaxLayers];   // the edge filters in BF16 (read by the message gathers)
 };

@@ -11,6 +11,16 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16): lane l holds
+// A[l%16][8(l/16)..8(l/16)+7] and B[8(l/16)..+7][l%16]; the result layout is that of mfma4.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int kPadB = 8;   // LDS row padding of BF16 operand tiles (elements)
+
+__device__ __forceinline__ floatx4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 // acc[rb][cb] += act_rb[16 x Kin] * Bt^T for rb < RB, where row i of block rb starts at
 // act + rb*rbs + i*ld (LDS) and Bt is [ncol][Kin] in global memory (row stride Kin); this wave
 // covers columns col0 .. col0 + 16*NB - 1 (v_mfma_f32_16x16x4f32).  Inside each 16-wide K

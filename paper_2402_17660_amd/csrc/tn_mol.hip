@@ -59,7 +59,7 @@ __host__ __device__ inline void plan_mol(WsPlan &p, int64_t F, int64_t L, int64_
   w->pairs = p.take<int32_t>(2 * MP);
   w->geo = p.take<float>(4 * MP);
   w->phi = p.take<float>(MP);
-  w->f0 = p.take<float>(MP * 3 * F);
+  w->f0 = p.take<float>(std::is_same<TA, float>::value ? MP * 3 * F / 2 : MP * 3 * F);   // BF16 in the BF16 path
   w->Xr = p.take<float>(N * 9 * F);
   w->T0 = p.take<float>(N * 9 * F);
   w->nrm0 = p.take<TA>(N * F);
@@ -118,7 +118,7 @@ __host__ __device__ inline void plan_mol(WsPlan &p, int64_t F, int64_t L, int64_
 }
 
 // Weight pointers of the model (FP32 copies for the FP32 stages, FP64 for the islands, BF16
-// for the BF16 pair tiles).
+// for the BF16 pair tiles and mixing).
 template <class T>
 struct IslandWeights {
   const T *ln_g, *ln_b, *W1, *b1, *W2, *b2, *oln_g, *oln_b, *Wo, *bo, *Wh, *bh, *wout, *bout;
@@ -129,6 +129,9 @@ struct MolWeights {
   IslandWeights<double> i64;
   IslandWeights<float> i32;
   const float *W1l[kMaxLayers][3], *W1Tl[kMaxLayers][3], *W2l[kMaxLayers][3], *W2Tl[kMaxLayers][3];
+  // BF16 copies of the mixing matrices (BF16 path)
+  const __bf16 *Wemb16[3], *WembT16[3];
+  const __bf16 *W1l16[kMaxLayers][3], *W1Tl16[kMaxLayers][3], *W2l16[kMaxLayers][3], *W2Tl16[kMaxLayers][3];
 };
 
 __device__ __forceinline__ const IslandWeights<double> &island(const MolWeights &w, double) { return w.i64; }
@@ -256,7 +259,8 @@ __device__ inline void layernorm_bwd_row_wave(int64_t r, int C, const TA *dy, co
 // tiles bring their own LDS arrays.
 template <int F>
 struct MolLds {
-  static constexpr size_t mixb = 16 * 5 * (F + 4) * 4;
+  static constexpr size_t mixb = 16 * 5 * (F + 4) * 4;   // FP32 staging; the BF16 staging is smaller
+  static_assert(16 * 5 * (F + kPadB) * 2 <= mixb, "BF16 mixing tile exceeds the buffer");
   static constexpr size_t gemmb = (32 + GBN) * (GBK + 1) * 8;
   static constexpr size_t bytes = mixb > gemmb ? mixb : gemmb;
 };
@@ -321,7 +325,6 @@ __global__ void __launch_bounds__(kMolThreads) k_mol_setup(MolCall c) {
   };
   auto gather = [&](BwdGather &g) {
     g.z = c.z;
-    g.f0 = w.f0;
     g.dXr = w.dXr;
     for (int l = 0; l < c.L; ++l) {
       g.Y[l] = w.Y[l];
@@ -340,7 +343,10 @@ __global__ void __launch_bounds__(kMolThreads) k_mol_setup(MolCall c) {
   }
   a->pf.geo = a->pfb.geo = w.geo;
   a->pf.phi = a->pfb.phi = w.phi;
-  a->pf.f0 = a->pfb.f0 = w.f0;
+  a->pf.f0 = w.f0;
+  a->pfb.f0 = reinterpret_cast<__bf16 *>(w.f0);
+  a->pb.g.f0 = w.f0;
+  a->pbb.g.f016 = reinterpret_cast<const __bf16 *>(w.f0);
   a->pb.gpair = a->pbb.gpair = w.gpair;
   for (int l = 0; l < c.L; ++l) {
     a->pf.z1[l] = w.z1[l];
@@ -500,8 +506,8 @@ __global__ void __launch_bounds__(kMolThreads, 1)
       }
     };
     atoms_waves([&](int32_t i, int f) {
-      embed_gather_wave<V, G>(i, f, w.rowbeg[i], w.rowbeg[i] + w.deg[i], w.nbr, w.pid, a.z, a.max_z, wt.U, wt.V,
-                              w.geo, w.phi, w.f0, w.Xr);
+      embed_gather_wave<V, G, TH>(i, f, w.rowbeg[i], w.rowbeg[i] + w.deg[i], w.nbr, w.pid, a.z, a.max_z, wt.U,
+                                  wt.V, w.geo, w.phi, reinterpret_cast<const TH *>(w.f0), w.Xr);
     });
     __syncthreads();
     auto per_channel = [&](int64_t per_atom, auto &&fn) {
@@ -528,13 +534,26 @@ __global__ void __launch_bounds__(kMolThreads, 1)
       for (int64_t blk = 0; blk < nb * mt; ++blk) gemm_tile<TA, 32>(s_gemm, blk, 0, As, Bs);
       __syncthreads();
     };
-    auto mix_rows = [&](const float *in, float *out, const float *const B[3], int acc, __bf16 *out16 = nullptr) {
-      const int64_t nt = (n + 15) / 16 * NCB * 3;
-      float *sA = reinterpret_cast<float *>(smem);
-      for (int64_t t = 0; t < nt; ++t) {
-        mix_tile<F, NBMIX>(in + a0 * 9 * F, out + a0 * 9 * F, n, B[0], B[1], B[2], acc, NCB, t, sA,
-                           out16 ? out16 + a0 * 9 * F : nullptr);
-        __syncthreads();
+    // channel mixing of the system's rows: FP32 matrix cores, or BF16 operands in the BF16 path
+    auto mix_rows = [&](const float *in, float *out, const float *const B[3], const __bf16 *const B16[3], int acc,
+                        __bf16 *out16 = nullptr) {
+      __bf16 *o16 = out16 ? out16 + a0 * 9 * F : nullptr;
+      if constexpr (BF16) {
+        constexpr int NB16 = MixBf16Shape<F>::NB, NCB16 = MixBf16Shape<F>::ncb;
+        const int64_t nt = (n + 15) / 16 * NCB16 * 3;
+        __bf16 *sA = reinterpret_cast<__bf16 *>(smem);
+        for (int64_t t = 0; t < nt; ++t) {
+          mix_tile_bf16<F, NB16>(in + a0 * 9 * F, out + a0 * 9 * F, n, B16[0], B16[1], B16[2], acc, NCB16, t, sA,
+                                 o16);
+          __syncthreads();
+        }
+      } else {
+        const int64_t nt = (n + 15) / 16 * NCB * 3;
+        float *sA = reinterpret_cast<float *>(smem);
+        for (int64_t t = 0; t < nt; ++t) {
+          mix_tile<F, NBMIX>(in + a0 * 9 * F, out + a0 * 9 * F, n, B[0], B[1], B[2], acc, NCB, t, sA, o16);
+          __syncthreads();
+        }
       }
     };
     // ---- embedding node stage (FP64)
@@ -544,7 +563,7 @@ __global__ void __launch_bounds__(kMolThreads, 1)
     __syncthreads();
     gemm_rows(linear_fwd_args<TA>(w.n0, n, F, iw.W1, iw.b1, 2 * F, w.ea1, w.ez1, 1));
     gemm_rows(linear_fwd_args<TA>(w.ea1, n, 2 * F, iw.W2, iw.b2, 3 * F, w.g, w.ez2, 1));
-    mix_rows(w.Xr, w.T0, wt.Wemb, 0);
+    mix_rows(w.Xr, w.T0, wt.Wemb, wt.Wemb16, 0);
     if (a.L > 0)
       per_channel(F, [&](int64_t t) { gate_normalize_at<TA, float>(t, F, w.g, w.T0, w.X[0], w.nX[0], w.Xb[0]); });
     else
@@ -552,7 +571,7 @@ __global__ void __launch_bounds__(kMolThreads, 1)
     __syncthreads();
     // ---- interaction layers
     for (int l = 0; l < a.L; ++l) {
-      mix_rows(w.Xb[l], w.Y[l], wt.W1l[l], 0, BF16 ? w.Y16[l] : nullptr);
+      mix_rows(w.Xb[l], w.Y[l], wt.W1l[l], wt.W1l16[l], 0, BF16 ? w.Y16[l] : nullptr);
       const TY *yg = BF16 ? reinterpret_cast<const TY *>(w.Y16[l]) : reinterpret_cast<const TY *>(w.Y[l]);
       atoms_waves([&](int32_t i, int f) {
         message_product_wave<V, G, TH, TY>(i, f, w.rowbeg[i], w.rowbeg[i] + w.deg[i], w.nbr, w.pid,
@@ -560,7 +579,7 @@ __global__ void __launch_bounds__(kMolThreads, 1)
                                            w.nP[l], w.Pb[l]);
       });
       __syncthreads();
-      mix_rows(w.Pb[l], w.D[l], wt.W2l[l], 0);
+      mix_rows(w.Pb[l], w.D[l], wt.W2l[l], wt.W2l16[l], 0);
       if (l + 1 < a.L)
         per_channel(F, [&](int64_t t) {
           residual_normalize_at<float>(t, F, w.Xb[l], w.D[l], w.X[l + 1], w.nX[l + 1], w.Xb[l + 1]);
@@ -609,7 +628,7 @@ __global__ void __launch_bounds__(kMolThreads, 1)
     for (int l = a.L - 1; l >= 0; --l) {
       per_channel(F, [&](int64_t t) { residual_bwd_at<float>(t, F, w.D[l], w.dX, w.dD); });
       __syncthreads();
-      mix_rows(w.dD, w.dPb, wt.W2Tl[l], 0);
+      mix_rows(w.dD, w.dPb, wt.W2Tl[l], wt.W2Tl16[l], 0);
       per_channel(F, [&](int64_t t) {
         product_bwd_at<float>(t, F, w.dPb, w.P[l], w.nP[l], w.Y[l], w.M[l], w.dY, w.dM[l],
                               BF16 ? w.dM16[l] : nullptr);
@@ -621,13 +640,13 @@ __global__ void __launch_bounds__(kMolThreads, 1)
                                    reinterpret_cast<const TH *>(w.h[l]), dmg, w.dY, 1);
       });
       __syncthreads();
-      mix_rows(w.dY, w.dX, wt.W1Tl[l], 1);
+      mix_rows(w.dY, w.dX, wt.W1Tl[l], wt.W1Tl16[l], 1);
       per_channel(F, [&](int64_t t) { normalize_bwd_at<float>(t, F, w.X[l], w.nX[l], w.dX); });
       __syncthreads();
     }
     per_channel(F, [&](int64_t t) { gate_bwd_at<TA, float>(t, F, w.dX, w.T0, w.g, w.dez2, w.dT0, w.ez2); });
     __syncthreads();
-    mix_rows(w.dT0, w.dXr, wt.WembT, 0);
+    mix_rows(w.dT0, w.dXr, wt.WembT, wt.WembT16, 0);
     gemm_rows(linear_bwd_args<TA>(w.dez2, n, 3 * F, iw.W2, 2 * F, w.dez1, w.ez1, 0));
     gemm_rows(linear_bwd_args<TA>(w.dez1, n, 2 * F, iw.W1, F, w.dn0, nullptr, 0));
     per_row_wave([&](int64_t r) { layernorm_bwd_row_wave(r, F, w.dn0, w.xhat0, w.rstd0, iw.ln_g, w.dnrm0); });
@@ -744,8 +763,10 @@ int molecule_setup(tn_model *m) {
   wt.U = W(o.U);
   wt.V = W(o.V);
   for (int q = 0; q < 3; ++q) {
-    wt.Wemb[q] = W(o.Wmix[q]);
+    wt.Wemb[q] = W(o.Wmixf[q]);
     wt.WembT[q] = W(o.WmixT[q]);
+    wt.Wemb16[q] = WB(o.Wmixf[q]);
+    wt.WembT16[q] = WB(o.WmixT[q]);
   }
   auto islands = [&](auto &iw, auto ptr) {
     iw.ln_g = ptr(o.ln_g);
@@ -767,10 +788,14 @@ int molecule_setup(tn_model *m) {
   islands(wt.i32, W);
   for (int64_t l = 0; l < L; ++l)
     for (int q = 0; q < 3; ++q) {
-      wt.W1l[l][q] = W(o.layer[l].W1[q]);
+      wt.W1l[l][q] = W(o.layer[l].W1f[q]);
       wt.W1Tl[l][q] = W(o.layer[l].W1T[q]);
-      wt.W2l[l][q] = W(o.layer[l].W2[q]);
+      wt.W2l[l][q] = W(o.layer[l].W2f[q]);
       wt.W2Tl[l][q] = W(o.layer[l].W2T[q]);
+      wt.W1l16[l][q] = WB(o.layer[l].W1f[q]);
+      wt.W1Tl16[l][q] = WB(o.layer[l].W1T[q]);
+      wt.W2l16[l][q] = WB(o.layer[l].W2f[q]);
+      wt.W2Tl16[l][q] = WB(o.layer[l].W2T[q]);
     }
   auto model_fields = [&](auto &p) {
     p.lat = Lattice{};

@@ -357,6 +357,139 @@ inline int launch_mix(hipStream_t s, const float *in, float *out, int64_t N, con
   return TN_OK;
 }
 
+// BF16 channel mixing (the BF16 precision mode): the tiles of mix_tile, with the part's
+// coordinates rounded to BF16 as they are staged in LDS, BF16 weights held in registers
+// (KC = F/32 fragments of 32 input channels per 16 output channels) and
+// v_mfma_f32_16x16x32_bf16; FP32 accumulation, FP32 output (plus the optional BF16 copy).
+// sA holds 16 * 5 * (F + kPadB) BF16 elements.  256 threads.
+template <int F, int NB>
+__device__ __forceinline__ void mix_tile_bf16(const float *__restrict__ in, float *__restrict__ out, int64_t N,
+                                              const __bf16 *__restrict__ B0, const __bf16 *__restrict__ B1,
+                                              const __bf16 *__restrict__ B2, int accumulate, int ncb, int64_t t,
+                                              __bf16 *__restrict__ sA, __bf16 *__restrict__ out16 = nullptr) {
+  constexpr int LD = F + kPadB;
+  constexpr int KC = F / 32;
+  const int64_t a0 = (t / (3 * ncb)) * 16;
+  const int part = (int)(t % 3);
+  const int cblk = (int)((t / 3) % ncb);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col0 = cblk * 64 * NB + wave * 16 * NB;
+  const int64_t navail = N - a0 < 16 ? N - a0 : 16;
+  const int r16 = lane & 15, q = lane >> 4;
+  auto run = [&](auto c0_tag, auto nc_tag, const __bf16 *Bt) {
+    constexpr int C0 = decltype(c0_tag)::value, NC = decltype(nc_tag)::value;
+    bf16x8 breg[KC][NB];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+        breg[kc][cb] = *reinterpret_cast<const bf16x8 *>(Bt + (size_t)(col0 + cb * 16 + r16) * F + 32 * kc + 8 * q);
+    const float4 *src = reinterpret_cast<const float4 *>(in + a0 * 9 * F);
+    constexpr int NE = 16 * NC * (F / 4), IT = (NE + 255) / 256;
+    float4 stage[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + 256 * it;
+      const int row = e / (F / 4), c4 = e % (F / 4);   // row = atom * NC + coordinate
+      const int at = row / NC, cc = row % NC;
+      stage[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NE && at < navail) stage[it] = src[(at * 9 + C0 + cc) * (F / 4) + c4];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + 256 * it;
+      const int row = e / (F / 4), c4 = e % (F / 4);
+      if (e < NE) {
+        bf16x4 v;
+        v[0] = (__bf16)stage[it].x;
+        v[1] = (__bf16)stage[it].y;
+        v[2] = (__bf16)stage[it].z;
+        v[3] = (__bf16)stage[it].w;
+        *reinterpret_cast<bf16x4 *>(sA + row * LD + 4 * c4) = v;
+      }
+    }
+    __syncthreads();
+    floatx4 acc[NC][NB];
+    zero_acc_rb<NC, NB>(acc);
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int rb = 0; rb < NC; ++rb) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sA + (r16 * NC + rb) * LD + 32 * kc + 8 * q);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = mfma_bf16(a, breg[kc][cb], acc[rb][cb]);
+      }
+    if (accumulate) {
+      float old[NC][NB][4];
+#pragma unroll
+      for (int rb = 0; rb < NC; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int at = 4 * q + e;
+            old[rb][cb][e] = at < navail ? out[((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16] : 0.f;
+          }
+#pragma unroll
+      for (int rb = 0; rb < NC; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[rb][cb][e] = old[rb][cb][e] + acc[rb][cb][e];
+    }
+#pragma unroll
+    for (int rb = 0; rb < NC; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int at = 4 * q + e;
+          if (at < navail) {
+            const int64_t o = ((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16;
+            out[o] = acc[rb][cb][e];
+            if (out16) out16[o] = (__bf16)acc[rb][cb][e];
+          }
+        }
+  };
+  if (part == 0)
+    run(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}, B0);
+  else if (part == 1)
+    run(std::integral_constant<int, 1>{}, std::integral_constant<int, 3>{}, B1);
+  else
+    run(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2);
+}
+
+template <int F, int NB>
+__global__ void __launch_bounds__(256) k_mix_bf16(const float *__restrict__ in, float *__restrict__ out, int64_t N,
+                                                  const __bf16 *__restrict__ B0, const __bf16 *__restrict__ B1,
+                                                  const __bf16 *__restrict__ B2, int accumulate, int ncb,
+                                                  int64_t ntiles, __bf16 *__restrict__ out16) {
+  __shared__ __attribute__((aligned(16))) __bf16 sA[16 * 5 * (F + kPadB)];
+  const int64_t per_xcd = (int64_t)gridDim.x / 8;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= ntiles) return;
+  mix_tile_bf16<F, NB>(in, out, N, B0, B1, B2, accumulate, ncb, t, sA, out16);
+}
+
+// output channels per BF16 mixing workgroup: all F for F <= 128 (each staged part is read once)
+template <int F>
+struct MixBf16Shape {
+  static constexpr int NB = F >= 128 ? 2 : 1;
+  static constexpr int ncb = F / (64 * NB);
+};
+
+template <int F>
+inline int launch_mix_bf16(hipStream_t s, const float *in, float *out, int64_t N, const __bf16 *const Bt[3],
+                           int accumulate, __bf16 *out16) {
+  constexpr int NB = MixBf16Shape<F>::NB, ncb = MixBf16Shape<F>::ncb;
+  const int64_t ntiles = (N + 15) / 16 * ncb * 3;
+  const int64_t grid = (ntiles + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_mix_bf16<F, NB>), dim3((unsigned)grid), dim3(256), 0, s, in, out, N, Bt[0], Bt[1], Bt[2],
+                     accumulate, ncb, ntiles, out16);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 // Per-part channel mixing of [N, 9, F] features: out[n,c,:] = W_part(c) in[n,c,:] (forward)
@@ -381,6 +514,20 @@ inline int mix(hipStream_t s, const T *in, T *out, int64_t N, int64_t F, const T
   g.M = N; g.N = F; g.K = F; g.zoff = F; g.zpart = 1; g.accumulate = accumulate;
   for (int q = 0; q < 3; ++q) g.Bz[q] = W[q];
   return gemm(s, g, 9);
+}
+
+// BF16 per-part channel mixing of FP32 [N, 9, F] features (see mix): Bt[p] is W_p (forward)
+// or its transpose (adjoint), BF16, 16-byte aligned.  F in {64, 128, 256}.
+inline int mix_bf16(hipStream_t s, const float *in, float *out, int64_t N, int64_t F, const __bf16 *const Bt[3],
+                    int accumulate, __bf16 *out16 = nullptr) {
+  if (N <= 0) return TN_OK;
+  bool ok = aligned16(in) && aligned16(out);
+  for (int q = 0; ok && q < 3; ++q) ok = Bt[q] != nullptr && aligned16(Bt[q]);
+  if (!ok) return TN_E_UNSUPPORTED;
+  if (F == 64) return launch_mix_bf16<64>(s, in, out, N, Bt, accumulate, out16);
+  if (F == 128) return launch_mix_bf16<128>(s, in, out, N, Bt, accumulate, out16);
+  if (F == 256) return launch_mix_bf16<256>(s, in, out, N, Bt, accumulate, out16);
+  return TN_E_UNSUPPORTED;
 }
 
 // ============================================================================ element kernels
@@ -1175,15 +1322,26 @@ __device__ __forceinline__ int group_channel() {
   return ((((int)threadIdx.x >> 6) % G) * 64 + ((int)threadIdx.x & 63)) * V;
 }
 
+// V consecutive values of a per-pair array stored as float or BF16, as floats.
+template <int V>
+__device__ __forceinline__ void ld_pair_row(const float *p, float (&o)[V]) {
+  ldv<V>(p, o);
+}
+template <int V>
+__device__ __forceinline__ void ld_pair_row(const __bf16 *p, float (&o)[V]) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) o[v] = (float)p[v];
+}
+
 // X_i = sum_j phi Z_ij (a 1 + b A0(u_ij) + c S0(u_ij)) for this lane's channels f .. f+V-1 of
-// atom i, whose CSR row is [e0, e1)
-template <int V, int G>
+// atom i, whose CSR row is [e0, e1); f0 = (a, b, c) per pair in FP32 or BF16 (TF)
+template <int V, int G, class TF>
 __device__ __forceinline__ void embed_gather_wave(int32_t i, int f, int32_t e0, int32_t e1,
                                                   const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
                                                   const int32_t *__restrict__ z, int max_z,
                                                   const float *__restrict__ U, const float *__restrict__ Vt,
                                                   const float *__restrict__ geo, const float *__restrict__ phi,
-                                                  const float *__restrict__ f0, float *__restrict__ X) {
+                                                  const TF *__restrict__ f0, float *__restrict__ X) {
   constexpr int F = 64 * V * G;
   float ui[V];
   ldv<V>(U + (int64_t)clamp_z(z[i], max_z) * F + f, ui);
@@ -1200,9 +1358,9 @@ __device__ __forceinline__ void embed_gather_wave(int32_t i, int f, int32_t e0, 
     const float ph = phi[p];
     float vj[V], a[V], b[V], cc[V];
     ldv<V>(Vt + (int64_t)clamp_z(z[j], max_z) * F + f, vj);
-    ldv<V>(f0 + p * 3 * F + f, a);
-    ldv<V>(f0 + p * 3 * F + F + f, b);
-    ldv<V>(f0 + p * 3 * F + 2 * F + f, cc);
+    ld_pair_row<V>(f0 + p * 3 * F + f, a);
+    ld_pair_row<V>(f0 + p * 3 * F + F + f, b);
+    ld_pair_row<V>(f0 + p * 3 * F + 2 * F + f, cc);
     float s5[5];
     s0_coords(ux, uy, uz, s5);
 #pragma unroll
@@ -1222,29 +1380,18 @@ __device__ __forceinline__ void embed_gather_wave(int32_t i, int f, int32_t e0, 
   for (int q = 0; q < 9; ++q) stv<V>(x + q * F, c[q]);
 }
 
-template <int V, int G = 1>
+template <int V, int G, class TF>
 __global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t *__restrict__ rowptr,
                                                         const int32_t *__restrict__ nbr,
                                                         const int32_t *__restrict__ pid, const int64_t *n_pairs,
                                                         int64_t max_pairs, const int32_t *__restrict__ z, int max_z,
                                                         const float *__restrict__ U, const float *__restrict__ Vt,
                                                         const float *__restrict__ geo, const float *__restrict__ phi,
-                                                        const float *__restrict__ f0, float *__restrict__ X) {
+                                                        const TF *__restrict__ f0, float *__restrict__ X) {
   const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  embed_gather_wave<V, G>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, z, max_z, U, Vt, geo, phi,
-                          f0, X);
-}
-
-// V consecutive values of a per-pair array stored as float or BF16, as floats.
-template <int V>
-__device__ __forceinline__ void ld_pair_row(const float *p, float (&o)[V]) {
-  ldv<V>(p, o);
-}
-template <int V>
-__device__ __forceinline__ void ld_pair_row(const __bf16 *p, float (&o)[V]) {
-#pragma unroll
-  for (int v = 0; v < V; ++v) o[v] = (float)p[v];
+  embed_gather_wave<V, G, TF>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, z, max_z, U, Vt, geo,
+                              phi, f0, X);
 }
 
 // c[q] = sum over the CSR row [e0, e1) of h_part(q)(pair) * Y_j[q]; h (TH) and the gathered
@@ -1439,26 +1586,29 @@ __global__ void __launch_bounds__(256) k_force_gather_w(int64_t n, const int32_t
                            gpair, forces);
 }
 
-// Launch one of the wave-per-atom gathers above: F = 64 one wave per atom; F = 128 and 256
-// two waves per atom with V = F/128 channels per lane.
-#define TN_WAVE_GATHER_LAUNCHER(NAME, KERNEL)                                                   \
-  template <class... A>                                                                         \
-  inline int NAME(hipStream_t s, int64_t F, int64_t n, A... a) {                                \
-    if (n <= 0) return TN_OK;                                                                   \
-    const dim3 b(256);                                                                          \
-    if (F == 64)                                                                                \
-      hipLaunchKernelGGL((KERNEL<1, 1>), dim3(wave_atom_grid(n)), b, 0, s, n, a...);           \
-    else if (F == 128)                                                                          \
-      hipLaunchKernelGGL((KERNEL<1, 2>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, a...);       \
-    else if (F == 256)                                                                          \
-      hipLaunchKernelGGL((KERNEL<2, 2>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, a...);       \
-    else                                                                                        \
-      return TN_E_UNSUPPORTED;                                                                  \
-    TN_LAUNCH_CHECK();                                                                          \
-    return TN_OK;                                                                               \
-  }
-TN_WAVE_GATHER_LAUNCHER(embed_gather_w, k_embed_gather_w)
-#undef TN_WAVE_GATHER_LAUNCHER
+// The embedding gather: F = 64 one wave per atom; F = 128 and 256 two waves per atom with
+// V = F/128 channels per lane; f0 in FP32 or BF16 (TF).
+template <class TF>
+inline int embed_gather_w(hipStream_t s, int64_t F, int64_t n, const int32_t *rowptr, const int32_t *nbr,
+                          const int32_t *pid, const int64_t *n_pairs, int64_t max_pairs, const int32_t *z, int max_z,
+                          const float *U, const float *Vt, const float *geo, const float *phi, const TF *f0,
+                          float *X) {
+  if (n <= 0) return TN_OK;
+  const dim3 b(256);
+  if (F == 64)
+    hipLaunchKernelGGL((k_embed_gather_w<1, 1, TF>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid, n_pairs,
+                       max_pairs, z, max_z, U, Vt, geo, phi, f0, X);
+  else if (F == 128)
+    hipLaunchKernelGGL((k_embed_gather_w<1, 2, TF>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr, pid,
+                       n_pairs, max_pairs, z, max_z, U, Vt, geo, phi, f0, X);
+  else if (F == 256)
+    hipLaunchKernelGGL((k_embed_gather_w<2, 2, TF>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr, pid,
+                       n_pairs, max_pairs, z, max_z, U, Vt, geo, phi, f0, X);
+  else
+    return TN_E_UNSUPPORTED;
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
 
 // The message gathers, with the edge filters h (TH) and the gathered atom rows (TY) in FP32 or
 // BF16.

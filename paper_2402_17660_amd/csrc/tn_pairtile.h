@@ -323,10 +323,10 @@ __device__ __forceinline__ void wave_pair_rows(const int32_t *pairs, int64_t max
   }
 }
 
-// The second atom's rows and the pair's f0 for the embedding adjoint.  The atom rows ("near":
-// mostly cache hits) and the pair's row ("far": written by the forward pass, read from HBM) can
-// be loaded one row ahead separately.
-template <int F>
+// The second atom's rows and the pair's f0 (FP32, or BF16 when TF is __bf16) for the embedding
+// adjoint.  The atom rows ("near": mostly cache hits) and the pair's row ("far": written by the
+// forward pass, read from HBM) can be loaded one row ahead separately.
+template <int F, class TF = float>
 struct EmbedRowJ {
   static constexpr int V = F / 64;
   float c[9][V], U[V], W[V], a[V], b[V], cc[V];
@@ -339,15 +339,20 @@ struct EmbedRowJ {
     ldv<V>(bg.V + zj * F + f, W);
   }
   __device__ __forceinline__ void load_far(const BwdGather &bg, int64_t p, int f) {
-    ldv<V>(bg.f0 + p * 3 * F + f, a);
-    ldv<V>(bg.f0 + p * 3 * F + F + f, b);
-    ldv<V>(bg.f0 + p * 3 * F + 2 * F + f, cc);
+    const TF *f0;
+    if constexpr (std::is_same<TF, float>::value)
+      f0 = bg.f0;
+    else
+      f0 = bg.f016;
+    ld_row<TF, V>(f0 + p * 3 * F + f, a);
+    ld_row<TF, V>(f0 + p * 3 * F + F + f, b);
+    ld_row<TF, V>(f0 + p * 3 * F + 2 * F + f, cc);
   }
 };
 
 // dE/df0 = (da, db, dc) for both directions of the pair -> lds[row][0..3F); returns the pair's
 // dE/dphi and dE/dvhat (embedding part) through the per-row LDS arrays.
-template <int F, int R, class TL, int NW = 4, int PF = 2>
+template <int F, int R, class TL, int NW = 4, int PF = 2, class TF = float>
 __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const int32_t *pairs, int64_t max_pairs,
                                                    int64_t p0, int nvalid, const float (*sU)[3], const float *sPhi,
                                                    TL *lds, int ld, float *sDphi, float (*sDv)[3]) {
@@ -362,7 +367,7 @@ __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const in
   // loaded one row ahead so that their latency overlaps a row's work
   int64_t prev_i = -1;
   float ci[9][V], Ui[V], Vi[V];
-  EmbedRowJ<F> nxt;
+  EmbedRowJ<F, TF> nxt;
   if constexpr (PF >= 1) nxt.load_far(bg, wave_row_pair<rows>(p0, nvalid, wave, 0), f);
   if constexpr (PF >= 2) nxt.load_near(bg, pj[0], f);
 #pragma unroll
@@ -379,7 +384,7 @@ __device__ __forceinline__ void embed_adjoint_rows(const BwdGather &bg, const in
       ldv<V>(bg.V + zi * F + f, Vi);
       prev_i = i;
     }
-    EmbedRowJ<F> cur = nxt;
+    EmbedRowJ<F, TF> cur = nxt;
     if constexpr (PF < 2) cur.load_near(bg, pj[rr], f);
     if constexpr (PF < 1) cur.load_far(bg, wave_row_pair<rows>(p0, nvalid, wave, rr), f);
     if (rr + 1 < rows) {
@@ -721,12 +726,6 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
 // (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..8(l/16)+7] and
 // B[8(l/16)..+7][l%16]).  Tiles of 16 RB pairs (RB 16-row blocks), so every weight fragment
 // read from L2 feeds RB MFMAs.  Pre-activations and the filters h are stored in BF16.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int kPadB = 8;   // LDS row padding (bf16 elements)
-
-__device__ __forceinline__ floatx4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
 
 // acc[rb][cb] += act[16*RB x Kin] (LDS bf16, row stride ld) * Bt^T (Bt [ncol][Kin] bf16 in global memory).
 template <int RB, int NB>
@@ -801,7 +800,7 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
     load_cols<NB>(a.b0, col0, br);
     wave_mm_bf16<RB, NB>(sE, LE, K, a.W0, col0, acc);
     for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
-      if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = v + br[cb];
+      if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = (__bf16)(v + br[cb]);
     });
   }
   for (int l = 0; l < a.L; ++l) {
@@ -891,7 +890,8 @@ __device__ __forceinline__ void pair_bwd_tile_bf16(const PairBwdArgsB &a, int64_
     sU[tid][2] = (float)g.u[2];
   }
   __syncthreads();
-  embed_adjoint_rows<F, TILE>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi, sDv);
+  embed_adjoint_rows<F, TILE, __bf16, 4, 2, __bf16>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi,
+                                                   sDv);
   __syncthreads();
   floatx4 de[RB][1];
   zero_acc_rb<RB, 1>(de);
