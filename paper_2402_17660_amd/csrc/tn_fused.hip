@@ -73,12 +73,13 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   per_layer(w->nX, N * F);
   per_layer(w->Xb, N * 9 * F);
   per_layer(w->Y, N * 9 * F);
-  // z1 and z2 of the FP32 pair kernels are stored in whole 16-pair blocks
+  // pre-activations per pair: row-major BF16 in the BF16 path; the FP32 kernels store z1 and z2
+  // in whole 16-pair blocks
   const int64_t MP16 = (MP + 15) / 16 * 16;
   per_layer(w->z1, bf16 ? MP * F / 2 : MP16 * F);
-  per_layer(w->z2, MP16 * 2 * F);
-  per_layer(w->z3, MP * 3 * F);
-  per_layer(w->h, MP * 3 * F);
+  per_layer(w->z2, bf16 ? MP * F : MP16 * 2 * F);
+  per_layer(w->z3, bf16 ? MP * 3 * F / 2 : MP * 3 * F);
+  per_layer(w->h, bf16 ? MP * 3 * F / 2 : MP * 3 * F);
   per_layer(w->M, N * 9 * F);
   per_layer(w->P, N * 9 * F);
   per_layer(w->nP, N * F);

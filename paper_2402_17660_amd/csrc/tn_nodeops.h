@@ -237,6 +237,38 @@ inline int linear_bwd(hipStream_t s, const T *dy, int64_t M, int64_t Nout, const
   return gemm(s, linear_bwd_args(dy, M, Nout, W, Kin, dx, gate, accumulate, Mdev));
 }
 
+// The mixing tiles' results from a transposed accumulator (weights as the instruction's first
+// operand): lane l holds atom a0 + l%16, channels col0 + cb*16 + 4(l/16) .. +3 of coordinate
+// C0 + rb, stored (or, accumulating, added to the old values, all loaded before the first
+// store) as one 16-byte access per block, and as 8 bytes to the optional BF16 copy.
+template <int F, int NC, int NB>
+__device__ __forceinline__ void mix_epilogue(floatx4 (&acc)[NC][NB], float *__restrict__ out,
+                                             __bf16 *__restrict__ out16, int64_t a0, int C0, int64_t navail,
+                                             int col0, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, q = lane >> 4;
+  if (r16 >= navail) return;
+  const int64_t o = ((a0 + r16) * 9 + C0) * F + col0 + 4 * q;
+  if (accumulate) {
+    floatx4 old[NC][NB];
+#pragma unroll
+    for (int rb = 0; rb < NC; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) old[rb][cb] = ld4(out + o + rb * F + cb * 16);
+#pragma unroll
+    for (int rb = 0; rb < NC; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = old[rb][cb] + acc[rb][cb];
+  }
+#pragma unroll
+  for (int rb = 0; rb < NC; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      st4(out + o + rb * F + cb * 16, acc[rb][cb]);
+      if (out16) st4(out16 + o + rb * F + cb * 16, acc[rb][cb]);
+    }
+}
+
 // FP32 channel mixing on the matrix cores.  A block takes one part (I, A or S: 1, 3 or 5
 // coordinates) of 16 atoms, stages those coordinates (contiguous per atom, F channels each)
 // in LDS with padded rows, and computes 64*NB output channels; each of the four waves takes
@@ -289,41 +321,10 @@ __device__ __forceinline__ void mix_tile(const float *__restrict__ in, float *__
     floatx4 acc[NC][NB];
     zero_acc_rb<NC, NB>(acc);
     if constexpr (kBreg)
-      wave_mm_rows_breg<NC, NB, KC>(sA, NC * LD, LD, breg, acc);
+      wave_mm_rows_breg<NC, NB, KC, true>(sA, NC * LD, LD, breg, acc);
     else
-      wave_mm_rows<NC, NB>(sA, NC * LD, LD, F, Bt, col0, acc);
-    // accumulating: all old values are loaded before the first store
-    if (accumulate) {
-      float old[NC][NB][4];
-#pragma unroll
-      for (int rb = 0; rb < NC; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int at = 4 * q + e;
-            old[rb][cb][e] = at < navail ? out[((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16] : 0.f;
-          }
-#pragma unroll
-      for (int rb = 0; rb < NC; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[rb][cb][e] = old[rb][cb][e] + acc[rb][cb][e];
-    }
-#pragma unroll
-    for (int rb = 0; rb < NC; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int at = 4 * q + e;
-          if (at < navail) {
-            const int64_t o = ((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16;
-            out[o] = acc[rb][cb][e];
-            if (out16) out16[o] = (__bf16)acc[rb][cb][e];
-          }
-        }
+      wave_mm_rows<NC, NB, true>(sA, NC * LD, LD, F, Bt, col0, acc);
+    mix_epilogue<F, NC, NB>(acc, out, out16, a0, C0, navail, col0, accumulate);
   };
   if (part == 0)
     run(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}, B0);
@@ -417,39 +418,9 @@ __device__ __forceinline__ void mix_tile_bf16(const float *__restrict__ in, floa
       for (int rb = 0; rb < NC; ++rb) {
         const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sA + (r16 * NC + rb) * LD + 32 * kc + 8 * q);
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = mfma_bf16(a, breg[kc][cb], acc[rb][cb]);
+        for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = mfma_bf16(breg[kc][cb], a, acc[rb][cb]);
       }
-    if (accumulate) {
-      float old[NC][NB][4];
-#pragma unroll
-      for (int rb = 0; rb < NC; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int at = 4 * q + e;
-            old[rb][cb][e] = at < navail ? out[((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16] : 0.f;
-          }
-#pragma unroll
-      for (int rb = 0; rb < NC; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[rb][cb][e] = old[rb][cb][e] + acc[rb][cb][e];
-    }
-#pragma unroll
-    for (int rb = 0; rb < NC; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int at = 4 * q + e;
-          if (at < navail) {
-            const int64_t o = ((a0 + at) * 9 + C0 + rb) * F + col0 + cb * 16 + r16;
-            out[o] = acc[rb][cb][e];
-            if (out16) out16[o] = (__bf16)acc[rb][cb][e];
-          }
-        }
+    mix_epilogue<F, NC, NB>(acc, out, out16, a0, C0, navail, col0, accumulate);
   };
   if (part == 0)
     run(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}, B0);

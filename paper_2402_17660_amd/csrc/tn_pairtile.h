@@ -14,7 +14,9 @@
 // Activations live in LDS (row padding of
 // 4 floats), weights stream from L2 as 16-byte loads.  The K index inside each 16-wide
 // chunk is permuted (lane group q takes k = 4q..4q+3) so that one 16-byte load feeds four
-// consecutive MFMAs for both operands.
+// consecutive MFMAs for both operands.  The BF16 forward kernel passes the weights as the
+// instruction's first operand, so each lane ends with four consecutive output channels of one
+// pair and stores them to the row-major BF16 arrays in one 8-byte access.
 #pragma once
 
 #include "tn_internal.h"
@@ -40,6 +42,32 @@ __device__ __forceinline__ void for_acc_rc(const floatx4 (&acc)[RB][NB], int col
 #pragma unroll
       for (int t = 0; t < 4; ++t)
         f(rb, cb, t, rb * 16 + 4 * (lane >> 4) + t, col0 + cb * 16 + (lane & 15), acc[rb][cb][t]);
+}
+
+// Visit this lane's blocks of a transposed accumulator (wave_mm_t, wave_mm_bf16_t):
+// f(rb, cb, row, col, v), where v (acc[rb][cb], writable) holds row `row`, columns col .. col+3.
+template <int RB, int NB, class Fn>
+__device__ __forceinline__ void for_acc_t(floatx4 (&acc)[RB][NB], int col0, Fn &&f) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) f(rb, cb, rb * 16 + (lane & 15), col0 + cb * 16 + 4 * (lane >> 4), acc[rb][cb]);
+}
+
+// This lane's four columns per column block of a per-column vector (bias) for a transposed
+// accumulator, loaded once before the products.
+template <int NB>
+__device__ __forceinline__ void load_cols_t(const float *v, int col0, floatx4 (&o)[NB]) {
+  const int c = col0 + 4 * ((threadIdx.x & 63) >> 4);
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) o[cb][t] = v[c + cb * 16 + t];
+}
+
+__device__ __forceinline__ floatx4 silu4(const floatx4 &z) {
+  return floatx4{fast_silu(z[0]), fast_silu(z[1]), fast_silu(z[2]), fast_silu(z[3])};
 }
 
 // This lane's columns of a per-column vector (bias), loaded once before the products.
@@ -727,8 +755,10 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
 // B[8(l/16)..+7][l%16]).  Tiles of 16 RB pairs (RB 16-row blocks), so every weight fragment
 // read from L2 feeds RB MFMAs.  Pre-activations and the filters h are stored in BF16.
 
-// acc[rb][cb] += act[16*RB x Kin] (LDS bf16, row stride ld) * Bt^T (Bt [ncol][Kin] bf16 in global memory).
-template <int RB, int NB>
+// acc[rb][cb] += act[16*RB x Kin] (LDS bf16, row stride ld) * Bt^T (Bt [ncol][Kin] bf16 in global
+// memory); with TR the operands of each instruction are swapped and the accumulator holds the
+// block transposed, as with wave_mm_t (visit it with for_acc_t).
+template <int RB, int NB, bool TR = false>
 __device__ __forceinline__ void wave_mm_bf16(const __bf16 *act, int ld, int Kin, const __bf16 *__restrict__ Bt,
                                              int col0, floatx4 (&acc)[RB][NB]) {
   const int lane = threadIdx.x & 63;
@@ -752,7 +782,7 @@ __device__ __forceinline__ void wave_mm_bf16(const __bf16 *act, int ld, int Kin,
     for (int rb = 0; rb < RB; ++rb) {
       const bf16x8 a = *reinterpret_cast<const bf16x8 *>(ap + rb * astride + k0);
 #pragma unroll
-      for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = mfma_bf16(a, b[cb], acc[rb][cb]);
+      for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = TR ? mfma_bf16(b[cb], a, acc[rb][cb]) : mfma_bf16(a, b[cb], acc[rb][cb]);
     }
   }
 }
@@ -796,11 +826,11 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
     floatx4 acc[RB][NB];
     zero_acc_rb<RB, NB>(acc);
     const int col0 = wave * (3 * F / 4);
-    float br[NB];
-    load_cols<NB>(a.b0, col0, br);
-    wave_mm_bf16<RB, NB>(sE, LE, K, a.W0, col0, acc);
-    for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
-      if (row < nvalid) a.f0[(p0 + row) * 3 * F + col] = (__bf16)(v + br[cb]);
+    floatx4 br[NB];
+    load_cols_t<NB>(a.b0, col0, br);
+    wave_mm_bf16<RB, NB, true>(sE, LE, K, a.W0, col0, acc);
+    for_acc_t(acc, col0, [&](int, int cb, int row, int col, floatx4 &v) {
+      if (row < nvalid) st4(a.f0 + (p0 + row) * 3 * F + col, v + br[cb]);
     });
   }
   for (int l = 0; l < a.L; ++l) {
@@ -809,14 +839,14 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 4);
-      float br[NB];
-      load_cols<NB>(a.ba[l], col0, br);
-      wave_mm_bf16<RB, NB>(sE, LE, K, a.Wa[l], col0, acc);
+      floatx4 br[NB];
+      load_cols_t<NB>(a.ba[l], col0, br);
+      wave_mm_bf16<RB, NB, true>(sE, LE, K, a.Wa[l], col0, acc);
       __bf16 *z1 = a.z1[l];
-      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
-        const float z = v + br[cb];
-        if (row < nvalid) z1[(p0 + row) * F + col] = (__bf16)z;
-        sA1[row * L1 + col] = (__bf16)fast_silu(z);
+      for_acc_t(acc, col0, [&](int, int cb, int row, int col, floatx4 &v) {
+        v += br[cb];
+        if (row < nvalid) st4(z1 + (p0 + row) * F + col, v);
+        st4(sA1 + row * L1 + col, silu4(v));
       });
     }
     __syncthreads();
@@ -825,14 +855,14 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (F / 2);
-      float br[NB];
-      load_cols<NB>(a.bb[l], col0, br);
-      wave_mm_bf16<RB, NB>(sA1, L1, F, a.Wb[l], col0, acc);
+      floatx4 br[NB];
+      load_cols_t<NB>(a.bb[l], col0, br);
+      wave_mm_bf16<RB, NB, true>(sA1, L1, F, a.Wb[l], col0, acc);
       __bf16 *z2 = a.z2[l];
-      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
-        const float z = v + br[cb];
-        if (row < nvalid) z2[(p0 + row) * 2 * F + col] = (__bf16)z;
-        sA2[row * L2 + col] = (__bf16)fast_silu(z);
+      for_acc_t(acc, col0, [&](int, int cb, int row, int col, floatx4 &v) {
+        v += br[cb];
+        if (row < nvalid) st4(z2 + (p0 + row) * 2 * F + col, v);
+        st4(sA2 + row * L2 + col, silu4(v));
       });
     }
     __syncthreads();
@@ -841,15 +871,15 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
       const int col0 = wave * (3 * F / 4);
-      float br[NB];
-      load_cols<NB>(a.bc[l], col0, br);
-      wave_mm_bf16<RB, NB>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
+      floatx4 br[NB];
+      load_cols_t<NB>(a.bc[l], col0, br);
+      wave_mm_bf16<RB, NB, true>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
       __bf16 *z3 = a.z3[l], *h = a.h[l];
-      for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
-        const float z = v + br[cb];
+      for_acc_t(acc, col0, [&](int, int cb, int row, int col, floatx4 &v) {
         if (row < nvalid) {
-          z3[(p0 + row) * 3 * F + col] = (__bf16)z;
-          h[(p0 + row) * 3 * F + col] = (__bf16)((float)sPhi[row] * fast_silu(z));
+          v += br[cb];
+          st4(z3 + (p0 + row) * 3 * F + col, v);
+          st4(h + (p0 + row) * 3 * F + col, (float)sPhi[row] * silu4(v));
         }
       });
     }
