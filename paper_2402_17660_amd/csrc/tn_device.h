@@ -71,6 +71,12 @@ __device__ __forceinline__ float fast_silu_grad(float x) {
   const float s = fast_sigmoid(x);
   return s * (1.0f + x * (1.0f - s));
 }
+// Both from one sigmoid: returns silu(x) and sets grad = silu'(x) (the same values as above).
+__device__ __forceinline__ float fast_silu_and_grad(float x, float &grad) {
+  const float s = fast_sigmoid(x);
+  grad = s * (1.0f + x * (1.0f - s));
+  return x * s;
+}
 
 // SiLU x*sigmoid(x) and its derivative sigmoid(x) * (1 + x * (1 - sigmoid(x))).
 template <class T> __device__ inline T sigmoid(T x) { return T(1) / (T(1) + dexp(-x)); }

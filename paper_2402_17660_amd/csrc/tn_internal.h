@@ -195,6 +195,8 @@ struct PairFwdArgs {
   const float *Wa[kMaxLayers], *ba[kMaxLayers], *Wb[kMaxLayers], *bb[kMaxLayers], *Wc[kMaxLayers], *bc[kMaxLayers];
   int L = 0;
   float *geo = nullptr, *phi = nullptr, *f0 = nullptr;
+  // per pair and layer: z1, z2 hold silu'(z1), silu'(z2) (the reverse pass's only use of them),
+  // z3 the pre-activation itself, h the filters
   float *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers], *h[kMaxLayers];
 };
 

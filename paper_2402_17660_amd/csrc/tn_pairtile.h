@@ -69,6 +69,16 @@ __device__ __forceinline__ void load_cols_t(const float *v, int col0, floatx4 (&
 __device__ __forceinline__ floatx4 silu4(const floatx4 &z) {
   return floatx4{fast_silu(z[0]), fast_silu(z[1]), fast_silu(z[2]), fast_silu(z[3])};
 }
+__device__ __forceinline__ floatx4 silu_and_grad4(const floatx4 &z, floatx4 &g) {
+  floatx4 o;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    float gt;
+    o[t] = fast_silu_and_grad(z[t], gt);
+    g[t] = gt;
+  }
+  return o;
+}
 
 // This lane's columns of a per-column vector (bias), loaded once before the products.
 template <int NB>
@@ -95,7 +105,7 @@ __device__ __forceinline__ void load_acc_rows(const TZ *z, int ldz, int64_t p0, 
     }
 }
 
-// The FP32 kernels store the pre-activations z1 and z2 in 16-pair blocks, column-major inside a
+// The FP32 kernels store silu'(z1) and silu'(z2) in 16-pair blocks, column-major inside a
 // block: entry (p, c) of a C-column array sits at ((p / 16) * C + c) * 16 + p % 16.  The four
 // rows an accumulator lane holds are then one 16-byte access, and the sixteen lanes of a row
 // group cover 1 KB without gaps.  Only rows below nvalid are written; the buffers hold whole
@@ -227,9 +237,10 @@ __device__ __forceinline__ void pair_fwd_tile(const PairFwdArgs &a, int64_t p0, 
       wave_mm_rb<RB, NB>(sE, LE, K, a.Wa[l], col0, acc);
       __syncthreads();   // the previous layer's last product has finished reading sA
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        const float z = v + br[cb];
-        acc[rb][cb][t] = z;
-        sA[row * L1 + col] = fast_silu(z);
+        // silu'(z1) is all the reverse pass needs of z1, so that is what is stored
+        float g;
+        sA[row * L1 + col] = fast_silu_and_grad(v + br[cb], g);
+        acc[rb][cb][t] = g;
       });
       store_acc_blocked<RB, NB>(a.z1[l], F, p0, nvalid, col0, acc);
     }
@@ -244,9 +255,9 @@ __device__ __forceinline__ void pair_fwd_tile(const PairFwdArgs &a, int64_t p0, 
       wave_mm_rb<RB, NB>(sA, L1, F, a.Wb[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        const float z = v + br[cb];
-        acc[rb][cb][t] = z;
-        sA[row * L2 + col] = fast_silu(z);
+        float g;
+        sA[row * L2 + col] = fast_silu_and_grad(v + br[cb], g);
+        acc[rb][cb][t] = g;   // stores silu'(z2)
       });
       store_acc_blocked<RB, NB>(a.z2[l], 2 * F, p0, nvalid, col0, acc);
     }
@@ -636,11 +647,13 @@ __device__ __forceinline__ void geometry_adjoint_tile(const PairGeo *sGeo, const
 // ============================================================================ reverse
 // One LDS buffer holds the tile's current adjoint: dE/df0, then per layer dz3, dz2, dz1, and
 // finally dE/de.  Each product keeps its result in registers until every wave has finished
-// reading the buffer, so the tile needs ~50 KB of LDS and two blocks share a CU.  The stored
-// pre-activations z1 and z2 are loaded, not recomputed: recomputing z1 = Wa e + ba from the
-// basis (8 kFLOP per pair and layer) made the reverse launch 0.47 ms slower on a 100,000-atom
-// box (19.45 against 18.98 ms) and the forward, which then skips the store, 0.21 ms faster;
-// recomputing f0 as well, 0.5 ms slower still.
+// reading the buffer, so the tile needs ~50 KB of LDS and two blocks share a CU.  Of z1 and z2
+// the reverse pass needs only silu'(z1) and silu'(z2), which the forward pass stores in their
+// place (it has the sigmoid at hand), so no transcendental is evaluated for them here.  They
+// are loaded, not recomputed: recomputing z1 = Wa e + ba from the basis (8 kFLOP per pair and
+// layer) made the reverse launch 0.47 ms slower on a 100,000-atom box (19.45 against 18.98 ms)
+// and the forward, which then skips the store, 0.21 ms faster; recomputing f0 as well, 0.5 ms
+// slower still.
 
 // PF: how much of the next row the prologues prefetch (by the register budget of the caller's
 // launch bound; 2 = pair row and atom rows, 1 = pair row, 0 = none)
@@ -701,7 +714,7 @@ __device__ __forceinline__ void pair_bwd_tile(const PairBwdArgs &a, int64_t p0, 
       wave_mm_rb<RB, NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        sG[row * L2 + col] = row < nvalid ? v * fast_silu_grad(zp[rb][cb][t]) : 0.f;
+        sG[row * L2 + col] = row < nvalid ? v * zp[rb][cb][t] : 0.f;   // zp = silu'(z2)
       });
     }
     __syncthreads();
@@ -715,7 +728,7 @@ __device__ __forceinline__ void pair_bwd_tile(const PairBwdArgs &a, int64_t p0, 
       wave_mm_rb<RB, NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        sG[row * L1 + col] = row < nvalid ? v * fast_silu_grad(zp[rb][cb][t]) : 0.f;
+        sG[row * L1 + col] = row < nvalid ? v * zp[rb][cb][t] : 0.f;   // zp = silu'(z1)
       });
     }
     __syncthreads();
@@ -844,9 +857,10 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
       wave_mm_bf16<RB, NB, true>(sE, LE, K, a.Wa[l], col0, acc);
       __bf16 *z1 = a.z1[l];
       for_acc_t(acc, col0, [&](int, int cb, int row, int col, floatx4 &v) {
-        v += br[cb];
-        if (row < nvalid) st4(z1 + (p0 + row) * F + col, v);
-        st4(sA1 + row * L1 + col, silu4(v));
+        floatx4 g;
+        const floatx4 sv = silu_and_grad4(v + br[cb], g);
+        if (row < nvalid) st4(z1 + (p0 + row) * F + col, g);   // silu'(z1): all the reverse pass needs of z1
+        st4(sA1 + row * L1 + col, sv);
       });
     }
     __syncthreads();
@@ -860,9 +874,10 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
       wave_mm_bf16<RB, NB, true>(sA1, L1, F, a.Wb[l], col0, acc);
       __bf16 *z2 = a.z2[l];
       for_acc_t(acc, col0, [&](int, int cb, int row, int col, floatx4 &v) {
-        v += br[cb];
-        if (row < nvalid) st4(z2 + (p0 + row) * 2 * F + col, v);
-        st4(sA2 + row * L2 + col, silu4(v));
+        floatx4 g;
+        const floatx4 sv = silu_and_grad4(v + br[cb], g);
+        if (row < nvalid) st4(z2 + (p0 + row) * 2 * F + col, g);   // silu'(z2)
+        st4(sA2 + row * L2 + col, sv);
       });
     }
     __syncthreads();
@@ -940,10 +955,11 @@ __device__ __forceinline__ void pair_bwd_tile_bf16(const PairBwdArgsB &a, int64_
       const int col0 = wave * (F / 2);
       float zp[RB][NB][4];
       load_acc_rows<RB, NB>(z2, 2 * F, p0, nvalid, col0, zp);
+      __builtin_amdgcn_sched_barrier(0);   // issue these loads before the product loop, not inside it
       wave_mm_bf16<RB, NB>(sG, L3, 3 * F, a.WcT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        sG[row * L2 + col] = (__bf16)(row < nvalid ? v * fast_silu_grad(zp[rb][cb][t]) : 0.f);
+        sG[row * L2 + col] = (__bf16)(row < nvalid ? v * zp[rb][cb][t] : 0.f);   // zp = silu'(z2)
       });
     }
     __syncthreads();
@@ -954,10 +970,11 @@ __device__ __forceinline__ void pair_bwd_tile_bf16(const PairBwdArgsB &a, int64_
       const int col0 = wave * (F / 4);
       float zp[RB][NB][4];
       load_acc_rows<RB, NB>(z1, F, p0, nvalid, col0, zp);
+      __builtin_amdgcn_sched_barrier(0);   // issue these loads before the product loop, not inside it
       wave_mm_bf16<RB, NB>(sG, L2, 2 * F, a.WbT[l], col0, acc);
       __syncthreads();
       for_acc_rc(acc, col0, [&](int rb, int cb, int t, int row, int col, float v) {
-        sG[row * L1 + col] = (__bf16)(row < nvalid ? v * fast_silu_grad(zp[rb][cb][t]) : 0.f);
+        sG[row * L1 + col] = (__bf16)(row < nvalid ? v * zp[rb][cb][t] : 0.f);   // zp = silu'(z1)
       });
     }
     __syncthreads();
