@@ -44,6 +44,16 @@ struct Dual {
   friend __host__ __device__ inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
   friend __host__ __device__ inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
 };
+// Lane shuffles of dual numbers, component by component (used by the wave reductions).
+template <class S>
+__device__ __forceinline__ Dual<S> lane_shfl_down(Dual<S> x, int off) {
+  return Dual<S>(__shfl_down(x.v, off, 64), __shfl_down(x.d, off, 64));
+}
+template <class S>
+__device__ __forceinline__ Dual<S> lane_shfl(Dual<S> x, int src) {
+  return Dual<S>(__shfl(x.v, src, 64), __shfl(x.d, src, 64));
+}
+
 
 template <class S> __device__ inline Dual<S> dexp(Dual<S> x) {
   const S e = dexp(x.v);

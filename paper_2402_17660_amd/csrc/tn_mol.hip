@@ -205,56 +205,6 @@ __device__ inline bool mol_pair_within(const float *pos, int64_t i, int64_t j, d
   return d2 < rc2;
 }
 
-// Sum over the 64 lanes in the order of a 64-thread shared-memory tree (pairs at distance 32,
-// then 16, ...), so the LayerNorm rows below round exactly as the grid kernels' rows; every
-// lane receives the result.
-template <class T>
-__device__ __forceinline__ T wave_tree_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return __shfl(v, 0, 64);
-}
-
-// LayerNorm of row r (length C) by one wave, as k_layernorm with 64 threads.
-template <class TA>
-__device__ inline void layernorm_row_wave(int64_t r, int C, const TA *x, const TA *gmul, const TA *badd, TA *y,
-                                          TA *xhat, TA *rstd) {
-  const int lane = threadIdx.x & 63;
-  TA s = TA(0);
-  for (int k = lane; k < C; k += 64) s += x[r * C + k];
-  const TA mean = wave_tree_sum(s) / TA(C);
-  TA v = TA(0);
-  for (int k = lane; k < C; k += 64) {
-    const TA d = x[r * C + k] - mean;
-    v += d * d;
-  }
-  const TA var = wave_tree_sum(v) / TA(C);
-  const TA rs = TA(1) / dsqrt(var + TA(1e-5));
-  for (int k = lane; k < C; k += 64) {
-    const TA hh = (x[r * C + k] - mean) * rs;
-    xhat[r * C + k] = hh;
-    y[r * C + k] = hh * gmul[k] + badd[k];
-  }
-  if (lane == 0) rstd[r] = rs;
-}
-
-// Its adjoint, as k_layernorm_bwd with 64 threads.
-template <class TA>
-__device__ inline void layernorm_bwd_row_wave(int64_t r, int C, const TA *dy, const TA *xhat, const TA *rstd,
-                                              const TA *gmul, TA *dx) {
-  const int lane = threadIdx.x & 63;
-  TA s1 = TA(0), s2 = TA(0);
-  for (int k = lane; k < C; k += 64) {
-    const TA gd = gmul[k] * dy[r * C + k];
-    s1 += gd;
-    s2 += gd * xhat[r * C + k];
-  }
-  const TA m1 = wave_tree_sum(s1) / TA(C);
-  const TA m2 = wave_tree_sum(s2) / TA(C);
-  const TA rs = rstd[r];
-  for (int k = lane; k < C; k += 64) dx[r * C + k] = rs * (gmul[k] * dy[r * C + k] - m1 - xhat[r * C + k] * m2);
-}
-
 // Shared memory of the molecule kernel's mixing and FP64 product stages (one buffer); the pair
 // tiles bring their own LDS arrays.
 template <int F>

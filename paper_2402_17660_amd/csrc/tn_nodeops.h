@@ -476,7 +476,7 @@ inline int mix(hipStream_t s, const T *in, T *out, int64_t N, int64_t F, const T
     bool ok = Bt != nullptr && aligned16(in) && aligned16(out);
     for (int q = 0; ok && q < 3; ++q) ok = Bt[q] != nullptr && aligned16(Bt[q]);
     if (ok && F == 64) return launch_mix<64, 1>(s, in, out, N, Bt, accumulate, out16);
-    if (ok && F == 128) return launch_mix<128, 1>(s, in, out, N, Bt, accumulate, out16);
+    if (ok && F == 128) return launch_mix<128, 2>(s, in, out, N, Bt, accumulate, out16);
     if (ok && F == 256) return launch_mix<256, 2>(s, in, out, N, Bt, accumulate, out16);
   }
   if (out16) return TN_E_UNSUPPORTED;
@@ -619,51 +619,78 @@ __device__ inline T block_sum(T v, T *lds) {
   return r;
 }
 
-// LayerNorm over rows of length C (population variance, eps 1e-5, affine g/b); one block per
-// row, launched with one wave (blockDim.x a power of two up to 128).
+// Sum over the 64 lanes in the order of a 64-thread shared-memory tree (pairs at distance 32,
+// then 16, ...); every lane receives the result.
 template <class T>
-__global__ void __launch_bounds__(128) k_layernorm(int64_t rows, int C, const T *x, const T *gmul, const T *badd,
-                                                   T *y, T *xhat, T *rstd) {
-  __shared__ T lds[128];
-  const int64_t r = blockIdx.x;
-  if (r >= rows) return;
-  T s = T(0);
-  for (int k = threadIdx.x; k < C; k += blockDim.x) s += x[r * C + k];
-  const T mean = block_sum(s, lds) / T(C);
-  T v = T(0);
-  for (int k = threadIdx.x; k < C; k += blockDim.x) {
-    const T d = x[r * C + k] - mean;
-    v += d * d;
-  }
-  const T var = block_sum(v, lds) / T(C);
-  const T rs = T(1) / dsqrt(var + T(1e-5));
-  for (int k = threadIdx.x; k < C; k += blockDim.x) {
-    const T h = (x[r * C + k] - mean) * rs;
-    xhat[r * C + k] = h;
-    y[r * C + k] = h * gmul[k] + badd[k];
-  }
-  if (threadIdx.x == 0) rstd[r] = rs;
+__device__ __forceinline__ T lane_shfl_down(T v, int off) { return __shfl_down(v, off, 64); }
+template <class T>
+__device__ __forceinline__ T lane_shfl(T v, int src) { return __shfl(v, src, 64); }
+template <class T>
+__device__ __forceinline__ T wave_tree_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += lane_shfl_down(v, off);
+  return lane_shfl(v, 0);
 }
 
-// dx = rstd * (g*dy - mean(g*dy) - xhat * mean(g*dy*xhat))
-template <class T>
-__global__ void __launch_bounds__(128) k_layernorm_bwd(int64_t rows, int C, const T *dy, const T *xhat,
-                                                       const T *rstd, const T *gmul, T *dx) {
-  __shared__ T lds[128];
-  const int64_t r = blockIdx.x;
-  if (r >= rows) return;
-  T s1 = T(0), s2 = T(0);
-  for (int k = threadIdx.x; k < C; k += blockDim.x) {
-    const T gd = gmul[k] * dy[r * C + k];
+// LayerNorm of row r (length C; population variance, eps 1e-5, affine g/b) by one wave: lane l
+// sums entries l, l + 64, ..., and the lanes' sums meet in the 64-lane tree.
+template <class TA>
+__device__ inline void layernorm_row_wave(int64_t r, int C, const TA *x, const TA *gmul, const TA *badd, TA *y,
+                                          TA *xhat, TA *rstd) {
+  const int lane = threadIdx.x & 63;
+  TA s = TA(0);
+  for (int k = lane; k < C; k += 64) s += x[r * C + k];
+  const TA mean = wave_tree_sum(s) / TA(C);
+  TA v = TA(0);
+  for (int k = lane; k < C; k += 64) {
+    const TA d = x[r * C + k] - mean;
+    v += d * d;
+  }
+  const TA var = wave_tree_sum(v) / TA(C);
+  const TA rs = TA(1) / dsqrt(var + TA(1e-5));
+  for (int k = lane; k < C; k += 64) {
+    const TA hh = (x[r * C + k] - mean) * rs;
+    xhat[r * C + k] = hh;
+    y[r * C + k] = hh * gmul[k] + badd[k];
+  }
+  if (lane == 0) rstd[r] = rs;
+}
+
+// Its adjoint: dx = rstd * (g*dy - mean(g*dy) - xhat * mean(g*dy*xhat)).
+template <class TA>
+__device__ inline void layernorm_bwd_row_wave(int64_t r, int C, const TA *dy, const TA *xhat, const TA *rstd,
+                                              const TA *gmul, TA *dx) {
+  const int lane = threadIdx.x & 63;
+  TA s1 = TA(0), s2 = TA(0);
+  for (int k = lane; k < C; k += 64) {
+    const TA gd = gmul[k] * dy[r * C + k];
     s1 += gd;
     s2 += gd * xhat[r * C + k];
   }
-  const T m1 = block_sum(s1, lds) / T(C);
-  const T m2 = block_sum(s2, lds) / T(C);
-  const T rs = rstd[r];
-  for (int k = threadIdx.x; k < C; k += blockDim.x)
-    dx[r * C + k] = rs * (gmul[k] * dy[r * C + k] - m1 - xhat[r * C + k] * m2);
+  const TA m1 = wave_tree_sum(s1) / TA(C);
+  const TA m2 = wave_tree_sum(s2) / TA(C);
+  const TA rs = rstd[r];
+  for (int k = lane; k < C; k += 64) dx[r * C + k] = rs * (gmul[k] * dy[r * C + k] - m1 - xhat[r * C + k] * m2);
 }
+
+// The grid kernels: one wave per row, four rows per 256-thread block.
+template <class T>
+__global__ void __launch_bounds__(256) k_layernorm(int64_t rows, int C, const T *x, const T *gmul, const T *badd,
+                                                   T *y, T *xhat, T *rstd) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows) return;
+  layernorm_row_wave<T>(r, C, x, gmul, badd, y, xhat, rstd);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_layernorm_bwd(int64_t rows, int C, const T *dy, const T *xhat,
+                                                       const T *rstd, const T *gmul, T *dx) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows) return;
+  layernorm_bwd_row_wave<T>(r, C, dy, xhat, rstd, gmul, dx);
+}
+
+inline unsigned layernorm_grid(int64_t rows) { return (unsigned)((rows + 3) / 4); }
 
 // X = g_part(c) * T0 (gating), product in T, features stored as TX.
 template <class T, class TX>

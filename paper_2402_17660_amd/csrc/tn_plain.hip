@@ -173,7 +173,7 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
   if (N > 0) {
     hipLaunchKernelGGL(k_node_norm<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XrA, w.nrm0);
     TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_layernorm<TA>, dim3((unsigned)N), dim3(64), 0, s, N, (int)F, w.nrm0, WA(o.ln_g),
+    hipLaunchKernelGGL(k_layernorm<TA>, dim3(layernorm_grid(N)), dim3(256), 0, s, N, (int)F, w.nrm0, WA(o.ln_g),
                        WA(o.ln_b), w.n0, w.xhat0, w.rstd0);
     TN_LAUNCH_CHECK();
   }
@@ -224,7 +224,7 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
   if (N > 0) {
     hipLaunchKernelGGL(k_out_norms<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XLA, w.on);
     TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_layernorm<TA>, dim3((unsigned)N), dim3(64), 0, s, N, (int)(3 * F), w.on, WA(o.oln_g),
+    hipLaunchKernelGGL(k_layernorm<TA>, dim3(layernorm_grid(N)), dim3(256), 0, s, N, (int)(3 * F), w.on, WA(o.oln_g),
                        WA(o.oln_b), w.q, w.oxhat, w.orstd);
     TN_LAUNCH_CHECK();
   }
@@ -257,7 +257,7 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
   if ((rc = linear_bwd<TA>(s, w.dhz, N, H, WA(o.Wh), F, w.dox, w.oz, 0))) return rc;
   if ((rc = linear_bwd<TA>(s, w.dox, N, F, WA(o.Wo), 3 * F, w.dq, nullptr, 0))) return rc;
   if (N > 0) {
-    hipLaunchKernelGGL(k_layernorm_bwd<TA>, dim3((unsigned)N), dim3(64), 0, s, N, (int)(3 * F), w.dq, w.oxhat,
+    hipLaunchKernelGGL(k_layernorm_bwd<TA>, dim3(layernorm_grid(N)), dim3(256), 0, s, N, (int)(3 * F), w.dq, w.oxhat,
                        w.orstd, WA(o.oln_g), w.don);
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_out_norms_bwd<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XLA, w.don, w.dXA);
@@ -323,7 +323,7 @@ static int run_plain(const tn_model *m, hipStream_t s, const Problem &pb, void *
   if ((rc = linear_bwd<TA>(s, w.dez2, N, 3 * F, WA(o.W2), 2 * F, w.dez1, w.ez1, 0))) return rc;
   if ((rc = linear_bwd<TA>(s, w.dez1, N, 2 * F, WA(o.W1), F, w.dn0, nullptr, 0))) return rc;
   if (N > 0) {
-    hipLaunchKernelGGL(k_layernorm_bwd<TA>, dim3((unsigned)N), dim3(64), 0, s, N, (int)F, w.dn0, w.xhat0, w.rstd0,
+    hipLaunchKernelGGL(k_layernorm_bwd<TA>, dim3(layernorm_grid(N)), dim3(256), 0, s, N, (int)F, w.dn0, w.xhat0, w.rstd0,
                        WA(o.ln_g), w.dnrm0);
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_norm_bwd_add<TA>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.XrA, w.dnrm0, w.dXrA);

@@ -898,7 +898,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_node_norm<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Xr, w.nrm0);
     TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_layernorm<D>, dim3((unsigned)N), dim3(64), 0, s, N, (int)F, (const D *)w.nrm0,
+    hipLaunchKernelGGL(k_layernorm<D>, dim3(layernorm_grid(N)), dim3(256), 0, s, N, (int)F, (const D *)w.nrm0,
                        W(o.ln_g), W(o.ln_b), w.n0, w.xhat0, w.rstd0);
     TN_LAUNCH_CHECK();
   }
@@ -943,7 +943,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
   if (N > 0) {
     hipLaunchKernelGGL(k_out_norms<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.X[L], w.on);
     TN_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_layernorm<D>, dim3((unsigned)N), dim3(64), 0, s, N, (int)(3 * F), (const D *)w.on,
+    hipLaunchKernelGGL(k_layernorm<D>, dim3(layernorm_grid(N)), dim3(256), 0, s, N, (int)(3 * F), (const D *)w.on,
                        W(o.oln_g), W(o.oln_b), w.q, w.oxhat, w.orstd);
     TN_LAUNCH_CHECK();
   }
@@ -965,7 +965,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
   if ((rc = red.coldot(s, w.dq, w.oxhat, nullptr, N, nullptr, (int)(3 * F), G(o.oln_g)))) return rc;
   if ((rc = red.coldot(s, w.dq, nullptr, nullptr, N, nullptr, (int)(3 * F), G(o.oln_b)))) return rc;
   if (N > 0) {
-    hipLaunchKernelGGL(k_layernorm_bwd<D>, dim3((unsigned)N), dim3(64), 0, s, N, (int)(3 * F), (const D *)w.dq,
+    hipLaunchKernelGGL(k_layernorm_bwd<D>, dim3(layernorm_grid(N)), dim3(256), 0, s, N, (int)(3 * F), (const D *)w.dq,
                        (const D *)w.oxhat, (const D *)w.orstd, W(o.oln_g), w.don);
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_out_norms_bwd<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.X[L],
@@ -1042,7 +1042,7 @@ static int run_train(const tn_model *m, hipStream_t s, const Problem &pb, const 
   if ((rc = red.coldot(s, w.dn0, w.xhat0, nullptr, N, nullptr, (int)F, G(o.ln_g)))) return rc;
   if ((rc = red.coldot(s, w.dn0, nullptr, nullptr, N, nullptr, (int)F, G(o.ln_b)))) return rc;
   if (N > 0) {
-    hipLaunchKernelGGL(k_layernorm_bwd<D>, dim3((unsigned)N), dim3(64), 0, s, N, (int)F, (const D *)w.dn0,
+    hipLaunchKernelGGL(k_layernorm_bwd<D>, dim3(layernorm_grid(N)), dim3(256), 0, s, N, (int)F, (const D *)w.dn0,
                        (const D *)w.xhat0, (const D *)w.rstd0, W(o.ln_g), w.dnrm0);
     TN_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_norm_bwd_add<D>, dim3(gNF), dim3(bs), 0, s, N, (int)F, (const D *)w.Xr, (const D *)w.dnrm0,
