@@ -1603,6 +1603,9 @@ inline int embed_gather_w(hipStream_t s, int64_t F, int64_t n, const int32_t *ro
   if (F == 64)
     hipLaunchKernelGGL((k_embed_gather_w<1, 1, TF>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid, n_pairs,
                        max_pairs, z, max_z, U, Vt, geo, phi, f0, X);
+  else if (F == 128 && std::is_same<TF, __bf16>::value)   // BF16 f0: two channels per lane, 4-byte loads
+    hipLaunchKernelGGL((k_embed_gather_w<2, 1, TF>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid, n_pairs,
+                       max_pairs, z, max_z, U, Vt, geo, phi, f0, X);
   else if (F == 128)
     hipLaunchKernelGGL((k_embed_gather_w<1, 2, TF>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr, pid,
                        n_pairs, max_pairs, z, max_z, U, Vt, geo, phi, f0, X);

@@ -327,6 +327,12 @@ template <class TL, int V>
 __device__ __forceinline__ void st_row(TL *p, const float (&o)[V]) {
   if constexpr (std::is_same<TL, float>::value) {
     stv<V>(p, o);
+  } else if constexpr (V == 2) {   // one 4-byte access (even channel offsets)
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    bf16x2 v;
+    v[0] = (__bf16)o[0];
+    v[1] = (__bf16)o[1];
+    *reinterpret_cast<bf16x2 *>(p) = v;
   } else {
 #pragma unroll
     for (int v = 0; v < V; ++v) p[v] = (TL)o[v];
@@ -337,6 +343,11 @@ template <class TZ, int V>
 __device__ __forceinline__ void ld_row(const TZ *p, float (&o)[V]) {
   if constexpr (std::is_same<TZ, float>::value) {
     ldv<V>(p, o);
+  } else if constexpr (V == 2) {   // one 4-byte access (even channel offsets)
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 v = *reinterpret_cast<const bf16x2 *>(p);
+    o[0] = (float)v[0];
+    o[1] = (float)v[1];
   } else {
 #pragma unroll
     for (int v = 0; v < V; ++v) o[v] = (float)p[v];
