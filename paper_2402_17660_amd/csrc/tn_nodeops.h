@@ -461,6 +461,128 @@ inline int launch_mix_bf16(hipStream_t s, const float *in, float *out, int64_t N
   return TN_OK;
 }
 
+// Persistent, software-pipelined mixing for F = 64 and 128 (all F output channels per
+// workgroup): workgroup b takes one part, whose weight fragments it loads into registers once,
+// and a contiguous range of 16-atom groups inside its XCD's share of the atoms; the next
+// group's coordinates are loaded into registers while the current group is multiplied and
+// stored.  The tiles and their arithmetic are those of mix_tile (BF = false: FP32 operands) and
+// mix_tile_bf16 (BF = true: coordinates rounded to BF16 in LDS, BF16 weights), so the results
+// are the same bits.  M workgroups per part and XCD; grid = 24 M.
+template <int F, int NB, bool BF>
+__global__ void __launch_bounds__(256, 2) k_mix_pipe(const float *__restrict__ in, float *__restrict__ out, int64_t N,
+                                                  const void *B0, const void *B1, const void *B2, int accumulate,
+                                                  int M, __bf16 *__restrict__ out16) {
+  static_assert(F / (64 * NB) == 1, "one column block per workgroup");
+  using TS = typename std::conditional<BF, __bf16, float>::type;
+  constexpr int LD = F + (BF ? kPadB : 4);
+  __shared__ __attribute__((aligned(16))) TS sA[16 * 5 * LD];
+  const int64_t G = (N + 15) / 16;
+  const int xcd = blockIdx.x % 8, r = blockIdx.x / 8;
+  const int part = r % 3, m = r / 3;
+  const int64_t gx0 = G * xcd / 8, gx1 = G * (xcd + 1) / 8;
+  const int64_t g0 = gx0 + (gx1 - gx0) * m / M, g1 = gx0 + (gx1 - gx0) * (m + 1) / M;
+  if (g0 >= g1) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int col0 = wave * 16 * NB;
+  auto run = [&](auto c0_tag, auto nc_tag, const void *Bv) {
+    constexpr int C0 = decltype(c0_tag)::value, NC = decltype(nc_tag)::value;
+    constexpr int NE = 16 * NC * (F / 4), IT = (NE + 255) / 256;
+    // this wave's weight fragments, once
+    constexpr int KC = BF ? F / 32 : F / 16;
+    using BFrag = typename std::conditional<BF, bf16x8, float4>::type;
+    BFrag breg[KC][NB];
+    if constexpr (BF) {
+      const __bf16 *Bt = static_cast<const __bf16 *>(Bv);
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+          breg[kc][cb] = *reinterpret_cast<const bf16x8 *>(Bt + (size_t)(col0 + cb * 16 + r16) * F + 32 * kc + 8 * q);
+    } else {
+      load_bfrag<NB, KC>(static_cast<const float *>(Bv), F, col0, breg);
+    }
+    float4 stage[IT];
+    auto load = [&](int64_t g) {
+      const int64_t a0 = g * 16;
+      const int64_t navail = N - a0 < 16 ? N - a0 : 16;
+      const float4 *src = reinterpret_cast<const float4 *>(in + a0 * 9 * F);
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int row = e / (F / 4), c4 = e % (F / 4);   // row = atom * NC + coordinate
+        const int at = row / NC, cc = row % NC;
+        stage[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < NE && at < navail) stage[it] = src[(at * 9 + C0 + cc) * (F / 4) + c4];
+      }
+    };
+    load(g0);
+    for (int64_t g = g0; g < g1; ++g) {
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int row = e / (F / 4), c4 = e % (F / 4);
+        if (e < NE) {
+          if constexpr (BF) {
+            bf16x4 v;
+            v[0] = (__bf16)stage[it].x;
+            v[1] = (__bf16)stage[it].y;
+            v[2] = (__bf16)stage[it].z;
+            v[3] = (__bf16)stage[it].w;
+            *reinterpret_cast<bf16x4 *>(sA + row * LD + 4 * c4) = v;
+          } else {
+            *reinterpret_cast<float4 *>(sA + row * LD + 4 * c4) = stage[it];
+          }
+        }
+      }
+      __syncthreads();
+      if (g + 1 < g1) load(g + 1);   // in flight during this group's products and stores
+      floatx4 acc[NC][NB];
+      zero_acc_rb<NC, NB>(acc);
+      if constexpr (BF) {
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+          for (int rb = 0; rb < NC; ++rb) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sA + (r16 * NC + rb) * LD + 32 * kc + 8 * q);
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = mfma_bf16(breg[kc][cb], a, acc[rb][cb]);
+          }
+      } else {
+        wave_mm_rows_breg<NC, NB, KC, true>(sA, NC * LD, LD, breg, acc);
+      }
+      const int64_t a0 = g * 16;
+      mix_epilogue<F, NC, NB>(acc, out, out16, a0, C0, N - a0 < 16 ? N - a0 : 16, col0, accumulate);
+      __syncthreads();   // every wave has read sA before the next group is staged
+    }
+  };
+  if (part == 0)
+    run(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}, B0);
+  else if (part == 1)
+    run(std::integral_constant<int, 1>{}, std::integral_constant<int, 3>{}, B1);
+  else
+    run(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2);
+}
+
+// Workgroups per part and XCD for k_mix_pipe: about eight 16-atom groups each, at most 21
+// (two resident workgroups per CU, the launch bound's occupancy, over an XCD's 32 CUs and the
+// three parts).
+inline int mix_pipe_m(int64_t N) {
+  const int64_t G = (N + 15) / 16;
+  int64_t M = (G / 8 + 7) / 8;
+  return (int)(M < 1 ? 1 : (M > 21 ? 21 : M));
+}
+
+template <int F, int NB, bool BF>
+inline int launch_mix_pipe(hipStream_t s, const float *in, float *out, int64_t N, const void *const Bt[3],
+                           int accumulate, __bf16 *out16) {
+  const int M = mix_pipe_m(N);
+  hipLaunchKernelGGL((k_mix_pipe<F, NB, BF>), dim3((unsigned)(24 * M)), dim3(256), 0, s, in, out, N, Bt[0], Bt[1],
+                     Bt[2], accumulate, M, out16);
+  TN_LAUNCH_CHECK();
+  return TN_OK;
+}
+
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 // Per-part channel mixing of [N, 9, F] features: out[n,c,:] = W_part(c) in[n,c,:] (forward)
@@ -475,8 +597,9 @@ inline int mix(hipStream_t s, const T *in, T *out, int64_t N, int64_t F, const T
     const T *const *Bt = adjoint ? WT : W;
     bool ok = Bt != nullptr && aligned16(in) && aligned16(out);
     for (int q = 0; ok && q < 3; ++q) ok = Bt[q] != nullptr && aligned16(Bt[q]);
-    if (ok && F == 64) return launch_mix<64, 1>(s, in, out, N, Bt, accumulate, out16);
-    if (ok && F == 128) return launch_mix<128, 2>(s, in, out, N, Bt, accumulate, out16);
+    const void *Bv[3] = {Bt[0], Bt[1], Bt[2]};
+    if (ok && F == 64) return launch_mix_pipe<64, 1, false>(s, in, out, N, Bv, accumulate, out16);
+    if (ok && F == 128) return launch_mix_pipe<128, 2, false>(s, in, out, N, Bv, accumulate, out16);
     if (ok && F == 256) return launch_mix<256, 2>(s, in, out, N, Bt, accumulate, out16);
   }
   if (out16) return TN_E_UNSUPPORTED;
@@ -495,8 +618,9 @@ inline int mix_bf16(hipStream_t s, const float *in, float *out, int64_t N, int64
   bool ok = aligned16(in) && aligned16(out);
   for (int q = 0; ok && q < 3; ++q) ok = Bt[q] != nullptr && aligned16(Bt[q]);
   if (!ok) return TN_E_UNSUPPORTED;
-  if (F == 64) return launch_mix_bf16<64>(s, in, out, N, Bt, accumulate, out16);
-  if (F == 128) return launch_mix_bf16<128>(s, in, out, N, Bt, accumulate, out16);
+  const void *Bv[3] = {Bt[0], Bt[1], Bt[2]};
+  if (F == 64) return launch_mix_pipe<64, 1, true>(s, in, out, N, Bv, accumulate, out16);
+  if (F == 128) return launch_mix_pipe<128, 2, true>(s, in, out, N, Bv, accumulate, out16);
   if (F == 256) return launch_mix_bf16<256>(s, in, out, N, Bt, accumulate, out16);
   return TN_E_UNSUPPORTED;
 }
