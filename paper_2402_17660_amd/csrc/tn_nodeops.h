@@ -1069,8 +1069,21 @@ __global__ void __launch_bounds__(128) k_energy_reduce(int64_t n, const T *eps, 
   const int32_t s = blockIdx.x;
   const int64_t lo = block_lower_bound(batch, n, s);
   const int64_t hi = block_lower_bound(batch, n, s + 1);
+  // thread t adds atoms lo + t, lo + t + 128, ... in that order; sixteen loads are issued at a
+  // time (unconditionally, the index clamped in range), so a large system does not wait for
+  // one load per term
   double acc = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += 128) acc += (double)eps[i];
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += 128 * 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t i = i0 + 128 * u;
+      v[u] = (double)eps[i < hi ? i : hi - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (i0 + 128 * u < hi) acc += v[u];
+  }
   const double tot = block_sum(acc, lds);
   if (threadIdx.x == 0) {
     E[s] = tot;
