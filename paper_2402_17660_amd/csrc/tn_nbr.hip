@@ -259,8 +259,33 @@ int box_info(const double *box, double cutoff, BoxInfo *bi) {
   return TN_OK;
 }
 
+// Cells are numbered brick by brick: 4 x 4 x 4 cells per brick, bricks in row-major order
+// (z fastest) and the cells of a brick likewise.  A run of consecutive atoms (cell order) is
+// then a compact block of space, whose neighbours' rows, gathered by the kernels that follow,
+// span fewer distinct atoms than a long pencil of cells would.  The index space is padded to
+// whole bricks; the padding cells stay empty.
+constexpr int kBrick = 4;
+__host__ __device__ inline int64_t cell_space(const int nc[3]) {
+  int64_t c = kBrick * kBrick * kBrick;
+  for (int a = 0; a < 3; ++a) c *= (nc[a] + kBrick - 1) / kBrick;
+  return c;
+}
+__host__ __device__ inline int cell_linear(int cx, int cy, int cz, const int nc[3]) {
+  const int nby = (nc[1] + kBrick - 1) / kBrick, nbz = (nc[2] + kBrick - 1) / kBrick;
+  const int brick = ((cx / kBrick) * nby + cy / kBrick) * nbz + cz / kBrick;
+  return (brick * kBrick + cx % kBrick) * kBrick * kBrick + (cy % kBrick) * kBrick + cz % kBrick;
+}
+__host__ __device__ inline void cell_coords(int c, const int nc[3], int &cx, int &cy, int &cz) {
+  const int nby = (nc[1] + kBrick - 1) / kBrick, nbz = (nc[2] + kBrick - 1) / kBrick;
+  const int brick = c / (kBrick * kBrick * kBrick), local = c % (kBrick * kBrick * kBrick);
+  const int bz = brick % nbz, by = (brick / nbz) % nby, bx = brick / (nbz * nby);
+  cx = bx * kBrick + local / (kBrick * kBrick);
+  cy = by * kBrick + (local / kBrick) % kBrick;
+  cz = bz * kBrick + local % kBrick;
+}
+
 void plan_neighbors(WsPlan &p, int64_t n, int64_t max_pairs, const BoxInfo &bi, NbrWs *w) {
-  const int64_t ncell = bi.cells ? (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2] : 0;
+  const int64_t ncell = bi.cells ? cell_space(bi.nc) : 0;
   if (bi.cells) {
     w->cell_of = p.take<int32_t>(n);
     w->cell_count = p.take<int32_t>(ncell + 1);
@@ -362,7 +387,7 @@ __global__ void k_cell_assign(const T *pos, int64_t n, BoxDev b, int32_t *cell_o
     cy = cell_coord(y, b.len[1], b.side[1], b.nc[1]);
     cz = cell_coord(z, b.len[2], b.side[2], b.nc[2]);
   }
-  const int c = (cx * b.nc[1] + cy) * b.nc[2] + cz;
+  const int c = cell_linear(cx, cy, cz, b.nc);
   cell_of[i] = c;
   atomicAdd(&cell_count[c], 1);
 }
@@ -485,10 +510,8 @@ __device__ inline void wave_candidates(int64_t s, const T *pos, const int32_t *b
   load_pos(pos, s, xi, yi, zi);
   const int32_t bs = batch[s];
   if (b.cells) {
-    const int c = scell[s];
-    const int cz = c % b.nc[2];
-    const int cy = (c / b.nc[2]) % b.nc[1];
-    const int cx = c / (b.nc[1] * b.nc[2]);
+    int cx, cy, cz;
+    cell_coords(scell[s], b.nc, cx, cy, cz);
     // distinct wrapped coordinates per axis, ascending (1 cell -> 1 value, 2 -> 2, else 3)
     int xs[3], ys[3], zs[3], nx, ny, nz;
     auto axis = [](int cc, int nc, int out[3], int &cnt) {
@@ -505,10 +528,26 @@ __device__ inline void wave_candidates(int64_t s, const T *pos, const int32_t *b
     axis(cy, b.nc[1], ys, ny);
     axis(cz, b.nc[2], zs, nz);
     const int ncells = nx * ny * nz;
-    int cs = 0, cnt = 0;
+    int cc = 0x7fffffff;
     if (lane < ncells) {
       const int ix = lane / (ny * nz), iy = (lane / nz) % ny, iz = lane % nz;
-      const int cc = (xs[ix] * b.nc[1] + ys[iy]) * b.nc[2] + zs[iz];
+      cc = cell_linear(xs[ix], ys[iy], zs[iz], b.nc);
+    }
+    // the stencil cells (distinct) in ascending linear order: lane r takes the cell of rank r,
+    // so the candidates, and with them the neighbour lists, come out sorted
+    int rank = 0;
+    for (int k = 0; k < 27; ++k) {
+      const int ck = __shfl(cc, k, 64);
+      if (k < ncells && ck < cc) ++rank;
+    }
+    int src = 0;
+    for (int k = 0; k < 27; ++k) {
+      const int rk = __shfl(rank, k, 64);
+      if (k < ncells && rk == lane) src = k;
+    }
+    cc = __shfl(cc, src, 64);
+    int cs = 0, cnt = 0;
+    if (lane < ncells) {
       cs = cell_start[cc];
       cnt = cell_start[cc + 1] - cs;
     }
@@ -679,7 +718,7 @@ int build_neighbors(hipStream_t s, int64_t n, const T *pos, const int32_t *z, co
   out.z = z;
   out.batch = batch;
   out.perm = nullptr;
-  const int64_t ncell = bi.cells ? (int64_t)bi.nc[0] * bi.nc[1] * bi.nc[2] : 0;
+  const int64_t ncell = bi.cells ? cell_space(bi.nc) : 0;
   if (n > 0) {   // the cell binning checks the positions itself
     hipLaunchKernelGGL(k_validate<T>, dim3(g), dim3(blk), 0, s, pos, z, batch, n, n_systems, max_z,
                        bi.cells ? 0 : 1, status, w.cell_count, bi.cells ? ncell + 1 : 0, w.cell_fill, ncell);
