@@ -564,14 +564,14 @@ __global__ void __launch_bounds__(256, 2) k_mix_pipe(const float *__restrict__ i
     run(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2);
 }
 
-// Workgroups per part and XCD for k_mix_pipe: about eight 16-atom groups each, at most 21
-// (two resident workgroups per CU, the launch bound's occupancy, over an XCD's 32 CUs and the
-// three parts).
-inline int mix_pipe_m(int64_t N) {
-  const int64_t G = (N + 15) / 16;
-  int64_t M = (G / 8 + 7) / 8;
-  return (int)(M < 1 ? 1 : (M > 21 ? 21 : M));
-}
+// Workgroups per part and XCD for k_mix_pipe: 21 (two resident workgroups per CU, the launch
+// bound's occupancy, over an XCD's 32 CUs and the three parts).  The pipelined kernel is used
+// only when each of them gets at least four 16-atom groups; smaller inputs run one tile per
+// workgroup (more tiles in parallel), which measured faster there (a 6000-atom box: 3.8
+// against 4.1 ms per call).
+constexpr int kMixPipeM = 21;
+inline bool mix_pipe_pays(int64_t N) { return (N + 15) / 16 >= 8 * kMixPipeM * 4; }
+inline int mix_pipe_m(int64_t) { return kMixPipeM; }
 
 template <int F, int NB, bool BF>
 inline int launch_mix_pipe(hipStream_t s, const float *in, float *out, int64_t N, const void *const Bt[3],
@@ -598,8 +598,13 @@ inline int mix(hipStream_t s, const T *in, T *out, int64_t N, int64_t F, const T
     bool ok = Bt != nullptr && aligned16(in) && aligned16(out);
     for (int q = 0; ok && q < 3; ++q) ok = Bt[q] != nullptr && aligned16(Bt[q]);
     const void *Bv[3] = {Bt[0], Bt[1], Bt[2]};
-    if (ok && F == 64) return launch_mix_pipe<64, 1, false>(s, in, out, N, Bv, accumulate, out16);
-    if (ok && F == 128) return launch_mix_pipe<128, 2, false>(s, in, out, N, Bv, accumulate, out16);
+    const bool pipe = mix_pipe_pays(N);
+    if (ok && F == 64)
+      return pipe ? launch_mix_pipe<64, 1, false>(s, in, out, N, Bv, accumulate, out16)
+                  : launch_mix<64, 1>(s, in, out, N, Bt, accumulate, out16);
+    if (ok && F == 128)
+      return pipe ? launch_mix_pipe<128, 2, false>(s, in, out, N, Bv, accumulate, out16)
+                  : launch_mix<128, 2>(s, in, out, N, Bt, accumulate, out16);
     if (ok && F == 256) return launch_mix<256, 2>(s, in, out, N, Bt, accumulate, out16);
   }
   if (out16) return TN_E_UNSUPPORTED;
@@ -619,8 +624,13 @@ inline int mix_bf16(hipStream_t s, const float *in, float *out, int64_t N, int64
   for (int q = 0; ok && q < 3; ++q) ok = Bt[q] != nullptr && aligned16(Bt[q]);
   if (!ok) return TN_E_UNSUPPORTED;
   const void *Bv[3] = {Bt[0], Bt[1], Bt[2]};
-  if (F == 64) return launch_mix_pipe<64, 1, true>(s, in, out, N, Bv, accumulate, out16);
-  if (F == 128) return launch_mix_pipe<128, 2, true>(s, in, out, N, Bv, accumulate, out16);
+  const bool pipe = mix_pipe_pays(N);
+  if (F == 64)
+    return pipe ? launch_mix_pipe<64, 1, true>(s, in, out, N, Bv, accumulate, out16)
+                : launch_mix_bf16<64>(s, in, out, N, Bt, accumulate, out16);
+  if (F == 128)
+    return pipe ? launch_mix_pipe<128, 2, true>(s, in, out, N, Bv, accumulate, out16)
+                : launch_mix_bf16<128>(s, in, out, N, Bt, accumulate, out16);
   if (F == 256) return launch_mix_bf16<256>(s, in, out, N, Bt, accumulate, out16);
   return TN_E_UNSUPPORTED;
 }
