@@ -467,20 +467,26 @@ inline int launch_mix_bf16(hipStream_t s, const float *in, float *out, int64_t N
 // group's coordinates are loaded into registers while the current group is multiplied and
 // stored.  The tiles and their arithmetic are those of mix_tile (BF = false: FP32 operands) and
 // mix_tile_bf16 (BF = true: coordinates rounded to BF16 in LDS, BF16 weights), so the results
-// are the same bits.  M workgroups per part and XCD; grid = 24 M.
+// are the same bits.  Part p gets Mp[p] workgroups per XCD (grid = 8 (Mp[0] + Mp[1] + Mp[2])),
+// chosen so that every workgroup takes about the same time (mix_pipe_split).
+struct MixPipeSplit {
+  int Mp[3];
+};
 template <int F, int NB, bool BF>
 __global__ void __launch_bounds__(256, 2) k_mix_pipe(const float *__restrict__ in, float *__restrict__ out, int64_t N,
                                                   const void *B0, const void *B1, const void *B2, int accumulate,
-                                                  int M, __bf16 *__restrict__ out16) {
+                                                  MixPipeSplit sp, __bf16 *__restrict__ out16) {
   static_assert(F / (64 * NB) == 1, "one column block per workgroup");
   using TS = typename std::conditional<BF, __bf16, float>::type;
   constexpr int LD = F + (BF ? kPadB : 4);
   __shared__ __attribute__((aligned(16))) TS sA[16 * 5 * LD];
   const int64_t G = (N + 15) / 16;
   const int xcd = blockIdx.x % 8, r = blockIdx.x / 8;
-  const int part = r % 3, m = r / 3;
+  const int part = r < sp.Mp[0] ? 0 : (r < sp.Mp[0] + sp.Mp[1] ? 1 : 2);
+  const int m = part == 0 ? r : (part == 1 ? r - sp.Mp[0] : r - sp.Mp[0] - sp.Mp[1]);
+  const int Mp = sp.Mp[part];   // workgroups of this part per XCD
   const int64_t gx0 = G * xcd / 8, gx1 = G * (xcd + 1) / 8;
-  const int64_t g0 = gx0 + (gx1 - gx0) * m / M, g1 = gx0 + (gx1 - gx0) * (m + 1) / M;
+  const int64_t g0 = gx0 + (gx1 - gx0) * m / Mp, g1 = gx0 + (gx1 - gx0) * (m + 1) / Mp;
   if (g0 >= g1) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r16 = lane & 15, q = lane >> 4;
@@ -564,21 +570,23 @@ __global__ void __launch_bounds__(256, 2) k_mix_pipe(const float *__restrict__ i
     run(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2);
 }
 
-// Workgroups per part and XCD for k_mix_pipe: 21 (two resident workgroups per CU, the launch
-// bound's occupancy, over an XCD's 32 CUs and the three parts).  The pipelined kernel is used
-// only when each of them gets at least four 16-atom groups; smaller inputs run one tile per
+// k_mix_pipe's workgroups per XCD and part: 63 in all (two resident per CU, the launch bound's
+// occupancy, over an XCD's 32 CUs).  A group of 16 atoms costs a fixed latency plus a time per
+// coordinate (measured on a 100k-atom box at F = 128: about 0.94 + 1.84 NC us per group and
+// workgroup with FP32 operands, 1.25 + 1.04 NC us with BF16), so the parts (NC = 1, 3, 5) get
+// workgroups in proportion to those costs and every workgroup ends at about the same time.
+// The pipelined kernel is used from 672 16-atom groups on; smaller inputs run one tile per
 // workgroup (more tiles in parallel), which measured faster there (a 6000-atom box: 3.8
 // against 4.1 ms per call).
-constexpr int kMixPipeM = 21;
-inline bool mix_pipe_pays(int64_t N) { return (N + 15) / 16 >= 8 * kMixPipeM * 4; }
-inline int mix_pipe_m(int64_t) { return kMixPipeM; }
+inline MixPipeSplit mix_pipe_split(bool bf16) { return bf16 ? MixPipeSplit{{11, 21, 31}} : MixPipeSplit{{9, 21, 33}}; }
+inline bool mix_pipe_pays(int64_t N) { return (N + 15) / 16 >= 672; }
 
 template <int F, int NB, bool BF>
 inline int launch_mix_pipe(hipStream_t s, const float *in, float *out, int64_t N, const void *const Bt[3],
                            int accumulate, __bf16 *out16) {
-  const int M = mix_pipe_m(N);
-  hipLaunchKernelGGL((k_mix_pipe<F, NB, BF>), dim3((unsigned)(24 * M)), dim3(256), 0, s, in, out, N, Bt[0], Bt[1],
-                     Bt[2], accumulate, M, out16);
+  const MixPipeSplit sp = mix_pipe_split(BF);
+  hipLaunchKernelGGL((k_mix_pipe<F, NB, BF>), dim3((unsigned)(8 * (sp.Mp[0] + sp.Mp[1] + sp.Mp[2]))), dim3(256), 0, s,
+                     in, out, N, Bt[0], Bt[1], Bt[2], accumulate, sp, out16);
   TN_LAUNCH_CHECK();
   return TN_OK;
 }
