@@ -42,6 +42,10 @@ struct FusedWs {
   std::vector<__bf16 *> Y16, dM16;   // BF16 copies of Y and dM for the gathers (BF16 path)
   TA *on, *oxhat, *orstd, *q, *oz, *ox, *hz, *hx, *eps, *eps_orig;
   float *dX = nullptr, *dD, *dPb, *dY, *dXr, *dT0;
+  // BF16 path: Pb, dD, dY + its gathered sum, and dT0 are read only by the next channel mixing,
+  // which rounds them to BF16, so their producers write them rounded, here (one at a time;
+  // the FP32 buffers Pb, dD and dT0 are then not allocated)
+  __bf16 *mix16 = nullptr;
   TA *dez2, *dez1, *dn0, *dnrm0, *dhz, *dox, *dq, *don;
   float *gpair;
 };
@@ -83,7 +87,12 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   per_layer(w->M, N * 9 * F);
   per_layer(w->P, N * 9 * F);
   per_layer(w->nP, N * F);
-  per_layer(w->Pb, N * 9 * F);
+  if (bf16) {   // Pb goes to mix16 in BF16
+    w->Pb.assign(L, nullptr);
+    w->mix16 = p.take<__bf16>(N * 9 * F);
+  } else {
+    per_layer(w->Pb, N * 9 * F);
+  }
   per_layer(w->D, N * 9 * F);
   if (bf16) {
     w->Y16.resize(L);
@@ -106,11 +115,11 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
     for (int64_t l = 0; l < L; ++l) w->dM16[l] = p.take<__bf16>(N * 9 * F);
   }
   w->dX = p.take<float>(N * 9 * F);
-  w->dD = p.take<float>(N * 9 * F);
+  w->dD = bf16 ? nullptr : p.take<float>(N * 9 * F);   // BF16: mix16
   w->dPb = p.take<float>(N * 9 * F);
   w->dY = p.take<float>(N * 9 * F);
   w->dXr = p.take<float>(N * 9 * F);
-  w->dT0 = p.take<float>(N * 9 * F);
+  w->dT0 = bf16 ? nullptr : p.take<float>(N * 9 * F);   // BF16: mix16
   w->dez2 = p.take<TA>(N * 3 * F);
   w->dez1 = p.take<TA>(N * 2 * F);
   w->dn0 = p.take<TA>(N * F);
@@ -163,6 +172,13 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     const float *Wm[3] = {W(Wf[0]), W(Wf[1]), W(Wf[2])};
     const float *WmT[3] = {W(WT[0]), W(WT[1]), W(WT[2])};
     return mix<float>(s, in, out, N, F, Wm, WmT, adjoint, accumulate, out16);
+  };
+  // the same mixing of an input already rounded to BF16 (BF16 path only)
+  auto mixing16 = [&](const __bf16 *in, float *out, const size_t Wf[3], const size_t WT[3], int adjoint,
+                      int accumulate) -> int {
+    const size_t *off = adjoint ? WT : Wf;
+    const __bf16 *Bt[3] = {WB(off[0]), WB(off[1]), WB(off[2])};
+    return mix_bf16(s, in, out, N, F, Bt, accumulate);
   };
   auto fill_common = [&](auto &pf) {
     pf.pairs = gr.pairs;
@@ -257,11 +273,18 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     if ((rc = mixing(w.Xb[l], w.Y[l], lo.W1f, lo.W1T, 0, 0, y16))) return rc;
     // the neighbours' rows from the BF16 copy in the BF16 path
     const TY *yg = BF16 ? reinterpret_cast<const TY *>(y16) : reinterpret_cast<const TY *>(w.Y[l]);
-    if ((rc = message_product_w(s, F, N, rowptr, nbr, pid, np, MP, reinterpret_cast<const TH *>(w.h[l]), yg, w.Y[l],
-                                w.M[l], w.P[l], w.nP[l],
-                                w.Pb[l])))
-      return rc;
-    if ((rc = mixing(w.Pb[l], w.D[l], lo.W2f, lo.W2T, 0, 0, nullptr))) return rc;
+    const TH *hl = reinterpret_cast<const TH *>(w.h[l]);
+    if (BF16) {
+      if ((rc = message_product_w(s, F, N, rowptr, nbr, pid, np, MP, hl, yg, w.mix16, w.Y[l], w.M[l], w.P[l],
+                                  w.nP[l])))
+        return rc;
+      if ((rc = mixing16(w.mix16, w.D[l], lo.W2f, lo.W2T, 0, 0))) return rc;
+    } else {
+      if ((rc = message_product_w(s, F, N, rowptr, nbr, pid, np, MP, hl, yg, w.Pb[l], w.Y[l], w.M[l], w.P[l],
+                                  w.nP[l])))
+        return rc;
+      if ((rc = mixing(w.Pb[l], w.D[l], lo.W2f, lo.W2T, 0, 0, nullptr))) return rc;
+    }
     if (N > 0) {
       if (l + 1 < L) {
         hipLaunchKernelGGL(k_residual_normalize<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.Xb[l], w.D[l],
@@ -318,32 +341,55 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
   }
   for (int64_t l = L - 1; l >= 0; --l) {
     const LayerOff &lo = o.layer[l];
-    if (N > 0) {
-      hipLaunchKernelGGL(k_residual_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.D[l], w.dX, w.dD);
-      TN_LAUNCH_CHECK();
+    if (BF16) {
+      if (N > 0) {
+        hipLaunchKernelGGL((k_residual_bwd<float, __bf16>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.D[l], w.dX,
+                           w.mix16);
+        TN_LAUNCH_CHECK();
+      }
+      if ((rc = mixing16(w.mix16, w.dPb, lo.W2f, lo.W2T, 1, 0))) return rc;
+    } else {
+      if (N > 0) {
+        hipLaunchKernelGGL(k_residual_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.D[l], w.dX, w.dD);
+        TN_LAUNCH_CHECK();
+      }
+      if ((rc = mixing(w.dD, w.dPb, lo.W2f, lo.W2T, 1, 0, nullptr))) return rc;
     }
-    if ((rc = mixing(w.dD, w.dPb, lo.W2f, lo.W2T, 1, 0, nullptr))) return rc;
     if (N > 0) {
       hipLaunchKernelGGL(k_product_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dPb, w.P[l], w.nP[l], w.Y[l],
                          w.M[l], w.dY, w.dM[l], BF16 ? w.dM16[l] : nullptr);
       TN_LAUNCH_CHECK();
     }
     const TY *dmg = BF16 ? reinterpret_cast<const TY *>(w.dM16[l]) : reinterpret_cast<const TY *>(w.dM[l]);
-    if ((rc = message_w(s, F, N, rowptr, nbr, pid, np, MP, reinterpret_cast<const TH *>(w.h[l]), dmg, w.dY, 1)))
-      return rc;
-    if ((rc = mixing(w.dY, w.dX, lo.W1f, lo.W1T, 1, 1, nullptr))) return rc;
+    const TH *hl = reinterpret_cast<const TH *>(w.h[l]);
+    if (BF16) {   // dY + the gathered sum, rounded to BF16 for the mixing
+      if ((rc = message_w(s, F, N, rowptr, nbr, pid, np, MP, hl, dmg, w.mix16, 1, (const float *)w.dY))) return rc;
+      if ((rc = mixing16(w.mix16, w.dX, lo.W1f, lo.W1T, 1, 1))) return rc;
+    } else {
+      if ((rc = message_w(s, F, N, rowptr, nbr, pid, np, MP, hl, dmg, w.dY, 1, (const float *)nullptr))) return rc;
+      if ((rc = mixing(w.dY, w.dX, lo.W1f, lo.W1T, 1, 1, nullptr))) return rc;
+    }
     if (N > 0) {
       hipLaunchKernelGGL(k_normalize_bwd<float>, dim3(gNF), dim3(bs), 0, s, N, (int)F, w.X[l], w.nX[l], w.dX);
       TN_LAUNCH_CHECK();
     }
   }
   // ---- embedding adjoint, node part in FP64
-  if (N > 0) {
-    hipLaunchKernelGGL((k_gate_bwd<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dX, w.T0, w.g, w.dez2,
-                       w.dT0, w.ez2);
-    TN_LAUNCH_CHECK();
+  if (BF16) {
+    if (N > 0) {
+      hipLaunchKernelGGL((k_gate_bwd<TA, float, __bf16>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dX, w.T0, w.g,
+                         w.dez2, w.mix16, w.ez2);
+      TN_LAUNCH_CHECK();
+    }
+    if ((rc = mixing16(w.mix16, w.dXr, o.Wmixf, o.WmixT, 1, 0))) return rc;
+  } else {
+    if (N > 0) {
+      hipLaunchKernelGGL((k_gate_bwd<TA, float>), dim3(gNF), dim3(bs), 0, s, N, (int)F, w.dX, w.T0, w.g, w.dez2,
+                         w.dT0, w.ez2);
+      TN_LAUNCH_CHECK();
+    }
+    if ((rc = mixing(w.dT0, w.dXr, o.Wmixf, o.WmixT, 1, 0, nullptr))) return rc;
   }
-  if ((rc = mixing(w.dT0, w.dXr, o.Wmixf, o.WmixT, 1, 0, nullptr))) return rc;
   if ((rc = linear_bwd<TA>(s, w.dez2, N, 3 * F, WA(o.W2), 2 * F, w.dez1, w.ez1, 0))) return rc;
   if ((rc = linear_bwd<TA>(s, w.dez1, N, 2 * F, WA(o.W1), F, w.dn0, nullptr, 0))) return rc;
   if (N > 0) {

@@ -358,13 +358,35 @@ inline int launch_mix(hipStream_t s, const float *in, float *out, int64_t N, con
   return TN_OK;
 }
 
+// Four consecutive staging values of a mixing input: FP32 (float4), or BF16 (bf16x4) when the
+// producer already rounded them, as the BF16 mixing would; stored to LDS as BF16.
+template <class TI> struct Stage4;
+template <> struct Stage4<float> {
+  using type = float4;
+  static __device__ __forceinline__ float4 zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  static __device__ __forceinline__ bf16x4 to_bf16(const float4 &v) {
+    bf16x4 o;
+    o[0] = (__bf16)v.x;
+    o[1] = (__bf16)v.y;
+    o[2] = (__bf16)v.z;
+    o[3] = (__bf16)v.w;
+    return o;
+  }
+};
+template <> struct Stage4<__bf16> {
+  using type = bf16x4;
+  static __device__ __forceinline__ bf16x4 zero() { return bf16x4{}; }
+  static __device__ __forceinline__ bf16x4 to_bf16(const bf16x4 &v) { return v; }
+};
+
 // BF16 channel mixing (the BF16 precision mode): the tiles of mix_tile, with the part's
 // coordinates rounded to BF16 as they are staged in LDS, BF16 weights held in registers
 // (KC = F/32 fragments of 32 input channels per 16 output channels) and
 // v_mfma_f32_16x16x32_bf16; FP32 accumulation, FP32 output (plus the optional BF16 copy).
-// sA holds 16 * 5 * (F + kPadB) BF16 elements.  256 threads.
-template <int F, int NB>
-__device__ __forceinline__ void mix_tile_bf16(const float *__restrict__ in, float *__restrict__ out, int64_t N,
+// The input is FP32 or already BF16 (TI).  sA holds 16 * 5 * (F + kPadB) BF16 elements.
+// 256 threads.
+template <int F, int NB, class TI = float>
+__device__ __forceinline__ void mix_tile_bf16(const TI *__restrict__ in, float *__restrict__ out, int64_t N,
                                               const __bf16 *__restrict__ B0, const __bf16 *__restrict__ B1,
                                               const __bf16 *__restrict__ B2, int accumulate, int ncb, int64_t t,
                                               __bf16 *__restrict__ sA, __bf16 *__restrict__ out16 = nullptr) {
@@ -385,29 +407,23 @@ __device__ __forceinline__ void mix_tile_bf16(const float *__restrict__ in, floa
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb)
         breg[kc][cb] = *reinterpret_cast<const bf16x8 *>(Bt + (size_t)(col0 + cb * 16 + r16) * F + 32 * kc + 8 * q);
-    const float4 *src = reinterpret_cast<const float4 *>(in + a0 * 9 * F);
+    using S4 = Stage4<TI>;
+    const typename S4::type *src = reinterpret_cast<const typename S4::type *>(in + a0 * 9 * F);
     constexpr int NE = 16 * NC * (F / 4), IT = (NE + 255) / 256;
-    float4 stage[IT];
+    typename S4::type stage[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int e = threadIdx.x + 256 * it;
       const int row = e / (F / 4), c4 = e % (F / 4);   // row = atom * NC + coordinate
       const int at = row / NC, cc = row % NC;
-      stage[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+      stage[it] = S4::zero();
       if (e < NE && at < navail) stage[it] = src[(at * 9 + C0 + cc) * (F / 4) + c4];
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int e = threadIdx.x + 256 * it;
       const int row = e / (F / 4), c4 = e % (F / 4);
-      if (e < NE) {
-        bf16x4 v;
-        v[0] = (__bf16)stage[it].x;
-        v[1] = (__bf16)stage[it].y;
-        v[2] = (__bf16)stage[it].z;
-        v[3] = (__bf16)stage[it].w;
-        *reinterpret_cast<bf16x4 *>(sA + row * LD + 4 * c4) = v;
-      }
+      if (e < NE) *reinterpret_cast<bf16x4 *>(sA + row * LD + 4 * c4) = S4::to_bf16(stage[it]);
     }
     __syncthreads();
     floatx4 acc[NC][NB];
@@ -430,8 +446,8 @@ __device__ __forceinline__ void mix_tile_bf16(const float *__restrict__ in, floa
     run(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{}, B2);
 }
 
-template <int F, int NB>
-__global__ void __launch_bounds__(256) k_mix_bf16(const float *__restrict__ in, float *__restrict__ out, int64_t N,
+template <int F, int NB, class TI>
+__global__ void __launch_bounds__(256) k_mix_bf16(const TI *__restrict__ in, float *__restrict__ out, int64_t N,
                                                   const __bf16 *__restrict__ B0, const __bf16 *__restrict__ B1,
                                                   const __bf16 *__restrict__ B2, int accumulate, int ncb,
                                                   int64_t ntiles, __bf16 *__restrict__ out16) {
@@ -439,7 +455,7 @@ __global__ void __launch_bounds__(256) k_mix_bf16(const float *__restrict__ in, 
   const int64_t per_xcd = (int64_t)gridDim.x / 8;
   const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= ntiles) return;
-  mix_tile_bf16<F, NB>(in, out, N, B0, B1, B2, accumulate, ncb, t, sA, out16);
+  mix_tile_bf16<F, NB, TI>(in, out, N, B0, B1, B2, accumulate, ncb, t, sA, out16);
 }
 
 // output channels per BF16 mixing workgroup: all F for F <= 128 (each staged part is read once)
@@ -449,13 +465,13 @@ struct MixBf16Shape {
   static constexpr int ncb = F / (64 * NB);
 };
 
-template <int F>
-inline int launch_mix_bf16(hipStream_t s, const float *in, float *out, int64_t N, const __bf16 *const Bt[3],
+template <int F, class TI>
+inline int launch_mix_bf16(hipStream_t s, const TI *in, float *out, int64_t N, const __bf16 *const Bt[3],
                            int accumulate, __bf16 *out16) {
   constexpr int NB = MixBf16Shape<F>::NB, ncb = MixBf16Shape<F>::ncb;
   const int64_t ntiles = (N + 15) / 16 * ncb * 3;
   const int64_t grid = (ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_mix_bf16<F, NB>), dim3((unsigned)grid), dim3(256), 0, s, in, out, N, Bt[0], Bt[1], Bt[2],
+  hipLaunchKernelGGL((k_mix_bf16<F, NB, TI>), dim3((unsigned)grid), dim3(256), 0, s, in, out, N, Bt[0], Bt[1], Bt[2],
                      accumulate, ncb, ntiles, out16);
   TN_LAUNCH_CHECK();
   return TN_OK;
@@ -472,11 +488,12 @@ inline int launch_mix_bf16(hipStream_t s, const float *in, float *out, int64_t N
 struct MixPipeSplit {
   int Mp[3];
 };
-template <int F, int NB, bool BF>
-__global__ void __launch_bounds__(256, 2) k_mix_pipe(const float *__restrict__ in, float *__restrict__ out, int64_t N,
+template <int F, int NB, bool BF, class TI = float>
+__global__ void __launch_bounds__(256, 2) k_mix_pipe(const TI *__restrict__ in, float *__restrict__ out, int64_t N,
                                                   const void *B0, const void *B1, const void *B2, int accumulate,
                                                   MixPipeSplit sp, __bf16 *__restrict__ out16) {
   static_assert(F / (64 * NB) == 1, "one column block per workgroup");
+  static_assert(BF || std::is_same<TI, float>::value, "BF16 inputs only for BF16 operands");
   using TS = typename std::conditional<BF, __bf16, float>::type;
   constexpr int LD = F + (BF ? kPadB : 4);
   __shared__ __attribute__((aligned(16))) TS sA[16 * 5 * LD];
@@ -508,17 +525,18 @@ __global__ void __launch_bounds__(256, 2) k_mix_pipe(const float *__restrict__ i
     } else {
       load_bfrag<NB, KC>(static_cast<const float *>(Bv), F, col0, breg);
     }
-    float4 stage[IT];
+    using S4 = Stage4<TI>;
+    typename S4::type stage[IT];
     auto load = [&](int64_t g) {
       const int64_t a0 = g * 16;
       const int64_t navail = N - a0 < 16 ? N - a0 : 16;
-      const float4 *src = reinterpret_cast<const float4 *>(in + a0 * 9 * F);
+      const typename S4::type *src = reinterpret_cast<const typename S4::type *>(in + a0 * 9 * F);
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int e = threadIdx.x + 256 * it;
         const int row = e / (F / 4), c4 = e % (F / 4);   // row = atom * NC + coordinate
         const int at = row / NC, cc = row % NC;
-        stage[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+        stage[it] = S4::zero();
         if (e < NE && at < navail) stage[it] = src[(at * 9 + C0 + cc) * (F / 4) + c4];
       }
     };
@@ -530,12 +548,7 @@ __global__ void __launch_bounds__(256, 2) k_mix_pipe(const float *__restrict__ i
         const int row = e / (F / 4), c4 = e % (F / 4);
         if (e < NE) {
           if constexpr (BF) {
-            bf16x4 v;
-            v[0] = (__bf16)stage[it].x;
-            v[1] = (__bf16)stage[it].y;
-            v[2] = (__bf16)stage[it].z;
-            v[3] = (__bf16)stage[it].w;
-            *reinterpret_cast<bf16x4 *>(sA + row * LD + 4 * c4) = v;
+            *reinterpret_cast<bf16x4 *>(sA + row * LD + 4 * c4) = S4::to_bf16(stage[it]);
           } else {
             *reinterpret_cast<float4 *>(sA + row * LD + 4 * c4) = stage[it];
           }
@@ -581,11 +594,11 @@ __global__ void __launch_bounds__(256, 2) k_mix_pipe(const float *__restrict__ i
 inline MixPipeSplit mix_pipe_split(bool bf16) { return bf16 ? MixPipeSplit{{11, 21, 31}} : MixPipeSplit{{9, 21, 33}}; }
 inline bool mix_pipe_pays(int64_t N) { return (N + 15) / 16 >= 672; }
 
-template <int F, int NB, bool BF>
-inline int launch_mix_pipe(hipStream_t s, const float *in, float *out, int64_t N, const void *const Bt[3],
+template <int F, int NB, bool BF, class TI = float>
+inline int launch_mix_pipe(hipStream_t s, const TI *in, float *out, int64_t N, const void *const Bt[3],
                            int accumulate, __bf16 *out16) {
   const MixPipeSplit sp = mix_pipe_split(BF);
-  hipLaunchKernelGGL((k_mix_pipe<F, NB, BF>), dim3((unsigned)(8 * (sp.Mp[0] + sp.Mp[1] + sp.Mp[2]))), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_mix_pipe<F, NB, BF, TI>), dim3((unsigned)(8 * (sp.Mp[0] + sp.Mp[1] + sp.Mp[2]))), dim3(256), 0, s,
                      in, out, N, Bt[0], Bt[1], Bt[2], accumulate, sp, out16);
   TN_LAUNCH_CHECK();
   return TN_OK;
@@ -623,9 +636,11 @@ inline int mix(hipStream_t s, const T *in, T *out, int64_t N, int64_t F, const T
   return gemm(s, g, 9);
 }
 
-// BF16 per-part channel mixing of FP32 [N, 9, F] features (see mix): Bt[p] is W_p (forward)
-// or its transpose (adjoint), BF16, 16-byte aligned.  F in {64, 128, 256}.
-inline int mix_bf16(hipStream_t s, const float *in, float *out, int64_t N, int64_t F, const __bf16 *const Bt[3],
+// BF16 per-part channel mixing of [N, 9, F] features (see mix), FP32 or already rounded to BF16
+// (TI, the same results): Bt[p] is W_p (forward) or its transpose (adjoint), BF16, 16-byte
+// aligned.  F in {64, 128, 256}.
+template <class TI>
+inline int mix_bf16(hipStream_t s, const TI *in, float *out, int64_t N, int64_t F, const __bf16 *const Bt[3],
                     int accumulate, __bf16 *out16 = nullptr) {
   if (N <= 0) return TN_OK;
   bool ok = aligned16(in) && aligned16(out);
@@ -634,12 +649,12 @@ inline int mix_bf16(hipStream_t s, const float *in, float *out, int64_t N, int64
   const void *Bv[3] = {Bt[0], Bt[1], Bt[2]};
   const bool pipe = mix_pipe_pays(N);
   if (F == 64)
-    return pipe ? launch_mix_pipe<64, 1, true>(s, in, out, N, Bv, accumulate, out16)
-                : launch_mix_bf16<64>(s, in, out, N, Bt, accumulate, out16);
+    return pipe ? launch_mix_pipe<64, 1, true, TI>(s, in, out, N, Bv, accumulate, out16)
+                : launch_mix_bf16<64, TI>(s, in, out, N, Bt, accumulate, out16);
   if (F == 128)
-    return pipe ? launch_mix_pipe<128, 2, true>(s, in, out, N, Bv, accumulate, out16)
-                : launch_mix_bf16<128>(s, in, out, N, Bt, accumulate, out16);
-  if (F == 256) return launch_mix_bf16<256>(s, in, out, N, Bt, accumulate, out16);
+    return pipe ? launch_mix_pipe<128, 2, true, TI>(s, in, out, N, Bv, accumulate, out16)
+                : launch_mix_bf16<128, TI>(s, in, out, N, Bt, accumulate, out16);
+  if (F == 256) return launch_mix_bf16<256, TI>(s, in, out, N, Bt, accumulate, out16);
   return TN_E_UNSUPPORTED;
 }
 
@@ -1142,8 +1157,9 @@ __global__ void k_out_norms_bwd(int64_t n, int F, const TX *X, const T *don, TX 
 }
 
 // X_out = Xb + D + DD:  dD = dX + rec^T(dQ D^T + D^T dQ) with dQ = dec^T(dX)
-template <class T>
-__device__ inline void residual_bwd_at(int64_t t, int F, const T *D, const T *dX, T *dD) {
+// dD in T or, for a consumer that rounds it to BF16 anyway, BF16 (TO)
+template <class T, class TO = T>
+__device__ inline void residual_bwd_at(int64_t t, int F, const T *D, const T *dX, TO *dD) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T dc[9], Dm[9], g[9], dQ[9], A1[9], A2[9], r[9];
@@ -1157,14 +1173,13 @@ __device__ inline void residual_bwd_at(int64_t t, int F, const T *D, const T *dX
   for (int q = 0; q < 9; ++q) A1[q] += A2[q];
   rec_adj(A1, r);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) r[q] += g[q];
-  store9(dD, i, F, f, r);
+  for (int q = 0; q < 9; ++q) dD[i * 9 * F + q * F + f] = (TO)(r[q] + g[q]);
 }
-template <class T>
-__global__ void k_residual_bwd(int64_t n, int F, const T *D, const T *dX, T *dD) {
+template <class T, class TO = T>
+__global__ void k_residual_bwd(int64_t n, int F, const T *D, const T *dX, TO *dD) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
-  residual_bwd_at<T>(t, F, D, dX, dD);
+  residual_bwd_at<T, TO>(t, F, D, dX, dD);
 }
 
 // Through Pb = P/(||P||+1) and P = Y M + M Y: dY (overwritten) and dM.
@@ -1283,8 +1298,10 @@ __global__ void __launch_bounds__(128) k_edge_bwd_top(int64_t max_pairs, const i
 
 // X0 = g * T0 (per part):  dg[part] = sum_{c in part} dX0_c T0_c;  dT0 = g dX0
 // With ez given, dg leaves multiplied by silu'(ez) (the adjoint of the MLP's last SiLU).
-template <class T, class TX>
-__device__ inline void gate_bwd_at(int64_t t, int F, const TX *dX, const TX *T0, const T *g, T *dg, TX *dT0, const T *ez) {
+// dT0 in TX or, for a consumer that rounds it to BF16 anyway, BF16 (TO)
+template <class T, class TX, class TO = TX>
+__device__ inline void gate_bwd_at(int64_t t, int F, const TX *dX, const TX *T0, const T *g, T *dg, TO *dT0,
+                                   const T *ez) {
   const int64_t i = t / F;
   const int f = (int)(t % F);
   T s[3] = {T(0), T(0), T(0)};
@@ -1293,7 +1310,7 @@ __device__ inline void gate_bwd_at(int64_t t, int F, const TX *dX, const TX *T0,
     const int64_t o = i * 9 * F + q * F + f;
     const int pt = coord_part(q);
     s[pt] += (T)dX[o] * (T)T0[o];
-    dT0[o] = (TX)(g[i * 3 * F + pt * F + f] * (T)dX[o]);
+    dT0[o] = (TO)(TX)(g[i * 3 * F + pt * F + f] * (T)dX[o]);
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -1301,12 +1318,12 @@ __device__ inline void gate_bwd_at(int64_t t, int F, const TX *dX, const TX *T0,
     dg[o] = ez ? s[q] * silu_grad(ez[o]) : s[q];
   }
 }
-template <class T, class TX = T>
-__global__ void k_gate_bwd(int64_t n, int F, const TX *dX, const TX *T0, const T *g, T *dg, TX *dT0,
+template <class T, class TX = T, class TO = TX>
+__global__ void k_gate_bwd(int64_t n, int F, const TX *dX, const TX *T0, const T *g, T *dg, TO *dT0,
                            const T *ez = nullptr) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n * F) return;
-  gate_bwd_at<T, TX>(t, F, dX, T0, g, dg, dT0, ez);
+  gate_bwd_at<T, TX, TO>(t, F, dX, T0, g, dg, dT0, ez);
 }
 
 template <class T>
@@ -1580,48 +1597,75 @@ __device__ __forceinline__ void gather_message(int32_t e0, int32_t e1, const int
   }
 }
 
-// M_i (+)= sum_j h_part(c)(d_ij) * Y_j[c]
-template <int V, int G, class TH, class TY>
+// V consecutive FP32 values stored as float or, rounded, as BF16 (one 4-byte access for V = 2).
+template <int V>
+__device__ __forceinline__ void st_vals(float *p, const float (&o)[V]) {
+  stv<V>(p, o);
+}
+template <int V>
+__device__ __forceinline__ void st_vals(__bf16 *p, const float (&o)[V]) {
+  if constexpr (V == 2) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    bf16x2 v;
+    v[0] = (__bf16)o[0];
+    v[1] = (__bf16)o[1];
+    *reinterpret_cast<bf16x2 *>(p) = v;
+    return;
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) p[v] = (__bf16)o[v];
+}
+
+// M_i (+)= sum_j h_part(c)(d_ij) * Y_j[c]; M in FP32 or, for a consumer that rounds it to BF16
+// anyway, BF16 (TO).  Accumulating, the old values are read from Mold (FP32), or from M itself
+// when Mold is null (TO = float only).
+template <int V, int G, class TH, class TY, class TO = float>
 __device__ __forceinline__ void message_wave(int32_t i, int f, int32_t e0, int32_t e1,
                                              const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
-                                             const TH *__restrict__ h, const TY *__restrict__ Y,
-                                             float *__restrict__ M, int accumulate) {
+                                             const TH *__restrict__ h, const TY *__restrict__ Y, TO *M,
+                                             int accumulate, const float *Mold = nullptr) {
   constexpr int F = 64 * V * G;
   float c[9][V];
   gather_message<V, G, TH, TY>(e0, e1, nbr, pid, h, Y, f, c);
-  float *m = M + (int64_t)i * 9 * F + f;
+  const int64_t base = (int64_t)i * 9 * F + f;
+  const float *src = Mold;
+  if constexpr (std::is_same<TO, float>::value) {
+    if (!src) src = M;
+  }
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     if (accumulate) {
       float old[V];
-      ldv<V>(m + q * F, old);
+      ldv<V>(src + base + q * F, old);
 #pragma unroll
       for (int v = 0; v < V; ++v) c[q][v] += old[v];
     }
-    stv<V>(m + q * F, c[q]);
+    st_vals<V>(M + base + q * F, c[q]);
   }
 }
 
-template <int V, int G, class TH, class TY>
+template <int V, int G, class TH, class TY, class TO>
 __global__ void __launch_bounds__(256) k_message_w(int64_t n, const int32_t *__restrict__ rowptr,
                                                    const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
                                                    const int64_t *n_pairs, int64_t max_pairs,
-                                                   const TH *__restrict__ h, const TY *__restrict__ Y,
-                                                   float *__restrict__ M, int accumulate) {
+                                                   const TH *__restrict__ h, const TY *__restrict__ Y, TO *M,
+                                                   int accumulate, const float *Mold) {
   const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  message_wave<V, G, TH, TY>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Y, M, accumulate);
+  message_wave<V, G, TH, TY, TO>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Y, M, accumulate,
+                                 Mold);
 }
 
 // M_i = sum_j h_part(c) * Y_j[c]; P = Y M + M Y; Pb = P / (||P|| + 1).  Writes M, P, ||P||, Pb.
-// The neighbours' rows come from Yg (TY: Y itself, or its BF16 copy), the atom's own from Y.
-template <int V, int G, class TH, class TY>
+// The neighbours' rows come from Yg (TY: Y itself, or its BF16 copy), the atom's own from Y;
+// Pb in FP32 or, for a consumer that rounds it to BF16 anyway, BF16 (TO).
+template <int V, int G, class TH, class TY, class TO = float>
 __device__ __forceinline__ void message_product_wave(int32_t i, int f, int32_t e0, int32_t e1,
                                                      const int32_t *__restrict__ nbr,
                                                      const int32_t *__restrict__ pid, const TH *__restrict__ h,
                                                      const TY *__restrict__ Yg, const float *__restrict__ Y,
                                                      float *__restrict__ M, float *__restrict__ P,
-                                                     float *__restrict__ nP, float *__restrict__ Pb) {
+                                                     float *__restrict__ nP, TO *__restrict__ Pb) {
   constexpr int F = 64 * V * G;
   float mc[9][V], yc[9][V];
   gather_message<V, G, TH, TY>(e0, e1, nbr, pid, h, Yg, f, mc);
@@ -1661,21 +1705,21 @@ __device__ __forceinline__ void message_product_wave(int32_t i, int f, int32_t e
     for (int q = 0; q < 9; ++q) pc[q][v] *= sc;
   }
 #pragma unroll
-  for (int q = 0; q < 9; ++q) stv<V>(Pb + base + q * F, pc[q]);
+  for (int q = 0; q < 9; ++q) st_vals<V>(Pb + base + q * F, pc[q]);
 }
 
-template <int V, int G, class TH, class TY>
+template <int V, int G, class TH, class TY, class TO>
 __global__ void __launch_bounds__(256) k_message_product_w(int64_t n, const int32_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ nbr,
                                                            const int32_t *__restrict__ pid, const int64_t *n_pairs,
                                                            int64_t max_pairs, const TH *__restrict__ h,
-                                                           const TY *__restrict__ Yg, const float *__restrict__ Y,
-                                                           float *__restrict__ M, float *__restrict__ P,
-                                                           float *__restrict__ nP, float *__restrict__ Pb) {
+                                                           const TY *__restrict__ Yg, TO *__restrict__ Pb,
+                                                           const float *__restrict__ Y, float *__restrict__ M,
+                                                           float *__restrict__ P, float *__restrict__ nP) {
   const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  message_product_wave<V, G, TH, TY>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Yg, Y, M, P,
-                                     nP, Pb);
+  message_product_wave<V, G, TH, TY, TO>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Yg, Y, M,
+                                         P, nP, Pb);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -1779,24 +1823,24 @@ inline int embed_gather_w(hipStream_t s, int64_t F, int64_t n, const int32_t *ro
 // atoms 1.51 / 1.28 ms per launch against 1.65 / 1.45; for FP32 rows the same shape is 1.3 ms
 // per step slower).  Each channel's sum runs over the same edges in the same order either way.
 #define TN_MESSAGE_LAUNCHER(NAME, KERNEL)                                                                   \
-  template <class TH, class TY, class... A>                                                               \
+  template <class TH, class TY, class TO, class... A>                                                     \
   inline int NAME(hipStream_t s, int64_t F, int64_t n, const int32_t *rowptr, const int32_t *nbr,          \
                   const int32_t *pid, const int64_t *n_pairs, int64_t max_pairs, const TH *h, const TY *y, \
-                  A... a) {                                                                                \
+                  TO *o, A... a) {                                                                         \
     if (n <= 0) return TN_OK;                                                                              \
     const dim3 b(256);                                                                                     \
     if (F == 64)                                                                                           \
-      hipLaunchKernelGGL((KERNEL<1, 1, TH, TY>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid,   \
-                         n_pairs, max_pairs, h, y, a...);                                                  \
+      hipLaunchKernelGGL((KERNEL<1, 1, TH, TY, TO>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid,   \
+                         n_pairs, max_pairs, h, y, o, a...);                                                  \
     else if (F == 128 && std::is_same<TY, __bf16>::value)                                                 \
-      hipLaunchKernelGGL((KERNEL<2, 1, TH, TY>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid,   \
-                         n_pairs, max_pairs, h, y, a...);                                                  \
+      hipLaunchKernelGGL((KERNEL<2, 1, TH, TY, TO>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid,   \
+                         n_pairs, max_pairs, h, y, o, a...);                                                  \
     else if (F == 128)                                                                                     \
-      hipLaunchKernelGGL((KERNEL<1, 2, TH, TY>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr,    \
-                         pid, n_pairs, max_pairs, h, y, a...);                                             \
+      hipLaunchKernelGGL((KERNEL<1, 2, TH, TY, TO>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr,    \
+                         pid, n_pairs, max_pairs, h, y, o, a...);                                             \
     else if (F == 256)                                                                                     \
-      hipLaunchKernelGGL((KERNEL<2, 2, TH, TY>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr,    \
-                         pid, n_pairs, max_pairs, h, y, a...);                                             \
+      hipLaunchKernelGGL((KERNEL<2, 2, TH, TY, TO>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr,    \
+                         pid, n_pairs, max_pairs, h, y, o, a...);                                             \
     else                                                                                                   \
       return TN_E_UNSUPPORTED;                                                                             \
     TN_LAUNCH_CHECK();                                                                                     \
