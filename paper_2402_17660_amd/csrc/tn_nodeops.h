@@ -53,9 +53,18 @@ __device__ __forceinline__ mf_f64x4 mfma_16x16x4(double a, double b, mf_f64x4 c)
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Epilogue inputs a GEMM launch uses (bits of EP): the row scale, the gate, the old output.
+// Kernels compiled for a subset hold registers only for those inputs.
+constexpr int kEpScale = 1, kEpGate = 2, kEpAcc = 4, kEpAll = 7;
+template <class T>
+__host__ __device__ inline int gemm_ep(const GemmArgs<T> &g) {
+  return (g.rowscale ? kEpScale : 0) | (g.gate ? kEpGate : 0) | (g.accumulate ? kEpAcc : 0);
+}
+
 // One BM x 64 output tile: blk is the flat (row tile, column tile) index, z the coordinate
 // batch index; As [BM][GBK+1] and Bs [GBN][GBK+1] are the caller's LDS.  256 threads.
-template <class T, int BM>
+// EP: the epilogue inputs this instance may use (each still checked at run time).
+template <class T, int BM, int EP = kEpAll>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int64_t blk, int z, T (*As)[GBK + 1],
                                           T (*Bs)[GBK + 1]) {
   using V = typename MfmaVec<T>::type;
@@ -144,7 +153,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int64_t blk, int
   auto ep_m = [&](int rb_, int t) -> int64_t {
     return m0 + wr + rb_ * 16 + (sizeof(T) == 4 ? 4 * q + t : 4 * t + q);
   };
-  T rs[RBW][2][4], gt[RBW][2][4], old[RBW][2][4];
+  constexpr int RS = (EP & kEpScale) ? RBW : 1, GT = (EP & kEpGate) ? RBW : 1, OL = (EP & kEpAcc) ? RBW : 1;
+  T rs[RS][2][4], gt[GT][2][4], old[OL][2][4];
 #pragma unroll
   for (int rb_ = 0; rb_ < RBW; ++rb_)
 #pragma unroll
@@ -153,9 +163,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int64_t blk, int
       for (int t = 0; t < 4; ++t) {
         const int64_t m = ep_m(rb_, t), n = n0 + wc + cb * 16 + r16;
         const bool ok = m < Mrows && n < g.N;
-        rs[rb_][cb][t] = (ok && g.rowscale) ? g.rowscale[m] : T(1);
-        gt[rb_][cb][t] = (ok && g.gate) ? g.gate[z * g.zoff + m * g.ldg + n] : T(0);
-        old[rb_][cb][t] = (ok && g.accumulate) ? C[m * g.ldc + n] : T(0);
+        if constexpr ((EP & kEpScale) != 0) rs[rb_][cb][t] = (ok && g.rowscale) ? g.rowscale[m] : T(1);
+        if constexpr ((EP & kEpGate) != 0) gt[rb_][cb][t] = (ok && g.gate) ? g.gate[z * g.zoff + m * g.ldg + n] : T(0);
+        if constexpr ((EP & kEpAcc) != 0) old[rb_][cb][t] = (ok && g.accumulate) ? C[m * g.ldc + n] : T(0);
       }
 #pragma unroll
   for (int rb_ = 0; rb_ < RBW; ++rb_)
@@ -168,18 +178,37 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int64_t blk, int
         T v = acc[rb_][cb][t] + bias[cb];
         if (g.Z) g.Z[z * g.zoff + m * g.ldz + n] = v;
         if (g.act == 1) v = silu(v);
-        if (g.rowscale) v *= rs[rb_][cb][t];
-        if (g.gate) v *= silu_grad(gt[rb_][cb][t]);
+        if constexpr ((EP & kEpScale) != 0)
+          if (g.rowscale) v *= rs[rb_][cb][t];
+        if constexpr ((EP & kEpGate) != 0)
+          if (g.gate) v *= silu_grad(gt[rb_][cb][t]);
         T *dst = C + m * g.ldc + n;
-        if (g.accumulate) *dst = old[rb_][cb][t] + v; else *dst = v;
+        if constexpr ((EP & kEpAcc) != 0) {
+          if (g.accumulate) *dst = old[rb_][cb][t] + v; else *dst = v;
+        } else {
+          *dst = v;
+        }
       }
 }
 
-template <class T, int BM>
-__global__ void __launch_bounds__(256) k_gemm_mfma(GemmArgs<T> g) {
+// The FP64 64-row tile is held to three waves per SIMD (160 registers, no spills; the compiler
+// otherwise takes 186 and leaves two): 343 -> 297 us per node-MLP product on 100k atoms.
+template <class T, int BM, int EP>
+__global__ void __launch_bounds__(256, (sizeof(T) == 8 && BM == 64) ? 3 : 1) k_gemm_mfma(GemmArgs<T> g) {
   __shared__ T As[BM][GBK + 1];
   __shared__ T Bs[GBN][GBK + 1];
-  gemm_tile<T, BM>(g, blockIdx.x, blockIdx.z, As, Bs);
+  gemm_tile<T, BM, EP>(g, blockIdx.x, blockIdx.z, As, Bs);
+}
+
+template <class T, int BM>
+inline void launch_gemm_ep(hipStream_t s, const GemmArgs<T> &g, dim3 grid) {
+  switch (gemm_ep(g)) {
+    case 0: hipLaunchKernelGGL((k_gemm_mfma<T, BM, 0>), grid, dim3(256), 0, s, g); break;
+    case kEpScale: hipLaunchKernelGGL((k_gemm_mfma<T, BM, kEpScale>), grid, dim3(256), 0, s, g); break;
+    case kEpGate: hipLaunchKernelGGL((k_gemm_mfma<T, BM, kEpGate>), grid, dim3(256), 0, s, g); break;
+    case kEpAcc: hipLaunchKernelGGL((k_gemm_mfma<T, BM, kEpAcc>), grid, dim3(256), 0, s, g); break;
+    default: hipLaunchKernelGGL((k_gemm_mfma<T, BM, kEpAll>), grid, dim3(256), 0, s, g); break;
+  }
 }
 
 // Products with few 64-row tiles use 32-row tiles: fewer than two per compute unit in FP32,
@@ -191,11 +220,9 @@ inline int gemm(hipStream_t s, const GemmArgs<T> &g, int zdim = 1) {
   const int64_t nb = (g.N + GBN - 1) / GBN;
   const int64_t tiles64 = nb * ((g.M + 63) / 64) * zdim;
   if (tiles64 < (sizeof(T) == 8 ? 2048 : 512)) {
-    dim3 grid((unsigned)(nb * ((g.M + 31) / 32)), 1, (unsigned)zdim);
-    hipLaunchKernelGGL((k_gemm_mfma<T, 32>), grid, dim3(256), 0, s, g);
+    launch_gemm_ep<T, 32>(s, g, dim3((unsigned)(nb * ((g.M + 31) / 32)), 1, (unsigned)zdim));
   } else {
-    dim3 grid((unsigned)(nb * ((g.M + 63) / 64)), 1, (unsigned)zdim);
-    hipLaunchKernelGGL((k_gemm_mfma<T, 64>), grid, dim3(256), 0, s, g);
+    launch_gemm_ep<T, 64>(s, g, dim3((unsigned)(nb * ((g.M + 63) / 64)), 1, (unsigned)zdim));
   }
   TN_LAUNCH_CHECK();
   return TN_OK;
