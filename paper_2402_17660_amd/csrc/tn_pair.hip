@@ -17,9 +17,9 @@ bool pair_kernels_support(int F, int K, int L, bool bf16) {
 //   FP32: 0 = 32 pairs, 4 waves, 3 per CU; 1 = 32, 4, 2; 2 = 16, 4, 4; 3 = 64, 4, 1;
 //         4 = 48, 4, 2
 //   BF16: 0 = 64 pairs, 4 waves, 1 per CU; 1 = 32, 4, 2; 2 = 48, 4, 2
-// (Eight-wave tiles, NW = 8, measured slower on the 6000-atom box: 32 pairs, and 48 pairs at
+// (FP32 eight-wave tiles, NW = 8, measured slower on the 6000-atom box: 32 pairs, and 48 pairs at
 // two workgroups per CU, where the 128-register cap spills; they are not built.)
-int pair_variant_count(bool bf16) { return bf16 ? 3 : 5; }
+int pair_variant_count(bool bf16) { return bf16 ? 5 : 5; }
 
 template <int TILE>
 static unsigned tile_grid(int64_t max_pairs) {
@@ -46,22 +46,22 @@ static int launch_bwd_v(hipStream_t s, const PairBwdArgs &a) {
   return TN_OK;
 }
 
-template <int F, int K, int RB, int MINB>
+template <int F, int K, int RB, int MINB, int NW = 4>
 static int launch_fwd_bf16_v(hipStream_t s, const PairFwdArgsB &a) {
   const unsigned grid = tile_grid<16 * RB>(a.max_pairs);
   if (grid == 0) return TN_OK;
   TimedScope ts("edge_fwd", s);
-  hipLaunchKernelGGL((k_pair_fwd_bf16<F, K, RB, MINB>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_pair_fwd_bf16<F, K, RB, MINB, NW>), dim3(grid), dim3(64 * NW), 0, s, a);
   TN_LAUNCH_CHECK();
   return TN_OK;
 }
 
-template <int F, int K, int RB, int MINB>
+template <int F, int K, int RB, int MINB, int NW = 4, int PF = 2>
 static int launch_bwd_bf16_v(hipStream_t s, const PairBwdArgsB &a) {
   const unsigned grid = tile_grid<16 * RB>(a.max_pairs);
   if (grid == 0) return TN_OK;
   TimedScope ts("edge_bwd", s);
-  hipLaunchKernelGGL((k_pair_bwd_bf16<F, K, RB, MINB>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_pair_bwd_bf16<F, K, RB, MINB, NW, PF>), dim3(grid), dim3(64 * NW), 0, s, a);
   TN_LAUNCH_CHECK();
   return TN_OK;
 }
@@ -88,10 +88,20 @@ static int launch_bwd(hipStream_t s, const PairBwdArgs &a, int v) {
   }
 }
 
+// BF16 shapes 3 and 4 (F = 128): eight-wave tiles, one workgroup per CU, each weight fragment
+// read once for twice (or more) the rows of the four-wave tiles: forward 96 and 112 pairs
+// (4.9 against 6.0 ms per launch on 100k atoms); reverse 96 pairs, its prologues loading one row
+// ahead or none (about as fast as shape 2: its gathers, not its weight reads, set its time;
+// 112 pairs spill).  F = 64 takes shape 2 for them.
 template <int F, int K>
 static int launch_fwd_bf16(hipStream_t s, const PairFwdArgsB &a, int v) {
   if (v == 1) return launch_fwd_bf16_v<F, K, 2, 2>(s, a);
   if (v == 2) return launch_fwd_bf16_v<F, K, 3, 2>(s, a);
+  if constexpr (F == 128) {
+    if (v == 3) return launch_fwd_bf16_v<F, K, 6, 1, 8>(s, a);
+    if (v == 4) return launch_fwd_bf16_v<F, K, 7, 1, 8>(s, a);
+  }
+  if (v >= 3) return launch_fwd_bf16_v<F, K, 3, 2>(s, a);
   return launch_fwd_bf16_v<F, K, 4, 1>(s, a);
 }
 
@@ -99,6 +109,11 @@ template <int F, int K>
 static int launch_bwd_bf16(hipStream_t s, const PairBwdArgsB &a, int v) {
   if (v == 1) return launch_bwd_bf16_v<F, K, 2, 2>(s, a);
   if (v == 2) return launch_bwd_bf16_v<F, K, 3, 2>(s, a);
+  if constexpr (F == 128 && K <= 128) {
+    if (v == 3) return launch_bwd_bf16_v<F, K, 6, 1, 8, 1>(s, a);
+    if (v == 4) return launch_bwd_bf16_v<F, K, 6, 1, 8, 0>(s, a);
+  }
+  if (v >= 3) return launch_bwd_bf16_v<F, K, 3, 2>(s, a);
   return launch_bwd_bf16_v<F, K, 4, 1>(s, a);
 }
 

@@ -812,9 +812,13 @@ __device__ __forceinline__ void wave_mm_bf16(const __bf16 *act, int ld, int Kin,
 }
 
 
-template <int F, int K, int RB>
+// NW waves per workgroup (4 or 8): wave w computes output columns [w C / NW, (w + 1) C / NW) of
+// every C-column product, so with eight waves a tile of twice the pairs reads each weight
+// fragment once for twice the rows.
+template <int F, int K, int RB, int NW = 4>
 __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_t p0, int nvalid) {
-  constexpr int TILE = 16 * RB;
+  static_assert(F % (16 * NW) == 0, "every wave takes whole 16-column blocks");
+  constexpr int TILE = 16 * RB, NT = 64 * NW;
   constexpr int LE = K + kPadB, L1 = F + kPadB, L2 = 2 * F + kPadB;
   __shared__ __attribute__((aligned(16))) __bf16 sE[TILE * LE];
   __shared__ __attribute__((aligned(16))) __bf16 sA1[TILE * L1];
@@ -838,7 +842,7 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
     sPhi[tid] = ph;
   }
   __syncthreads();
-  for (int t = tid; t < TILE * K; t += 256) {
+  for (int t = tid; t < TILE * K; t += NT) {
     const int row = t / K, k = t % K;
     const double u = sD[row];
     const double x = u - a.mu[k];
@@ -846,10 +850,10 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
   }
   __syncthreads();
   {
-    constexpr int NB = 3 * F / 64;
+    constexpr int NB = 3 * F / (16 * NW);
     floatx4 acc[RB][NB];
     zero_acc_rb<RB, NB>(acc);
-    const int col0 = wave * (3 * F / 4);
+    const int col0 = wave * (3 * F / NW);
     floatx4 br[NB];
     load_cols_t<NB>(a.b0, col0, br);
     wave_mm_bf16<RB, NB, true>(sE, LE, K, a.W0, col0, acc);
@@ -859,10 +863,10 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
   }
   for (int l = 0; l < a.L; ++l) {
     {
-      constexpr int NB = F / 64;
+      constexpr int NB = F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (F / 4);
+      const int col0 = wave * (F / NW);
       floatx4 br[NB];
       load_cols_t<NB>(a.ba[l], col0, br);
       wave_mm_bf16<RB, NB, true>(sE, LE, K, a.Wa[l], col0, acc);
@@ -876,10 +880,10 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
     }
     __syncthreads();
     {
-      constexpr int NB = F / 32;
+      constexpr int NB = 2 * F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (F / 2);
+      const int col0 = wave * (2 * F / NW);
       floatx4 br[NB];
       load_cols_t<NB>(a.bb[l], col0, br);
       wave_mm_bf16<RB, NB, true>(sA1, L1, F, a.Wb[l], col0, acc);
@@ -893,10 +897,10 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
     }
     __syncthreads();
     {
-      constexpr int NB = 3 * F / 64;
+      constexpr int NB = 3 * F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (3 * F / 4);
+      const int col0 = wave * (3 * F / NW);
       floatx4 br[NB];
       load_cols_t<NB>(a.bc[l], col0, br);
       wave_mm_bf16<RB, NB, true>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
@@ -912,29 +916,34 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
   }
 }
 
-template <int F, int K, int RB, int MINB>
-__global__ void __launch_bounds__(256, MINB) k_pair_fwd_bf16(PairFwdArgsB a) {
+template <int F, int K, int RB, int MINB, int NW = 4>
+__global__ void __launch_bounds__(64 * NW, MINB) k_pair_fwd_bf16(PairFwdArgsB a) {
   constexpr int TILE = 16 * RB;
   const int64_t P = *a.n_pairs <= a.max_pairs ? *a.n_pairs : 0;   // no pair list after an overflow
   const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
   if (tile < 0) return;
   const int64_t p0 = tile * TILE;
-  pair_fwd_tile_bf16<F, K, RB>(a, p0, (int)((P - p0) < TILE ? (P - p0) : TILE));
+  pair_fwd_tile_bf16<F, K, RB, NW>(a, p0, (int)((P - p0) < TILE ? (P - p0) : TILE));
 }
 
 
-template <int F, int K, int RB>
+// NW waves per workgroup (4 or 8), as pair_fwd_tile_bf16; PF: how far the prologues load ahead
+// (embed_adjoint_rows, filter_adjoint_rows).
+template <int F, int K, int RB, int NW = 4, int PF = 2>
 __device__ __forceinline__ void pair_bwd_tile_bf16(const PairBwdArgsB &a, int64_t p0, int nvalid) {
+  static_assert(F % (16 * NW) == 0 && NW >= K / 16, "every wave takes whole 16-column blocks");
   constexpr int TILE = 16 * RB;
   constexpr int L3 = 3 * F + kPadB, L2 = 2 * F + kPadB, L1 = F + kPadB, LE = K + 4;
-  static_assert(TILE * LE * 4 <= TILE * L3 * 2, "dE/de must fit in the adjoint buffer");
-  __shared__ __attribute__((aligned(16))) __bf16 sG[TILE * L3];   // df0, dz3, dz2, dz1; finally dE/de (f32)
+  __shared__ __attribute__((aligned(16))) __bf16 sG[TILE * L3];   // df0, dz3, dz2, dz1
+  // dE/de between its products (the embedding's and each layer's): an FP32 accumulator kept in
+  // LDS instead of registers and reloaded exactly, so the sums are those of one register chain
+  __shared__ float sDE[TILE * LE];
   __shared__ float sPhi[TILE], sDphi[TILE], sU[TILE][3], sDv[TILE][3];
   const int tid = threadIdx.x, wave = tid >> 6;
   constexpr int NWDE = K / 16;
-  PairGeo g{};
   if (tid < TILE) {
     float ph = 0.f;
+    PairGeo g{};
     if (tid < nvalid) {
       const int64_t p = p0 + tid;
       g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.lat, a.r_c);
@@ -946,24 +955,38 @@ __device__ __forceinline__ void pair_bwd_tile_bf16(const PairBwdArgsB &a, int64_
     sU[tid][2] = (float)g.u[2];
   }
   __syncthreads();
-  embed_adjoint_rows<F, TILE, __bf16, 4, 2, __bf16>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi,
+  embed_adjoint_rows<F, TILE, __bf16, NW, PF, __bf16>(a.g, a.pairs, a.max_pairs, p0, nvalid, sU, sPhi, sG, L3, sDphi,
                                                    sDv);
   __syncthreads();
-  floatx4 de[RB][1];
-  zero_acc_rb<RB, 1>(de);
-  if (wave < NWDE) wave_mm_bf16<RB, 1>(sG, L3, 3 * F, a.W0T, wave * 16, de);
+  // de += act * Bt^T for this wave's 16 columns of dE/de (waves < NWDE), through sDE
+  auto de_product = [&](const __bf16 *act, int ld, int Kin, const __bf16 *Bt, bool first) {
+    if (wave >= NWDE) return;
+    floatx4 de[RB][1];
+    if (first) {
+      zero_acc_rb<RB, 1>(de);
+    } else {
+      const int lane = tid & 63;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) de[rb][0][t] = sDE[(rb * 16 + 4 * (lane >> 4) + t) * LE + wave * 16 + (lane & 15)];
+    }
+    wave_mm_bf16<RB, 1>(act, ld, Kin, Bt, wave * 16, de);
+    for_acc_rc(de, wave * 16, [&](int, int, int, int row, int col, float v) { sDE[row * LE + col] = v; });
+  };
+  de_product(sG, L3, 3 * F, a.W0T, true);
   __syncthreads();
   for (int l = 0; l < a.L; ++l) {
     const __bf16 *z1 = a.z1[l], *z2 = a.z2[l];
-    filter_adjoint_rows<F, TILE, __bf16, __bf16, 4, 2, __bf16>(a.Y16[l], a.dM16[l], a.z3[l], a.pairs, a.max_pairs, p0,
+    filter_adjoint_rows<F, TILE, __bf16, __bf16, NW, PF, __bf16>(a.Y16[l], a.dM16[l], a.z3[l], a.pairs, a.max_pairs, p0,
                                                             nvalid, sPhi, sG, L3,
                                    sDphi);
     __syncthreads();
     {
-      constexpr int NB = F / 32;
+      constexpr int NB = 2 * F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (F / 2);
+      const int col0 = wave * (2 * F / NW);
       float zp[RB][NB][4];
       load_acc_rows<RB, NB>(z2, 2 * F, p0, nvalid, col0, zp);
       __builtin_amdgcn_sched_barrier(0);   // issue these loads before the product loop, not inside it
@@ -975,10 +998,10 @@ __device__ __forceinline__ void pair_bwd_tile_bf16(const PairBwdArgsB &a, int64_
     }
     __syncthreads();
     {
-      constexpr int NB = F / 64;
+      constexpr int NB = F / (16 * NW);
       floatx4 acc[RB][NB];
       zero_acc_rb<RB, NB>(acc);
-      const int col0 = wave * (F / 4);
+      const int col0 = wave * (F / NW);
       float zp[RB][NB][4];
       load_acc_rows<RB, NB>(z1, F, p0, nvalid, col0, zp);
       __builtin_amdgcn_sched_barrier(0);   // issue these loads before the product loop, not inside it
@@ -989,26 +1012,25 @@ __device__ __forceinline__ void pair_bwd_tile_bf16(const PairBwdArgsB &a, int64_
       });
     }
     __syncthreads();
-    if (wave < NWDE) wave_mm_bf16<RB, 1>(sG, L1, F, a.WaT[l], wave * 16, de);
+    de_product(sG, L1, F, a.WaT[l], false);
     __syncthreads();
   }
-  float *sDE = reinterpret_cast<float *>(sG);
-  if (wave < NWDE)
-    for_acc_rc(de, wave * 16, [&](int, int, int, int row, int col, float v) { sDE[row * LE + col] = v; });
-  __syncthreads();
-  if (tid < nvalid)
+  if (tid < nvalid) {   // the geometry again (the same arithmetic), rather than held in registers throughout
+    const int64_t p = p0 + tid;
+    const PairGeo g = pair_geometry(a.pos, a.pairs[p], a.pairs[a.max_pairs + p], a.lat, a.r_c);
     geometry_adjoint_rows<K>(g, sDE + tid * LE, 0, sDphi[tid], sDv[tid], a.alpha, a.r_lo, a.mu, a.beta,
-                             a.gpair + 3 * (p0 + tid));
+                             a.gpair + 3 * p);
+  }
 }
 
-template <int F, int K, int RB, int MINB>
-__global__ void __launch_bounds__(256, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
+template <int F, int K, int RB, int MINB, int NW = 4, int PF = 2>
+__global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd_bf16(PairBwdArgsB a) {
   constexpr int TILE = 16 * RB;
   const int64_t P = *a.n_pairs <= a.max_pairs ? *a.n_pairs : 0;   // no pair list after an overflow
   const int64_t tile = xcd_block_of((P + TILE - 1) / TILE);
   if (tile < 0) return;
   const int64_t p0 = tile * TILE;
-  pair_bwd_tile_bf16<F, K, RB>(a, p0, (int)((P - p0) < TILE ? (P - p0) : TILE));
+  pair_bwd_tile_bf16<F, K, RB, NW, PF>(a, p0, (int)((P - p0) < TILE ? (P - p0) : TILE));
 }
 
 }  // namespace tn
