@@ -1599,12 +1599,15 @@ __global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t
 }
 
 // c[q] = sum over the CSR row [e0, e1) of h_part(q)(pair) * Y_j[q]; h (TH) and the gathered
-// rows Y (TY) in FP32 or BF16
-template <int V, int G, class TH, class TY>
+// rows Y (TY) in FP32 or BF16.  With HZ, h holds the pre-activations z3 (FP32) and the filter is
+// formed here as phi silu(z3), the expression the forward pair kernel would have stored.
+template <int V, int G, class TH, class TY, bool HZ = false>
 __device__ __forceinline__ void gather_message(int32_t e0, int32_t e1, const int32_t *__restrict__ nbr,
                                                const int32_t *__restrict__ pid, const TH *__restrict__ h,
-                                               const TY *__restrict__ Y, int f, float (&c)[9][V]) {
+                                               const TY *__restrict__ Y, int f, float (&c)[9][V],
+                                               const float *__restrict__ hphi = nullptr) {
   constexpr int F = 64 * V * G;
+  static_assert(!HZ || std::is_same<TH, float>::value, "z3 is FP32");
 #pragma unroll
   for (int q = 0; q < 9; ++q)
 #pragma unroll
@@ -1615,6 +1618,13 @@ __device__ __forceinline__ void gather_message(int32_t e0, int32_t e1, const int
     float hh[3][V], y[9][V];
 #pragma unroll
     for (int pt = 0; pt < 3; ++pt) ld_pair_row<V>(h + p * 3 * F + pt * F + f, hh[pt]);
+    if constexpr (HZ) {
+      const float ph = hphi[p];
+#pragma unroll
+      for (int pt = 0; pt < 3; ++pt)
+#pragma unroll
+        for (int v = 0; v < V; ++v) hh[pt][v] = ph * fast_silu(hh[pt][v]);
+    }
 #pragma unroll
     for (int q = 0; q < 9; ++q) ld_pair_row<V>(Y + j * 9 * F + q * F + f, y[q]);
 #pragma unroll
@@ -1646,14 +1656,15 @@ __device__ __forceinline__ void st_vals(__bf16 *p, const float (&o)[V]) {
 // M_i (+)= sum_j h_part(c)(d_ij) * Y_j[c]; M in FP32 or, for a consumer that rounds it to BF16
 // anyway, BF16 (TO).  Accumulating, the old values are read from Mold (FP32), or from M itself
 // when Mold is null (TO = float only).
-template <int V, int G, class TH, class TY, class TO = float>
+template <int V, int G, class TH, class TY, class TO = float, bool HZ = false>
 __device__ __forceinline__ void message_wave(int32_t i, int f, int32_t e0, int32_t e1,
                                              const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
                                              const TH *__restrict__ h, const TY *__restrict__ Y, TO *M,
-                                             int accumulate, const float *Mold = nullptr) {
+                                             int accumulate, const float *Mold = nullptr,
+                                             const float *hphi = nullptr) {
   constexpr int F = 64 * V * G;
   float c[9][V];
-  gather_message<V, G, TH, TY>(e0, e1, nbr, pid, h, Y, f, c);
+  gather_message<V, G, TH, TY, HZ>(e0, e1, nbr, pid, h, Y, f, c, hphi);
   const int64_t base = (int64_t)i * 9 * F + f;
   const float *src = Mold;
   if constexpr (std::is_same<TO, float>::value) {
@@ -1671,31 +1682,33 @@ __device__ __forceinline__ void message_wave(int32_t i, int f, int32_t e0, int32
   }
 }
 
-template <int V, int G, class TH, class TY, class TO>
+template <int V, int G, class TH, class TY, class TO, bool HZ>
 __global__ void __launch_bounds__(256) k_message_w(int64_t n, const int32_t *__restrict__ rowptr,
                                                    const int32_t *__restrict__ nbr, const int32_t *__restrict__ pid,
                                                    const int64_t *n_pairs, int64_t max_pairs,
-                                                   const TH *__restrict__ h, const TY *__restrict__ Y, TO *M,
-                                                   int accumulate, const float *Mold) {
+                                                   const TH *__restrict__ h, const float *__restrict__ hphi,
+                                                   const TY *__restrict__ Y, TO *M, int accumulate,
+                                                   const float *Mold) {
   const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  message_wave<V, G, TH, TY, TO>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Y, M, accumulate,
-                                 Mold);
+  message_wave<V, G, TH, TY, TO, HZ>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Y, M,
+                                     accumulate, Mold, hphi);
 }
 
 // M_i = sum_j h_part(c) * Y_j[c]; P = Y M + M Y; Pb = P / (||P|| + 1).  Writes M, P, ||P||, Pb.
 // The neighbours' rows come from Yg (TY: Y itself, or its BF16 copy), the atom's own from Y;
 // Pb in FP32 or, for a consumer that rounds it to BF16 anyway, BF16 (TO).
-template <int V, int G, class TH, class TY, class TO = float>
+template <int V, int G, class TH, class TY, class TO = float, bool HZ = false>
 __device__ __forceinline__ void message_product_wave(int32_t i, int f, int32_t e0, int32_t e1,
                                                      const int32_t *__restrict__ nbr,
                                                      const int32_t *__restrict__ pid, const TH *__restrict__ h,
                                                      const TY *__restrict__ Yg, const float *__restrict__ Y,
                                                      float *__restrict__ M, float *__restrict__ P,
-                                                     float *__restrict__ nP, TO *__restrict__ Pb) {
+                                                     float *__restrict__ nP, TO *__restrict__ Pb,
+                                                     const float *hphi = nullptr) {
   constexpr int F = 64 * V * G;
   float mc[9][V], yc[9][V];
-  gather_message<V, G, TH, TY>(e0, e1, nbr, pid, h, Yg, f, mc);
+  gather_message<V, G, TH, TY, HZ>(e0, e1, nbr, pid, h, Yg, f, mc, hphi);
   const int64_t base = (int64_t)i * 9 * F + f;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -1735,18 +1748,19 @@ __device__ __forceinline__ void message_product_wave(int32_t i, int f, int32_t e
   for (int q = 0; q < 9; ++q) st_vals<V>(Pb + base + q * F, pc[q]);
 }
 
-template <int V, int G, class TH, class TY, class TO>
+template <int V, int G, class TH, class TY, class TO, bool HZ>
 __global__ void __launch_bounds__(256) k_message_product_w(int64_t n, const int32_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ nbr,
                                                            const int32_t *__restrict__ pid, const int64_t *n_pairs,
                                                            int64_t max_pairs, const TH *__restrict__ h,
-                                                           const TY *__restrict__ Yg, TO *__restrict__ Pb,
-                                                           const float *__restrict__ Y, float *__restrict__ M,
-                                                           float *__restrict__ P, float *__restrict__ nP) {
+                                                           const float *__restrict__ hphi, const TY *__restrict__ Yg,
+                                                           TO *__restrict__ Pb, const float *__restrict__ Y,
+                                                           float *__restrict__ M, float *__restrict__ P,
+                                                           float *__restrict__ nP) {
   const int32_t i = group_atom<G>();
   if (i >= n || !pairs_ok(n_pairs, max_pairs)) return;
-  message_product_wave<V, G, TH, TY, TO>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Yg, Y, M,
-                                         P, nP, Pb);
+  message_product_wave<V, G, TH, TY, TO, HZ>(i, group_channel<V, G>(), rowptr[i], rowptr[i + 1], nbr, pid, h, Yg, Y,
+                                             M, P, nP, Pb, hphi);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -1849,33 +1863,43 @@ inline int embed_gather_w(hipStream_t s, int64_t F, int64_t n, const int32_t *ro
 // wave per atom, two channels per lane, so each load moves 4 bytes instead of 2 (on 100k
 // atoms 1.51 / 1.28 ms per launch against 1.65 / 1.45; for FP32 rows the same shape is 1.3 ms
 // per step slower).  Each channel's sum runs over the same edges in the same order either way.
+// hphi: when given (FP32 h only), h holds z3 and the kernels form phi silu(z3) themselves.
+#define TN_MESSAGE_LAUNCH_HZ(KERNEL, VV, GG, GRID)                                                         \
+  if (hphi) {                                                                                              \
+    if constexpr (std::is_same<TH, float>::value)                                                         \
+      hipLaunchKernelGGL((KERNEL<VV, GG, TH, TY, TO, true>), dim3(GRID), b, 0, s, n, rowptr, nbr, pid,      \
+                         n_pairs, max_pairs, h, hphi, y, o, a...);                                        \
+    else                                                                                                   \
+      return TN_E_UNSUPPORTED;                                                                             \
+  } else {                                                                                                 \
+    hipLaunchKernelGGL((KERNEL<VV, GG, TH, TY, TO, false>), dim3(GRID), b, 0, s, n, rowptr, nbr, pid,       \
+                       n_pairs, max_pairs, h, hphi, y, o, a...);                                          \
+  }
 #define TN_MESSAGE_LAUNCHER(NAME, KERNEL)                                                                   \
   template <class TH, class TY, class TO, class... A>                                                     \
   inline int NAME(hipStream_t s, int64_t F, int64_t n, const int32_t *rowptr, const int32_t *nbr,          \
-                  const int32_t *pid, const int64_t *n_pairs, int64_t max_pairs, const TH *h, const TY *y, \
-                  TO *o, A... a) {                                                                         \
+                  const int32_t *pid, const int64_t *n_pairs, int64_t max_pairs, const TH *h,              \
+                  const float *hphi, const TY *y, TO *o, A... a) {                                         \
     if (n <= 0) return TN_OK;                                                                              \
     const dim3 b(256);                                                                                     \
-    if (F == 64)                                                                                           \
-      hipLaunchKernelGGL((KERNEL<1, 1, TH, TY, TO>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid,   \
-                         n_pairs, max_pairs, h, y, o, a...);                                                  \
-    else if (F == 128 && std::is_same<TY, __bf16>::value)                                                 \
-      hipLaunchKernelGGL((KERNEL<2, 1, TH, TY, TO>), dim3(wave_atom_grid(n)), b, 0, s, n, rowptr, nbr, pid,   \
-                         n_pairs, max_pairs, h, y, o, a...);                                                  \
-    else if (F == 128)                                                                                     \
-      hipLaunchKernelGGL((KERNEL<1, 2, TH, TY, TO>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr,    \
-                         pid, n_pairs, max_pairs, h, y, o, a...);                                             \
-    else if (F == 256)                                                                                     \
-      hipLaunchKernelGGL((KERNEL<2, 2, TH, TY, TO>), dim3(wave_atom_grid(2 * n)), b, 0, s, n, rowptr, nbr,    \
-                         pid, n_pairs, max_pairs, h, y, o, a...);                                             \
-    else                                                                                                   \
+    if (F == 64) {                                                                                         \
+      TN_MESSAGE_LAUNCH_HZ(KERNEL, 1, 1, wave_atom_grid(n))                                                \
+    } else if (F == 128 && std::is_same<TY, __bf16>::value) {                                              \
+      TN_MESSAGE_LAUNCH_HZ(KERNEL, 2, 1, wave_atom_grid(n))                                                \
+    } else if (F == 128) {                                                                                 \
+      TN_MESSAGE_LAUNCH_HZ(KERNEL, 1, 2, wave_atom_grid(2 * n))                                            \
+    } else if (F == 256) {                                                                                 \
+      TN_MESSAGE_LAUNCH_HZ(KERNEL, 2, 2, wave_atom_grid(2 * n))                                            \
+    } else {                                                                                               \
       return TN_E_UNSUPPORTED;                                                                             \
+    }                                                                                                      \
     TN_LAUNCH_CHECK();                                                                                     \
     return TN_OK;                                                                                          \
   }
 TN_MESSAGE_LAUNCHER(message_w, k_message_w)
 TN_MESSAGE_LAUNCHER(message_product_w, k_message_product_w)
 #undef TN_MESSAGE_LAUNCHER
+#undef TN_MESSAGE_LAUNCH_HZ
 
 template <class TI, class TO>
 inline int convert(hipStream_t s, const TI *in, TO *out, int64_t n) {

@@ -270,12 +270,14 @@ __device__ __forceinline__ void pair_fwd_tile(const PairFwdArgs &a, int64_t p0, 
       float br[NB];
       load_cols<NB>(a.bc[l], col0, br);
       wave_mm_rb<RB, NB>(sA, L2, 2 * F, a.Wc[l], col0, acc);
+      // h is stored only when given: its consumers may instead form it from z3 and phi,
+      // with this same expression
       float *z3 = a.z3[l], *h = a.h[l];
       for_acc_rc(acc, col0, [&](int, int cb, int, int row, int col, float v) {
         const float z = v + br[cb];
         if (row < nvalid) {
           z3[(p0 + row) * 3 * F + col] = z;
-          h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * fast_silu(z);
+          if (h) h[(p0 + row) * 3 * F + col] = (float)sPhi[row] * fast_silu(z);
         }
       });
     }

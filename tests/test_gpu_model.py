@@ -170,15 +170,16 @@ def test_100k_box_full_size(dev, precision):
     assert np.abs(F.sum(0)).max() < 1e-3 * np.abs(F).max()
 
 
-@pytest.mark.parametrize("precision,path", [("fp32", "fused"), ("bf16", "fused"), ("fp32", "plain")])
-def test_copies_of_a_molecule_match_it_bitwise(dev, precision, path):
+@pytest.mark.parametrize("precision,path,F", [("fp32", "fused", 128), ("bf16", "fused", 128), ("fp32", "plain", 128),
+                                              ("fp32", "fused", 64), ("bf16", "fused", 64)])
+def test_copies_of_a_molecule_match_it_bitwise(dev, precision, path, F):
     """768 copies of one 20-atom molecule (15,360 atoms, so the node kernels take their
     large-input shapes, the pipelined channel mixing among them) give every copy the energy
     and forces of the molecule computed alone, bit for bit: every per-atom and per-pair step
     is independent of where its rows sit in the batch."""
     n, copies = 20, 768
     pos1, z1 = random_molecule(n, 90)
-    blob = small_blob(F=128, K=32, L=2, seed=91)
+    blob = small_blob(F=F, K=32, L=2, seed=91)
     m = TensorNet(blob, dev)
     pdt = np.float64 if precision == "fp64" else np.float32
     E1, F1 = gpu_ef(dev, m, pos1.astype(pdt), z1, np.zeros(n, np.int32), None, 1, precision, path)
