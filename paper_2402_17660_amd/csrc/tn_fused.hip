@@ -83,11 +83,8 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   per_layer(w->z1, bf16 ? MP * F / 2 : MP16 * F);
   per_layer(w->z2, bf16 ? MP * F : MP16 * 2 * F);
   per_layer(w->z3, bf16 ? MP * 3 * F / 2 : MP * 3 * F);
-  // h per pair: BF16 path only; the FP32 gathers form it from z3 and phi
-  if (bf16)
-    per_layer(w->h, MP * 3 * F / 2);
-  else
-    w->h.assign(L, nullptr);
+  // no h per pair: the message gathers form it from z3 and phi
+  w->h.assign(L, nullptr);
   per_layer(w->M, N * 9 * F);
   per_layer(w->P, N * 9 * F);
   per_layer(w->nP, N * F);
@@ -213,7 +210,7 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
       pf.z1[l] = reinterpret_cast<__bf16 *>(w.z1[l]);
       pf.z2[l] = reinterpret_cast<__bf16 *>(w.z2[l]);
       pf.z3[l] = reinterpret_cast<__bf16 *>(w.z3[l]);
-      pf.h[l] = reinterpret_cast<__bf16 *>(w.h[l]);
+      pf.h[l] = nullptr;   // not stored: the message gathers form it from z3 and phi
     }
     pf.geo = w.geo;
     pf.phi = w.phi;
@@ -277,9 +274,9 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
     if ((rc = mixing(w.Xb[l], w.Y[l], lo.W1f, lo.W1T, 0, 0, y16))) return rc;
     // the neighbours' rows from the BF16 copy in the BF16 path
     const TY *yg = BF16 ? reinterpret_cast<const TY *>(y16) : reinterpret_cast<const TY *>(w.Y[l]);
-    // BF16: the stored BF16 filters; FP32: z3, from which the gathers form h = phi silu(z3)
-    const TH *hl = reinterpret_cast<const TH *>(BF16 ? w.h[l] : w.z3[l]);
-    const float *hphi = BF16 ? nullptr : w.phi;
+    // z3, from which the gathers form h = phi silu(z3)
+    const TH *hl = reinterpret_cast<const TH *>(w.z3[l]);
+    const float *hphi = w.phi;
     if (BF16) {
       if ((rc = message_product_w(s, F, N, rowptr, nbr, pid, np, MP, hl, hphi, yg, w.mix16, w.Y[l], w.M[l],
                                   w.P[l], w.nP[l])))
@@ -367,8 +364,8 @@ int run_fused(const tn_model *m, hipStream_t s, const Problem &pb, void *ws, siz
       TN_LAUNCH_CHECK();
     }
     const TY *dmg = BF16 ? reinterpret_cast<const TY *>(w.dM16[l]) : reinterpret_cast<const TY *>(w.dM[l]);
-    const TH *hl = reinterpret_cast<const TH *>(BF16 ? w.h[l] : w.z3[l]);
-    const float *hphi = BF16 ? nullptr : w.phi;
+    const TH *hl = reinterpret_cast<const TH *>(w.z3[l]);
+    const float *hphi = w.phi;
     if (BF16) {   // dY + the gathered sum, rounded to BF16 for the mixing
       if ((rc = message_w(s, F, N, rowptr, nbr, pid, np, MP, hl, hphi, dmg, w.mix16, 1, (const float *)w.dY)))
         return rc;

@@ -78,7 +78,7 @@ __host__ __device__ inline void plan_mol(WsPlan &p, int64_t F, int64_t L, int64_
     w->z1[l] = p.take<float>(MP * F);   // MP is a multiple of 16 (whole 16-pair blocks)
     w->z2[l] = p.take<float>(MP * 2 * F);
     w->z3[l] = p.take<float>(MP * 3 * F);
-    w->h[l] = p.take<float>(MP * 3 * F);
+    w->h[l] = nullptr;   // not stored (formed from z3 and phi where needed)
     w->M[l] = p.take<float>(N * 9 * F);
     w->P[l] = p.take<float>(N * 9 * F);
     w->nP[l] = p.take<float>(N * F);
@@ -302,14 +302,14 @@ __global__ void __launch_bounds__(kMolThreads) k_mol_setup(MolCall c) {
     a->pf.z1[l] = w.z1[l];
     a->pf.z2[l] = w.z2[l];
     a->pf.z3[l] = w.z3[l];
-    a->pf.h[l] = w.h[l];
+    a->pf.h[l] = nullptr;   // not stored: the message gathers form h from z3 and phi
     a->pb.z1[l] = w.z1[l];
     a->pb.z2[l] = w.z2[l];
     a->pb.z3[l] = w.z3[l];
     a->pfb.z1[l] = reinterpret_cast<__bf16 *>(w.z1[l]);
     a->pfb.z2[l] = reinterpret_cast<__bf16 *>(w.z2[l]);
     a->pfb.z3[l] = reinterpret_cast<__bf16 *>(w.z3[l]);
-    a->pfb.h[l] = reinterpret_cast<__bf16 *>(w.h[l]);
+    a->pfb.h[l] = nullptr;
     a->pbb.z1[l] = reinterpret_cast<const __bf16 *>(w.z1[l]);
     a->pbb.z2[l] = reinterpret_cast<const __bf16 *>(w.z2[l]);
     a->pbb.z3[l] = reinterpret_cast<const __bf16 *>(w.z3[l]);
@@ -524,9 +524,9 @@ __global__ void __launch_bounds__(kMolThreads, 1)
       mix_rows(w.Xb[l], w.Y[l], wt.W1l[l], wt.W1l16[l], 0, BF16 ? w.Y16[l] : nullptr);
       const TY *yg = BF16 ? reinterpret_cast<const TY *>(w.Y16[l]) : reinterpret_cast<const TY *>(w.Y[l]);
       atoms_waves([&](int32_t i, int f) {
-        message_product_wave<V, G, TH, TY>(i, f, w.rowbeg[i], w.rowbeg[i] + w.deg[i], w.nbr, w.pid,
-                                           reinterpret_cast<const TH *>(w.h[l]), yg, w.Y[l], w.M[l], w.P[l],
-                                           w.nP[l], w.Pb[l]);
+        message_product_wave<V, G, TH, TY, float, true>(i, f, w.rowbeg[i], w.rowbeg[i] + w.deg[i], w.nbr, w.pid,
+                                                        reinterpret_cast<const TH *>(w.z3[l]), yg, w.Y[l], w.M[l],
+                                                        w.P[l], w.nP[l], w.Pb[l], w.phi);
       });
       __syncthreads();
       mix_rows(w.Pb[l], w.D[l], wt.W2l[l], wt.W2l16[l], 0);
@@ -586,8 +586,9 @@ __global__ void __launch_bounds__(kMolThreads, 1)
       __syncthreads();
       const TY *dmg = BF16 ? reinterpret_cast<const TY *>(w.dM16[l]) : reinterpret_cast<const TY *>(w.dM[l]);
       atoms_waves([&](int32_t i, int f) {
-        message_wave<V, G, TH, TY>(i, f, w.rowbeg[i], w.rowbeg[i] + w.deg[i], w.nbr, w.pid,
-                                   reinterpret_cast<const TH *>(w.h[l]), dmg, w.dY, 1);
+        message_wave<V, G, TH, TY, float, true>(i, f, w.rowbeg[i], w.rowbeg[i] + w.deg[i], w.nbr, w.pid,
+                                                reinterpret_cast<const TH *>(w.z3[l]), dmg, w.dY, 1, nullptr,
+                                                w.phi);
       });
       __syncthreads();
       mix_rows(w.dY, w.dX, wt.W1Tl[l], wt.W1Tl16[l], 1);

@@ -1599,15 +1599,15 @@ __global__ void __launch_bounds__(256) k_embed_gather_w(int64_t n, const int32_t
 }
 
 // c[q] = sum over the CSR row [e0, e1) of h_part(q)(pair) * Y_j[q]; h (TH) and the gathered
-// rows Y (TY) in FP32 or BF16.  With HZ, h holds the pre-activations z3 (FP32) and the filter is
-// formed here as phi silu(z3), the expression the forward pair kernel would have stored.
+// rows Y (TY) in FP32 or BF16.  With HZ, h holds the pre-activations z3 (TH: FP32, or BF16 in
+// the BF16 path) and the filter is formed here as phi silu(z3), in FP32: in FP32 the expression
+// the forward pair kernel would have stored, bit for bit.
 template <int V, int G, class TH, class TY, bool HZ = false>
 __device__ __forceinline__ void gather_message(int32_t e0, int32_t e1, const int32_t *__restrict__ nbr,
                                                const int32_t *__restrict__ pid, const TH *__restrict__ h,
                                                const TY *__restrict__ Y, int f, float (&c)[9][V],
                                                const float *__restrict__ hphi = nullptr) {
   constexpr int F = 64 * V * G;
-  static_assert(!HZ || std::is_same<TH, float>::value, "z3 is FP32");
 #pragma unroll
   for (int q = 0; q < 9; ++q)
 #pragma unroll
@@ -1863,14 +1863,11 @@ inline int embed_gather_w(hipStream_t s, int64_t F, int64_t n, const int32_t *ro
 // wave per atom, two channels per lane, so each load moves 4 bytes instead of 2 (on 100k
 // atoms 1.51 / 1.28 ms per launch against 1.65 / 1.45; for FP32 rows the same shape is 1.3 ms
 // per step slower).  Each channel's sum runs over the same edges in the same order either way.
-// hphi: when given (FP32 h only), h holds z3 and the kernels form phi silu(z3) themselves.
+// hphi: when given, h holds z3 and the kernels form phi silu(z3) themselves.
 #define TN_MESSAGE_LAUNCH_HZ(KERNEL, VV, GG, GRID)                                                         \
   if (hphi) {                                                                                              \
-    if constexpr (std::is_same<TH, float>::value)                                                         \
-      hipLaunchKernelGGL((KERNEL<VV, GG, TH, TY, TO, true>), dim3(GRID), b, 0, s, n, rowptr, nbr, pid,      \
-                         n_pairs, max_pairs, h, hphi, y, o, a...);                                        \
-    else                                                                                                   \
-      return TN_E_UNSUPPORTED;                                                                             \
+    hipLaunchKernelGGL((KERNEL<VV, GG, TH, TY, TO, true>), dim3(GRID), b, 0, s, n, rowptr, nbr, pid,        \
+                       n_pairs, max_pairs, h, hphi, y, o, a...);                                          \
   } else {                                                                                                 \
     hipLaunchKernelGGL((KERNEL<VV, GG, TH, TY, TO, false>), dim3(GRID), b, 0, s, n, rowptr, nbr, pid,       \
                        n_pairs, max_pairs, h, hphi, y, o, a...);                                          \

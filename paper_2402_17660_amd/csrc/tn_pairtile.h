@@ -906,12 +906,12 @@ __device__ __forceinline__ void pair_fwd_tile_bf16(const PairFwdArgsB &a, int64_
       floatx4 br[NB];
       load_cols_t<NB>(a.bc[l], col0, br);
       wave_mm_bf16<RB, NB, true>(sA2, L2, 2 * F, a.Wc[l], col0, acc);
-      __bf16 *z3 = a.z3[l], *h = a.h[l];
+      __bf16 *z3 = a.z3[l], *h = a.h[l];   // h only when given (see pair_fwd_tile)
       for_acc_t(acc, col0, [&](int, int cb, int row, int col, floatx4 &v) {
         if (row < nvalid) {
           v += br[cb];
           st4(z3 + (p0 + row) * 3 * F + col, v);
-          st4(h + (p0 + row) * 3 * F + col, (float)sPhi[row] * silu4(v));
+          if (h) st4(h + (p0 + row) * 3 * F + col, (float)sPhi[row] * silu4(v));
         }
       });
     }
