@@ -5,9 +5,10 @@
 // mixing is linear and runs in FP32) and the output network in FP64 ("islands"), reading and
 // writing the FP32 feature arrays directly; the per-system energy sum and the per-atom force
 // sum in FP64.  The BF16 variant feeds the pair kernels' GEMMs and the channel mixing BF16
-// operands (FP32 accumulation and FP32 feature arrays), stores the edge filters h and copies
+// operands (FP32 accumulation and FP32 feature arrays), stores the pre-activations and copies
 // of Y and dE/dM in BF16 for the message gathers, and runs the islands in FP32 (its error
-// budget is set by the BF16 operands).
+// budget is set by the BF16 operands).  In both precisions the edge filters h = phi silu(z3)
+// are not stored: the message gathers form them from z3 and phi.
 #include "tn_nodeops.h"
 
 namespace tn {

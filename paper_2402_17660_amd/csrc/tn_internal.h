@@ -196,7 +196,8 @@ struct PairFwdArgs {
   int L = 0;
   float *geo = nullptr, *phi = nullptr, *f0 = nullptr;
   // per pair and layer: z1, z2 hold silu'(z1), silu'(z2) (the reverse pass's only use of them),
-  // z3 the pre-activation itself, h the filters
+  // z3 the pre-activation itself, h the filters phi silu(z3) (null: not stored; the fused and
+  // molecule paths form them from z3 in the message gathers)
   float *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers], *h[kMaxLayers];
 };
 
@@ -230,7 +231,7 @@ struct PairBwdArgs {
 int launch_pair_fwd(hipStream_t s, int F, int K, const PairFwdArgs &a, int variant);
 int launch_pair_bwd(hipStream_t s, int F, int K, const PairBwdArgs &a, int variant);
 
-// BF16-operand variants: weights, stored pre-activations and the edge filters h in BF16;
+// BF16-operand variants: weights, stored pre-activations and (when stored) the edge filters h in BF16;
 // biases, basis constants, f0 and every other stored quantity in FP32/FP64 as above.
 struct PairFwdArgsB {
   const int32_t *pairs = nullptr;
@@ -248,7 +249,7 @@ struct PairFwdArgsB {
   float *geo = nullptr, *phi = nullptr;
   __bf16 *f0 = nullptr;   // the embedding map W0 e + b0 in BF16
   __bf16 *z1[kMaxLayers], *z2[kMaxLayers], *z3[kMaxLayers];
-  __bf16 *h[kMaxLayers];   // the edge filters in BF16 (read by the message gathers)
+  __bf16 *h[kMaxLayers];   // the edge filters in BF16, or null: not stored (formed from z3 by the gathers)
 };
 
 struct PairBwdArgsB {

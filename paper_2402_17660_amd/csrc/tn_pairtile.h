@@ -5,11 +5,12 @@
 // evaluated once per unordered pair, in one pass over pair tiles:
 //   forward   geometry + basis (FP64) -> f0 = W0 e + b0 -> per layer
 //             z1 = Wa e + ba, z2 = Wb silu(z1) + bb, z3 = Wc silu(z2) + bc, h = phi silu(z3)
+//             (h stored only when asked for: the message gathers can form it from z3)
 //   reverse   dE/df0, dE/dphi, dE/dvhat of the embedding and, per layer, dh from the two
 //             atoms' adjoint rows (gathered in the tile's prologue), then per layer
 //             dz3 = dh phi silu'(z3), dz2 = (dz3 Wc) silu'(z2), dz1 = (dz2 Wb) silu'(z1),
 //             de += dz1 Wa;  de += df0 W0;  then dE/dv from de, dE/dphi, dE/dvhat (FP64)
-// Tiles hold 16 RB pairs (RB = 1 to 4; see the launchers); the NW waves of a workgroup
+// Tiles hold 16 RB pairs (RB = 1 to 7; see the launchers); the NW waves of a workgroup
 // split the output columns, each wave covering all rows in RB 16-row MFMA blocks.
 // Activations live in LDS (row padding of
 // 4 floats), weights stream from L2 as 16-byte loads.  The K index inside each 16-wide
@@ -779,7 +780,8 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_pair_bwd(PairBwdArgs a) {
 // GEMM operands (basis, activations, adjoints and weights) in BF16, FP32 accumulation
 // (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..8(l/16)+7] and
 // B[8(l/16)..+7][l%16]).  Tiles of 16 RB pairs (RB 16-row blocks), so every weight fragment
-// read from L2 feeds RB MFMAs.  Pre-activations and the filters h are stored in BF16.
+// read from L2 feeds RB MFMAs.  Pre-activations (and, when asked for, the filters h) are stored
+// in BF16.
 
 // acc[rb][cb] += act[16*RB x Kin] (LDS bf16, row stride ld) * Bt^T (Bt [ncol][Kin] bf16 in global
 // memory); with TR the operands of each instruction are swapped and the accumulator holds the
