@@ -87,8 +87,9 @@ void plan_fused(WsPlan &p, const tn_model *m, int64_t N, int64_t MP, const BoxIn
   // no h per pair: the message gathers form it from z3 and phi
   w->h.assign(L, nullptr);
   per_layer(w->M, N * 9 * F);
-  per_layer(w->P, N * 9 * F);
-  per_layer(w->nP, N * F);
+  // P and ||P|| are formed again by the reverse pass (product_bwd_at), not stored
+  w->P.assign(L, nullptr);
+  w->nP.assign(L, nullptr);
   if (bf16) {   // Pb goes to mix16 in BF16
     w->Pb.assign(L, nullptr);
     w->mix16 = p.take<__bf16>(N * 9 * F);

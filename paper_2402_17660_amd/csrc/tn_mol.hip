@@ -80,8 +80,8 @@ __host__ __device__ inline void plan_mol(WsPlan &p, int64_t F, int64_t L, int64_
     w->z3[l] = p.take<float>(MP * 3 * F);
     w->h[l] = nullptr;   // not stored (formed from z3 and phi where needed)
     w->M[l] = p.take<float>(N * 9 * F);
-    w->P[l] = p.take<float>(N * 9 * F);
-    w->nP[l] = p.take<float>(N * F);
+    w->P[l] = nullptr;   // formed again by the reverse pass, as in the fused path
+    w->nP[l] = nullptr;
     w->Pb[l] = p.take<float>(N * 9 * F);
     w->D[l] = p.take<float>(N * 9 * F);
     w->Y16[l] = std::is_same<TA, float>::value ? p.take<__bf16>(N * 9 * F) : nullptr;

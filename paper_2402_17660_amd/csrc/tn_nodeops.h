@@ -1209,7 +1209,23 @@ __global__ void k_residual_bwd(int64_t n, int F, const T *D, const T *dX, TO *dD
   residual_bwd_at<T, TO>(t, F, D, dX, dD);
 }
 
-// Through Pb = P/(||P||+1) and P = Y M + M Y: dY (overwritten) and dM.
+// P = Y M + M Y for one channel (the product of the interaction layer), from the nine
+// coordinates of Y and M to those of P.
+template <class T>
+__device__ __forceinline__ void sym_product(const T y9[9], const T m9[9], T p9[9]) {
+  T Ym[9], Mm[9], A1[9], A2[9];
+  rec(y9, Ym);
+  rec(m9, Mm);
+  mm(Ym, Mm, A1);
+  mm(Mm, Ym, A2);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) A1[q] += A2[q];
+  dec(A1, p9);
+}
+
+// Through Pb = P/(||P||+1) and P = Y M + M Y: dY (overwritten) and dM.  With P null, P and
+// ||P|| are formed again from Y and M (sym_product, norm9: the forward's arithmetic) instead
+// of being read.
 template <class T>
 __device__ inline void product_bwd_at(int64_t t, int F, const T *dPb, const T *P, const T *nP, const T *Y, const T *M, T *dY, T *dM,
                                __bf16 *dM16 = nullptr) {
@@ -1217,8 +1233,18 @@ __device__ inline void product_bwd_at(int64_t t, int F, const T *dPb, const T *P
   const int f = (int)(t % F);
   T g[9], pc[9], gn[9];
   load9(dPb, i, F, f, g);
-  load9(P, i, F, f, pc);
-  const T s = T(1) / (nP[i * F + f] + T(1));
+  T pn;
+  if (P) {
+    load9(P, i, F, f, pc);
+    pn = nP[i * F + f];
+  } else {
+    T y9[9], m9[9];
+    load9(Y, i, F, f, y9);
+    load9(M, i, F, f, m9);
+    sym_product(y9, m9, pc);
+    pn = norm9(pc);
+  }
+  const T s = T(1) / (pn + T(1));
   T dot = T(0);
 #pragma unroll
   for (int q = 0; q < 9; ++q) dot += g[q] * pc[q];
@@ -1713,7 +1739,8 @@ __global__ void __launch_bounds__(256) k_message_w(int64_t n, const int32_t *__r
                                      accumulate, Mold, hphi);
 }
 
-// M_i = sum_j h_part(c) * Y_j[c]; P = Y M + M Y; Pb = P / (||P|| + 1).  Writes M, P, ||P||, Pb.
+// M_i = sum_j h_part(c) * Y_j[c]; P = Y M + M Y; Pb = P / (||P|| + 1).  Writes M, Pb and, when
+// P is given, P and ||P||.
 // The neighbours' rows come from Yg (TY: Y itself, or its BF16 copy), the atom's own from Y;
 // Pb in FP32 or, for a consumer that rounds it to BF16 anyway, BF16 (TO).
 template <int V, int G, class TH, class TY, class TO = float, bool HZ = false>
@@ -1736,26 +1763,22 @@ __device__ __forceinline__ void message_product_wave(int32_t i, int f, int32_t e
   float pc[9][V], nn[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    float y9[9], m9[9], Ym[9], Mm[9], A1[9], A2[9], p9[9];
+    float y9[9], m9[9], p9[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       y9[q] = yc[q][v];
       m9[q] = mc[q][v];
     }
-    rec(y9, Ym);
-    rec(m9, Mm);
-    mm(Ym, Mm, A1);
-    mm(Mm, Ym, A2);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) A1[q] += A2[q];
-    dec(A1, p9);
+    sym_product(y9, m9, p9);
 #pragma unroll
     for (int q = 0; q < 9; ++q) pc[q][v] = p9[q];
     nn[v] = norm9(p9);
   }
+  if (P) {   // null: the reverse pass forms P and its norms again from Y and M
 #pragma unroll
-  for (int q = 0; q < 9; ++q) stv<V>(P + base + q * F, pc[q]);
-  stv<V>(nP + (int64_t)i * F + f, nn);
+    for (int q = 0; q < 9; ++q) stv<V>(P + base + q * F, pc[q]);
+    stv<V>(nP + (int64_t)i * F + f, nn);
+  }
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const float sc = 1.f / (nn[v] + 1.f);
